@@ -1,0 +1,241 @@
+"""FP64 CPU oracle for the perspective-relaxation hot path (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+library never calls it, shares no code with it, and has no fallback to it.
+
+All arrays are numpy float64 (vectors) plus the stored design matrix in its
+storage dtype (column-major, i.e. a C-contiguous ``(p, n)`` array whose row j
+is column j of X).  Function names follow the paper: ``g`` is Algorithm 1,
+``prox_gstar`` Algorithm 2, ``prox_g`` the Moreau identity (prox:gN), ``gstar``
+the closed form of the conjugate, ``dual`` the Fenchel dual objective.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+FREE, ZERO, ONE = 0, 1, 2
+LSQ, LOGISTIC = 0, 1
+F64, F32, BF16 = 0, 1, 2
+CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
+
+_lib = None
+
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_p = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.orc_huber.restype = _d
+        L.orc_huber.argtypes = [_d, _d]
+        L.orc_prox_huber.restype = _d
+        L.orc_prox_huber.argtypes = [_d, _d, _d]
+        L.orc_g.restype = _d
+        L.orc_g.argtypes = [_p, _p, _i64, _i32]
+        L.orc_in_dom.restype = ctypes.c_int
+        L.orc_in_dom.argtypes = [_p, _p, _i64, _i32, _d, _d]
+        L.orc_gstar.restype = _d
+        L.orc_gstar.argtypes = [_p, _p, _i64, _i32, _d]
+        L.orc_prox_gstar.restype = None
+        L.orc_prox_gstar.argtypes = [_p, _p, _i64, _d, _i32, _d, _p]
+        L.orc_prox_g.restype = None
+        L.orc_prox_g.argtypes = [_p, _p, _i64, _d, _i32, _d, _p]
+        L.orc_loss.restype = _d
+        L.orc_loss.argtypes = [ctypes.c_int, _p, _p, _i64]
+        L.orc_loss_grad.restype = None
+        L.orc_loss_grad.argtypes = [ctypes.c_int, _p, _p, _i64, _p]
+        L.orc_neg_conj.restype = _d
+        L.orc_neg_conj.argtypes = [ctypes.c_int, _p, _p, _i64]
+        L.orc_matvec.restype = None
+        L.orc_matvec.argtypes = [_p, ctypes.c_int, _i64, _i64, _p, _p]
+        L.orc_rmatvec.restype = None
+        L.orc_rmatvec.argtypes = [_p, ctypes.c_int, _i64, _i64, _p, _p]
+        L.orc_power_norm2.restype = _d
+        L.orc_power_norm2.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, _d]
+        L.orc_primal.restype = _d
+        L.orc_primal.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p, _p]
+        L.orc_dual.restype = _d
+        L.orc_dual.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p, _p]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_solve.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p,
+                                _d, _d, _d, _i64, _d, _p, _p, _p, _p, _p, _i64]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _st(status, p):
+    if status is None:
+        return np.zeros(p, dtype=np.int8)
+    s = np.ascontiguousarray(status, dtype=np.int8)
+    assert s.shape == (p,)
+    return s
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _xinfo(Xcm):
+    """(pointer-holding array, dtype code, n, p) for a column-major matrix
+    given as a C-contiguous (p, n) array (float64, float32 or uint16 bf16 bits)."""
+    X = np.ascontiguousarray(Xcm)
+    if X.dtype == np.float64:
+        code = F64
+    elif X.dtype == np.float32:
+        code = F32
+    elif X.dtype == np.uint16:
+        code = BF16
+    else:
+        raise TypeError(f"unsupported matrix dtype {X.dtype}")
+    p, n = X.shape
+    return X, code, n, p
+
+
+def status_vector(p, J0=(), J1=()):
+    s = np.zeros(p, dtype=np.int8)
+    s[list(J0)] = ZERO
+    s[list(J1)] = ONE
+    return s
+
+
+def huber(a, M):
+    return lib().orc_huber(float(a), float(M))
+
+
+def prox_huber(u, c, M):
+    return lib().orc_prox_huber(float(u), float(c), float(M))
+
+
+def g(beta, k, status=None):
+    b = _f64(beta)
+    s = _st(status, b.size)
+    return lib().orc_g(_ptr(b), _ptr(s), b.size, int(k))
+
+
+def in_dom(beta, k, M, status=None, rtol=1e-9):
+    b = _f64(beta)
+    s = _st(status, b.size)
+    return bool(lib().orc_in_dom(_ptr(b), _ptr(s), b.size, int(k), float(M), float(rtol)))
+
+
+def gstar(alpha, k, M, status=None):
+    a = _f64(alpha)
+    s = _st(status, a.size)
+    return lib().orc_gstar(_ptr(a), _ptr(s), a.size, int(k), float(M))
+
+
+def prox_gstar(b, rho, k, M, status=None):
+    b = _f64(b)
+    s = _st(status, b.size)
+    out = np.empty_like(b)
+    lib().orc_prox_gstar(_ptr(b), _ptr(s), b.size, float(rho), int(k), float(M), _ptr(out))
+    return out
+
+
+def prox_g(v, rho, k, M, status=None):
+    v = _f64(v)
+    s = _st(status, v.size)
+    out = np.empty_like(v)
+    lib().orc_prox_g(_ptr(v), _ptr(s), v.size, float(rho), int(k), float(M), _ptr(out))
+    return out
+
+
+def loss(kind, u, y):
+    u = _f64(u)
+    y = _f64(y)
+    return lib().orc_loss(int(kind), _ptr(u), _ptr(y), u.size)
+
+
+def loss_grad(kind, u, y):
+    u = _f64(u)
+    y = _f64(y)
+    out = np.empty_like(u)
+    lib().orc_loss_grad(int(kind), _ptr(u), _ptr(y), u.size, _ptr(out))
+    return out
+
+
+def neg_conj(kind, zeta, y):
+    z = _f64(zeta)
+    y = _f64(y)
+    return lib().orc_neg_conj(int(kind), _ptr(z), _ptr(y), z.size)
+
+
+def matvec(Xcm, b):
+    X, code, n, p = _xinfo(Xcm)
+    b = _f64(b)
+    out = np.empty(n)
+    lib().orc_matvec(_ptr(X), code, n, p, _ptr(b), _ptr(out))
+    return out
+
+
+def rmatvec(Xcm, r):
+    X, code, n, p = _xinfo(Xcm)
+    r = _f64(r)
+    out = np.empty(p)
+    lib().orc_rmatvec(_ptr(X), code, n, p, _ptr(r), _ptr(out))
+    return out
+
+
+def power_norm2(Xcm, max_iter=2000, tol=1e-12):
+    X, code, n, p = _xinfo(Xcm)
+    return lib().orc_power_norm2(_ptr(X), code, n, p, int(max_iter), float(tol))
+
+
+def primal(Xcm, y, beta, kind, lambda2, M, k, status=None):
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    b = _f64(beta)
+    s = _st(status, p)
+    return lib().orc_primal(_ptr(X), code, _ptr(y), n, p, int(kind), float(lambda2), float(M),
+                            int(k), _ptr(s), _ptr(b))
+
+
+def dual(Xcm, y, zeta, kind, lambda2, M, k, status=None):
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    z = _f64(zeta)
+    s = _st(status, p)
+    return lib().orc_dual(_ptr(X), code, _ptr(y), n, p, int(kind), float(lambda2), float(M),
+                          int(k), _ptr(s), _ptr(z))
+
+
+def solve(Xcm, y, kind, lambda2, M, k, status=None, L=0.0, tol=1e-8, eta=math.exp(3.0),
+          max_iter=100000, cutoff=float("nan"), beta0=None, trace_cap=0):
+    """FISTA + duality-gap restart.  Returns a dict with lb, ub, rel_gap, L,
+    iters, restarts, status, beta, zeta (dual vector attaining lb), trace."""
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    s = _st(status, p)
+    b0 = None if beta0 is None else _f64(beta0)
+    beta = np.empty(p)
+    zeta = np.empty(n)
+    res = np.zeros(8)
+    trace = np.full(max(trace_cap, 1), np.nan)
+    lib().orc_solve(_ptr(X), code, _ptr(y), n, p, int(kind), float(lambda2), float(M), int(k),
+                    _ptr(s), float(L), float(tol), float(eta), int(max_iter), float(cutoff),
+                    None if b0 is None else _ptr(b0), _ptr(beta), _ptr(zeta), _ptr(res),
+                    _ptr(trace) if trace_cap > 0 else None, int(trace_cap))
+    return dict(lb=res[0], ub=res[1], rel_gap=res[2], L=res[3], iters=int(res[4]),
+                restarts=int(res[5]), status=int(res[6]), beta=beta, zeta=zeta,
+                trace=trace[: int(res[4]) + 1] if trace_cap > 0 else None)
+
+
+def num_threads():
+    return lib().orc_num_threads()
