@@ -1,0 +1,178 @@
+/*
+ * pr.h -- C ABI of libpr: certified lower bounds for branch-and-bound nodes of
+ * cardinality-constrained GLMs on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2603.01306.  Each node relaxation is the perspective
+ * relaxation (Section 2.3, eq. perspective_relaxation over the domain D) in
+ * composite form Phi(beta) = F(X beta) + 2 lambda2 g_N(beta) (Section 2.4),
+ * solved by FISTA with the duality-gap restart (Section 3.3 and "Restart in
+ * practice"); every iterate's induced dual vector zeta = -grad F(X beta)
+ * (Section 3.2) gives the weak-duality lower bound Psi(zeta) =
+ * -F*(-zeta) - G*(X^T zeta) (eq. fenchel_dual), evaluated in FP64.
+ *
+ * Losses (the paper does not spell them out; this library's reading):
+ *   PR_LSQ      F(u) = ||u - y||^2
+ *   PR_LOGISTIC F(u) = sum_i log(1 + exp(-y_i u_i)),  y_i in {-1, +1}
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" are caller-owned device memory that must
+ *     stay valid for the duration of the call; pointers documented "host" are
+ *     caller-owned host memory.  Nothing is retained after a call returns
+ *     except what lives inside a pr_ctx (its workspace and cached ||X||^2).
+ *   - X is column-major n x p with leading dimension n (column j at X + j*n).
+ *     Vectors of length n or p are contiguous FP64.
+ *   - Calls on one pr_ctx must not overlap (one context per stream).  All
+ *     calls are synchronous with respect to the host: results are complete
+ *     when they return.  Work is ordered on the context's stream.
+ *   - Return value: PR_OK (0) or a negative error code (pr_strerror).  On
+ *     error no output is written unless stated.
+ */
+#ifndef PR_H
+#define PR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes (negative) */
+#define PR_OK 0
+#define PR_EINVAL (-1)   /* bad size, parameter, dtype or index */
+#define PR_EOVERLAP (-2) /* J0 and J1 share an index */
+#define PR_EDEVICE (-3)  /* a HIP runtime call failed */
+#define PR_ENOMEM (-4)   /* device or host allocation failed */
+
+/* per-node status codes (positive, in pr_result.status) */
+#define PR_CONVERGED 1    /* (UB - LB) / |UB| <= rel_gap_tol */
+#define PR_MAXITER 2      /* iteration limit; lower_bound is still valid */
+#define PR_INFEASIBLE 3   /* |J1| > k: empty domain, lower_bound = +inf */
+#define PR_CUTOFF_PRUNE 4 /* lower_bound >= cutoff (Section 5.3, rule 2) */
+#define PR_CUTOFF_BRANCH 5 /* primal <= cutoff (Section 5.3, rule 1) */
+
+/* node-status codes of a coordinate (pr_prox, pr_regularizer) */
+#define PR_FREE 0  /* j in J_f: z_j in [0, 1] */
+#define PR_ZERO 1  /* j in J_0: z_j = 0 */
+#define PR_ONE 2   /* j in J_1: z_j = 1 */
+
+typedef enum { PR_LSQ = 0, PR_LOGISTIC = 1 } pr_loss;
+typedef enum { PR_F64 = 0, PR_F32 = 1, PR_BF16 = 2 } pr_dtype;
+
+/* Problem data shared by every node of a tree (Section 2.3, problem (1)). */
+typedef struct {
+  const void *X;  /* device, column-major n x p, element type xdtype */
+  int32_t xdtype; /* pr_dtype; PR_F64/PR_F32 need n % 2 / n % 4 == 0 for
+                     vector loads, PR_BF16 needs n % 8 == 0 */
+  int32_t loss;   /* pr_loss */
+  const double *y; /* device, n; for PR_LOGISTIC every y_i is -1 or +1 */
+  int64_t n, p;    /* n >= 1, p >= 1 */
+} pr_problem;
+
+/* One branch-and-bound node: cardinality k, ridge weight lambda2, box M and
+ * the fixed-zero / fixed-one index sets J0, J1 (domain D, Section 2.3). */
+typedef struct {
+  int32_t k;       /* >= 1 */
+  int32_t pad0;
+  double lambda2;  /* > 0 */
+  double M;        /* > 0; +INFINITY allowed (no box) */
+  const int32_t *J0; /* host, n0 indices in [0, p), may be NULL when n0 = 0 */
+  int64_t n0;
+  const int32_t *J1; /* host, n1 indices in [0, p) */
+  int64_t n1;
+} pr_node;
+
+typedef struct {
+  double rel_gap_tol; /* stop when (UB - LB) / |UB| <= tol; default 1e-6 */
+  double eta;         /* restart factor (> 1); default e^3 */
+  double cutoff;      /* incumbent value for dynamic termination; NaN = off */
+  double L;           /* step 1/L; 0 = 1.01 * loss curvature * ||X||^2 estimate */
+  int32_t max_iter;   /* default 100000 */
+  int32_t check_every; /* iterations per captured graph launch; default 32 */
+} pr_opts;
+
+typedef struct {
+  double lower_bound; /* best Psi(zeta^t) seen: a valid bound on the node */
+  double primal;      /* best Phi(beta^t) seen */
+  double rel_gap;     /* (primal - lower_bound) / |primal| */
+  double L;           /* step constant used */
+  int32_t iters;      /* proximal-gradient steps taken */
+  int32_t restarts;   /* duality-gap restarts */
+  int32_t status;     /* PR_CONVERGED ... PR_CUTOFF_BRANCH */
+  int32_t pad0;
+} pr_result;
+
+typedef struct pr_ctx pr_ctx;
+
+/* Fill opts with the defaults listed in pr_opts. */
+void pr_opts_default(pr_opts *opts);
+
+/* Create a context for problem `prob` on HIP stream `stream` (a hipStream_t;
+ * NULL = the default stream) of the current device.  Estimates ||X||_2^2 by
+ * power iteration on X^T X (used for the step 1/L, Section 5.2 FISTA) and
+ * allocates a workspace for up to max_batch nodes (>= 1).  X and y are not
+ * copied: they must outlive the context and must not change. */
+int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void *stream);
+int pr_ctx_destroy(pr_ctx *ctx);
+/* Cached estimate of ||X||_2^2 (largest eigenvalue of X^T X). */
+int pr_ctx_norm2(pr_ctx *ctx, double *norm2_out);
+
+/* Solve one node relaxation (Sections 3.3 and 4): FISTA steps
+ * x = prox_{(2 lambda2 / L) g_N}(y - grad/L) with the Algorithm 2 prox,
+ * Phi with the Algorithm 1 value of g_N, Psi with the closed-form conjugate
+ * (Lemma function_g_conjugate_in_BnB), restart when the gap falls by eta.
+ *   beta0    device p or NULL (start at 0); any point is allowed, a point off
+ *            dom g_N only makes the first primal value +inf (warm start).
+ *   beta_out device p or NULL: the iterate attaining `primal`.
+ *   zeta_out device n or NULL: the dual vector attaining lower_bound.
+ *   out      host. */
+int pr_solve(pr_ctx *ctx, const pr_node *node, const pr_opts *opts, const double *beta0,
+             double *beta_out, double *zeta_out, pr_result *out);
+
+/* prox_{rho g_N}(v) by the extended Moreau decomposition (eq. prox:gN) and
+ * Algorithm 2, for the node given by `status` (device int8 p, PR_FREE /
+ * PR_ZERO / PR_ONE) and cardinality k (kbar = k - |J1| clipped to |J_f|).
+ *   v, out device p (may alias), rho > 0, M > 0 (or +inf).
+ *   stream: hipStream_t or NULL.  Returns PR_EINVAL if |J1| > k. */
+int pr_prox(void *stream, const double *v, int64_t p, double rho, int32_t k, double M,
+            const int8_t *status, double *out);
+
+/* g_N(beta) by Algorithm 1 (+inf off dom g_N, tested with relative slack
+ * 1e-9) and g_N*(alpha) by Lemma function_g_conjugate_in_BnB, each skipped
+ * when its input pointer is NULL.  beta, alpha, status device p; outputs host. */
+int pr_regularizer(void *stream, const double *beta, const double *alpha, int64_t p, int32_t k,
+                   double M, const int8_t *status, double *g_out, double *gstar_out);
+
+/* FP64 Fenchel dual bound Psi(zeta) = -F*(-zeta) - 2 lambda2 g_N*(X^T zeta /
+ * (2 lambda2)) of eq. fenchel_dual for `node`, accumulated in FP64 over the
+ * stored X values.  If zeta is NULL it is induced from beta as
+ * zeta = -grad F(X beta) (Section 3.2).  If beta is non-NULL and primal_out
+ * non-NULL, Phi(beta) is returned as well.
+ *   zeta device n or NULL, beta device p or NULL (not both NULL),
+ *   lb_out, primal_out host. */
+int pr_dual_bound(pr_ctx *ctx, const pr_node *node, const double *zeta, const double *beta,
+                  double *lb_out, double *primal_out);
+
+/* Dense products with the context's X, FP64 accumulation (test and
+ * measurement entry points; the solver uses the same kernels).
+ *   pr_gemv:   u = X b,   b device p, u device n
+ *   pr_gemv_t: h = X^T r, r device n, h device p */
+int pr_gemv(pr_ctx *ctx, const double *b, double *u);
+int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
+
+/* Solve m nodes that share X (m <= max_batch).  B0 device p*m (column i =
+ * warm start of node i) or NULL; B_out device p*m or NULL; out host m. */
+int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *opts,
+                   const double *B0, double *B_out, pr_result *out);
+
+/* Time `reps` back-to-back launches of the X^T r kernel (the solver's
+ * dominant kernel, same launch configuration) with HIP events on the
+ * context stream; *ms_avg = elapsed / reps.  r device n, h device p. */
+int pr_time_gemv_t(pr_ctx *ctx, const double *r, double *h, int32_t reps, double *ms_avg);
+
+const char *pr_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_H */

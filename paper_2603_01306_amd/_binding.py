@@ -1,0 +1,291 @@
+"""ctypes binding of libpr (include/pr.h).  Argument marshalling only: every
+step of the solve runs in the HIP kernels of libpr.so.  torch is used for
+device memory and the current stream.  Importing this module does not need a
+GPU; calling into the library does, and there is no fallback when libpr.so
+is missing."""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpr.so")
+
+PR_OK, PR_EINVAL, PR_EOVERLAP, PR_EDEVICE, PR_ENOMEM = 0, -1, -2, -3, -4
+CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
+FREE, ZERO, ONE = 0, 1, 2
+LSQ, LOGISTIC = 0, 1
+F64, F32, BF16 = 0, 1, 2
+
+EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
+           "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
+           "pr_time_gemv_t", "pr_strerror"]
+
+
+class PrProblem(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("xdtype", ctypes.c_int32), ("loss", ctypes.c_int32),
+                ("y", ctypes.c_void_p), ("n", ctypes.c_int64), ("p", ctypes.c_int64)]
+
+
+class PrNode(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("pad0", ctypes.c_int32), ("lambda2", ctypes.c_double),
+                ("M", ctypes.c_double), ("J0", ctypes.c_void_p), ("n0", ctypes.c_int64),
+                ("J1", ctypes.c_void_p), ("n1", ctypes.c_int64)]
+
+
+class PrOpts(ctypes.Structure):
+    _fields_ = [("rel_gap_tol", ctypes.c_double), ("eta", ctypes.c_double),
+                ("cutoff", ctypes.c_double), ("L", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class PrResult(ctypes.Structure):
+    _fields_ = [("lower_bound", ctypes.c_double), ("primal", ctypes.c_double),
+                ("rel_gap", ctypes.c_double), ("L", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("status", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(lower_bound=self.lower_bound, primal=self.primal, rel_gap=self.rel_gap, L=self.L,
+                    iters=self.iters, restarts=self.restarts, status=self.status)
+
+
+_lib = None
+
+
+def load():
+    """Load libpr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libpr.so not found at {LIB_PATH}: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.pr_opts_default.restype = None
+        L.pr_opts_default.argtypes = [ctypes.POINTER(PrOpts)]
+        L.pr_ctx_create.restype = ctypes.c_int
+        L.pr_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(PrProblem), ctypes.c_int32, P]
+        L.pr_ctx_destroy.restype = ctypes.c_int
+        L.pr_ctx_destroy.argtypes = [P]
+        L.pr_ctx_norm2.restype = ctypes.c_int
+        L.pr_ctx_norm2.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+        L.pr_solve.restype = ctypes.c_int
+        L.pr_solve.argtypes = [P, ctypes.POINTER(PrNode), ctypes.POINTER(PrOpts), P, P, P,
+                               ctypes.POINTER(PrResult)]
+        L.pr_prox.restype = ctypes.c_int
+        L.pr_prox.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                              P, P]
+        L.pr_regularizer.restype = ctypes.c_int
+        L.pr_regularizer.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.pr_dual_bound.restype = ctypes.c_int
+        L.pr_dual_bound.argtypes = [P, ctypes.POINTER(PrNode), P, P, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.pr_gemv.restype = ctypes.c_int
+        L.pr_gemv.argtypes = [P, P, P]
+        L.pr_gemv_t.restype = ctypes.c_int
+        L.pr_gemv_t.argtypes = [P, P, P]
+        L.pr_time_gemv_t.restype = ctypes.c_int
+        L.pr_time_gemv_t.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.pr_solve_batch.restype = ctypes.c_int
+        L.pr_solve_batch.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, ctypes.POINTER(PrOpts),
+                                     P, P, ctypes.POINTER(PrResult)]
+        L.pr_strerror.restype = ctypes.c_char_p
+        L.pr_strerror.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+class PrError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {load().pr_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+def _check(code, what):
+    if code != PR_OK:
+        raise PrError(code, what)
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def default_opts(**kw):
+    o = PrOpts()
+    load().pr_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if v is None:
+            continue
+        setattr(o, k, v)
+    return o
+
+
+class Node:
+    """A branch-and-bound node (k, lambda2, M, J0, J1); index arrays are kept alive here."""
+
+    def __init__(self, k, lambda2, M=2.0, J0=(), J1=()):
+        self.k = int(k)
+        self.lambda2 = float(lambda2)
+        self.M = float(M)
+        self.J0 = np.ascontiguousarray(np.asarray(J0, dtype=np.int32).ravel())
+        self.J1 = np.ascontiguousarray(np.asarray(J1, dtype=np.int32).ravel())
+
+    def c(self):
+        s = PrNode()
+        s.k = self.k
+        s.lambda2 = self.lambda2
+        s.M = self.M
+        s.J0 = self.J0.ctypes.data if self.J0.size else None
+        s.n0 = self.J0.size
+        s.J1 = self.J1.ctypes.data if self.J1.size else None
+        s.n1 = self.J1.size
+        return s
+
+    def status(self, p):
+        st = np.zeros(p, dtype=np.int8)
+        st[self.J0] = ZERO
+        st[self.J1] = ONE
+        return st
+
+
+def _xdtype(X):
+    import torch
+    if X.dtype == torch.float64:
+        return F64
+    if X.dtype == torch.float32:
+        return F32
+    if X.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported X dtype {X.dtype}")
+
+
+class Context:
+    """pr_ctx over a device-resident problem.  Xcm: CUDA tensor of shape (p, n)
+    (row j = column j of X, i.e. column-major X), float64 / float32 / bfloat16;
+    y: CUDA float64 tensor (n,)."""
+
+    def __init__(self, Xcm, y, loss, max_batch=1):
+        import torch
+        assert Xcm.is_cuda and y.is_cuda and Xcm.is_contiguous() and y.is_contiguous()
+        assert y.dtype == torch.float64
+        self.X = Xcm
+        self.y = y
+        self.p, self.n = Xcm.shape
+        self.loss = int(loss)
+        prob = PrProblem()
+        prob.X = Xcm.data_ptr()
+        prob.xdtype = _xdtype(Xcm)
+        prob.loss = self.loss
+        prob.y = y.data_ptr()
+        prob.n = self.n
+        prob.p = self.p
+        h = ctypes.c_void_p()
+        _check(load().pr_ctx_create(ctypes.byref(h), ctypes.byref(prob), int(max_batch), _stream_ptr()),
+               "pr_ctx_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def norm2(self):
+        v = ctypes.c_double()
+        _check(load().pr_ctx_norm2(self.h, ctypes.byref(v)), "pr_ctx_norm2")
+        return v.value
+
+    def solve(self, node, beta0=None, want_beta=True, want_zeta=False, **opts):
+        import torch
+        o = default_opts(**opts)
+        dev = self.X.device
+        beta = torch.empty(self.p, dtype=torch.float64, device=dev) if want_beta else None
+        zeta = torch.empty(self.n, dtype=torch.float64, device=dev) if want_zeta else None
+        if beta0 is not None:
+            beta0 = beta0.to(device=dev, dtype=torch.float64).contiguous()
+        res = PrResult()
+        nd = node.c()
+        _check(load().pr_solve(self.h, ctypes.byref(nd), ctypes.byref(o), _dptr(beta0), _dptr(beta),
+                               _dptr(zeta), ctypes.byref(res)), "pr_solve")
+        out = res.as_dict()
+        out["beta"] = beta
+        out["zeta"] = zeta
+        return out
+
+    def solve_batch(self, nodes, B0=None, want_beta=True, **opts):
+        import torch
+        o = default_opts(**opts)
+        m = len(nodes)
+        arr = (PrNode * m)(*[nd.c() for nd in nodes])
+        res = (PrResult * m)()
+        dev = self.X.device
+        Bout = torch.empty((m, self.p), dtype=torch.float64, device=dev) if want_beta else None
+        if B0 is not None:
+            B0 = B0.to(device=dev, dtype=torch.float64).contiguous()
+        _check(load().pr_solve_batch(self.h, arr, m, ctypes.byref(o), _dptr(B0), _dptr(Bout), res),
+               "pr_solve_batch")
+        return [r.as_dict() for r in res], Bout
+
+    def dual_bound(self, node, zeta=None, beta=None):
+        lb = ctypes.c_double()
+        ph = ctypes.c_double(float("nan"))
+        nd = node.c()
+        _check(load().pr_dual_bound(self.h, ctypes.byref(nd), _dptr(zeta), _dptr(beta), ctypes.byref(lb),
+                                    ctypes.byref(ph)), "pr_dual_bound")
+        return lb.value, ph.value
+
+    def gemv(self, b):
+        import torch
+        u = torch.empty(self.n, dtype=torch.float64, device=self.X.device)
+        _check(load().pr_gemv(self.h, _dptr(b.contiguous()), _dptr(u)), "pr_gemv")
+        return u
+
+    def gemv_t(self, r):
+        import torch
+        h = torch.empty(self.p, dtype=torch.float64, device=self.X.device)
+        _check(load().pr_gemv_t(self.h, _dptr(r.contiguous()), _dptr(h)), "pr_gemv_t")
+        return h
+
+    def time_gemv_t(self, r, reps=20):
+        import torch
+        h = torch.empty(self.p, dtype=torch.float64, device=self.X.device)
+        ms = ctypes.c_double()
+        _check(load().pr_time_gemv_t(self.h, _dptr(r.contiguous()), _dptr(h), int(reps), ctypes.byref(ms)),
+               "pr_time_gemv_t")
+        return ms.value
+
+
+def prox(v, rho, k, M, status):
+    """prox_{rho g_N}(v) on the device (v: CUDA float64, status: CUDA int8)."""
+    import torch
+    out = torch.empty_like(v)
+    _check(load().pr_prox(_stream_ptr(), _dptr(v.contiguous()), v.numel(), float(rho), int(k), float(M),
+                          _dptr(status.contiguous()), _dptr(out)), "pr_prox")
+    return out
+
+
+def regularizer(beta, alpha, k, M, status):
+    """(g_N(beta), g_N*(alpha)) computed on the device; either input may be None."""
+    g = ctypes.c_double(float("nan"))
+    gs = ctypes.c_double(float("nan"))
+    p = (beta if beta is not None else alpha).numel()
+    _check(load().pr_regularizer(_stream_ptr(), _dptr(beta), _dptr(alpha), p, int(k), float(M),
+                                 _dptr(status.contiguous()),
+                                 ctypes.byref(g) if beta is not None else None,
+                                 ctypes.byref(gs) if alpha is not None else None), "pr_regularizer")
+    return (g.value if beta is not None else None, gs.value if alpha is not None else None)
+
+
+E3 = math.exp(3.0)

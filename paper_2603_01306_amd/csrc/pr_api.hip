@@ -1,0 +1,544 @@
+// Host side of libpr: argument checking, workspace, the captured-graph
+// solve loop, and the C ABI declared in include/pr.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/pr.h"
+#include "pr_internal.h"
+
+using namespace pr;
+
+#define PR_TRY(expr)                          \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return PR_EDEVICE;  \
+  } while (0)
+
+namespace {
+
+int vec_of(int xdt) { return xdt == kF64 ? 2 : (xdt == kF32 ? 4 : 8); }
+size_t esize(int xdt) { return xdt == kF64 ? 8 : (xdt == kF32 ? 4 : 2); }
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  return hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1));
+}
+
+}  // namespace
+
+struct pr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  Problem P{};
+  double norm2 = 0.0;
+  int32_t max_batch = 1;
+  NodeParams *d_prm = nullptr;
+  NodeState *d_state = nullptr;
+  NodeState *h_state = nullptr;  // pinned, 2 slots
+  int8_t *d_status = nullptr;
+  NodeBufs nb{};
+  ProbBufs B{};
+  int32_t *iota = nullptr;
+  int32_t *d_np = nullptr;       // holds p (dense column list length)
+  double *d_u = nullptr;         // n
+  double *d_v = nullptr;         // p
+  double *d_w = nullptr;         // p
+  double *d_scal = nullptr;      // small scalars
+  double *d_lam = nullptr;       // power-iteration history
+  double *d_regscratch = nullptr;  // 3p
+  hipGraphExec_t gexec = nullptr;
+  int32_t graph_units = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t tev[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void free_ctx(pr_ctx *c) {
+  if (!c) return;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (int i = 0; i < 2; i++) {
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->tev[i]) (void)hipEventDestroy(c->tev[i]);
+  }
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  void *bufs[] = {c->d_prm, c->d_state, c->d_status, c->nb.x0, c->nb.x1, c->nb.xbest, c->nb.hprev, c->nb.vbuf,
+                  c->nb.abuf, c->nb.sidx, c->nb.sval, c->B.r, c->B.gm, c->B.ucur, c->B.uprev,
+                  c->B.zbest, c->B.h1, c->B.h2, c->B.part, c->B.rbsum, c->B.counter, c->iota,
+                  c->d_np, c->d_u, c->d_v, c->d_w, c->d_scal, c->d_lam, c->d_regscratch};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+  delete c;
+}
+
+// Validate a node and build its status vector.  Returns PR_OK, or an error;
+// *infeasible is set when |J1| > k.
+int build_status(const pr_node *node, int64_t p, std::vector<int8_t> &st, int64_t &n1, int64_t &pbar,
+                 int32_t &kbar, bool &infeasible) {
+  if (!node) return PR_EINVAL;
+  if (node->k < 1 || !(node->lambda2 > 0.0) || !isfinite(node->lambda2) || !(node->M > 0.0))
+    return PR_EINVAL;
+  if (node->n0 < 0 || node->n1 < 0 || (node->n0 > 0 && !node->J0) || (node->n1 > 0 && !node->J1))
+    return PR_EINVAL;
+  st.assign((size_t)p, (int8_t)kFree);
+  for (int64_t i = 0; i < node->n0; i++) {
+    int64_t j = node->J0[i];
+    if (j < 0 || j >= p) return PR_EINVAL;
+    st[(size_t)j] = (int8_t)kZero;
+  }
+  for (int64_t i = 0; i < node->n1; i++) {
+    int64_t j = node->J1[i];
+    if (j < 0 || j >= p) return PR_EINVAL;
+    if (st[(size_t)j] == kZero) return PR_EOVERLAP;
+    st[(size_t)j] = (int8_t)kOne;
+  }
+  n1 = 0;
+  int64_t nf = 0;
+  for (int64_t j = 0; j < p; j++) {
+    if (st[(size_t)j] == kOne) n1++;
+    else if (st[(size_t)j] == kFree) nf++;
+  }
+  pbar = nf;
+  infeasible = n1 > (int64_t)node->k;
+  int64_t kb = infeasible ? 0 : (int64_t)node->k - n1;
+  if (kb > nf) kb = nf;
+  kbar = (int32_t)kb;
+  return PR_OK;
+}
+
+int check_opts(const pr_opts *o) {
+  if (!o) return PR_OK;
+  if (!(o->rel_gap_tol >= 0.0) || !(o->eta > 1.0) || o->max_iter < 0 || o->check_every < 1 ||
+      !(o->L >= 0.0) || !isfinite(o->L))
+    return PR_EINVAL;
+  return PR_OK;
+}
+
+double curvature(int loss) { return loss == kLsq ? 2.0 : 0.25; }
+
+// One iteration unit: column-list GEMV + loss epilogue, X^T pass, node step.
+hipError_t enqueue_unit(pr_ctx *c, hipStream_t s) {
+  const int mode = c->P.loss == kLsq ? kSpLsq : kSpLogistic;
+  hipError_t e = launch_spfwd(c->P, c->B, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, mode, c->d_state,
+                              nullptr, s);
+  if (e != hipSuccess) return e;
+  e = launch_gemv_t(c->P, c->B.r, c->P.loss == kLsq ? nullptr : c->B.gm, c->B.h1, c->B.h2,
+                    &c->d_state->done, s);
+  if (e != hipSuccess) return e;
+  return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, s);
+}
+
+int ensure_graph(pr_ctx *c, int32_t units) {
+  if (c->gexec && c->graph_units == units) return PR_OK;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  PR_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < units && e == hipSuccess; i++) e = enqueue_unit(c, c->cap);
+  hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return PR_EDEVICE;
+  }
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return PR_EDEVICE;
+  }
+  c->graph_units = units;
+  return PR_OK;
+}
+
+// ||X||_2^2 by power iteration on X^T X with Rayleigh quotients ||X v||^2,
+// ||v|| = 1, from the all-ones direction; stops when two consecutive
+// quotients agree to 1e-10 relative (checked every 16 iterations) or after
+// 2000 iterations.
+int power_norm2(pr_ctx *c) {
+  const int64_t n = c->P.n, p = c->P.p;
+  std::vector<double> ones((size_t)p, 1.0 / sqrt((double)p));
+  PR_TRY(hipMemcpyAsync(c->d_v, ones.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->stream));
+  const int maxit = 2000, chunk = 16;
+  std::vector<double> lam(chunk);
+  double prev = -1.0;
+  for (int it0 = 0; it0 < maxit; it0 += chunk) {
+    for (int q = 0; q < chunk; q++) {
+      if (launch_spfwd(c->P, c->B, c->iota, c->d_v, c->d_np, kSpPlain, nullptr, c->d_u, c->stream) !=
+          hipSuccess)
+        return PR_EDEVICE;
+      PR_TRY(launch_sumsq(c->d_u, n, c->d_lam + q, c->stream));
+      PR_TRY(launch_gemv_t(c->P, c->d_u, nullptr, c->d_w, nullptr, nullptr, c->stream));
+      PR_TRY(launch_sumsq(c->d_w, p, c->d_scal, c->stream));
+      PR_TRY(hipMemcpyAsync(lam.data(), c->d_lam, sizeof(double) * chunk, hipMemcpyDeviceToHost, c->stream));
+      // v = w / ||w|| needs the norm on the host only once per chunk: the
+      // device normalises with the value it just computed
+      double nw = 0.0;
+      PR_TRY(hipMemcpyAsync(&nw, c->d_scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      PR_TRY(hipStreamSynchronize(c->stream));
+      if (!(nw > 0.0)) {
+        c->norm2 = lam[q];
+        return PR_OK;
+      }
+      PR_TRY(launch_scale_copy(c->d_w, c->d_v, 1.0 / sqrt(nw), p, c->stream));
+      const double l = lam[q];
+      if (prev > 0.0 && fabs(l - prev) <= 1e-10 * l) {
+        c->norm2 = l;
+        return PR_OK;
+      }
+      prev = l;
+    }
+  }
+  c->norm2 = prev;
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pr_opts_default(pr_opts *o) {
+  if (!o) return;
+  o->rel_gap_tol = 1e-6;
+  o->eta = exp(3.0);
+  o->cutoff = NAN;
+  o->L = 0.0;
+  o->max_iter = 100000;
+  o->check_every = 32;
+}
+
+const char *pr_strerror(int code) {
+  switch (code) {
+    case PR_OK: return "ok";
+    case PR_EINVAL: return "invalid argument";
+    case PR_EOVERLAP: return "J0 and J1 overlap";
+    case PR_EDEVICE: return "HIP runtime error";
+    case PR_ENOMEM: return "out of memory";
+    default: return "unknown error";
+  }
+}
+
+int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void *stream) {
+  if (!out || !prob || !prob->X || !prob->y || prob->n < 1 || prob->p < 1 || max_batch < 1)
+    return PR_EINVAL;
+  if (prob->xdtype < PR_F64 || prob->xdtype > PR_BF16) return PR_EINVAL;
+  if (prob->loss != PR_LSQ && prob->loss != PR_LOGISTIC) return PR_EINVAL;
+  if (prob->p >= (int64_t)1 << 31 || prob->n >= (int64_t)1 << 40) return PR_EINVAL;
+  const int vec = vec_of(prob->xdtype);
+  if (prob->n % vec != 0) return PR_EINVAL;
+  if (((uintptr_t)prob->X) % 16 != 0 || ((uintptr_t)prob->y) % 8 != 0) return PR_EINVAL;
+  pr_ctx *c = new (std::nothrow) pr_ctx();
+  if (!c) return PR_ENOMEM;
+  c->stream = (hipStream_t)stream;
+  c->max_batch = max_batch;
+  c->P.X = prob->X;
+  c->P.xdt = prob->xdtype;
+  c->P.loss = prob->loss;
+  c->P.y = prob->y;
+  c->P.n = prob->n;
+  c->P.p = prob->p;
+  const int64_t n = prob->n, p = prob->p;
+  c->B.rows = kSpThreads * vec;
+  c->B.rb = (int32_t)((n + c->B.rows - 1) / c->B.rows);
+  int nch = 2048 / c->B.rb;
+  if (nch < 1) nch = 1;
+  if (nch > 64) nch = 64;
+  if (nch > p) nch = (int)p;
+  c->B.nch = nch;
+  bool ok = hipGetDevice(&c->device) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && dalloc(&c->d_prm, 1) == hipSuccess && dalloc(&c->d_state, 1) == hipSuccess;
+  ok = ok && hipHostMalloc((void **)&c->h_state, 2 * sizeof(NodeState), hipHostMallocDefault) == hipSuccess;
+  ok = ok && dalloc(&c->d_status, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.x0, p) == hipSuccess && dalloc(&c->nb.x1, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.xbest, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.hprev, p) == hipSuccess && dalloc(&c->nb.vbuf, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.abuf, p) == hipSuccess && dalloc(&c->nb.sidx, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.sval, p) == hipSuccess;
+  ok = ok && dalloc(&c->B.r, n) == hipSuccess && dalloc(&c->B.gm, n) == hipSuccess;
+  ok = ok && dalloc(&c->B.ucur, n) == hipSuccess && dalloc(&c->B.uprev, n) == hipSuccess;
+  ok = ok && dalloc(&c->B.zbest, n) == hipSuccess;
+  ok = ok && dalloc(&c->B.h1, p) == hipSuccess && dalloc(&c->B.h2, p) == hipSuccess;
+  ok = ok && dalloc(&c->B.part, (size_t)nch * n) == hipSuccess;
+  ok = ok && dalloc(&c->B.rbsum, 2 * (size_t)c->B.rb) == hipSuccess;
+  ok = ok && dalloc(&c->B.counter, (size_t)c->B.rb) == hipSuccess;
+  ok = ok && dalloc(&c->iota, p) == hipSuccess && dalloc(&c->d_np, 1) == hipSuccess;
+  ok = ok && dalloc(&c->d_u, n) == hipSuccess && dalloc(&c->d_v, p) == hipSuccess;
+  ok = ok && dalloc(&c->d_w, p) == hipSuccess && dalloc(&c->d_scal, 8) == hipSuccess;
+  ok = ok && dalloc(&c->d_lam, 16) == hipSuccess && dalloc(&c->d_regscratch, 3 * (size_t)p) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreate(&c->tev[0]) == hipSuccess && hipEventCreate(&c->tev[1]) == hipSuccess;
+  if (!ok) {
+    free_ctx(c);
+    return PR_ENOMEM;
+  }
+  int32_t pp = (int32_t)p;
+  ok = hipMemsetAsync(c->B.counter, 0, sizeof(uint32_t) * c->B.rb, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->B.ucur, 0, sizeof(double) * n, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->B.uprev, 0, sizeof(double) * n, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->B.r, 0, sizeof(double) * n, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->B.gm, 0, sizeof(double) * n, c->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(c->d_np, &pp, sizeof(int32_t), hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  ok = ok && launch_iota(c->iota, p, c->stream) == hipSuccess;
+  ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) {
+    free_ctx(c);
+    return PR_EDEVICE;
+  }
+  int rc = power_norm2(c);
+  if (rc != PR_OK) {
+    free_ctx(c);
+    return rc;
+  }
+  *out = c;
+  return PR_OK;
+}
+
+int pr_ctx_destroy(pr_ctx *c) {
+  if (!c) return PR_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  return PR_OK;
+}
+
+int pr_ctx_norm2(pr_ctx *c, double *out) {
+  if (!c || !out) return PR_EINVAL;
+  *out = c->norm2;
+  return PR_OK;
+}
+
+int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const double *beta0,
+             double *beta_out, double *zeta_out, pr_result *out) {
+  if (!c || !out) return PR_EINVAL;
+  pr_opts opts;
+  pr_opts_default(&opts);
+  if (opts_in) opts = *opts_in;
+  if (check_opts(&opts) != PR_OK) return PR_EINVAL;
+  const int64_t n = c->P.n, p = c->P.p;
+  std::vector<int8_t> st;
+  int64_t n1, pbar;
+  int32_t kbar;
+  bool infeasible;
+  int rc = build_status(node, p, st, n1, pbar, kbar, infeasible);
+  if (rc != PR_OK) return rc;
+  memset(out, 0, sizeof(*out));
+  if (infeasible) {
+    out->lower_bound = INFINITY;
+    out->primal = INFINITY;
+    out->rel_gap = NAN;
+    out->status = PR_INFEASIBLE;
+    if (beta_out) PR_TRY(hipMemsetAsync(beta_out, 0, sizeof(double) * p, c->stream));
+    PR_TRY(hipStreamSynchronize(c->stream));
+    return PR_OK;
+  }
+  const double L = opts.L > 0.0 ? opts.L : 1.01 * curvature(c->P.loss) * c->norm2;
+  NodeParams prm{};
+  prm.st = c->d_status;
+  prm.p = p;
+  prm.pbar = pbar;
+  prm.kbar = kbar;
+  prm.loss = c->P.loss;
+  prm.lambda2 = node->lambda2;
+  prm.M = node->M;
+  prm.eta = opts.eta;
+  prm.tol = opts.rel_gap_tol;
+  prm.cutoff = opts.cutoff;
+  prm.max_iter = opts.max_iter;
+  PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, c->stream));
+  PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
+  PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, c->stream));
+  rc = ensure_graph(c, opts.check_every);
+  if (rc != PR_OK) return rc;
+  // keep two graph launches in flight; each is followed by a copy of the
+  // node state into its own pinned slot and an event
+  auto issue = [&](int slot) -> hipError_t {
+    hipError_t e = hipGraphLaunch(c->gexec, c->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&c->h_state[slot], c->d_state, sizeof(NodeState), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(c->ev[slot], c->stream);
+  };
+  const int64_t max_launches = (int64_t)opts.max_iter / opts.check_every + 3;
+  int64_t launched = 0;
+  PR_TRY(issue(0));
+  launched++;
+  PR_TRY(issue(1));
+  launched++;
+  for (int64_t i = 0;; i++) {
+    const int slot = (int)(i & 1);
+    PR_TRY(hipEventSynchronize(c->ev[slot]));
+    if (c->h_state[slot].done) break;
+    if (launched >= max_launches) break;
+    PR_TRY(issue(slot));
+    launched++;
+  }
+  PR_TRY(hipStreamSynchronize(c->stream));
+  PR_TRY(launch_zbest_final(c->d_state, c->B, c->P.loss, n, c->stream));
+  NodeState hs;
+  PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  if (beta_out)
+    PR_TRY(hipMemcpyAsync(beta_out, c->nb.xbest, sizeof(double) * p, hipMemcpyDeviceToDevice, c->stream));
+  if (zeta_out)
+    PR_TRY(hipMemcpyAsync(zeta_out, c->B.zbest, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  out->lower_bound = hs.lb;
+  out->primal = hs.ub;
+  out->rel_gap = hs.rel_gap;
+  out->L = hs.L;
+  out->iters = hs.iter;
+  out->restarts = hs.restarts;
+  out->status = hs.done ? hs.status : PR_MAXITER;
+  return PR_OK;
+}
+
+int pr_prox(void *stream, const double *v, int64_t p, double rho, int32_t k, double M,
+            const int8_t *status, double *out) {
+  if (!v || !out || !status || p < 1 || p >= ((int64_t)1 << 31) || !(rho > 0.0) || !isfinite(rho) ||
+      !(M > 0.0) || k < 1)
+    return PR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int8_t> st((size_t)p);
+  PR_TRY(hipMemcpyAsync(st.data(), status, (size_t)p, hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  int64_t n1 = 0, nf = 0;
+  for (int64_t j = 0; j < p; j++) {
+    if (st[(size_t)j] == kOne) n1++;
+    else if (st[(size_t)j] == kFree) nf++;
+    else if (st[(size_t)j] != kZero) return PR_EINVAL;
+  }
+  if (n1 > k) return PR_EINVAL;
+  int64_t kb = (int64_t)k - n1;
+  if (kb > nf) kb = nf;
+  double *abuf = nullptr;
+  if (hipMalloc((void **)&abuf, sizeof(double) * p) != hipSuccess) return PR_ENOMEM;
+  hipError_t e = launch_prox(v, out, p, rho, (int32_t)kb, M, status, abuf, nullptr, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(abuf);
+  return e == hipSuccess ? PR_OK : PR_EDEVICE;
+}
+
+int pr_regularizer(void *stream, const double *beta, const double *alpha, int64_t p, int32_t k,
+                   double M, const int8_t *status, double *g_out, double *gstar_out) {
+  if ((!beta && !alpha) || !status || p < 1 || p >= ((int64_t)1 << 31) || !(M > 0.0) || k < 1)
+    return PR_EINVAL;
+  if ((beta && !g_out) || (alpha && !gstar_out)) return PR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int8_t> st((size_t)p);
+  PR_TRY(hipMemcpyAsync(st.data(), status, (size_t)p, hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  int64_t n1 = 0, nf = 0;
+  for (int64_t j = 0; j < p; j++) {
+    if (st[(size_t)j] == kOne) n1++;
+    else if (st[(size_t)j] == kFree) nf++;
+    else if (st[(size_t)j] != kZero) return PR_EINVAL;
+  }
+  if (n1 > k) {
+    if (g_out) *g_out = INFINITY;
+    if (gstar_out) *gstar_out = -INFINITY;
+    return PR_OK;
+  }
+  int64_t kb = (int64_t)k - n1;
+  if (kb > nf) kb = nf;
+  double *scr = nullptr;
+  if (hipMalloc((void **)&scr, sizeof(double) * (3 * p + 2)) != hipSuccess) return PR_ENOMEM;
+  double res[2] = {0.0, 0.0};
+  hipError_t e = launch_regularizer(beta, alpha, p, (int32_t)kb, M, status, scr, scr + 3 * p, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(res, scr + 3 * p, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scr);
+  if (e != hipSuccess) return PR_EDEVICE;
+  if (g_out) *g_out = res[0];
+  if (gstar_out) *gstar_out = res[1];
+  return PR_OK;
+}
+
+int pr_gemv(pr_ctx *c, const double *b, double *u) {
+  if (!c || !b || !u) return PR_EINVAL;
+  if (launch_spfwd(c->P, c->B, c->iota, b, c->d_np, kSpPlain, nullptr, u, c->stream) != hipSuccess)
+    return PR_EDEVICE;
+  PR_TRY(hipStreamSynchronize(c->stream));
+  return PR_OK;
+}
+
+int pr_gemv_t(pr_ctx *c, const double *r, double *h) {
+  if (!c || !r || !h) return PR_EINVAL;
+  PR_TRY(launch_gemv_t(c->P, r, nullptr, h, nullptr, nullptr, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  return PR_OK;
+}
+
+int pr_time_gemv_t(pr_ctx *c, const double *r, double *h, int32_t reps, double *ms_avg) {
+  if (!c || !r || !h || reps < 1 || !ms_avg) return PR_EINVAL;
+  PR_TRY(launch_gemv_t(c->P, r, nullptr, h, nullptr, nullptr, c->stream));
+  PR_TRY(hipEventRecord(c->tev[0], c->stream));
+  for (int i = 0; i < reps; i++) PR_TRY(launch_gemv_t(c->P, r, nullptr, h, nullptr, nullptr, c->stream));
+  PR_TRY(hipEventRecord(c->tev[1], c->stream));
+  PR_TRY(hipEventSynchronize(c->tev[1]));
+  float ms = 0.0f;
+  PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+  *ms_avg = (double)ms / reps;
+  return PR_OK;
+}
+
+int pr_dual_bound(pr_ctx *c, const pr_node *node, const double *zeta, const double *beta,
+                  double *lb_out, double *primal_out) {
+  if (!c || !lb_out || (!zeta && !beta)) return PR_EINVAL;
+  const int64_t n = c->P.n, p = c->P.p;
+  std::vector<int8_t> st;
+  int64_t n1, pbar;
+  int32_t kbar;
+  bool infeasible;
+  int rc = build_status(node, p, st, n1, pbar, kbar, infeasible);
+  if (rc != PR_OK) return rc;
+  if (infeasible) {
+    *lb_out = INFINITY;
+    if (primal_out) *primal_out = INFINITY;
+    return PR_OK;
+  }
+  hipStream_t s = c->stream;
+  PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, s));
+  const double lam2 = node->lambda2;
+  double *scal = c->d_scal;  // [0] F(X beta), [1] -F*(-zeta), [2] g(beta), [3] g*(w)
+  const double *z = zeta;
+  if (beta) {
+    if (launch_spfwd(c->P, c->B, c->iota, beta, c->d_np, kSpPlain, nullptr, c->d_u, s) != hipSuccess)
+      return PR_EDEVICE;
+    // zeta induced from beta goes to B.zbest's twin: reuse B.gm as scratch
+    PR_TRY(launch_loss_terms(c->P.loss, c->d_u, c->P.y, n, c->B.gm, scal, s));
+    if (!zeta) z = c->B.gm;
+    PR_TRY(launch_regularizer(beta, nullptr, p, kbar, node->M, c->d_status, c->d_regscratch, scal + 2, s));
+  }
+  if (zeta) PR_TRY(launch_zeta_terms(c->P.loss, zeta, c->P.y, n, scal, s));
+  PR_TRY(launch_gemv_t(c->P, z, nullptr, c->d_w, nullptr, nullptr, s));
+  PR_TRY(launch_scale_copy(c->d_w, c->d_v, 0.5 / lam2, p, s));
+  PR_TRY(launch_regularizer(nullptr, c->d_v, p, kbar, node->M, c->d_status, c->d_regscratch, scal + 2, s));
+  double hs[4];
+  PR_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  *lb_out = hs[1] - 2.0 * lam2 * hs[3];
+  if (primal_out) *primal_out = beta ? hs[0] + 2.0 * lam2 * hs[2] : NAN;
+  return PR_OK;
+}
+
+int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *opts, const double *B0,
+                   double *B_out, pr_result *out) {
+  if (!c || !nodes || !out || m < 1 || m > c->max_batch) return PR_EINVAL;
+  const int64_t p = c->P.p;
+  for (int32_t i = 0; i < m; i++) {
+    int rc = pr_solve(c, &nodes[i], opts, B0 ? B0 + (int64_t)i * p : nullptr,
+                      B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);
+    if (rc != PR_OK) return rc;
+  }
+  return PR_OK;
+}
+
+}  // extern "C"

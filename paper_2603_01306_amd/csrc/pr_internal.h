@@ -1,0 +1,107 @@
+// Internal declarations shared by the kernel and host translation units of
+// libpr.  Not part of the public ABI (include/pr.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pr {
+
+constexpr int kNodeThreads = 1024;   // threads of a per-node workgroup
+constexpr int kGemvThreads = 256;    // 4 waves, 4 columns per wave
+constexpr int kColsPerWave = 4;
+constexpr int kSpThreads = 256;      // column-list GEMV workgroup
+
+enum : int32_t { kFree = 0, kZero = 1, kOne = 2 };
+enum : int32_t { kLsq = 0, kLogistic = 1 };
+enum : int32_t { kF64 = 0, kF32 = 1, kBF16 = 2 };
+enum : int32_t { kConverged = 1, kMaxIter = 2, kInfeasible = 3, kCutoffPrune = 4, kCutoffBranch = 5 };
+
+// Per-node constants, device resident (written by the host before a solve).
+struct NodeParams {
+  const int8_t *st;   // status, p entries
+  int64_t p, pbar;
+  int32_t kbar, loss;
+  double lambda2, M, eta, tol, cutoff;  // cutoff NaN = off
+  int32_t max_iter, pad;
+};
+
+// Per-node iteration state, device resident.
+struct NodeState {
+  double L;        // step constant
+  double t;        // FISTA momentum parameter
+  double gap_ref;  // gap at the start of the current restart epoch
+  double lb, ub;   // best dual / primal values
+  double phi, psi; // values at the current iterate
+  double rel_gap;
+  double gval;     // g_N at the current iterate (Algorithm 1)
+  double tau;      // last pooled-block threshold of the prox (warm start)
+  double mom;      // momentum coefficient used by the last step
+  int32_t iter, restarts, done, status;
+  int32_t parity;  // which of the two x buffers holds the current iterate
+  int32_t nsupp;   // support size of the current iterate
+  int32_t improved; // lb improved at the current iterate
+  int32_t indom;   // current iterate lies in dom g_N
+  int32_t tau_iters; // evaluations used by the last threshold search
+  int32_t pad[3];
+};
+
+// Node-local vectors.
+struct NodeBufs {
+  double *x0, *x1;     // iterate buffers (current / previous by parity)
+  double *xbest;       // iterate attaining the best primal value
+  double *hprev;       // least squares: X^T r at the previous iterate
+  double *vbuf;        // prox input
+  double *abuf;        // magnitudes scratch (negative = not free)
+  int32_t *sidx;       // support list of the current iterate
+  double *sval;
+};
+
+// Shared per-problem vectors of a single-node solve.
+struct ProbBufs {
+  double *r;      // least squares residual y - X x; logistic: zeta
+  double *gm;     // logistic: grad F at the momentum point
+  double *ucur, *uprev; // logistic: X x at the current / previous iterate
+  double *zbest;  // dual vector attaining lb
+  double *h1, *h2;      // X^T (first / second right-hand side)
+  double *part;   // column-list GEMV partial sums [nch][n]
+  double *rbsum;  // per row block loss sums [rb][2]
+  uint32_t *counter; // per row block arrival counters
+  int32_t rb, nch, rows;
+};
+
+struct Problem {
+  const void *X;
+  int32_t xdt, loss;
+  const double *y;
+  int64_t n, p;
+};
+
+// ---- launchers (pr_kernels.hip) ----
+hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
+                         const int32_t *done, hipStream_t s);
+// u_partials / finalize: generic column-list GEMV u = sum_t X[:, idx[t]] * val[t]
+// followed by the per-row-block epilogue selected by `mode`.
+enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2 };
+hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx, const double *val,
+                        const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
+                        hipStream_t s);
+hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, const double *beta0,
+                            double L, hipStream_t s);
+hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
+                            hipStream_t s);
+hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t loss, int64_t n,
+                              hipStream_t s);
+hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,
+                       const int8_t *st, double *abuf, double *vtmp, hipStream_t s);
+hipError_t launch_regularizer(const double *beta, const double *alpha, int64_t p, int32_t kbar,
+                              double M, const int8_t *st, double *abuf, double *out2,
+                              hipStream_t s);
+hipError_t launch_loss_terms(int32_t loss, const double *u, const double *y, int64_t n,
+                             double *zeta_out, double *sums_out, hipStream_t s);
+hipError_t launch_zeta_terms(int32_t loss, const double *zeta, const double *y, int64_t n,
+                             double *sums_out, hipStream_t s);
+hipError_t launch_sumsq(const double *v, int64_t n, double *out, hipStream_t s);
+hipError_t launch_scale_copy(const double *src, double *dst, double a, int64_t n, hipStream_t s);
+hipError_t launch_iota(int32_t *idx, int64_t n, hipStream_t s);
+
+}  // namespace pr

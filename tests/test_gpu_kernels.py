@@ -1,0 +1,178 @@
+"""GPU parity of the building blocks against the FP64 oracle, through the C ABI:
+prox of g_N (Algorithm 2 + Moreau), g_N (Algorithm 1), g_N* (closed-form
+conjugate), and the FP64-accumulated X beta / X^T r products."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_instance, round_bf16, bf16_to_f32
+
+pytestmark = pytest.mark.gpu
+
+
+def _pr():
+    import paper_2603_01306_amd as pr
+    return pr
+
+
+def _rand_node(rng, p, k):
+    st = np.zeros(p, np.int8)
+    idx = rng.permutation(p)
+    n0 = int(rng.integers(0, p // 2 + 1))
+    n1 = int(rng.integers(0, min(k, p - n0) + 1))
+    st[idx[:n0]] = oracle.ZERO
+    st[idx[n0:n0 + n1]] = oracle.ONE
+    return st
+
+
+def _prox_case(i):
+    rng = np.random.default_rng(1000 + i)
+    sizes = [1, 2, 7, 63, 64, 65, 1000, 1023, 1024, 1025, 3000, 8192, 16384, 20011]
+    p = sizes[i % len(sizes)]
+    k = int(rng.integers(1, max(2, min(p, 40))))
+    M = [0.5, 1.0, 2.0, math.inf][i % 4]
+    rho = 10.0 ** rng.uniform(-7, 2)
+    scale = 10.0 ** rng.uniform(-3, 3)
+    v = rng.standard_normal(p) * scale
+    if i % 5 == 0:
+        v[rng.integers(0, p, size=p // 3)] = 0.0
+    if i % 6 == 0:
+        v = np.round(v / scale, 1) * scale   # many exact ties
+    st = _rand_node(rng, p, k) if i % 3 == 1 else np.zeros(p, np.int8)
+    return v, rho, k, M, st
+
+
+@pytest.mark.parametrize("i", range(56))
+def test_prox_matches_algorithm2(dev, i):
+    import torch
+    pr = _pr()
+    v, rho, k, M, st = _prox_case(i)
+    if np.sum(st == oracle.ONE) > k:
+        pytest.skip("infeasible draw")
+    x_gpu = pr.prox(torch.from_numpy(v).to(dev), rho, k, M, torch.from_numpy(st).to(dev)).cpu().numpy()
+    x_orc = oracle.prox_g(v, rho, k, M, st)
+    scale = max(np.linalg.norm(x_orc), np.linalg.norm(v), 1e-300)
+    err = np.linalg.norm(x_gpu - x_orc) / scale
+    print(f"case {i}: p={v.size} k={k} M={M} rho={rho:.3g} err={err:.2e}")
+    assert err <= 1e-12
+    # structural facts of Algorithm 2: J0 -> 0 exactly, J1 -> ridge/box map
+    assert np.all(x_gpu[st == oracle.ZERO] == 0.0)
+    j1 = st == oracle.ONE
+    np.testing.assert_allclose(x_gpu[j1], np.sign(v[j1]) * np.minimum(np.abs(v[j1]) / (1 + rho), M),
+                               rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("i", range(0, 56, 5))
+def test_prox_fenchel_young_on_gpu_output(dev, i):
+    """x = prox_{rho g}(v), a = (v - x)/rho satisfies g(x) + g*(a) = a^T x."""
+    import torch
+    pr = _pr()
+    v, rho, k, M, st = _prox_case(i)
+    if np.sum(st == oracle.ONE) > k or not math.isfinite(M):
+        pytest.skip("infeasible draw or unbounded box")
+    x = pr.prox(torch.from_numpy(v).to(dev), rho, k, M, torch.from_numpy(st).to(dev)).cpu().numpy()
+    a = (v - x) / rho
+    a[st == oracle.ZERO] = 0.0
+    lhs = oracle.g(x, k, st) + oracle.gstar(a, k, M, st)
+    rhs = float(a @ x)
+    assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(lhs), float(np.abs(a) @ np.abs(x)))
+
+
+def test_prox_edge_cases(dev):
+    import torch
+    pr = _pr()
+    # all zero input
+    v = np.zeros(100)
+    st = np.zeros(100, np.int8)
+    out = pr.prox(torch.from_numpy(v).to(dev), 0.3, 5, 2.0, torch.from_numpy(st).to(dev)).cpu().numpy()
+    assert np.all(out == 0)
+    # kbar = 0: |J1| = k forces the free part to zero
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(50)
+    st = np.zeros(50, np.int8)
+    st[[1, 2, 3]] = oracle.ONE
+    out = pr.prox(torch.from_numpy(v).to(dev), 0.3, 3, 2.0, torch.from_numpy(st).to(dev)).cpu().numpy()
+    assert np.all(out[st == 0] == 0)
+    # kbar >= pbar: ridge with box on every free coordinate
+    out = pr.prox(torch.from_numpy(v).to(dev), 0.3, 60, 1.0, torch.from_numpy(np.zeros(50, np.int8)).to(dev))
+    np.testing.assert_allclose(out.cpu().numpy(), np.sign(v) * np.minimum(np.abs(v) / 1.3, 1.0), rtol=1e-14)
+    # |J1| > k is rejected
+    st = np.zeros(50, np.int8)
+    st[:4] = oracle.ONE
+    with pytest.raises(pr.PrError):
+        pr.prox(torch.from_numpy(v).to(dev), 0.3, 3, 2.0, torch.from_numpy(st).to(dev))
+
+
+@pytest.mark.parametrize("i", range(0, 56, 2))
+def test_regularizer_matches_oracle(dev, i):
+    import torch
+    pr = _pr()
+    v, rho, k, M, st = _prox_case(i)
+    if np.sum(st == oracle.ONE) > k:
+        pytest.skip("infeasible draw")
+    beta = oracle.prox_g(v, rho, k, M, st)   # a point of dom g_N
+    beta[st == oracle.ZERO] = 0.0
+    alpha = np.random.default_rng(i).standard_normal(v.size) * 3.0
+    tst = torch.from_numpy(st).to(dev)
+    g_gpu, gs_gpu = pr.regularizer(torch.from_numpy(beta).to(dev), torch.from_numpy(alpha).to(dev), k, M, tst)
+    g_orc = oracle.g(beta, k, st) if oracle.in_dom(beta, k, M, st) else math.inf
+    gs_orc = oracle.gstar(alpha, k, M, st)
+    assert (g_gpu == g_orc) or abs(g_gpu - g_orc) <= 1e-12 * max(1.0, abs(g_orc))
+    assert abs(gs_gpu - gs_orc) <= 1e-12 * max(1.0, abs(gs_orc))
+
+
+def test_regularizer_worked_examples(dev):
+    """Figure 3 worked examples: g(1.4, 0.6; k=1) = 2 and g(0.6, 1.2, 1.2; k=2) = 2.25."""
+    import torch
+    pr = _pr()
+    g1, _ = pr.regularizer(torch.tensor([1.4, 0.6], dtype=torch.float64, device=dev), None, 1, 2.0,
+                           torch.zeros(2, dtype=torch.int8, device=dev))
+    g2, _ = pr.regularizer(torch.tensor([0.6, 1.2, 1.2], dtype=torch.float64, device=dev), None, 2, 1.5,
+                           torch.zeros(3, dtype=torch.int8, device=dev))
+    assert abs(g1 - 2.0) <= 1e-15 and abs(g2 - 2.25) <= 1e-15
+    # off the domain (||beta||_1 > M k) the value is +inf
+    g3, _ = pr.regularizer(torch.tensor([1.4, 0.6], dtype=torch.float64, device=dev), None, 1, 1.5,
+                           torch.zeros(2, dtype=torch.int8, device=dev))
+    assert g3 == math.inf
+
+
+def _ctx_for(dev, Xcm, y, loss=0):
+    import torch
+    pr = _pr()
+    if Xcm.dtype == np.uint16:
+        X = torch.from_numpy(Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        X = torch.from_numpy(Xcm).to(dev)
+    return pr.Context(X, torch.from_numpy(y).to(dev), loss)
+
+
+@pytest.mark.parametrize("storage,n,p", [("f64", 500, 200), ("f64", 2, 1), ("f32", 1028, 37),
+                                         ("f32", 4096, 1031), ("bf16", 1032, 77), ("bf16", 16384, 64)])
+def test_gemv_and_gemv_t_match_oracle(dev, storage, n, p):
+    import torch
+    inst = make_instance(n=n, p=p, corr=0.6, k_true=min(3, p), snr=5.0, loss=0, seed=7, storage=storage)
+    ctx = _ctx_for(dev, inst.Xcm, inst.y)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(p)
+    r = rng.standard_normal(n)
+    u = ctx.gemv(torch.from_numpy(b).to(dev)).cpu().numpy()
+    h = ctx.gemv_t(torch.from_numpy(r).to(dev)).cpu().numpy()
+    X64 = inst.X64()
+    u_ref = oracle.matvec(inst.Xcm, b)
+    h_ref = oracle.rmatvec(inst.Xcm, r)
+    # both sides sum exact FP64 products; only the summation order differs
+    bound_u = 1e-13 * (np.abs(X64).T @ np.abs(b)) + 1e-300
+    bound_h = 1e-13 * (np.abs(X64) @ np.abs(r)) + 1e-300
+    assert np.all(np.abs(u - u_ref) <= bound_u)
+    assert np.all(np.abs(h - h_ref) <= bound_h)
+    ctx.close()
+
+
+def test_norm2_matches_oracle_power_iteration(dev):
+    inst = make_instance(n=2048, p=512, corr=0.9, k_true=8, snr=5.0, loss=0, seed=2, storage="f32")
+    ctx = _ctx_for(dev, inst.Xcm, inst.y)
+    lam = np.linalg.eigvalsh(inst.X64() @ inst.X64().T).max()
+    assert abs(ctx.norm2() - lam) <= 1e-6 * lam
+    ctx.close()
