@@ -29,12 +29,19 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "ls_root_n16384_p8192_f32"
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemv_t_ls_n16384_p8192_f32_pmc.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2603_01306_amd", "csrc", "pr_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_01306_amd", "csrc", f) for f in ("pr_gemv.hip", "pr_device.h")]
 
 
 def _gemv_t_bytes(n, p, xbytes):
     # algorithmic bytes of one X^T r launch: X once, r (FP64) once, h (FP64) once
     return n * p * xbytes + n * 8 + p * 8
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def _traffic_from_summary():
@@ -47,7 +54,7 @@ def _traffic_from_summary():
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src_hash = kernel_source_hash()
     if kv.get("kernel_source_sha256") != src_hash:
         return None
     try:

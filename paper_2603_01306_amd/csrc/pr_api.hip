@@ -68,7 +68,7 @@ void free_ctx(pr_ctx *c) {
   if (c->cap) (void)hipStreamDestroy(c->cap);
   void *bufs[] = {c->d_prm, c->d_state, c->d_status, c->nb.x0, c->nb.x1, c->nb.xbest, c->nb.hprev, c->nb.vbuf,
                   c->nb.abuf, c->nb.sidx, c->nb.sval, c->B.r, c->B.gm, c->B.ucur, c->B.uprev,
-                  c->B.zbest, c->B.h1, c->B.h2, c->B.part, c->B.rbsum, c->B.counter, c->iota,
+                  c->B.zbest, c->B.h1, c->B.h2, c->B.part, c->B.rbsum, c->iota,
                   c->d_np, c->d_u, c->d_v, c->d_w, c->d_scal, c->d_lam, c->d_regscratch};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -130,7 +130,7 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s) {
   e = launch_gemv_t(c->P, c->B.r, c->P.loss == kLsq ? nullptr : c->B.gm, c->B.h1, c->B.h2,
                     &c->d_state->done, s);
   if (e != hipSuccess) return e;
-  return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, s);
+  return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s);
 }
 
 int ensure_graph(pr_ctx *c, int32_t units) {
@@ -247,11 +247,12 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   const int64_t n = prob->n, p = prob->p;
   c->B.rows = kSpThreads * vec;
   c->B.rb = (int32_t)((n + c->B.rows - 1) / c->B.rows);
-  int nch = 2048 / c->B.rb;
+  int nch = 512 / c->B.rb;
   if (nch < 1) nch = 1;
   if (nch > 64) nch = 64;
   if (nch > p) nch = (int)p;
   c->B.nch = nch;
+  c->B.nfin = spfwd_final_blocks(n);
   bool ok = hipGetDevice(&c->device) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess;
   ok = ok && dalloc(&c->d_prm, 1) == hipSuccess && dalloc(&c->d_state, 1) == hipSuccess;
@@ -267,8 +268,7 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   ok = ok && dalloc(&c->B.zbest, n) == hipSuccess;
   ok = ok && dalloc(&c->B.h1, p) == hipSuccess && dalloc(&c->B.h2, p) == hipSuccess;
   ok = ok && dalloc(&c->B.part, (size_t)nch * n) == hipSuccess;
-  ok = ok && dalloc(&c->B.rbsum, 2 * (size_t)c->B.rb) == hipSuccess;
-  ok = ok && dalloc(&c->B.counter, (size_t)c->B.rb) == hipSuccess;
+  ok = ok && dalloc(&c->B.rbsum, 2 * (size_t)c->B.nfin) == hipSuccess;
   ok = ok && dalloc(&c->iota, p) == hipSuccess && dalloc(&c->d_np, 1) == hipSuccess;
   ok = ok && dalloc(&c->d_u, n) == hipSuccess && dalloc(&c->d_v, p) == hipSuccess;
   ok = ok && dalloc(&c->d_w, p) == hipSuccess && dalloc(&c->d_scal, 8) == hipSuccess;
@@ -281,8 +281,7 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
     return PR_ENOMEM;
   }
   int32_t pp = (int32_t)p;
-  ok = hipMemsetAsync(c->B.counter, 0, sizeof(uint32_t) * c->B.rb, c->stream) == hipSuccess;
-  ok = ok && hipMemsetAsync(c->B.ucur, 0, sizeof(double) * n, c->stream) == hipSuccess;
+  ok = hipMemsetAsync(c->B.ucur, 0, sizeof(double) * n, c->stream) == hipSuccess;
   ok = ok && hipMemsetAsync(c->B.uprev, 0, sizeof(double) * n, c->stream) == hipSuccess;
   ok = ok && hipMemsetAsync(c->B.r, 0, sizeof(double) * n, c->stream) == hipSuccess;
   ok = ok && hipMemsetAsync(c->B.gm, 0, sizeof(double) * n, c->stream) == hipSuccess;
@@ -354,7 +353,7 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   prm.max_iter = opts.max_iter;
   PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, c->stream));
   PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
-  PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, c->stream));
+  PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, p, c->stream));
   rc = ensure_graph(c, opts.check_every);
   if (rc != PR_OK) return rc;
   // keep two graph launches in flight; each is followed by a copy of the

@@ -1,0 +1,188 @@
+// Device helpers shared by the kernel translation units of libpr (gfx950,
+// wave64): deterministic workgroup reductions and scans, 16-byte vector loads
+// of the stored X (FP64 / FP32 / BF16, exact upcast to FP64), and the scalar
+// maps of the method (Huber function, softplus, FISTA momentum sequence).
+#pragma once
+#include <math.h>
+
+#include "pr_internal.h"
+
+namespace pr {
+namespace dev {
+
+constexpr int NT = kNodeThreads;
+constexpr int NW = NT / 64;
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum of K values over a workgroup of NTH threads.  Every thread adds the
+// per-wave totals in wave order, so all threads get the same, run-to-run
+// reproducible result.  `red` needs NTH/64*K doubles of LDS.
+template <int NTH, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *red) {
+  constexpr int NWV = NTH / 64;
+#pragma unroll
+  for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k++) red[wave_id() * K + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double s = 0.0;
+    for (int w = 0; w < NWV; w++) s += red[w * K + k];
+    v[k] = s;
+  }
+}
+
+template <int NTH>
+__device__ __forceinline__ double block_max(double v, double *red) {
+  constexpr int NWV = NTH / 64;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < NWV; w++) s = fmax(s, red[w]);
+  return s;
+}
+
+// Exclusive prefix sum of an int over the workgroup (thread order).
+template <int NTH>
+__device__ __forceinline__ int block_excl_scan(int v, int *lds, int *total) {
+  constexpr int NWV = NTH / 64;
+  const int lane = lane_id(), w = wave_id();
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < NWV; i++) {
+    int t = lds[i];
+    if (i < w) off += t;
+    tot += t;
+  }
+  *total = tot;
+  return off + x - v;
+}
+
+// Descending bitonic sort of one double per lane of a wave.
+__device__ __forceinline__ double wave_sort_desc(double v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      double o = __shfl_xor(v, stride, 64);
+      bool desc = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      bool take_max = (lower == desc);
+      v = take_max ? (v > o ? v : o) : (v < o ? v : o);
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ double huber(double a, double M) {
+  double x = fabs(a);
+  return (x <= M) ? 0.5 * x * x : M * x - 0.5 * M * M;
+}
+
+__device__ __forceinline__ double softplus(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+
+__device__ __forceinline__ double fista_next_t(double t) { return 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t)); }
+
+template <typename T>
+struct XLoad;
+
+template <>
+struct XLoad<float> {
+  static constexpr int VEC = 4;
+  __device__ __forceinline__ static void load(const float *p, double (&d)[4]) {
+    f4_t v = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(p));
+    d[0] = (double)v.x;
+    d[1] = (double)v.y;
+    d[2] = (double)v.z;
+    d[3] = (double)v.w;
+  }
+};
+
+template <>
+struct XLoad<double> {
+  static constexpr int VEC = 2;
+  __device__ __forceinline__ static void load(const double *p, double (&d)[2]) {
+    d2_t v = __builtin_nontemporal_load(reinterpret_cast<const d2_t *>(p));
+    d[0] = v.x;
+    d[1] = v.y;
+  }
+};
+
+// bf16 stored as uint16_t bit patterns
+template <>
+struct XLoad<uint16_t> {
+  static constexpr int VEC = 8;
+  __device__ __forceinline__ static void load(const uint16_t *p, double (&d)[8]) {
+    u4_t v = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(p));
+    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      d[2 * q] = (double)__uint_as_float(w[q] << 16);
+      d[2 * q + 1] = (double)__uint_as_float(w[q] & 0xffff0000u);
+    }
+  }
+};
+
+template <int VEC>
+__device__ __forceinline__ void load_rhs(const double *__restrict__ r, int64_t i, double (&d)[VEC]) {
+#pragma unroll
+  for (int q = 0; q < VEC; q += 2) {
+    d2_t v = *reinterpret_cast<const d2_t *>(r + i + q);
+    d[q] = v.x;
+    d[q + 1] = v.y;
+  }
+}
+
+// Deterministic transpose-reduction of 4 per-lane partial sums (one per
+// column) over the 64 lanes: afterwards lane 16*c holds the total of column c.
+__device__ __forceinline__ double reduce4(double (&v)[4]) {
+  const int lane = lane_id();
+  const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+  double s0 = b5 ? v[0] : v[2], s1 = b5 ? v[1] : v[3];
+  double k0 = b5 ? v[2] : v[0], k1 = b5 ? v[3] : v[1];
+  k0 += __shfl_xor(s0, 32, 64);
+  k1 += __shfl_xor(s1, 32, 64);
+  double s = b4 ? k0 : k1;
+  double k = b4 ? k1 : k0;
+  k += __shfl_xor(s, 16, 64);
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+  return k;
+}
+
+
+}  // namespace dev
+}  // namespace pr

@@ -6,7 +6,7 @@
 
 namespace pr {
 
-constexpr int kNodeThreads = 1024;   // threads of a per-node workgroup
+constexpr int kNodeThreads = 512;    // threads of a per-node workgroup
 constexpr int kGemvThreads = 256;    // 4 waves, 4 columns per wave
 constexpr int kColsPerWave = 4;
 constexpr int kSpThreads = 256;      // column-list GEMV workgroup
@@ -64,9 +64,8 @@ struct ProbBufs {
   double *zbest;  // dual vector attaining lb
   double *h1, *h2;      // X^T (first / second right-hand side)
   double *part;   // column-list GEMV partial sums [nch][n]
-  double *rbsum;  // per row block loss sums [rb][2]
-  uint32_t *counter; // per row block arrival counters
-  int32_t rb, nch, rows;
+  double *rbsum;  // per finalize-block loss sums [nfin][2]
+  int32_t rb, nch, rows, nfin;
 };
 
 struct Problem {
@@ -85,10 +84,11 @@ enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2 };
 hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx, const double *val,
                         const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
                         hipStream_t s);
+int spfwd_final_blocks(int64_t n);
 hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, const double *beta0,
-                            double L, hipStream_t s);
+                            double L, int64_t p, hipStream_t s);
 hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
-                            hipStream_t s);
+                            int64_t p, hipStream_t s);
 hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t loss, int64_t n,
                               hipStream_t s);
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,

@@ -1,133 +1,20 @@
-// HIP kernels of libpr for gfx950 (MI355X, wave64).
+// Per-node kernels of libpr on gfx950: one 512-thread workgroup per node.
 //
-// Matrix products (HBM bound):
-//   k_gemv_t   h = X^T r (1 or 2 right-hand sides), FP32/BF16/FP64 X loaded
-//              16 bytes per lane with non-temporal loads, FP64 accumulation,
-//              one wave per 4 adjacent columns, deterministic in-wave
-//              transpose-reduction.  Bytes per launch: n*p*sizeof(X) plus the
-//              right-hand sides (read from L2).
-//   k_spfwd    u = sum_t X[:, idx[t]] val[t] over a column list (the support
-//              of the iterate, or all columns), split over row blocks x column
-//              chunks; the last workgroup of a row block sums the chunk
-//              partials in fixed order and runs the loss epilogue (residual /
-//              induced dual vector, F and -F*(-zeta) partial sums).
-// Per-node work (one 1024-thread workgroup per node):
-//   k_node_step  dual value (closed-form conjugate, exact top-kbar selection),
-//                gap / restart / termination, FISTA momentum, the prox of
-//                Algorithm 2 in its pooled-threshold form, Algorithm 1 value of
-//                the new iterate, support compaction.
-#include <math.h>
-
-#include "pr_internal.h"
+//   k_node_step  dual value at the current iterate (closed-form conjugate of
+//                Lemma function_g_conjugate_in_BnB with an exact radix top-kbar
+//                selection), gap / restart / termination (Section 3.3), FISTA
+//                momentum, the prox of Algorithm 2 + Moreau in pooled-threshold
+//                form, Algorithm 1 value of the new iterate, support list.
+//   k_node_init  start point: support, Algorithm 1 value, dom test.
+//   k_prox, k_regularizer, k_loss_terms, ...: entry points of the C ABI.
+//
+// Two variants: register-resident (p <= 16384, coordinates j = tid + e*512
+// held in registers across all passes) and a global-memory one for larger p.
+#include "pr_device.h"
 
 namespace pr {
 namespace {
-
-constexpr int NT = kNodeThreads;
-constexpr int NW = NT / 64;
-
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef double d2_t __attribute__((ext_vector_type(2)));
-typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Sum of K values over a workgroup of NTH threads.  Every thread adds the
-// per-wave totals in wave order, so all threads get the same, run-to-run
-// reproducible result.  `red` needs NTH/64*K doubles of LDS.
-template <int NTH, int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *red) {
-  constexpr int NWV = NTH / 64;
-#pragma unroll
-  for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
-  __syncthreads();
-  if (lane_id() == 0) {
-#pragma unroll
-    for (int k = 0; k < K; k++) red[wave_id() * K + k] = v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; k++) {
-    double s = 0.0;
-    for (int w = 0; w < NWV; w++) s += red[w * K + k];
-    v[k] = s;
-  }
-}
-
-template <int NTH>
-__device__ __forceinline__ double block_max(double v, double *red) {
-  constexpr int NWV = NTH / 64;
-  v = wave_max(v);
-  __syncthreads();
-  if (lane_id() == 0) red[wave_id()] = v;
-  __syncthreads();
-  double s = red[0];
-  for (int w = 1; w < NWV; w++) s = fmax(s, red[w]);
-  return s;
-}
-
-// Exclusive prefix sum of an int over the workgroup (thread order).
-template <int NTH>
-__device__ __forceinline__ int block_excl_scan(int v, int *lds, int *total) {
-  constexpr int NWV = NTH / 64;
-  const int lane = lane_id(), w = wave_id();
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  __syncthreads();
-  if (lane == 63) lds[w] = x;
-  __syncthreads();
-  int off = 0, tot = 0;
-  for (int i = 0; i < NWV; i++) {
-    int t = lds[i];
-    if (i < w) off += t;
-    tot += t;
-  }
-  *total = tot;
-  return off + x - v;
-}
-
-// Descending bitonic sort of one double per lane of a wave.
-__device__ __forceinline__ double wave_sort_desc(double v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      double o = __shfl_xor(v, stride, 64);
-      bool desc = (lane & size) == 0;
-      bool lower = (lane & stride) == 0;
-      bool take_max = (lower == desc);
-      v = take_max ? (v > o ? v : o) : (v < o ? v : o);
-    }
-  }
-  return v;
-}
-
-__device__ __forceinline__ double huber(double a, double M) {
-  double x = fabs(a);
-  return (x <= M) ? 0.5 * x * x : M * x - 0.5 * M * M;
-}
-
-__device__ __forceinline__ double softplus(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
-
-__device__ __forceinline__ double fista_next_t(double t) { return 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t)); }
+using namespace dev;
 
 // ------------------------------------------------------------ selection
 
@@ -138,6 +25,33 @@ struct SelLds {
   int bin, above, cnt, ngat;
   double result;
 };
+
+// Locate, in a 2048-bin histogram scanned from the top bin down, the bin that
+// holds the k-th largest entry given `above` entries in higher bins.  Each
+// thread owns 2048 / NT consecutive bins (descending).
+__device__ __forceinline__ void hist_locate(SelLds &sm, int above, int k) {
+  constexpr int BPT = 2048 / NT;
+  const int tid = threadIdx.x;
+  int c[BPT];
+  int loc = 0;
+#pragma unroll
+  for (int q = 0; q < BPT; q++) {
+    c[q] = (int)sm.hist[2047 - BPT * tid - q];
+    loc += c[q];
+  }
+  int tot;
+  int acc = above + block_excl_scan<NT>(loc, sm.scan, &tot);
+#pragma unroll
+  for (int q = 0; q < BPT; q++) {
+    if (acc < k && k <= acc + c[q]) {
+      sm.bin = 2047 - BPT * tid - q;
+      sm.above = acc;
+      sm.cnt = c[q];
+    }
+    acc += c[q];
+  }
+  __syncthreads();
+}
 
 // Exact k-th largest (1-based) of the entries a[j] >= 0, j in [0, p)
 // (negative entries are ignored).  Radix selection on the IEEE bit pattern
@@ -162,22 +76,7 @@ __device__ double select_kth(const double *__restrict__ a, int64_t p, int k, Sel
       }
     }
     __syncthreads();
-    const int b0 = 2047 - 2 * tid, b1 = 2046 - 2 * tid;
-    const int c0 = (int)sm.hist[b0], c1 = (int)sm.hist[b1];
-    int tot;
-    const int ex = block_excl_scan<NT>(c0 + c1, sm.scan, &tot);
-    const int a0 = above + ex;
-    if (a0 < k && k <= a0 + c0) {
-      sm.bin = b0;
-      sm.above = a0;
-      sm.cnt = c0;
-    }
-    if (a0 + c0 < k && k <= a0 + c0 + c1) {
-      sm.bin = b1;
-      sm.above = a0 + c0;
-      sm.cnt = c1;
-    }
-    __syncthreads();
+    hist_locate(sm, above, k);
     const int B = sm.bin, cnt = sm.cnt;
     above = sm.above;
     prefix = (prefix << width) | (unsigned long long)B;
@@ -512,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
 
   // loss-side terms of this iterate, summed over row blocks in fixed order
   double Fk = 0.0, negconj = 0.0;
-  for (int i = 0; i < B.rb; i++) {
+  for (int i = 0; i < B.nfin; i++) {
     Fk += B.rbsum[2 * i];
     negconj += B.rbsum[2 * i + 1];
   }
@@ -788,320 +687,517 @@ __global__ void k_iota(int32_t *idx, int64_t n) {
     idx[i] = (int32_t)i;
 }
 
-// ------------------------------------------------------------ X^T r
 
-template <typename T>
-struct XLoad;
+// ------------------------------------------------------------ register-resident node routines
+//
+// For p <= 16384 every thread keeps EPT = ceil(p / 512) coordinates
+// j = tid + e * 512 (coalesced) in one register array, with the node status
+// packed 2 bits per coordinate (3 = beyond p).  The passes of the selection,
+// the threshold search and Algorithm 1 read their entries through a functor
+// aval(e) (>= 0: a free entry; < 0: ignored), so only one FP64 array is live.
 
-template <>
-struct XLoad<float> {
-  static constexpr int VEC = 4;
-  __device__ __forceinline__ static void load(const float *p, double (&d)[4]) {
-    f4_t v = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(p));
-    d[0] = (double)v.x;
-    d[1] = (double)v.y;
-    d[2] = (double)v.z;
-    d[3] = (double)v.w;
-  }
-};
-
-template <>
-struct XLoad<double> {
-  static constexpr int VEC = 2;
-  __device__ __forceinline__ static void load(const double *p, double (&d)[2]) {
-    d2_t v = __builtin_nontemporal_load(reinterpret_cast<const d2_t *>(p));
-    d[0] = v.x;
-    d[1] = v.y;
-  }
-};
-
-// bf16 stored as uint16_t bit patterns
-template <>
-struct XLoad<uint16_t> {
-  static constexpr int VEC = 8;
-  __device__ __forceinline__ static void load(const uint16_t *p, double (&d)[8]) {
-    u4_t v = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(p));
-    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
+template <int EPT>
+struct PackedStatus {
+  uint32_t w[(EPT + 15) / 16];
+  __device__ __forceinline__ int operator()(int e) const { return (int)((w[e >> 4] >> (2 * (e & 15))) & 3u); }
+  __device__ __forceinline__ void load(const int8_t *__restrict__ st, int64_t p) {
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      d[2 * q] = (double)__uint_as_float(w[q] << 16);
-      d[2 * q + 1] = (double)__uint_as_float(w[q] & 0xffff0000u);
+    for (int q = 0; q < (EPT + 15) / 16; q++) w[q] = 0u;
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int64_t j = tid + (int64_t)e * NT;
+      const uint32_t c = (j < p) ? (uint32_t)st[j] : 3u;
+      w[e >> 4] |= c << (2 * (e & 15));
     }
   }
 };
 
-template <int VEC>
-__device__ __forceinline__ void load_rhs(const double *__restrict__ r, int64_t i, double (&d)[VEC]) {
+template <int EPT, class F>
+__device__ double select_kth_f(F aval, int k, SelLds &sm) {
+  const int tid = threadIdx.x;
+  unsigned long long prefix = 0ull;
+  int above = 0, shift = 52, width = 11;
+  for (;;) {
+    for (int b = tid; b < 2048; b += NT) sm.hist[b] = 0u;
+    __syncthreads();
+    const unsigned long long mask = (1ull << width) - 1ull;
 #pragma unroll
-  for (int q = 0; q < VEC; q += 2) {
-    d2_t v = *reinterpret_cast<const d2_t *>(r + i + q);
-    d[q] = v.x;
-    d[q + 1] = v.y;
-  }
-}
-
-// Deterministic transpose-reduction of 4 per-lane partial sums (one per
-// column) over the 64 lanes: afterwards lane 16*c holds the total of column c.
-__device__ __forceinline__ double reduce4(double (&v)[4]) {
-  const int lane = lane_id();
-  const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
-  double s0 = b5 ? v[0] : v[2], s1 = b5 ? v[1] : v[3];
-  double k0 = b5 ? v[2] : v[0], k1 = b5 ? v[3] : v[1];
-  k0 += __shfl_xor(s0, 32, 64);
-  k1 += __shfl_xor(s1, 32, 64);
-  double s = b4 ? k0 : k1;
-  double k = b4 ? k1 : k0;
-  k += __shfl_xor(s, 16, 64);
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
-  return k;
-}
-
-template <typename T, int NRHS>
-__global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X, int64_t n, int64_t p,
-                                                         const double *__restrict__ r1,
-                                                         const double *__restrict__ r2,
-                                                         double *__restrict__ h1,
-                                                         double *__restrict__ h2,
-                                                         const int32_t *__restrict__ done) {
-  if (done && *done) return;
-  constexpr int VEC = XLoad<T>::VEC;
-  constexpr int U = 2;  // row steps in flight
-  const int lane = lane_id();
-  const int64_t col0 = ((int64_t)blockIdx.x * (kGemvThreads / 64) + wave_id()) * kColsPerWave;
-  if (col0 >= p) return;
-  const T *c[4];
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const int64_t cj = (col0 + q < p) ? col0 + q : p - 1;
-    c[q] = X + cj * n;
-  }
-  double acc[NRHS][4];
-#pragma unroll
-  for (int h = 0; h < NRHS; h++)
-#pragma unroll
-    for (int q = 0; q < 4; q++) acc[h][q] = 0.0;
-  const int64_t step = 64 * VEC;
-  int64_t i = (int64_t)lane * VEC;
-  for (; i + (U - 1) * step + VEC <= n; i += U * step) {
-    double xv[U][4][VEC];
-    double rv[U][NRHS][VEC];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) XLoad<T>::load(c[q] + i + u * step, xv[u][q]);
-      load_rhs<VEC>(r1, i + u * step, rv[u][0]);
-      if (NRHS > 1) load_rhs<VEC>(r2, i + u * step, rv[u][NRHS - 1]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-#pragma unroll
-      for (int h = 0; h < NRHS; h++)
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-#pragma unroll
-          for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[u][q][e], rv[u][h][e], acc[h][q]);
-  }
-  for (; i + VEC <= n; i += step) {
-    double xv[4][VEC];
-    double rv[NRHS][VEC];
-#pragma unroll
-    for (int q = 0; q < 4; q++) XLoad<T>::load(c[q] + i, xv[q]);
-    load_rhs<VEC>(r1, i, rv[0]);
-    if (NRHS > 1) load_rhs<VEC>(r2, i, rv[NRHS - 1]);
-#pragma unroll
-    for (int h = 0; h < NRHS; h++)
-#pragma unroll
-      for (int q = 0; q < 4; q++)
-#pragma unroll
-        for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[q][e], rv[h][e], acc[h][q]);
-  }
-  const int64_t col = col0 + (lane >> 4);
-  const bool writer = (lane & 15) == 0 && col < p;
-  {
-    double t = reduce4(acc[0]);
-    if (writer) h1[col] = t;
-  }
-  if (NRHS > 1) {
-    double t = reduce4(acc[NRHS - 1]);
-    if (writer) h2[col] = t;
-  }
-}
-
-// ------------------------------------------------------------ column-list GEMV
-
-template <typename T>
-__global__ __launch_bounds__(kSpThreads) void k_spfwd(const T *__restrict__ X, int64_t n,
-                                                      const double *__restrict__ y, ProbBufs B,
-                                                      const int32_t *__restrict__ idx,
-                                                      const double *__restrict__ val,
-                                                      const int32_t *__restrict__ nlist, int32_t mode,
-                                                      const NodeState *S, double *u_out) {
-  constexpr int VEC = XLoad<T>::VEC;
-  __shared__ double red[(kSpThreads / 64) * 4];
-  __shared__ int last;
-  if (S && S->done) return;
-  const int rb = blockIdx.x, ch = blockIdx.y;
-  const int ns = *nlist;
-  const int cs = (ns + B.nch - 1) / B.nch;
-  const int t0 = ch * cs;
-  const int t1 = (t0 + cs < ns) ? t0 + cs : ns;
-  const int64_t row0 = (int64_t)rb * B.rows + (int64_t)threadIdx.x * VEC;
-  const bool active = row0 < n;
-  double acc[VEC];
-#pragma unroll
-  for (int e = 0; e < VEC; e++) acc[e] = 0.0;
-  if (active) {
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
-      double xv[4][VEC];
-      double w[4];
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        XLoad<T>::load(X + (int64_t)idx[t + q] * n + row0, xv[q]);
-        w[q] = val[t + q];
+    for (int e = 0; e < EPT; e++) {
+      const double x = aval(e);
+      if (x >= 0.0) {
+        const unsigned long long key = (unsigned long long)__double_as_longlong(x);
+        if ((key >> (shift + width)) == prefix) atomicAdd(&sm.hist[(key >> shift) & mask], 1u);
       }
-#pragma unroll
-      for (int q = 0; q < 4; q++)
-#pragma unroll
-        for (int e = 0; e < VEC; e++) acc[e] = fma(xv[q][e], w[q], acc[e]);
     }
-    for (; t < t1; t++) {
-      double xv[VEC];
-      XLoad<T>::load(X + (int64_t)idx[t] * n + row0, xv);
-      const double w = val[t];
-#pragma unroll
-      for (int e = 0; e < VEC; e++) acc[e] = fma(xv[e], w, acc[e]);
+    __syncthreads();
+    hist_locate(sm, above, k);
+    const int B = sm.bin, cnt = sm.cnt;
+    above = sm.above;
+    prefix = (prefix << width) | (unsigned long long)B;
+    if (shift == 0) {
+      __syncthreads();
+      return __longlong_as_double((long long)prefix);
     }
-    double *part = B.part + (int64_t)ch * n + row0;
+    if (cnt <= 64) {
+      if (tid == 0) sm.ngat = 0;
+      __syncthreads();
 #pragma unroll
-    for (int e = 0; e < VEC; e++) __hip_atomic_store(part + e, acc[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int e = 0; e < EPT; e++) {
+        const double x = aval(e);
+        if (x >= 0.0) {
+          const unsigned long long key = (unsigned long long)__double_as_longlong(x);
+          if ((key >> shift) == prefix) {
+            const int pos = atomicAdd(&sm.ngat, 1);
+            if (pos < 64) sm.gat[pos] = x;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < 64) {
+        double v = (tid < cnt) ? sm.gat[tid] : -1.0;
+        v = wave_sort_desc(v);
+        if (tid == k - above - 1) sm.result = v;
+      }
+      __syncthreads();
+      const double r = sm.result;
+      __syncthreads();
+      return r;
+    }
+    const int nw = shift < 11 ? shift : 11;
+    shift -= nw;
+    width = nw;
   }
-  __threadfence();
+}
+
+template <int EPT, class F>
+__device__ double topsum_huber_f(F aval, int kbar, double M, SelLds &sm, double *red) {
+  if (kbar <= 0) return 0.0;
+  const double t = select_kth_f<EPT>(aval, kbar, sm);
+  const double Ht = huber(t, M);
+  double v[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const double x = aval(e);
+    if (x >= 0.0) v[0] += fmax(huber(x, M) - Ht, 0.0);
+  }
+  block_sum<NT, 1>(v, red);
+  return (double)kbar * Ht + v[0];
+}
+
+template <int EPT, class F>
+__device__ double solve_tau_f(F aval, int kbar, double rho, double M, double warm, double *red, int *evals) {
+  double st[2] = {0.0, 0.0};
+  double mx = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const double x = aval(e);
+    if (x > 0.0) {
+      st[0] += 1.0;
+      st[1] += x;
+      mx = fmax(mx, x);
+    }
+  }
+  block_sum<NT, 2>(st, red);
+  const double amax = block_max<NT>(mx, red);
+  *evals = 0;
+  if (kbar <= 0) return INFINITY;
+  const double K = (double)kbar;
+  if (st[0] <= K) return 0.0;
+  const bool finM = isfinite(M);
+  auto Dof = [&](double t) { return finM ? fmin(t / rho, M) : t / rho; };
+  auto froot = [&](double h, double nb, double sB) -> double {
+    if (nb <= 0.0) return NAN;
+    if (finM) {
+      const double Sf = h + (sB - nb * rho * M) / M;
+      if (Sf >= K) return (sB - M * (K - h)) / nb;
+    }
+    return rho * sB / (K - h + rho * nb);
+  };
+  double lo = 0.0, hi = amax;
+  double tau = (warm > lo && warm < hi) ? warm : froot(0.0, st[0], st[1]);
+  if (!(tau > lo && tau < hi)) tau = 0.5 * (lo + hi);
+  bool from_root = false;
+  double ph = -1.0, pb = -1.0;
+  int nsteps = 0;
+  double wref = hi - lo;
+  for (int it = 0; it < 200; it++) {
+    const double D = Dof(tau);
+    double v[3] = {0.0, 0.0, 0.0};
+    const double top = tau + D;
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double x = aval(e);
+      if (x > tau) {
+        v[1] += 1.0;
+        if (x > top) v[0] += 1.0;
+        else v[2] += x;
+      }
+    }
+    block_sum<NT, 3>(v, red);
+    *evals = it + 1;
+    if (from_root && v[0] == ph && v[1] == pb) return tau;
+    const double S = v[0] + (v[2] - (v[1] - v[0]) * tau) / D;
+    if (S > K) lo = tau;
+    else if (S < K) hi = tau;
+    else return tau;
+    double c = froot(v[0], v[1] - v[0], v[2]);
+    if (c == tau) return tau;
+    if (nsteps >= 2 && hi - lo > 0.5 * wref) {
+      nsteps = 0;
+      wref = hi - lo;
+      c = NAN;
+    }
+    if (c > lo && c < hi) {
+      from_root = true;
+      nsteps++;
+    } else {
+      c = 0.5 * (lo + hi);
+      from_root = false;
+      nsteps = 0;
+      wref = hi - lo;
+    }
+    ph = v[0];
+    pb = v[1];
+    if (!(c > lo && c < hi)) return c;
+    tau = c;
+  }
+  return tau;
+}
+
+template <int EPT, class F>
+__device__ double alg1_f(F aval, int kbar, double theta, double *red) {
+  if (kbar <= 0 || !(theta > 0.0)) return 0.0;
+  const double K = (double)kbar;
+  double s = theta / K;
+  double prevK = 0.0;
+  for (int it = 0; it <= kbar + 1; it++) {
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double x = aval(e);
+      if (x >= 0.0) {
+        if (x > s) {
+          v[0] += 1.0;
+          v[2] += x * x;
+        } else {
+          v[1] += x;
+        }
+      }
+    }
+    block_sum<NT, 3>(v, red);
+    if (v[0] == prevK || v[0] >= K) return 0.5 * (v[2] + (K - v[0]) * s * s);
+    prevK = v[0];
+    s = fmin(s, v[1] / (K - v[0]));
+  }
+  return NAN;
+}
+
+struct NodeLds {
+  double red[NW * 4];
+  int scan[NW];
+  int cnt_ew[256];   // EPT * NW <= 256
+  SelLds sel;
+  double bcd[4];
+  int bci[4];
+};
+
+// Support list (ascending j), Algorithm 1 value and dom test of the iterate x
+// held in registers.
+template <int EPT>
+__device__ IterStats finish_r(const double (&x)[EPT], const PackedStatus<EPT> &sv, int kbar, double M,
+                              int32_t *__restrict__ sidx, double *__restrict__ sval, NodeLds &L) {
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+  double v[2] = {0.0, 0.0};  // theta, sum_{J1} x^2
+  double amax = 0.0, j0max = 0.0, boxmax = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    const double xj = x[e];
+    const double ax = fabs(xj);
+    if (s != 3) {
+      amax = fmax(amax, ax);
+      if (s == kZero) j0max = fmax(j0max, ax);
+      else boxmax = fmax(boxmax, ax);
+      if (s == kFree) v[0] += ax;
+      else if (s == kOne) v[1] += xj * xj;
+    }
+    const unsigned long long m = __ballot(s != 3 && xj != 0.0);
+    if (lane == 0) L.cnt_ew[e * NW + w] = __popcll(m);
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int prev = atomicAdd(&B.counter[rb], 1u);
-    last = (prev == (unsigned int)(B.nch - 1));
+  const int c = (tid < EPT * NW) ? L.cnt_ew[tid] : 0;
+  int tot;
+  const int off = block_excl_scan<NT>(c, L.scan, &tot);
+  __syncthreads();
+  if (tid < EPT * NW) L.cnt_ew[tid] = off;
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const bool nz = sv(e) != 3 && x[e] != 0.0;
+    const unsigned long long m = __ballot(nz);
+    if (nz) {
+      const int pos = L.cnt_ew[e * NW + w] + __popcll(m & below);
+      sidx[pos] = (int32_t)(tid + e * NT);
+      sval[pos] = x[e];
+    }
+  }
+  block_sum<NT, 2>(v, L.red);
+  const double gA = block_max<NT>(amax, L.red);
+  const double g0 = block_max<NT>(j0max, L.red);
+  const double gB = block_max<NT>(boxmax, L.red);
+  const double zt = 1e-9 * fmax(1.0, gA);
+  int ok = (g0 <= zt);
+  if (isfinite(M) && gB > M * (1.0 + 1e-9)) ok = 0;
+  if (kbar == 0) {
+    if (v[0] > zt) ok = 0;
+  } else if (isfinite(M) && v[0] > M * (double)kbar * (1.0 + 1e-9)) {
+    ok = 0;
+  }
+  auto aval = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
+  const double gv = 0.5 * v[1] + alg1_f<EPT>(aval, kbar, v[0], L.red);
+  return IterStats{gv, ok, tot};
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_node_init_r(const NodeParams *__restrict__ prm, NodeState *S,
+                                                    NodeBufs nb, const double *__restrict__ beta0, double L) {
+  __shared__ NodeLds lds;
+  const int tid = threadIdx.x;
+  const int64_t p = prm->p;
+  PackedStatus<EPT> sv;
+  sv.load(prm->st, p);
+  double x[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int64_t j = tid + (int64_t)e * NT;
+    x[e] = 0.0;
+    if (j < p) {
+      const double b = beta0 ? beta0[j] : 0.0;
+      x[e] = b;
+      nb.x0[j] = b;
+      nb.xbest[j] = b;
+      nb.x1[j] = 0.0;
+      nb.hprev[j] = 0.0;
+    }
+  }
+  IterStats is = finish_r<EPT>(x, sv, prm->kbar, prm->M, nb.sidx, nb.sval, lds);
+  if (tid == 0) {
+    NodeState s{};
+    s.L = L;
+    s.t = 1.0;
+    s.gap_ref = INFINITY;
+    s.lb = -INFINITY;
+    s.ub = INFINITY;
+    s.phi = INFINITY;
+    s.psi = -INFINITY;
+    s.rel_gap = INFINITY;
+    s.gval = is.gval;
+    s.tau = -1.0;
+    s.status = kMaxIter;
+    s.nsupp = is.nsupp;
+    s.indom = is.indom;
+    *S = s;
+  }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict__ prm, NodeState *S,
+                                                    NodeBufs nb, ProbBufs B) {
+  __shared__ NodeLds lds;
+  if (S->done) return;
+  const int tid = threadIdx.x;
+  const int64_t p = prm->p;
+  const int kbar = prm->kbar, loss = prm->loss;
+  const double lam2 = prm->lambda2, M = prm->M;
+  const int parity = S->parity;
+  const double L = S->L;
+  PackedStatus<EPT> sv;
+  sv.load(prm->st, p);
+  double Fk = 0.0, negconj = 0.0;
+  for (int i = 0; i < B.nfin; i++) {
+    Fk += B.rbsum[2 * i];
+    negconj += B.rbsum[2 * i + 1];
+  }
+  // dual value at x^k: w = X^T zeta / (2 lambda2)
+  const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
+  double x[EPT];
+  double sj1[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    x[e] = 0.0;
+    const int s = sv(e);
+    if (s != 3) {
+      x[e] = B.h1[tid + (int64_t)e * NT] * wscale;
+      if (s == kOne) sj1[0] += huber(x[e], M);
+    }
+  }
+  block_sum<NT, 1>(sj1, lds.red);
+  auto aval = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
+  const double topsum = topsum_huber_f<EPT>(aval, kbar, M, lds.sel, lds.red);
+  const double psi = negconj - 2.0 * lam2 * (sj1[0] + topsum);
+  const double phi = S->indom ? Fk + 2.0 * lam2 * S->gval : INFINITY;
+  if (tid == 0) {
+    const int it = S->iter;
+    const double gap = phi - psi;
+    double lb = S->lb, ub = S->ub;
+    int improved = 0, ub_improved = 0;
+    if (psi > lb) {
+      lb = psi;
+      improved = 1;
+    }
+    if (phi < ub) {
+      ub = phi;
+      ub_improved = 1;
+    }
+    const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
+    int done = 0, status = kMaxIter;
+    if (rel <= prm->tol) {
+      done = 1;
+      status = kConverged;
+    } else if (!isnan(prm->cutoff) && lb >= prm->cutoff) {
+      done = 1;
+      status = kCutoffPrune;
+    } else if (!isnan(prm->cutoff) && ub <= prm->cutoff) {
+      done = 1;
+      status = kCutoffBranch;
+    } else if (it >= prm->max_iter) {
+      done = 1;
+      status = kMaxIter;
+    }
+    double m = 0.0, t = S->t, gap_ref = S->gap_ref;
+    int restart = 0, restarts = S->restarts;
+    if (!done) {
+      if (it == 0) {
+        restart = 1;
+        gap_ref = gap;
+      } else if (gap <= gap_ref / prm->eta) {
+        restart = 1;
+        gap_ref = gap;
+        restarts++;
+      }
+      if (restart) {
+        m = 0.0;
+        t = 1.0;
+      } else {
+        const double tn = fista_next_t(t);
+        m = (t - 1.0) / tn;
+        t = tn;
+      }
+    }
+    S->phi = phi;
+    S->psi = psi;
+    S->lb = lb;
+    S->ub = ub;
+    S->rel_gap = rel;
+    S->improved = improved;
+    S->status = status;
+    S->t = t;
+    S->gap_ref = gap_ref;
+    S->restarts = restarts;
+    S->mom = m;
+    if (done) S->done = 1;
+    lds.bcd[0] = m;
+    lds.bci[0] = done;
+    lds.bci[1] = restart;
+    lds.bci[2] = ub_improved;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (threadIdx.x == 0) B.counter[rb] = 0u;
-  double u[VEC];
+  double *__restrict__ xc = parity ? nb.x1 : nb.x0;
+  double *__restrict__ xn = parity ? nb.x0 : nb.x1;  // holds x^{k-1}, receives x^{k+1}
+  if (lds.bci[2]) {
 #pragma unroll
-  for (int e = 0; e < VEC; e++) u[e] = 0.0;
-  if (active) {
-    for (int c = 0; c < B.nch; c++) {
-      const double *part = B.part + (int64_t)c * n + row0;
-#pragma unroll
-      for (int e = 0; e < VEC; e++) u[e] += __hip_atomic_load(part + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) nb.xbest[tid + (int64_t)e * NT] = xc[tid + (int64_t)e * NT];
   }
-  double sums[2] = {0.0, 0.0};
-  if (mode == kSpPlain) {
-    if (active)
+  if (lds.bci[0]) return;
+  const double m = lds.bcd[0];
+  const int restart = lds.bci[1];
+  const double invL = 1.0 / L;
+  // gradient step at the momentum point; x[] now holds v
 #pragma unroll
-      for (int e = 0; e < VEC; e++) u_out[row0 + e] = u[e];
-    return;
-  }
-  const int improved = S->improved;
-  if (mode == kSpLsq) {
-    if (active) {
-#pragma unroll
-      for (int e = 0; e < VEC; e++) {
-        const int64_t i = row0 + e;
-        if (improved) B.zbest[i] = 2.0 * B.r[i];
-        const double yi = y[i];
-        const double ri = yi - u[e];
-        B.r[i] = ri;
-        sums[0] += ri * ri;
-        sums[1] += 2.0 * ri * yi - ri * ri;
+  for (int e = 0; e < EPT; e++) {
+    x[e] = 0.0;
+    if (sv(e) != 3) {
+      const int64_t j = tid + (int64_t)e * NT;
+      const double xk = xc[j], xq = xn[j];
+      const double yj = xk + m * (xk - xq);
+      double gj;
+      if (loss == kLsq) {
+        const double h = B.h1[j], hp = nb.hprev[j];
+        gj = -2.0 * ((1.0 + m) * h - m * hp);
+        nb.hprev[j] = h;
+      } else {
+        gj = restart ? -B.h1[j] : B.h2[j];
       }
-    }
-  } else {
-    const double t = S->t;
-    const double mt = (t - 1.0) / fista_next_t(t);
-    if (active) {
-#pragma unroll
-      for (int e = 0; e < VEC; e++) {
-        const int64_t i = row0 + e;
-        const double uo = B.ucur[i];
-        B.uprev[i] = uo;
-        B.ucur[i] = u[e];
-        if (improved) B.zbest[i] = B.r[i];
-        const double yi = y[i];
-        const double z = yi * u[e];
-        const double a = 1.0 / (1.0 + exp(z));
-        B.r[i] = yi * a;
-        sums[0] += softplus(-z);
-        sums[1] += a * softplus(z) + (1.0 - a) * softplus(-z);
-        const double sm = (1.0 + mt) * u[e] - mt * uo;
-        B.gm[i] = -yi / (1.0 + exp(yi * sm));
-      }
+      x[e] = yj - gj * invL;
     }
   }
-  block_sum<kSpThreads, 2>(sums, red);
-  if (threadIdx.x == 0) {
-    B.rbsum[2 * rb] = sums[0];
-    B.rbsum[2 * rb + 1] = sums[1];
+  const double rho = 2.0 * lam2 * invL;
+  int evals = 0;
+  const double tau = solve_tau_f<EPT>(aval, kbar, rho, M, S->tau, lds.red, &evals);
+  const double inv1p = 1.0 / (1.0 + rho);
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    double xv = 0.0;
+    if (s != 3) {
+      if (s != kZero) {
+        const double av = fabs(x[e]);
+        double r = fmin(av * inv1p, M);
+        if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
+        xv = (r == 0.0) ? 0.0 : copysign(r, x[e]);
+      }
+      xn[tid + (int64_t)e * NT] = xv;
+    }
+    x[e] = xv;
+  }
+  IterStats is = finish_r<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds);
+  if (tid == 0) {
+    S->gval = is.gval;
+    S->indom = is.indom;
+    S->nsupp = is.nsupp;
+    S->tau = tau;
+    S->tau_iters = evals;
+    S->parity = parity ^ 1;
+    S->iter = S->iter + 1;
   }
 }
 
 }  // namespace
 
-// ------------------------------------------------------------ launchers
-
-hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
-                         const int32_t *done, hipStream_t s) {
-  const int cols_per_block = (kGemvThreads / 64) * kColsPerWave;
-  dim3 grid((unsigned)((P.p + cols_per_block - 1) / cols_per_block));
-  dim3 block(kGemvThreads);
-  const bool two = (r2 != nullptr);
-  switch (P.xdt) {
-    case kF32:
-      if (two) k_gemv_t<float, 2><<<grid, block, 0, s>>>((const float *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      else k_gemv_t<float, 1><<<grid, block, 0, s>>>((const float *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      break;
-    case kF64:
-      if (two) k_gemv_t<double, 2><<<grid, block, 0, s>>>((const double *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      else k_gemv_t<double, 1><<<grid, block, 0, s>>>((const double *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      break;
-    default:
-      if (two) k_gemv_t<uint16_t, 2><<<grid, block, 0, s>>>((const uint16_t *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      else k_gemv_t<uint16_t, 1><<<grid, block, 0, s>>>((const uint16_t *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx, const double *val,
-                        const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
-                        hipStream_t s) {
-  dim3 grid((unsigned)B.rb, (unsigned)B.nch);
-  dim3 block(kSpThreads);
-  switch (P.xdt) {
-    case kF32:
-      k_spfwd<float><<<grid, block, 0, s>>>((const float *)P.X, P.n, P.y, B, idx, val, nlist, mode, S, u_out);
-      break;
-    case kF64:
-      k_spfwd<double><<<grid, block, 0, s>>>((const double *)P.X, P.n, P.y, B, idx, val, nlist, mode, S, u_out);
-      break;
-    default:
-      k_spfwd<uint16_t><<<grid, block, 0, s>>>((const uint16_t *)P.X, P.n, P.y, B, idx, val, nlist, mode, S, u_out);
-      break;
-  }
-  return hipGetLastError();
+int node_ept(int64_t p) {
+  for (int e = 1; e <= 32; e *= 2)
+    if (p <= (int64_t)e * NT) return e;
+  return 0;
 }
 
 hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, const double *beta0,
-                            double L, hipStream_t s) {
-  k_node_init<<<1, NT, 0, s>>>(prm, S, nb, beta0, L);
+                            double L, int64_t p, hipStream_t s) {
+  switch (node_ept(p)) {
+    case 1: k_node_init_r<1><<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+    case 2: k_node_init_r<2><<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+    case 4: k_node_init_r<4><<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+    case 8: k_node_init_r<8><<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+    case 16: k_node_init_r<16><<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+    case 32: k_node_init_r<32><<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+    default: k_node_init<<<1, NT, 0, s>>>(prm, S, nb, beta0, L); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
-                            hipStream_t s) {
-  k_node_step<<<1, NT, 0, s>>>(prm, S, nb, B);
+                            int64_t p, hipStream_t s) {
+  switch (node_ept(p)) {
+    case 1: k_node_step_r<1><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+    case 2: k_node_step_r<2><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+    case 4: k_node_step_r<4><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+    case 8: k_node_step_r<8><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+    case 16: k_node_step_r<16><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+    case 32: k_node_step_r<32><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+    default: k_node_step<<<1, NT, 0, s>>>(prm, S, nb, B); break;
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,202 @@
+// Column-list GEMV on gfx950: u = sum_t X[:, idx[t]] val[t] over the support
+// of the iterate (or all columns), FP64 accumulation, followed by the loss
+// epilogue of the solver.  Two kernels:
+//
+// k_spfwd_part  grid = row blocks x column chunks.  The list entries of a
+//               chunk are wave-uniform, so column bases live in scalar
+//               registers and every lane keeps 16 independent 16-byte
+//               non-temporal loads in flight (4 to 8 rows per lane), converted
+//               to FP64 at the FMA.  Writes its partial sums to part[chunk][n].
+// k_spfwd_final grid over rows: sums the chunk partials in chunk order (so the
+//               result does not depend on scheduling) and runs the epilogue:
+//   least squares: r = y - u, F = ||r||^2, -F*(-zeta) = 2 r^T y - ||r||^2;
+//   logistic:      zeta = y sigma(-y u), F, binary entropies, and the gradient
+//                  at the momentum point (1+m)u - m u_prev.
+// Bytes per launch pair: |list| * n * sizeof(X) + 16 * nch * n (partials)
+// + the epilogue vectors.
+#include "pr_device.h"
+
+namespace pr {
+namespace {
+using namespace dev;
+
+constexpr int kSpInFlight = 16;   // columns in flight per lane
+constexpr int kFinThreads = 256;
+constexpr int kFinRows = 2;       // rows per thread in the finalize kernel
+
+// 16 raw bytes of X and their FP64 value e (exact upcast)
+template <typename T>
+struct XRaw;
+template <>
+struct XRaw<float> {
+  static constexpr int VEC = 4;
+  __device__ __forceinline__ static double at(const u4_t &r, int e) { return (double)__uint_as_float(r[e]); }
+};
+template <>
+struct XRaw<double> {
+  static constexpr int VEC = 2;
+  __device__ __forceinline__ static double at(const u4_t &r, int e) {
+    return __hiloint2double((int)r[2 * e + 1], (int)r[2 * e]);
+  }
+};
+template <>
+struct XRaw<uint16_t> {
+  static constexpr int VEC = 8;
+  __device__ __forceinline__ static double at(const u4_t &r, int e) {
+    const unsigned int w = r[e >> 1];
+    return (double)__uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kSpThreads) void k_spfwd_part(const T *__restrict__ X, int64_t n, ProbBufs B,
+                                                           const int32_t *__restrict__ idx,
+                                                           const double *__restrict__ val,
+                                                           const int32_t *__restrict__ nlist,
+                                                           const NodeState *S) {
+  constexpr int VEC = XRaw<T>::VEC;
+  if (S && S->done) return;
+  const int rb = blockIdx.x, ch = blockIdx.y;
+  const int ns = *nlist;
+  const int cs = (ns + B.nch - 1) / B.nch;
+  const int t0 = ch * cs;
+  const int t1 = (t0 + cs < ns) ? t0 + cs : ns;
+  const int64_t row0 = (int64_t)rb * B.rows + (int64_t)threadIdx.x * VEC;
+  if (row0 >= n) return;
+  double acc[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; e++) acc[e] = 0.0;
+  int t = t0;
+  for (; t + kSpInFlight <= t1; t += kSpInFlight) {
+    u4_t raw[kSpInFlight];
+#pragma unroll
+    for (int c = 0; c < kSpInFlight; c++) {
+      const T *col = X + (int64_t)idx[t + c] * n;   // wave-uniform column base
+      raw[c] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
+    }
+#pragma unroll
+    for (int c = 0; c < kSpInFlight; c++) {
+      const double w = val[t + c];
+#pragma unroll
+      for (int e = 0; e < VEC; e++) acc[e] = fma(XRaw<T>::at(raw[c], e), w, acc[e]);
+    }
+  }
+  for (; t < t1; t++) {
+    const T *col = X + (int64_t)idx[t] * n;
+    const u4_t raw = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
+    const double w = val[t];
+#pragma unroll
+    for (int e = 0; e < VEC; e++) acc[e] = fma(XRaw<T>::at(raw, e), w, acc[e]);
+  }
+  double *part = B.part + (int64_t)ch * n + row0;
+#pragma unroll
+  for (int e = 0; e < VEC; e += 2) *reinterpret_cast<d2_t *>(part + e) = d2_t{acc[e], acc[e + 1]};
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const double *__restrict__ y, ProbBufs B,
+                                                             int32_t mode, const NodeState *S, double *u_out) {
+  constexpr int VEC = kFinRows;
+  __shared__ double red[(kFinThreads / 64) * 4];
+  if (S && S->done) return;
+  const int fb = blockIdx.x;
+  const int64_t row0 = ((int64_t)fb * kFinThreads + threadIdx.x) * VEC;
+  const bool active = row0 < n;
+  double u[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; e++) u[e] = 0.0;
+  if (active) {
+    const int nch = B.nch;
+    int c = 0;
+    for (; c + 8 <= nch; c += 8) {
+      d2_t pv[8];
+#pragma unroll
+      for (int q = 0; q < 8; q++) pv[q] = *reinterpret_cast<const d2_t *>(B.part + (int64_t)(c + q) * n + row0);
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        u[0] += pv[q].x;
+        u[1] += pv[q].y;
+      }
+    }
+    for (; c < nch; c++) {
+      const d2_t pv = *reinterpret_cast<const d2_t *>(B.part + (int64_t)c * n + row0);
+      u[0] += pv.x;
+      u[1] += pv.y;
+    }
+  }
+  double sums[2] = {0.0, 0.0};
+  if (mode == kSpPlain) {
+    if (active)
+#pragma unroll
+      for (int e = 0; e < VEC; e++) u_out[row0 + e] = u[e];
+    return;
+  }
+  const int improved = S->improved;
+  if (mode == kSpLsq) {
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < VEC; e++) {
+        const int64_t i = row0 + e;
+        if (improved) B.zbest[i] = 2.0 * B.r[i];
+        const double yi = y[i];
+        const double ri = yi - u[e];
+        B.r[i] = ri;
+        sums[0] += ri * ri;
+        sums[1] += 2.0 * ri * yi - ri * ri;
+      }
+    }
+  } else {
+    const double t = S->t;
+    const double mt = (t - 1.0) / fista_next_t(t);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < VEC; e++) {
+        const int64_t i = row0 + e;
+        const double uo = B.ucur[i];
+        B.uprev[i] = uo;
+        B.ucur[i] = u[e];
+        if (improved) B.zbest[i] = B.r[i];
+        const double yi = y[i];
+        const double z = yi * u[e];
+        const double a = 1.0 / (1.0 + exp(z));
+        B.r[i] = yi * a;
+        sums[0] += softplus(-z);
+        sums[1] += a * softplus(z) + (1.0 - a) * softplus(-z);
+        const double sm = (1.0 + mt) * u[e] - mt * uo;
+        B.gm[i] = -yi / (1.0 + exp(yi * sm));
+      }
+    }
+  }
+  block_sum<kSpThreads, 2>(sums, red);
+  if (threadIdx.x == 0) {
+    B.rbsum[2 * fb] = sums[0];
+    B.rbsum[2 * fb + 1] = sums[1];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx, const double *val,
+                        const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
+                        hipStream_t s) {
+  dim3 grid((unsigned)B.rb, (unsigned)B.nch);
+  dim3 block(kSpThreads);
+  switch (P.xdt) {
+    case kF32:
+      k_spfwd_part<float><<<grid, block, 0, s>>>((const float *)P.X, P.n, B, idx, val, nlist, S);
+      break;
+    case kF64:
+      k_spfwd_part<double><<<grid, block, 0, s>>>((const double *)P.X, P.n, B, idx, val, nlist, S);
+      break;
+    default:
+      k_spfwd_part<uint16_t><<<grid, block, 0, s>>>((const uint16_t *)P.X, P.n, B, idx, val, nlist, S);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_spfwd_final<<<(unsigned)B.nfin, kFinThreads, 0, s>>>(P.n, P.y, B, mode, S, u_out);
+  return hipGetLastError();
+}
+
+int spfwd_final_blocks(int64_t n) { return (int)((n + kFinThreads * kFinRows - 1) / (kFinThreads * kFinRows)); }
+
+}  // namespace pr
