@@ -169,6 +169,18 @@ int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *
  * context stream; *ms_avg = elapsed / reps.  r device n, h device p. */
 int pr_time_gemv_t(pr_ctx *ctx, const double *r, double *h, int32_t reps, double *ms_avg);
 
+/* FP64 MFMA product used by pr_solve_batch for both of its matrix products
+ * (test and measurement entry point): C[z][r][c] = sum over k in split z of
+ * A[c][k] * B[r][k].  A is Mc x K, row-major BF16 bit patterns (uint16,
+ * converted exactly), leading dimension lda (multiple of 4); B is Nr x K,
+ * row-major FP64, leading dimension ldb (even); FP64 accumulation, output C
+ * FP64, KS x Nr x Mc (one plane per split of the reduction dimension into KS
+ * equal parts).  Requires Mc a multiple of 128, Nr of 64, K of 16*KS; A 8-byte,
+ * B 16-byte aligned.  A, B, C device; the call synchronises the stream
+ * (hipStream_t or NULL).  PR_EINVAL on a violated requirement. */
+int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
+            int64_t Nr, int64_t K, int32_t KS);
+
 const char *pr_strerror(int code);
 
 #ifdef __cplusplus

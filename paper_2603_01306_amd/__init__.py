@@ -4,6 +4,6 @@ The solver (FISTA with duality-gap restarts on the perspective relaxation,
 arXiv 2603.01306) lives in the HIP library libpr.so behind the C ABI of
 include/pr.h; this package is its Python binding.
 """
-from ._binding import (Context, Node, prox, regularizer, default_opts, load, PrError,  # noqa: F401
+from ._binding import (Context, Node, prox, regularizer, gemm, default_opts, load, PrError,  # noqa: F401
                        CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH,
                        FREE, ZERO, ONE, LSQ, LOGISTIC, F64, F32, BF16, EXPORTS, LIB_PATH)

@@ -20,7 +20,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_strerror"]
+           "pr_time_gemv_t", "pr_gemm", "pr_strerror"]
 
 
 class PrProblem(ctypes.Structure):
@@ -91,6 +91,9 @@ def load():
         L.pr_solve_batch.restype = ctypes.c_int
         L.pr_solve_batch.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, ctypes.POINTER(PrOpts),
                                      P, P, ctypes.POINTER(PrResult)]
+        L.pr_gemm.restype = ctypes.c_int
+        L.pr_gemm.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
+                              ctypes.c_int64, ctypes.c_int32]
         L.pr_strerror.restype = ctypes.c_char_p
         L.pr_strerror.argtypes = [ctypes.c_int]
         _lib = L
@@ -274,6 +277,21 @@ def prox(v, rho, k, M, status):
     _check(load().pr_prox(_stream_ptr(), _dptr(v.contiguous()), v.numel(), float(rho), int(k), float(M),
                           _dptr(status.contiguous()), _dptr(out)), "pr_prox")
     return out
+
+
+def gemm(A, B, KS=1):
+    """C[z] = B[:, split z] @ A[:, split z]^T for a bfloat16 CUDA tensor A
+    (Mc x K) and a float64 CUDA tensor B (Nr x K), FP64 MFMA; returns
+    (KS, Nr, Mc) float64."""
+    import torch
+    if A.dtype != torch.bfloat16 or B.dtype != torch.float64 or A.stride(1) != 1 or B.stride(1) != 1:
+        raise ValueError("gemm: A bfloat16 and B float64, both row-major")
+    Mc, K = A.shape
+    Nr = B.shape[0]
+    C = torch.empty((KS, Nr, Mc), dtype=torch.float64, device=A.device)
+    _check(load().pr_gemm(_stream_ptr(), _dptr(A), A.stride(0), _dptr(B), B.stride(0), _dptr(C), Mc, Nr, K, int(KS)),
+           "pr_gemm")
+    return C
 
 
 def regularizer(beta, alpha, k, M, status):

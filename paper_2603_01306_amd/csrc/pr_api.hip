@@ -54,6 +54,25 @@ struct pr_ctx {
   int32_t graph_units = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
+  // batched path (least squares, BF16 X, n and p multiples of 128, p <= 16384)
+  bool batch_ok = false;
+  int32_t KS = 1, KSF = 1, nfb = 0;
+  uint16_t *Xrow = nullptr;  // row-major copy of X (n x p)
+  double *Bx = nullptr;      // [cap padded][p] FP64 current iterates
+  double *Rd = nullptr;      // [cap padded][n] FP64 residuals
+  double *CF = nullptr;      // [KSF][cap padded][n]
+  double *CT = nullptr;      // [KS][cap padded][p]
+  double *fsum = nullptr;    // [cap][nfb][2]
+  double *bx0 = nullptr, *bx1 = nullptr, *bxbest = nullptr, *bhprev = nullptr, *bsval = nullptr;
+  int32_t *bsidx = nullptr;
+  int8_t *bstatus = nullptr;
+  NodeParams *d_bprm = nullptr;
+  NodeState *d_bstate = nullptr;
+  NodeState *h_bstate = nullptr;  // pinned, cap
+  int32_t *d_active = nullptr;
+  int32_t *h_active = nullptr;    // pinned, 2 slots
+  hipGraphExec_t bgexec = nullptr;
+  int32_t bgraph_units = 0, bgraph_m = 0;
 };
 
 namespace {
@@ -61,6 +80,13 @@ namespace {
 void free_ctx(pr_ctx *c) {
   if (!c) return;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
+  void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
+                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active};
+  for (void *b : bb)
+    if (b) (void)hipFree(b);
+  if (c->h_bstate) (void)hipHostFree(c->h_bstate);
+  if (c->h_active) (void)hipHostFree(c->h_active);
   for (int i = 0; i < 2; i++) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->tev[i]) (void)hipEventDestroy(c->tev[i]);
@@ -200,6 +226,105 @@ int power_norm2(pr_ctx *c) {
   return PR_OK;
 }
 
+int nr_of(int32_t m) { return (m + 63) / 64 * 64; }
+
+int alloc_batch(pr_ctx *c) {
+  const int64_t n = c->P.n, p = c->P.p;
+  const int cap = c->max_batch;
+  const int NrMax = nr_of(cap);
+  // split the reductions so that each GEMM has >= ~1024 workgroups at full batch
+  const int tiles_t = (int)(p / 128) * (NrMax / 64);
+  int KS = 1;
+  while (KS < 16 && tiles_t * KS < 512 && (n / (2 * KS)) % 16 == 0) KS *= 2;
+  const int tiles_f = (int)(n / 128) * (NrMax / 64);
+  int KSF = 1;
+  while (KSF < 16 && tiles_f * KSF < 512 && (p / (2 * KSF)) % 16 == 0) KSF *= 2;
+  c->KS = KS;
+  c->KSF = KSF;
+  c->nfb = batch_resid_blocks(n);
+  bool ok = dalloc(&c->Xrow, (size_t)n * p) == hipSuccess;
+  ok = ok && dalloc(&c->Bx, (size_t)NrMax * p) == hipSuccess;
+  ok = ok && dalloc(&c->Rd, (size_t)NrMax * n) == hipSuccess;
+  ok = ok && dalloc(&c->CF, (size_t)KSF * NrMax * n) == hipSuccess;
+  ok = ok && dalloc(&c->CT, (size_t)KS * NrMax * p) == hipSuccess;
+  ok = ok && dalloc(&c->fsum, (size_t)2 * cap * c->nfb) == hipSuccess;
+  ok = ok && dalloc(&c->bx0, (size_t)cap * p) == hipSuccess && dalloc(&c->bx1, (size_t)cap * p) == hipSuccess;
+  ok = ok && dalloc(&c->bxbest, (size_t)cap * p) == hipSuccess && dalloc(&c->bhprev, (size_t)cap * p) == hipSuccess;
+  ok = ok && dalloc(&c->bsval, (size_t)cap * p) == hipSuccess && dalloc(&c->bsidx, (size_t)cap * p) == hipSuccess;
+  ok = ok && dalloc(&c->bstatus, (size_t)cap * p) == hipSuccess;
+  ok = ok && dalloc(&c->d_bprm, cap) == hipSuccess && dalloc(&c->d_bstate, cap) == hipSuccess;
+  ok = ok && dalloc(&c->d_active, 2) == hipSuccess;
+  ok = ok && hipHostMalloc((void **)&c->h_bstate, sizeof(NodeState) * cap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void **)&c->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+  if (!ok) return PR_ENOMEM;
+  ok = hipMemsetAsync(c->Bx, 0, sizeof(double) * NrMax * p, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->Rd, 0, sizeof(double) * NrMax * n, c->stream) == hipSuccess;
+  ok = ok && launch_transpose_bf16((const uint16_t *)c->P.X, c->Xrow, n, p, c->stream) == hipSuccess;
+  ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) return PR_EDEVICE;
+  c->batch_ok = true;
+  return PR_OK;
+}
+
+BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
+  BatchBufs bb{};
+  bb.m = m;
+  bb.Nr = nr_of(m);
+  bb.KS = c->KS;
+  bb.nfb = c->nfb;
+  bb.x0 = c->bx0;
+  bb.x1 = c->bx1;
+  bb.xbest = c->bxbest;
+  bb.hprev = c->bhprev;
+  bb.sidx = c->bsidx;
+  bb.sval = c->bsval;
+  bb.CT = c->CT;
+  bb.fsum = c->fsum;
+  bb.Bx = c->Bx;
+  bb.active = c->d_active;
+  bb.gap_factor = 0.99;
+  return bb;
+}
+
+// One batched iteration: forward GEMM, residual split, X^T R GEMM, node steps.
+hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
+  const int64_t n = c->P.n, p = c->P.p;
+  const int Nr = nr_of(m);
+  hipError_t e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, s);
+  if (e != hipSuccess) return e;
+  e = launch_batch_resid(c->CF, c->KSF, n, m, Nr, c->P.y, c->Rd, c->fsum, c->d_bstate, s);
+  if (e != hipSuccess) return e;
+  e = launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, c->d_active, s);
+  if (e != hipSuccess) return e;
+  return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
+}
+
+int ensure_batch_graph(pr_ctx *c, int32_t m, int32_t units) {
+  if (c->bgexec && c->bgraph_units == units && c->bgraph_m == m) return PR_OK;
+  if (c->bgexec) {
+    (void)hipGraphExecDestroy(c->bgexec);
+    c->bgexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  PR_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < units && e == hipSuccess; i++) e = enqueue_batch_unit(c, m, c->cap);
+  hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return PR_EDEVICE;
+  }
+  e = hipGraphInstantiate(&c->bgexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->bgexec = nullptr;
+    return PR_EDEVICE;
+  }
+  c->bgraph_units = units;
+  c->bgraph_m = m;
+  return PR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -296,6 +421,14 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   if (rc != PR_OK) {
     free_ctx(c);
     return rc;
+  }
+  if (max_batch > 1 && prob->xdtype == PR_BF16 && prob->loss == PR_LSQ && n % 128 == 0 && p % 128 == 0 &&
+      p <= 16384 && n % 64 == 0) {
+    rc = alloc_batch(c);
+    if (rc != PR_OK) {
+      free_ctx(c);
+      return rc;
+    }
   }
   *out = c;
   return PR_OK;
@@ -396,6 +529,18 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   out->iters = hs.iter;
   out->restarts = hs.restarts;
   out->status = hs.done ? hs.status : PR_MAXITER;
+  return PR_OK;
+}
+
+int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
+            int64_t Nr, int64_t K, int32_t KS) {
+  if (!A || !B || !C || Mc < 128 || Nr < 64 || K < 16 || KS < 1 || Mc % 128 || Nr % 64 ||
+      K % (16 * (int64_t)KS) || lda < K || ldb < K || lda % 4 || ldb % 2)
+    return PR_EINVAL;
+  if (((uintptr_t)A) % 8 || ((uintptr_t)B) % 16 || ((uintptr_t)C) % 8) return PR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  PR_TRY(launch_gemm_f64(A, lda, B, ldb, C, Mc, Nr, K, KS, nullptr, s));
+  PR_TRY(hipStreamSynchronize(s));
   return PR_OK;
 }
 
@@ -528,15 +673,142 @@ int pr_dual_bound(pr_ctx *c, const pr_node *node, const double *zeta, const doub
   return PR_OK;
 }
 
-int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *opts, const double *B0,
+int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *opts_in, const double *B0,
                    double *B_out, pr_result *out) {
   if (!c || !nodes || !out || m < 1 || m > c->max_batch) return PR_EINVAL;
-  const int64_t p = c->P.p;
+  pr_opts opts;
+  pr_opts_default(&opts);
+  if (opts_in) opts = *opts_in;
+  if (check_opts(&opts) != PR_OK) return PR_EINVAL;
+  const int64_t n = c->P.n, p = c->P.p;
+  // validate every node first: nothing runs if any node is malformed
+  std::vector<std::vector<int8_t>> sts((size_t)m);
+  std::vector<int32_t> kbars((size_t)m);
+  std::vector<int64_t> pbars((size_t)m);
+  std::vector<char> infeas((size_t)m);
   for (int32_t i = 0; i < m; i++) {
-    int rc = pr_solve(c, &nodes[i], opts, B0 ? B0 + (int64_t)i * p : nullptr,
-                      B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);
+    int64_t n1;
+    bool inf;
+    int rc = build_status(&nodes[i], p, sts[(size_t)i], n1, pbars[(size_t)i], kbars[(size_t)i], inf);
     if (rc != PR_OK) return rc;
+    infeas[(size_t)i] = inf;
   }
+  if (!c->batch_ok || !isnan(opts.cutoff)) {
+    for (int32_t i = 0; i < m; i++) {
+      int rc = pr_solve(c, &nodes[i], &opts, B0 ? B0 + (int64_t)i * p : nullptr,
+                        B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);
+      if (rc != PR_OK) return rc;
+    }
+    return PR_OK;
+  }
+  hipStream_t s = c->stream;
+  std::vector<int32_t> slot_of;  // batch slot -> node index
+  for (int32_t i = 0; i < m; i++) {
+    memset(&out[i], 0, sizeof(pr_result));
+    if (infeas[(size_t)i]) {
+      out[i].lower_bound = INFINITY;
+      out[i].primal = INFINITY;
+      out[i].rel_gap = NAN;
+      out[i].status = PR_INFEASIBLE;
+      if (B_out) PR_TRY(hipMemsetAsync(B_out + (int64_t)i * p, 0, sizeof(double) * p, s));
+    } else {
+      slot_of.push_back(i);
+    }
+  }
+  const int32_t mb = (int32_t)slot_of.size();
+  if (mb == 0) {
+    PR_TRY(hipStreamSynchronize(s));
+    return PR_OK;
+  }
+  const double L = opts.L > 0.0 ? opts.L : 1.01 * curvature(c->P.loss) * c->norm2;
+  std::vector<NodeParams> prm((size_t)mb);
+  for (int32_t q = 0; q < mb; q++) {
+    const int32_t i = slot_of[(size_t)q];
+    NodeParams &pp = prm[(size_t)q];
+    pp.st = c->bstatus + (int64_t)q * p;
+    pp.p = p;
+    pp.pbar = pbars[(size_t)i];
+    pp.kbar = kbars[(size_t)i];
+    pp.loss = c->P.loss;
+    pp.lambda2 = nodes[i].lambda2;
+    pp.M = nodes[i].M;
+    pp.eta = opts.eta;
+    pp.tol = opts.rel_gap_tol;
+    pp.cutoff = NAN;
+    pp.max_iter = opts.max_iter;
+    PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
+    if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
+                                  hipMemcpyDeviceToDevice, s));
+  }
+  PR_TRY(hipMemcpyAsync(c->d_bprm, prm.data(), sizeof(NodeParams) * mb, hipMemcpyHostToDevice, s));
+  int32_t act = mb;
+  PR_TRY(hipMemcpyAsync(c->d_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  BatchBufs bb = batch_bufs(c, mb);
+  PR_TRY(launch_batch_init(c->d_bprm, c->d_bstate, bb, B0 ? c->bxbest : nullptr, L, p, s));
+  int rc = ensure_batch_graph(c, mb, opts.check_every);
+  if (rc != PR_OK) return rc;
+  auto issue = [&](int slot) -> hipError_t {
+    hipError_t e = hipGraphLaunch(c->bgexec, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&c->h_active[slot], c->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(c->ev[slot], s);
+  };
+  const int64_t max_launches = (int64_t)opts.max_iter / opts.check_every + 3;
+  int64_t launched = 0;
+  PR_TRY(issue(0));
+  launched++;
+  PR_TRY(issue(1));
+  launched++;
+  for (int64_t k = 0;; k++) {
+    const int slot = (int)(k & 1);
+    PR_TRY(hipEventSynchronize(c->ev[slot]));
+    if (c->h_active[slot] <= 0) break;
+    if (launched >= max_launches) break;
+    PR_TRY(issue(slot));
+    launched++;
+  }
+  PR_TRY(hipStreamSynchronize(s));
+  PR_TRY(hipMemcpy(c->h_bstate, c->d_bstate, sizeof(NodeState) * mb, hipMemcpyDeviceToHost));
+  // FP64 certification of every node over the stored X, at the iterate whose
+  // gap passed; nodes that do not certify continue on the single-node path.
+  for (int32_t q = 0; q < mb; q++) {
+    const int32_t i = slot_of[(size_t)q];
+    const NodeState &hs = c->h_bstate[q];
+    double *xq = c->bxbest + (int64_t)q * p;
+    if (!hs.done) {
+      // the graph loop stopped at the iteration limit before this node did
+      PR_TRY(hipMemcpyAsync(xq, (hs.parity ? c->bx1 : c->bx0) + (int64_t)q * p, sizeof(double) * p,
+                            hipMemcpyDeviceToDevice, s));
+    }
+    // certify with the dual vector of the stopping iterate, zeta = 2 (y - X x),
+    // by Phi(x) and Psi(zeta) recomputed over the stored X
+    double lb = -INFINITY, ub = INFINITY;
+    PR_TRY(launch_batch_zeta(c->CF, c->KSF, n, nr_of(mb), q, c->P.y, c->B.zbest, s));
+    rc = pr_dual_bound(c, &nodes[i], c->B.zbest, xq, &lb, &ub);
+    if (rc != PR_OK) return rc;
+    const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
+    pr_result &r = out[i];
+    if (rel <= opts.rel_gap_tol) {
+      r.lower_bound = lb;
+      r.primal = ub;
+      r.rel_gap = rel;
+      r.L = L;
+      r.iters = hs.iter;
+      r.restarts = hs.restarts;
+      r.status = PR_CONVERGED;
+      if (B_out) PR_TRY(hipMemcpyAsync(B_out + (int64_t)i * p, xq, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    } else {
+      pr_opts o2 = opts;  // a fresh iteration budget on the single-node FP64 path
+      rc = pr_solve(c, &nodes[i], &o2, xq, B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &r);
+      if (rc != PR_OK) return rc;
+      if (r.lower_bound < lb) r.lower_bound = lb;  // both are valid bounds
+      r.rel_gap = (r.primal - r.lower_bound) / fmax(fabs(r.primal), 1e-300);
+      r.iters += hs.iter;
+      r.restarts += hs.restarts;
+    }
+  }
+  PR_TRY(hipStreamSynchronize(s));
   return PR_OK;
 }
 

@@ -68,6 +68,19 @@ struct ProbBufs {
   int32_t rb, nch, rows, nfin;
 };
 
+// Batched solve buffers (m nodes, node i's vectors at offset i * p).
+struct BatchBufs {
+  int32_t m, Nr, KS, nfb;  // nodes, GEMM rows (m padded to 64), X^T split, residual row blocks
+  double *x0, *x1, *xbest, *hprev;
+  int32_t *sidx;
+  double *sval;
+  const double *CT;   // [KS][Nr][p] partial products X^T r
+  const double *fsum; // [m][nfb][2] partial sums of r^2 and 2 r^T y - r^T r
+  double *Bx;         // [Nr][p] current iterates (rows of the forward GEMM)
+  int32_t *active;    // number of nodes not yet done
+  double gap_factor;  // stop when Phi - Psi <= gap_factor * tol * |Phi| (margin for the host re-check)
+};
+
 struct Problem {
   const void *X;
   int32_t xdt, loss;
@@ -89,6 +102,17 @@ hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, co
                             double L, int64_t p, hipStream_t s);
 hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
                             int64_t p, hipStream_t s);
+hipError_t launch_batch_init(const NodeParams *prm, NodeState *S, BatchBufs bb, const double *B0, double L,
+                             int64_t p, hipStream_t s);
+hipError_t launch_batch_step(const NodeParams *prm, NodeState *S, BatchBufs bb, int64_t p, hipStream_t s);
+hipError_t launch_transpose_bf16(const uint16_t *in, uint16_t *out, int64_t n, int64_t p, hipStream_t s);
+int batch_resid_blocks(int64_t n);
+hipError_t launch_batch_resid(const double *U, int KSF, int64_t n, int m, int Nr, const double *y, double *R,
+                              double *fsum, const NodeState *S, hipStream_t s);
+hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
+                           int64_t Nr, int64_t K, int KS, const int32_t *active, hipStream_t s);
+hipError_t launch_batch_zeta(const double *U, int KSF, int64_t n, int Nr, int node, const double *y, double *zeta,
+                             hipStream_t s);
 hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t loss, int64_t n,
                               hipStream_t s);
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,

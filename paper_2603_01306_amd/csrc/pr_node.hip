@@ -1165,6 +1165,224 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   }
 }
 
+
+// ------------------------------------------------------------ batched node kernels
+//
+// One workgroup per node (grid = m).  u = X x and h = X^T r (r = y - u,
+// zeta = 2 r) come from the FP64 MFMA GEMMs of the batch, summed over the
+// reduction splits; Phi(x), Psi(zeta), the gap, restart and termination then
+// follow the single-node step exactly.  The host recomputes Phi and Psi of
+// every stopped node over the stored X with the single-node FP64 kernels.
+// Least squares.
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_batch_init(const NodeParams *__restrict__ prmA, NodeState *SA, BatchBufs bb,
+                                                   const double *__restrict__ B0, double L) {
+  __shared__ NodeLds lds;
+  const int node = blockIdx.x;
+  const NodeParams *prm = prmA + node;
+  NodeState *S = SA + node;
+  const int tid = threadIdx.x;
+  const int64_t p = prm->p;
+  const int64_t off = (int64_t)node * p;
+  PackedStatus<EPT> sv;
+  sv.load(prm->st, p);
+  double x[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int64_t j = tid + (int64_t)e * NT;
+    x[e] = 0.0;
+    if (j < p) {
+      const double b = B0 ? B0[off + j] : 0.0;
+      x[e] = b;
+      bb.x0[off + j] = b;
+      bb.xbest[off + j] = b;
+      bb.x1[off + j] = 0.0;
+      bb.hprev[off + j] = 0.0;
+      bb.Bx[off + j] = b;
+    }
+  }
+  IterStats is = finish_r<EPT>(x, sv, prm->kbar, prm->M, bb.sidx + off, bb.sval + off, lds);
+  if (tid == 0) {
+    NodeState s{};
+    s.L = L;
+    s.t = 1.0;
+    s.gap_ref = INFINITY;
+    s.lb = -INFINITY;
+    s.ub = INFINITY;
+    s.phi = INFINITY;
+    s.psi = -INFINITY;
+    s.rel_gap = INFINITY;
+    s.gval = is.gval;
+    s.tau = -1.0;
+    s.status = kMaxIter;
+    s.nsupp = is.nsupp;
+    s.indom = is.indom;
+    *S = s;
+  }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict__ prmA, NodeState *SA, BatchBufs bb) {
+  __shared__ NodeLds lds;
+  const int node = blockIdx.x;
+  const NodeParams *prm = prmA + node;
+  NodeState *S = SA + node;
+  if (S->done) return;
+  const int tid = threadIdx.x;
+  const int64_t p = prm->p;
+  const int64_t off = (int64_t)node * p;
+  const int kbar = prm->kbar;
+  const double lam2 = prm->lambda2, M = prm->M;
+  const int parity = S->parity;
+  const double L = S->L;
+  double *__restrict__ xc = (parity ? bb.x1 : bb.x0) + off;
+  double *__restrict__ xn = (parity ? bb.x0 : bb.x1) + off;
+  PackedStatus<EPT> sv;
+  sv.load(prm->st, p);
+  double Fk = 0.0, negconj = 0.0;
+  for (int i = 0; i < bb.nfb; i++) {
+    Fk += bb.fsum[2 * ((int64_t)node * bb.nfb + i)];
+    negconj += bb.fsum[2 * ((int64_t)node * bb.nfb + i) + 1];
+  }
+  // h = X^T r from the GEMM split partials; w = h / lambda2 (= X^T zeta / (2 lambda2))
+  const int64_t stride = (int64_t)bb.Nr * p;
+  const double *__restrict__ Hn = bb.CT + off;
+  double h[EPT];
+  double acc[2] = {0.0, 0.0};  // sum_{J1} H_M(w_j), w^T x
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    h[e] = 0.0;
+    const int s = sv(e);
+    if (s != 3) {
+      const int64_t j = tid + (int64_t)e * NT;
+      double hv = 0.0;
+      for (int z = 0; z < bb.KS; z++) hv += Hn[z * stride + j];
+      h[e] = hv;
+      const double wv = hv / lam2;
+      if (s == kOne) acc[0] += huber(wv, M);
+      acc[1] += wv * xc[j];
+    }
+  }
+  block_sum<NT, 2>(acc, lds.red);
+  auto wabs = [&](int e) { return sv(e) == kFree ? fabs(h[e] / lam2) : -1.0; };
+  const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
+  const double gstar = acc[0] + topsum;
+  // Psi(zeta) and Phi(x) from the FP64 products of this pass
+  const double psi = negconj - 2.0 * lam2 * gstar;
+  const double phi = S->indom ? Fk + 2.0 * lam2 * S->gval : INFINITY;
+  const double gap = phi - psi;
+  if (tid == 0) {
+    const int it = S->iter;
+    double lb = S->lb, ub = S->ub;
+    if (psi > lb) lb = psi;
+    if (phi < ub) ub = phi;
+    // the stopping test uses the current pair (x, zeta(x)): it is the pair the
+    // host re-certifies, so no per-node snapshot of zeta is kept
+    const double rel = gap / fmax(fabs(phi), 1e-300);
+    int done = 0, status = kMaxIter;
+    if (rel <= bb.gap_factor * prm->tol) {
+      done = 1;
+      status = kConverged;
+    } else if (it >= prm->max_iter) {
+      done = 1;
+      status = kMaxIter;
+    }
+    double m = 0.0, t = S->t, gap_ref = S->gap_ref;
+    int restart = 0, restarts = S->restarts;
+    if (!done) {
+      if (it == 0) {
+        restart = 1;
+        gap_ref = gap;
+      } else if (gap <= gap_ref / prm->eta) {
+        restart = 1;
+        gap_ref = gap;
+        restarts++;
+      }
+      if (restart) {
+        m = 0.0;
+        t = 1.0;
+      } else {
+        const double tn = fista_next_t(t);
+        m = (t - 1.0) / tn;
+        t = tn;
+      }
+    }
+    S->phi = phi;
+    S->psi = psi;
+    S->lb = lb;
+    S->ub = ub;
+    S->rel_gap = rel;
+    S->status = status;
+    S->t = t;
+    S->gap_ref = gap_ref;
+    S->restarts = restarts;
+    S->mom = m;
+    if (done) {
+      S->done = 1;
+      atomicSub(bb.active, 1);
+    }
+    lds.bcd[0] = m;
+    lds.bci[0] = done;
+  }
+  __syncthreads();
+  if (lds.bci[0]) {
+    // the certified point is the iterate whose gap passed the test
+#pragma unroll
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xc[tid + (int64_t)e * NT];
+    return;
+  }
+  const double m = lds.bcd[0];
+  const double invL = 1.0 / L;
+  double *__restrict__ hp = bb.hprev + off;
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    double v = 0.0;
+    if (sv(e) != 3) {
+      const int64_t j = tid + (int64_t)e * NT;
+      const double xk = xc[j], xq = xn[j];
+      const double yj = xk + m * (xk - xq);
+      const double gj = -2.0 * ((1.0 + m) * h[e] - m * hp[j]);
+      hp[j] = h[e];
+      v = yj - gj * invL;
+    }
+    h[e] = v;  // h[] now holds v
+  }
+  const double rho = 2.0 * lam2 * invL;
+  int evals = 0;
+  auto vabs = [&](int e) { return sv(e) == kFree ? fabs(h[e]) : -1.0; };
+  const double tau = solve_tau_f<EPT>(vabs, kbar, rho, M, S->tau, lds.red, &evals);
+  const double inv1p = 1.0 / (1.0 + rho);
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    double xv = 0.0;
+    if (s != 3) {
+      if (s != kZero) {
+        const double av = fabs(h[e]);
+        double r = fmin(av * inv1p, M);
+        if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
+        xv = (r == 0.0) ? 0.0 : copysign(r, h[e]);
+      }
+      const int64_t j = tid + (int64_t)e * NT;
+      xn[j] = xv;
+      bb.Bx[off + j] = xv;
+    }
+    h[e] = xv;
+  }
+  IterStats is = finish_r<EPT>(h, sv, kbar, M, bb.sidx + off, bb.sval + off, lds);
+  if (tid == 0) {
+    S->gval = is.gval;
+    S->indom = is.indom;
+    S->nsupp = is.nsupp;
+    S->tau = tau;
+    S->tau_iters = evals;
+    S->parity = parity ^ 1;
+    S->iter = S->iter + 1;
+  }
+}
+
 }  // namespace
 
 int node_ept(int64_t p) {
@@ -1197,6 +1415,35 @@ hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, co
     case 16: k_node_step_r<16><<<1, NT, 0, s>>>(prm, S, nb, B); break;
     case 32: k_node_step_r<32><<<1, NT, 0, s>>>(prm, S, nb, B); break;
     default: k_node_step<<<1, NT, 0, s>>>(prm, S, nb, B); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const NodeParams *prm, NodeState *S, BatchBufs bb, const double *B0, double L,
+                             int64_t p, hipStream_t s) {
+  const unsigned g = (unsigned)bb.m;
+  switch (node_ept(p)) {
+    case 1: k_batch_init<1><<<g, NT, 0, s>>>(prm, S, bb, B0, L); break;
+    case 2: k_batch_init<2><<<g, NT, 0, s>>>(prm, S, bb, B0, L); break;
+    case 4: k_batch_init<4><<<g, NT, 0, s>>>(prm, S, bb, B0, L); break;
+    case 8: k_batch_init<8><<<g, NT, 0, s>>>(prm, S, bb, B0, L); break;
+    case 16: k_batch_init<16><<<g, NT, 0, s>>>(prm, S, bb, B0, L); break;
+    case 32: k_batch_init<32><<<g, NT, 0, s>>>(prm, S, bb, B0, L); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const NodeParams *prm, NodeState *S, BatchBufs bb, int64_t p, hipStream_t s) {
+  const unsigned g = (unsigned)bb.m;
+  switch (node_ept(p)) {
+    case 1: k_batch_step<1><<<g, NT, 0, s>>>(prm, S, bb); break;
+    case 2: k_batch_step<2><<<g, NT, 0, s>>>(prm, S, bb); break;
+    case 4: k_batch_step<4><<<g, NT, 0, s>>>(prm, S, bb); break;
+    case 8: k_batch_step<8><<<g, NT, 0, s>>>(prm, S, bb); break;
+    case 16: k_batch_step<16><<<g, NT, 0, s>>>(prm, S, bb); break;
+    case 32: k_batch_step<32><<<g, NT, 0, s>>>(prm, S, bb); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -1,0 +1,136 @@
+"""Batched node relaxations (pr_solve_batch): both products of the iteration
+are FP64 MFMA GEMMs over the BF16 design, every stopped node is re-certified
+over the stored X.  Checked node by node against the FP64 oracle on small
+instances, against the single-node GPU path, and at full size by the oracle
+re-certifying the returned (beta, bound) pairs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_instance, make_nodes, config_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def _pr():
+    import paper_2603_01306_amd as pr
+    return pr
+
+
+def _ctx(dev, inst, max_batch):
+    import torch
+    pr = _pr()
+    X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    return pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
+
+
+@pytest.fixture(scope="module")
+def small(dev):
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=0, seed=21, storage="bf16")
+    ctx = _ctx(dev, inst, 16)
+    yield inst, ctx
+    ctx.close()
+
+
+def test_batch_small_matches_oracle_per_node(small):
+    inst, ctx = small
+    pr = _pr()
+    raw = make_nodes(inst.p, 11, seed=3, max_j0=40, max_j1=6)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    nodes.append(pr.Node(3, 0.2, 2.0, J1=[1, 2, 3, 4]))    # infeasible: |J1| > k
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-7)
+    lam = float(np.linalg.eigvalsh(inst.X64() @ inst.X64().T).max())
+    for i, (nd, r) in enumerate(zip(nodes, res)):
+        if i == len(nodes) - 1:
+            assert r["status"] == pr.INFEASIBLE and r["lower_bound"] == math.inf
+            continue
+        st = nd.status(inst.p)
+        ref = oracle.solve(inst.Xcm, inst.y, 0, 0.2, 2.0, 8, status=st, L=2.02 * lam, tol=1e-10)
+        print(i, r["iters"], ref["iters"], r["lower_bound"], ref["lb"], r["rel_gap"])
+        assert r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-7
+        assert abs(r["lower_bound"] - ref["lb"]) <= 1.5e-7 * abs(r["primal"])
+        # the returned beta attains the reported primal value (oracle recomputation)
+        # and the bound is valid: below the oracle's upper bound
+        beta = B[i].cpu().numpy()
+        phi = oracle.primal(inst.Xcm, inst.y, beta, 0, 0.2, 2.0, 8, status=st)
+        assert abs(phi - r["primal"]) <= 1e-11 * abs(phi)
+        assert r["lower_bound"] <= ref["ub"] * (1 + 1e-12)
+
+
+def test_batch_agrees_with_single_node_path(small):
+    inst, ctx = small
+    pr = _pr()
+    raw = make_nodes(inst.p, 6, seed=9, max_j0=30, max_j1=5)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    res, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-7)
+    for nd, r in zip(nodes, res):
+        s = ctx.solve(nd, rel_gap_tol=1e-7)
+        assert abs(s["lower_bound"] - r["lower_bound"]) <= 2e-7 * abs(s["primal"])
+
+
+def test_batch_warm_start_and_repeat(small):
+    import torch
+    inst, ctx = small
+    pr = _pr()
+    raw = make_nodes(inst.p, 4, seed=5, max_j0=20, max_j1=4)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    r1, B1 = ctx.solve_batch(nodes, rel_gap_tol=1e-7)
+    r2, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-7)
+    assert [a["lower_bound"] for a in r1] == [b["lower_bound"] for b in r2]   # deterministic
+    rw, _ = ctx.solve_batch(nodes, B0=B1, rel_gap_tol=1e-7)
+    for a, b in zip(r1, rw):
+        assert b["iters"] <= max(5, a["iters"] // 4)
+        assert abs(a["lower_bound"] - b["lower_bound"]) <= 2e-7 * abs(a["primal"])
+
+
+def test_batch_full_size_256_nodes(dev):
+    """256 nodes on the BF16 copy of the n=16384, p=8192 design; the oracle
+    re-certifies 8 seeded nodes from the returned betas."""
+    pr = _pr()
+    inst = config_instance("ls_batch256_n16384_p8192_bf16")
+    ctx = _ctx(dev, inst, 256)
+    raw = make_nodes(inst.p, 256, seed=1, max_j0=64, max_j1=19)
+    nodes = [pr.Node(20, 0.1, 2.0, J0=a, J1=b) for a, b in raw]
+    res, B = ctx.solve_batch(nodes, max_iter=4000)
+    print("iters", sorted(r["iters"] for r in res)[::32], flush=True)
+    assert all(r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-6 for r in res)
+    for i in np.random.default_rng(0).choice(256, 8, replace=False):
+        st = nodes[i].status(inst.p)
+        beta = B[i].cpu().numpy()
+        phi = oracle.primal(inst.Xcm, inst.y, beta, 0, 0.1, 2.0, 20, status=st)
+        assert abs(phi - res[i]["primal"]) <= 1e-10 * abs(phi)
+        assert 0.0 <= (phi - res[i]["lower_bound"]) / abs(phi) <= 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("Mc,Nr,K,KS", [(128, 64, 16, 1), (256, 192, 1024, 2), (1024, 512, 4096, 4), (384, 128, 96, 3)])
+def test_gemm_matches_float64_reference(dev, Mc, Nr, K, KS):
+    """FP64 MFMA product over a BF16 A: within FP64 summation error of the
+    exact product, |C - C_ref| <= 2 K 2^-53 (|B| |A|^T) per split."""
+    import torch
+    pr = _pr()
+    g = torch.Generator().manual_seed(Mc + K)
+    A = torch.randn(Mc, K, generator=g).to(torch.bfloat16)
+    B = torch.randn(Nr, K, generator=g, dtype=torch.float64)
+    C = pr.gemm(A.to(dev), B.to(dev), KS).cpu()
+    Ad = A.double()
+    kc = K // KS
+    for z in range(KS):
+        sl = slice(z * kc, (z + 1) * kc)
+        ref = B[:, sl] @ Ad[:, sl].T     # (Nr, Mc)
+        bound = 2.0 * kc * 2.0 ** -53 * (B[:, sl].abs() @ Ad[:, sl].abs().T) + 1e-300
+        assert torch.all((C[z] - ref).abs() <= bound)
+
+
+def test_gemm_rejects_bad_shapes(dev):
+    import torch
+    pr = _pr()
+    A = torch.zeros(100, 64, dtype=torch.bfloat16, device=dev)
+    B = torch.zeros(64, 64, dtype=torch.float64, device=dev)
+    with pytest.raises(pr.PrError):
+        pr.gemm(A, B)           # Mc not a multiple of 128
+    A = torch.zeros(128, 64, dtype=torch.bfloat16, device=dev)
+    with pytest.raises(pr.PrError):
+        pr.gemm(A, B, KS=3)     # K not a multiple of 16 * KS
