@@ -12,6 +12,12 @@ Also reported: the dominant kernel (X^T r, FP64 accumulation) against the
 HBM roofline, timed with HIP events on the stream it runs on, and the FP64
 CPU oracle on a bounded sample of the same workload.
 
+"batch": 256 branch-and-bound node relaxations (uneven fixed-zero / fixed-one
+sets of sizes 0-64 / 0-19) sharing a BF16 copy of the same design, solved
+together by pr_solve_batch to the same 1e-6 FP64 gap, against the single-node
+path on the first nodes of the same list; its GEMMs against the FP64 MFMA
+roofline.
+
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
 """
@@ -27,7 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "ls_root_n16384_p8192_f32"
+BATCH_WORKLOAD = "ls_batch256_n16384_p8192_bf16"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "gemv_t_ls_n16384_p8192_f32_pmc.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_01306_amd", "csrc", f) for f in ("pr_gemv.hip", "pr_device.h")]
 
@@ -121,6 +129,55 @@ def cpu_baseline(inst, cfg, gpu_iters_per_solve, budget_s=20.0):
                        f"solve to 1e-6 takes")}
 
 
+def batch_bench(dev, steps, n_single=16):
+    """Nodes/s of pr_solve_batch on the 256-node workload and of the single-node
+    path on its first n_single nodes, both to the same FP64 gap."""
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import config_instance, make_nodes, CONFIGS
+    cfg = CONFIGS[BATCH_WORKLOAD]
+    inst = config_instance(BATCH_WORKLOAD)
+    m = cfg["m"]
+    X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    ctx = pr.Context(X, torch.from_numpy(inst.y).to(dev), pr.LSQ, max_batch=m)
+    raw = make_nodes(inst.p, m, seed=cfg["node_seed"], max_j0=64, max_j1=19)
+    nodes = [pr.Node(cfg["k"], cfg["lambda2"], cfg["M"], J0=a, J1=b) for a, b in raw]
+    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])      # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    res = runs[-1]
+    ok_b = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for run in runs for r in run)
+    it = np.array([r["iters"] for r in res])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [ctx.solve(nd, want_beta=False, rel_gap_tol=cfg["tol"]) for nd in nodes[:n_single]]
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    ok_s = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in single)
+    ms_f, ms_t = ctx.time_batch_gemm(m, reps=10)
+    nr = (m + 63) // 64 * 64
+    flop = 2.0 * inst.n * inst.p * nr
+    ach = flop / (ms_t * 1e-3) / 1e12
+    out = {"workload": BATCH_WORKLOAD, "nodes": m, "x_storage": "bf16", "rel_gap_tol": cfg["tol"],
+           "value": round(m * steps / dt_b, 3), "unit": "node relaxations/s", "steps": steps,
+           "ms_per_step": round(1e3 * dt_b / steps, 2), "all_converged": ok_b,
+           "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 1),
+           "single_path": {"value": round(n_single / dt_s, 3), "unit": "node relaxations/s",
+                           "nodes": n_single, "all_converged": ok_s,
+                           "iters_mean": round(sum(r["iters"] for r in single) / n_single, 1)},
+           "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(ach / FP64_MFMA_PEAK_TFS, 4), "traffic": None, "kernel": "k_gemm_f64 (X^T R)",
+                        "flop_per_launch": flop, "avg_launch_ms": round(ms_t, 4),
+                        "forward_avg_launch_ms": round(ms_f, 4)}}
+    out["speedup_vs_single"] = round(out["value"] / out["single_path"]["value"], 2)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel-probe", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -169,10 +227,12 @@ def main():
             "all_converged": ok, "lower_bound": results[-1]["lower_bound"],
             "setup_s_per_matrix": round(setup_s, 3),
             "roofline": roof}
+    ctx.close()
+    if args.batch_steps > 0:
+        line["batch"] = batch_bench(dev, args.batch_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst, cfg, iters / args.steps)
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

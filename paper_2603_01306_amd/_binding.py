@@ -20,7 +20,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_gemm", "pr_strerror"]
+           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_gemm", "pr_strerror"]
 
 
 class PrProblem(ctypes.Structure):
@@ -91,6 +91,9 @@ def load():
         L.pr_solve_batch.restype = ctypes.c_int
         L.pr_solve_batch.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, ctypes.POINTER(PrOpts),
                                      P, P, ctypes.POINTER(PrResult)]
+        L.pr_time_batch_gemm.restype = ctypes.c_int
+        L.pr_time_batch_gemm.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
         L.pr_gemm.restype = ctypes.c_int
         L.pr_gemm.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
                               ctypes.c_int64, ctypes.c_int32]
@@ -240,6 +243,14 @@ class Context:
         _check(load().pr_solve_batch(self.h, arr, m, ctypes.byref(o), _dptr(B0), _dptr(Bout), res),
                "pr_solve_batch")
         return [r.as_dict() for r in res], Bout
+
+    def time_batch_gemm(self, m, reps=20):
+        """(ms forward GEMM, ms transpose GEMM) per launch for a batch of m nodes."""
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(load().pr_time_batch_gemm(self.h, int(m), int(reps), ctypes.byref(a), ctypes.byref(b)),
+               "pr_time_batch_gemm")
+        return a.value, b.value
 
     def dual_bound(self, node, zeta=None, beta=None):
         lb = ctypes.c_double()

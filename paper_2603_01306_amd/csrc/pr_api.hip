@@ -57,6 +57,7 @@ struct pr_ctx {
   // batched path (least squares, BF16 X, n and p multiples of 128, p <= 16384)
   bool batch_ok = false;
   int32_t KS = 1, KSF = 1, nfb = 0;
+  int32_t fmaxF = 1, fmaxT = 1;  // largest extra split factors of the two GEMMs
   uint16_t *Xrow = nullptr;  // row-major copy of X (n x p)
   double *Bx = nullptr;      // [cap padded][p] FP64 current iterates
   double *Rd = nullptr;      // [cap padded][n] FP64 residuals
@@ -70,6 +71,8 @@ struct pr_ctx {
   NodeState *d_bstate = nullptr;
   NodeState *h_bstate = nullptr;  // pinned, cap
   int32_t *d_active = nullptr;
+  int32_t *d_rowmap = nullptr;    // [cap padded] slots of the nodes still iterating
+  int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split}
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
@@ -82,7 +85,7 @@ void free_ctx(pr_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
-                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active};
+                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split};
   for (void *b : bb)
     if (b) (void)hipFree(b);
   if (c->h_bstate) (void)hipHostFree(c->h_bstate);
@@ -239,14 +242,20 @@ int alloc_batch(pr_ctx *c) {
   const int tiles_f = (int)(n / 128) * (NrMax / 64);
   int KSF = 1;
   while (KSF < 16 && tiles_f * KSF < 512 && (p / (2 * KSF)) % 16 == 0) KSF *= 2;
+  // as nodes finish the splits grow by up to NrMax / 64 (fewer row tiles)
+  int fF = 1, fT = 1;
+  while (2 * fF <= NrMax / 64 && (p / (2 * fF * KSF)) % 16 == 0) fF *= 2;
+  while (2 * fT <= NrMax / 64 && (n / (2 * fT * KS)) % 16 == 0) fT *= 2;
   c->KS = KS;
   c->KSF = KSF;
+  c->fmaxF = fF;
+  c->fmaxT = fT;
   c->nfb = batch_resid_blocks(n);
   bool ok = dalloc(&c->Xrow, (size_t)n * p) == hipSuccess;
   ok = ok && dalloc(&c->Bx, (size_t)NrMax * p) == hipSuccess;
   ok = ok && dalloc(&c->Rd, (size_t)NrMax * n) == hipSuccess;
-  ok = ok && dalloc(&c->CF, (size_t)KSF * NrMax * n) == hipSuccess;
-  ok = ok && dalloc(&c->CT, (size_t)KS * NrMax * p) == hipSuccess;
+  ok = ok && dalloc(&c->CF, (size_t)KSF * fF * NrMax * n) == hipSuccess;
+  ok = ok && dalloc(&c->CT, (size_t)KS * fT * NrMax * p) == hipSuccess;
   ok = ok && dalloc(&c->fsum, (size_t)2 * cap * c->nfb) == hipSuccess;
   ok = ok && dalloc(&c->bx0, (size_t)cap * p) == hipSuccess && dalloc(&c->bx1, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->bxbest, (size_t)cap * p) == hipSuccess && dalloc(&c->bhprev, (size_t)cap * p) == hipSuccess;
@@ -254,6 +263,7 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && dalloc(&c->bstatus, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->d_bprm, cap) == hipSuccess && dalloc(&c->d_bstate, cap) == hipSuccess;
   ok = ok && dalloc(&c->d_active, 2) == hipSuccess;
+  ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 4) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_bstate, sizeof(NodeState) * cap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   if (!ok) return PR_ENOMEM;
@@ -270,7 +280,7 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   BatchBufs bb{};
   bb.m = m;
   bb.Nr = nr_of(m);
-  bb.KS = c->KS;
+  bb.ksp = c->d_split + 2;
   bb.nfb = c->nfb;
   bb.x0 = c->bx0;
   bb.x1 = c->bx1;
@@ -290,11 +300,15 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
 hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
   const int64_t n = c->P.n, p = c->P.p;
   const int Nr = nr_of(m);
-  hipError_t e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, s);
+  hipError_t e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->KSF, c->fmaxF, c->KS, c->fmaxT, s);
   if (e != hipSuccess) return e;
-  e = launch_batch_resid(c->CF, c->KSF, n, m, Nr, c->P.y, c->Rd, c->fsum, c->d_bstate, s);
+  e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
+                      c->d_split + 1, c->KSF * c->fmaxF, s);
   if (e != hipSuccess) return e;
-  e = launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, c->d_active, s);
+  e = launch_batch_resid(c->CF, c->d_split + 1, n, m, Nr, c->P.y, c->Rd, c->fsum, c->d_bstate, s);
+  if (e != hipSuccess) return e;
+  e = launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, c->d_active, c->d_rowmap,
+                      c->d_split, c->d_split + 2, c->KS * c->fmaxT, s);
   if (e != hipSuccess) return e;
   return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
 }
@@ -539,8 +553,7 @@ int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64
     return PR_EINVAL;
   if (((uintptr_t)A) % 8 || ((uintptr_t)B) % 16 || ((uintptr_t)C) % 8) return PR_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  PR_TRY(launch_gemm_f64(A, lda, B, ldb, C, Mc, Nr, K, KS, nullptr, s));
-  PR_TRY(hipStreamSynchronize(s));
+  PR_TRY(launch_gemm_f64(A, lda, B, ldb, C, Mc, Nr, K, KS, nullptr, nullptr, nullptr, nullptr, 0, s));
   return PR_OK;
 }
 
@@ -630,6 +643,32 @@ int pr_time_gemv_t(pr_ctx *c, const double *r, double *h, int32_t reps, double *
   float ms = 0.0f;
   PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
   *ms_avg = (double)ms / reps;
+  return PR_OK;
+}
+
+int pr_time_batch_gemm(pr_ctx *c, int32_t m, int32_t reps, double *ms_fwd, double *ms_t) {
+  if (!c || !c->batch_ok || m < 1 || m > c->max_batch || reps < 1 || !ms_fwd || !ms_t) return PR_EINVAL;
+  const int64_t n = c->P.n, p = c->P.p;
+  const int Nr = nr_of(m);
+  hipStream_t s = c->stream;
+  auto fwd = [&]() {
+    return launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, nullptr, nullptr, nullptr, nullptr, 0, s);
+  };
+  auto trn = [&]() {
+    return launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, nullptr, nullptr,
+                           nullptr, nullptr, 0, s);
+  };
+  double *outs[2] = {ms_fwd, ms_t};
+  for (int w = 0; w < 2; w++) {
+    PR_TRY(w ? trn() : fwd());
+    PR_TRY(hipEventRecord(c->tev[0], s));
+    for (int i = 0; i < reps; i++) PR_TRY(w ? trn() : fwd());
+    PR_TRY(hipEventRecord(c->tev[1], s));
+    PR_TRY(hipEventSynchronize(c->tev[1]));
+    float ms = 0.0f;
+    PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+    *outs[w] = (double)ms / reps;
+  }
   return PR_OK;
 }
 
@@ -784,7 +823,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     // certify with the dual vector of the stopping iterate, zeta = 2 (y - X x),
     // by Phi(x) and Psi(zeta) recomputed over the stored X
     double lb = -INFINITY, ub = INFINITY;
-    PR_TRY(launch_batch_zeta(c->CF, c->KSF, n, nr_of(mb), q, c->P.y, c->B.zbest, s));
+    PR_TRY(launch_batch_zeta(c->Rd, n, q, c->B.zbest, s));
     rc = pr_dual_bound(c, &nodes[i], c->B.zbest, xq, &lb, &ub);
     if (rc != PR_OK) return rc;
     const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);

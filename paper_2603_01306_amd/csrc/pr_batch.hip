@@ -31,11 +31,22 @@ typedef unsigned short us4_t __attribute__((ext_vector_type(4)));
 // 64 x 32 = 4 x 2 MFMA tiles of 16 x 16.  Within a reduction step of 16 the
 // lanes of quarter q take the 4 consecutive indices 4q..4q+3 (one 8-byte A load,
 // one 32-byte B load per tile) and MFMA s combines index 4q+s of every quarter.
+//
+// Row compaction: with rowmap != NULL only the first *nrow rows are computed,
+// local row l reading B row rowmap[l] and writing C row rowmap[l]; r tiles
+// past *nrow exit at once.  Rows of finished nodes thus cost nothing.
+// The split count may also come from the device (ksp != NULL): the grid is
+// sized for the largest count and the groups past MT * (*ksp) exit.
 __global__ __launch_bounds__(256) void k_gemm_f64(const uint16_t *__restrict__ A, int64_t lda,
                                                   const double *__restrict__ B, int64_t ldb, double *__restrict__ C,
-                                                  int64_t Mc, int64_t Nr, int64_t Kc, int MT, int NT, int KS,
-                                                  const int32_t *__restrict__ active) {
+                                                  int64_t Mc, int64_t Nr, int64_t K, int MT, int NT, int KS,
+                                                  const int32_t *__restrict__ active,
+                                                  const int32_t *__restrict__ rowmap,
+                                                  const int32_t *__restrict__ nrow,
+                                                  const int32_t *__restrict__ ksp) {
   if (active && *active == 0) return;
+  if (ksp) KS = *ksp;
+  const int64_t Kc = K / KS;
   const int b = blockIdx.x;
   const int x = b & 7, qq = b >> 3;
   const int g = qq / NT, nt = qq - g * NT;
@@ -47,12 +58,28 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const uint16_t *__restrict__ A
   const int64_t c0 = (int64_t)mt * 128 + (w & 1) * 64;
   const int64_t r0 = (int64_t)nt * 64 + (w >> 1) * 32;
   const int64_t k0 = (int64_t)z * Kc + 4 * q;
+  // B row of each of the lane's two r positions, and the C row it is stored
+  // to (-1: past the compacted rows, read a valid row and store nothing)
+  int64_t brow[2], orow[2];
+  if (rowmap) {
+    const int nr = *nrow;
+    if ((int64_t)nt * 64 >= nr) return;  // so nr >= 1 below
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      const int64_t l = r0 + 16 * u + rr;
+      orow[u] = l < nr ? rowmap[l] : -1;
+      brow[u] = l < nr ? orow[u] : rowmap[0];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 2; u++) orow[u] = brow[u] = r0 + 16 * u + rr;
+  }
   const uint16_t *pa[4];
   const double *pb[2];
 #pragma unroll
   for (int t = 0; t < 4; t++) pa[t] = A + (c0 + 16 * t + rr) * lda + k0;
 #pragma unroll
-  for (int u = 0; u < 2; u++) pb[u] = B + (r0 + 16 * u + rr) * ldb + k0;
+  for (int u = 0; u < 2; u++) pb[u] = B + brow[u] * ldb + k0;
   d4v_t acc[4][2];
 #pragma unroll
   for (int t = 0; t < 4; t++)
@@ -84,11 +111,53 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const uint16_t *__restrict__ A
   // MFMA output: register v of lane l is (c = 4v + l/16, r = l%16)
   double *Cz = C + (int64_t)z * Nr * Mc;
 #pragma unroll
-  for (int t = 0; t < 4; t++)
+  for (int u = 0; u < 2; u++) {
+    if (orow[u] < 0) continue;
 #pragma unroll
-    for (int u = 0; u < 2; u++)
+    for (int t = 0; t < 4; t++)
 #pragma unroll
-      for (int v = 0; v < 4; v++) Cz[(r0 + 16 * u + rr) * Mc + c0 + 16 * t + 4 * v + q] = acc[t][u][v];
+      for (int v = 0; v < 4; v++) Cz[orow[u] * Mc + c0 + 16 * t + 4 * v + q] = acc[t][u][v];
+  }
+}
+
+// Compacted row list of the batch: rowmap[0..nrow) = the slots of the nodes
+// that are still iterating, in increasing order, and the reduction split of
+// each GEMM for this iteration: the base split times the largest power of two
+// f <= min(fmax, NT / ceil(nrow / 64)), so the number of busy workgroups stays
+// near that of the full batch.  sp = {nrow, forward split, transpose split}.
+// One block of 256 threads.
+__global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restrict__ S, int m,
+                                                      int32_t *__restrict__ rowmap, int32_t *__restrict__ sp,
+                                                      int NT, int ksf, int fmaxf, int kst, int fmaxt) {
+  __shared__ int base;
+  __shared__ int wsum[4];
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < m; i0 += 256) {
+    const int i = i0 + (int)threadIdx.x;
+    const bool act = i < m && !S[i].done;
+    const unsigned long long bal = __ballot(act);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    for (int v = 0; v < w; v++) off += wsum[v];
+    if (act) rowmap[off + before] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int nta = (base + 63) / 64;
+    const int room = nta > 0 ? NT / nta : 1;
+    int ff = 1, ft = 1;
+    while (2 * ff <= fmaxf && 2 * ff <= room) ff *= 2;
+    while (2 * ft <= fmaxt && 2 * ft <= room) ft *= 2;
+    sp[0] = base;
+    sp[1] = ksf * ff;
+    sp[2] = kst * ft;
+  }
 }
 
 // Row-major copy of a column-major BF16 matrix (n x p): out[i][j] = in[j][i].
@@ -112,12 +181,14 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const uint16_t *__restri
 // Residuals of the batch: u_i = sum_z U[z][i] (FP64), r_i = y - u_i into row i
 // of R ([Nr][n], FP64), and per (node, row block) sums of r^2 and
 // 2 r^T y - r^T r.  grid = (ceil(n / 512), m); 2 rows per thread.
-__global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ U, int KSF, int64_t n, int Nr,
-                                                     const double *__restrict__ y, double *__restrict__ R,
-                                                     double *__restrict__ fsum, const NodeState *S) {
+__global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ U, const int32_t *__restrict__ ksp,
+                                                     int64_t n, int Nr, const double *__restrict__ y,
+                                                     double *__restrict__ R, double *__restrict__ fsum,
+                                                     const NodeState *S) {
   __shared__ double red[4 * 4];
   const int node = blockIdx.y;
   if (S[node].done) return;
+  const int KSF = *ksp;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   const int64_t plane = (int64_t)Nr * n;
   double s[2] = {0.0, 0.0};
@@ -140,25 +211,29 @@ __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ 
   }
 }
 
-// zeta = 2 (y - u) of one node from the forward partials (certification input).
-__global__ void k_batch_zeta(const double *__restrict__ U, int KSF, int64_t n, int Nr, int node,
-                             const double *__restrict__ y, double *__restrict__ zeta) {
-  const int64_t plane = (int64_t)Nr * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double u = 0.0;
-    for (int z = 0; z < KSF; z++) u += U[(int64_t)z * plane + (int64_t)node * n + i];
-    zeta[i] = 2.0 * (y[i] - u);
-  }
+// zeta = 2 r of one node from its last residual row (certification input).
+__global__ void k_batch_zeta(const double *__restrict__ R, int64_t n, int node, double *__restrict__ zeta) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    zeta[i] = 2.0 * R[(int64_t)node * n + i];
 }
 
 }  // namespace
 
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
-                           int64_t Nr, int64_t K, int KS, const int32_t *active, hipStream_t s) {
+                           int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, hipStream_t s) {
   const int MT = (int)(Mc / 128), NT = (int)(Nr / 64);
-  const int groups = MT * KS;
+  const int groups = MT * (ksp ? ks_max : KS);
   const int gpad = (groups + 7) / 8 * 8;
-  k_gemm_f64<<<(unsigned)(gpad * NT), 256, 0, s>>>(A, lda, B, ldb, C, Mc, Nr, K / KS, MT, NT, KS, active);
+  k_gemm_f64<<<(unsigned)(gpad * NT), 256, 0, s>>>(A, lda, B, ldb, C, Mc, Nr, K, MT, NT, KS, active, rowmap, nrow,
+                                                    ksp);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int ksf, int fmaxf, int kst,
+                               int fmaxt, hipStream_t s) {
+  const int NT = (m + 63) / 64;
+  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, NT, ksf, fmaxf, kst, fmaxt);
   return hipGetLastError();
 }
 
@@ -170,16 +245,15 @@ hipError_t launch_transpose_bf16(const uint16_t *in, uint16_t *out, int64_t n, i
 
 int batch_resid_blocks(int64_t n) { return (int)((n + 511) / 512); }
 
-hipError_t launch_batch_resid(const double *U, int KSF, int64_t n, int m, int Nr, const double *y, double *R,
-                              double *fsum, const NodeState *S, hipStream_t s) {
+hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, int m, int Nr, const double *y,
+                              double *R, double *fsum, const NodeState *S, hipStream_t s) {
   dim3 grid((unsigned)batch_resid_blocks(n), (unsigned)m);
-  k_batch_resid<<<grid, 256, 0, s>>>(U, KSF, n, Nr, y, R, fsum, S);
+  k_batch_resid<<<grid, 256, 0, s>>>(U, ksp, n, Nr, y, R, fsum, S);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_zeta(const double *U, int KSF, int64_t n, int Nr, int node, const double *y, double *zeta,
-                             hipStream_t s) {
-  k_batch_zeta<<<64, 256, 0, s>>>(U, KSF, n, Nr, node, y, zeta);
+hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s) {
+  k_batch_zeta<<<64, 256, 0, s>>>(R, n, node, zeta);
   return hipGetLastError();
 }
 

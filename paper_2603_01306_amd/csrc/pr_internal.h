@@ -70,11 +70,12 @@ struct ProbBufs {
 
 // Batched solve buffers (m nodes, node i's vectors at offset i * p).
 struct BatchBufs {
-  int32_t m, Nr, KS, nfb;  // nodes, GEMM rows (m padded to 64), X^T split, residual row blocks
+  int32_t m, Nr, nfb;     // nodes, GEMM rows (m padded to 64), residual row blocks
+  const int32_t *ksp;     // device: number of X^T R partial planes written this iteration
   double *x0, *x1, *xbest, *hprev;
   int32_t *sidx;
   double *sval;
-  const double *CT;   // [KS][Nr][p] partial products X^T r
+  const double *CT;   // [*ksp][Nr][p] partial products X^T r
   const double *fsum; // [m][nfb][2] partial sums of r^2 and 2 r^T y - r^T r
   double *Bx;         // [Nr][p] current iterates (rows of the forward GEMM)
   int32_t *active;    // number of nodes not yet done
@@ -107,12 +108,14 @@ hipError_t launch_batch_init(const NodeParams *prm, NodeState *S, BatchBufs bb, 
 hipError_t launch_batch_step(const NodeParams *prm, NodeState *S, BatchBufs bb, int64_t p, hipStream_t s);
 hipError_t launch_transpose_bf16(const uint16_t *in, uint16_t *out, int64_t n, int64_t p, hipStream_t s);
 int batch_resid_blocks(int64_t n);
-hipError_t launch_batch_resid(const double *U, int KSF, int64_t n, int m, int Nr, const double *y, double *R,
-                              double *fsum, const NodeState *S, hipStream_t s);
+hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, int m, int Nr, const double *y,
+                              double *R, double *fsum, const NodeState *S, hipStream_t s);
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
-                           int64_t Nr, int64_t K, int KS, const int32_t *active, hipStream_t s);
-hipError_t launch_batch_zeta(const double *U, int KSF, int64_t n, int Nr, int node, const double *y, double *zeta,
-                             hipStream_t s);
+                           int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, hipStream_t s);
+hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int ksf, int fmaxf, int kst,
+                               int fmaxt, hipStream_t s);
+hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
 hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t loss, int64_t n,
                               hipStream_t s);
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,

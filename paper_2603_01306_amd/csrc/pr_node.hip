@@ -1247,6 +1247,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   }
   // h = X^T r from the GEMM split partials; w = h / lambda2 (= X^T zeta / (2 lambda2))
   const int64_t stride = (int64_t)bb.Nr * p;
+  const int KS = *bb.ksp;
   const double *__restrict__ Hn = bb.CT + off;
   double h[EPT];
   double acc[2] = {0.0, 0.0};  // sum_{J1} H_M(w_j), w^T x
@@ -1257,7 +1258,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     if (s != 3) {
       const int64_t j = tid + (int64_t)e * NT;
       double hv = 0.0;
-      for (int z = 0; z < bb.KS; z++) hv += Hn[z * stride + j];
+      for (int z = 0; z < KS; z++) hv += Hn[z * stride + j];
       h[e] = hv;
       const double wv = hv / lam2;
       if (s == kOne) acc[0] += huber(wv, M);
