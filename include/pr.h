@@ -190,6 +190,68 @@ int pr_time_batch_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms_fwd, dou
 int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
             int64_t Nr, int64_t K, int32_t KS);
 
+/* ---- Learned warm start for child nodes --------------------------------
+ * Not part of the paper's method (which warm-starts a child from its
+ * parent's solution).  A per-coordinate network proposes how each coordinate
+ * of a child's solution differs from the parent's; pr_mlp_warm_start keeps the
+ * proposal only if its FP64 duality gap on the child is below the parent
+ * solution's, so no bound ever depends on the network.
+ *
+ * Network 8 -> 64 -> 64 -> 1 with ReLU.  Parameters: one flat FP32 device
+ * vector of PR_MLP_NPARAM values, W1 (64 x 8) | b1 (64) | W2 (64 x 64) |
+ * b2 (64) | w3 (64) | b3, weights row-major (out = w3 . relu(W2 relu(W1 f +
+ * b1) + b2) + b3).  The kernels round weights and hidden activations to BF16
+ * for the MFMA products and accumulate in FP32.
+ *
+ * Features (one row of PR_MLP_NFEAT BF16 values per coordinate j of a child
+ * node, from the parent solution beta): beta_j; w_j / max_i |w_i| with
+ * w = X^T zeta, zeta = -grad F(X beta) (0 if w = 0); #{i : |beta_i| >
+ * |beta_j|} / p; the child's status of j (-1 fixed to zero, 0 free, +1 fixed
+ * to one); lambda2; |J1| / k; |J0| / k; kbar / k. */
+#define PR_MLP_NFEAT 8
+#define PR_MLP_NPARAM 4801
+
+/* Feature rows of m child nodes (host array nodes[m]) from their parents'
+ * solutions Bparent (device, m x p FP64, row i = parent of node i).  F
+ * (device, m x p x 8 BF16 bit patterns, 16-byte aligned) receives the rows,
+ * node-major.  If Bchild (device, m x p) is given, T (device, m x p FP32)
+ * receives the training targets Bchild - Bparent.  Synchronises the context
+ * stream.  PR_EINVAL / PR_EOVERLAP as pr_solve for a malformed node. */
+int pr_mlp_features(pr_ctx *ctx, const pr_node *nodes, int32_t m, const double *Bparent, const double *Bchild,
+                    uint16_t *F, float *T);
+
+/* out[r] = network output for feature row r, r < rows (device buffers, F
+ * 16-byte aligned).  Enqueued on `stream`, not waited for. */
+int pr_mlp_forward(void *stream, const float *params, const uint16_t *F, int64_t rows, float *out);
+
+/* Number of floats of device workspace pr_mlp_grad needs for `rows` rows. */
+int64_t pr_mlp_workspace(int64_t rows);
+
+/* Gradient of the mean squared error (1/rows) sum_r (out_r - T_r)^2 with
+ * respect to the parameters: grad (device, PR_MLP_NPARAM + 1 floats) receives
+ * the gradient and, in its last entry, the loss.  work: device workspace of
+ * pr_mlp_workspace(rows) floats.  The sum over rows is in a fixed order (the
+ * result is deterministic).  Enqueued on `stream`, not waited for. */
+int pr_mlp_grad(void *stream, const float *params, const uint16_t *F, const float *T, int64_t rows, float *work,
+                float *grad);
+
+/* One Adam step (step counts from 1, bias-corrected) on the FP32 master
+ * parameters, with first / second moment vectors m1, m2 (device,
+ * PR_MLP_NPARAM floats each, zero before step 1).  Enqueued on `stream`. */
+int pr_mlp_adam(void *stream, float *params, const float *grad, float *m1, float *m2, int32_t step, double lr,
+                double beta1, double beta2, double eps);
+
+/* Starting points for m child nodes.  For node i the candidate is
+ * prox_{rho g_N}(beta_parent + network output) with rho = 2 lambda2 / L (the
+ * solver's default step); B0 row i (device, m x p FP64) receives the candidate
+ * if its FP64 duality gap Phi(x) - Psi(zeta(x)) on the child is smaller than
+ * that of the parent solution, else the parent solution.  choice (host, m,
+ * optional): 1 where the candidate was kept.  gaps (host, 2m, optional):
+ * {parent gap, candidate gap} per node (+inf outside the domain or for an
+ * infeasible node).  Synchronises the context stream. */
+int pr_mlp_warm_start(pr_ctx *ctx, const pr_node *nodes, int32_t m, const float *params, const double *Bparent,
+                      double *B0, int32_t *choice, double *gaps);
+
 const char *pr_strerror(int code);
 
 #ifdef __cplusplus

@@ -20,7 +20,10 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_gemm", "pr_strerror"]
+           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
+           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_strerror"]
+
+MLP_NFEAT, MLP_NPARAM = 8, 4801
 
 
 class PrProblem(ctypes.Structure):
@@ -97,6 +100,20 @@ def load():
         L.pr_gemm.restype = ctypes.c_int
         L.pr_gemm.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
                               ctypes.c_int64, ctypes.c_int32]
+        L.pr_mlp_features.restype = ctypes.c_int
+        L.pr_mlp_features.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, P, P, P, P]
+        L.pr_mlp_forward.restype = ctypes.c_int
+        L.pr_mlp_forward.argtypes = [P, P, P, ctypes.c_int64, P]
+        L.pr_mlp_workspace.restype = ctypes.c_int64
+        L.pr_mlp_workspace.argtypes = [ctypes.c_int64]
+        L.pr_mlp_grad.restype = ctypes.c_int
+        L.pr_mlp_grad.argtypes = [P, P, P, P, ctypes.c_int64, P, P]
+        L.pr_mlp_adam.restype = ctypes.c_int
+        L.pr_mlp_adam.argtypes = [P, P, P, P, P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double]
+        L.pr_mlp_warm_start.restype = ctypes.c_int
+        L.pr_mlp_warm_start.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, P, P, P,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
         L.pr_strerror.restype = ctypes.c_char_p
         L.pr_strerror.argtypes = [ctypes.c_int]
         _lib = L
@@ -185,6 +202,7 @@ class Context:
         self.y = y
         self.p, self.n = Xcm.shape
         self.loss = int(loss)
+        self.max_batch = int(max_batch)
         prob = PrProblem()
         prob.X = Xcm.data_ptr()
         prob.xdtype = _xdtype(Xcm)
@@ -252,6 +270,38 @@ class Context:
                "pr_time_batch_gemm")
         return a.value, b.value
 
+    def mlp_features(self, nodes, Bparent, Bchild=None):
+        """Feature rows (m*p, 8) bfloat16 of child nodes from their parents'
+        solutions (m, p) float64; with Bchild also the targets (m*p,) float32."""
+        import torch
+        m = len(nodes)
+        dev = self.X.device
+        arr = (PrNode * m)(*[nd.c() for nd in nodes])
+        Bparent = Bparent.to(device=dev, dtype=torch.float64).contiguous()
+        F = torch.empty((m * self.p, MLP_NFEAT), dtype=torch.bfloat16, device=dev)
+        T = None
+        if Bchild is not None:
+            Bchild = Bchild.to(device=dev, dtype=torch.float64).contiguous()
+            T = torch.empty(m * self.p, dtype=torch.float32, device=dev)
+        _check(load().pr_mlp_features(self.h, arr, m, _dptr(Bparent), _dptr(Bchild), _dptr(F), _dptr(T)),
+               "pr_mlp_features")
+        return F, T
+
+    def mlp_warm_start(self, nodes, params, Bparent):
+        """(B0, choice, gaps): starting points for child nodes, the FP64 gap
+        deciding between the network's candidate and the parent solution."""
+        import torch
+        m = len(nodes)
+        dev = self.X.device
+        arr = (PrNode * m)(*[nd.c() for nd in nodes])
+        Bparent = Bparent.to(device=dev, dtype=torch.float64).contiguous()
+        B0 = torch.empty_like(Bparent)
+        choice = (ctypes.c_int32 * max(m, 1))()
+        gaps = (ctypes.c_double * max(2 * m, 1))()
+        _check(load().pr_mlp_warm_start(self.h, arr, m, _dptr(params.contiguous()), _dptr(Bparent), _dptr(B0),
+                                        choice, gaps), "pr_mlp_warm_start")
+        return B0, np.array(choice[:m], dtype=np.int32), np.array(gaps[:2 * m]).reshape(m, 2)
+
     def dual_bound(self, node, zeta=None, beta=None):
         lb = ctypes.c_double()
         ph = ctypes.c_double(float("nan"))
@@ -303,6 +353,39 @@ def gemm(A, B, KS=1):
     _check(load().pr_gemm(_stream_ptr(), _dptr(A), A.stride(0), _dptr(B), B.stride(0), _dptr(C), Mc, Nr, K, int(KS)),
            "pr_gemm")
     return C
+
+
+def mlp_forward(params, F):
+    """Network output (rows,) float32 for feature rows F (rows, 8) bfloat16."""
+    import torch
+    out = torch.empty(F.shape[0], dtype=torch.float32, device=F.device)
+    _check(load().pr_mlp_forward(_stream_ptr(), _dptr(params), _dptr(F.contiguous()), F.shape[0], _dptr(out)),
+           "pr_mlp_forward")
+    return out
+
+
+def mlp_workspace(rows):
+    return int(load().pr_mlp_workspace(int(rows)))
+
+
+def mlp_grad(params, F, T, work=None, grad=None):
+    """(gradient (4801,), loss) of the mean squared error; work / grad may be
+    preallocated float32 device tensors of mlp_workspace(rows) / 4802 entries."""
+    import torch
+    rows = F.shape[0]
+    if work is None:
+        work = torch.empty(mlp_workspace(rows), dtype=torch.float32, device=F.device)
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM + 1, dtype=torch.float32, device=F.device)
+    _check(load().pr_mlp_grad(_stream_ptr(), _dptr(params), _dptr(F), _dptr(T), rows, _dptr(work), _dptr(grad)),
+           "pr_mlp_grad")
+    return grad
+
+
+def mlp_adam(params, grad, m1, m2, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on params (float32 device) from grad[:4801]."""
+    _check(load().pr_mlp_adam(_stream_ptr(), _dptr(params), _dptr(grad), _dptr(m1), _dptr(m2), int(step),
+                              float(lr), float(beta1), float(beta2), float(eps)), "pr_mlp_adam")
 
 
 def regularizer(beta, alpha, k, M, status):

@@ -76,6 +76,12 @@ struct pr_ctx {
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
+  // learned warm start (allocated on first use)
+  uint16_t *mF = nullptr;  // [p][8] features of one node
+  float *mout = nullptr;   // [p] network outputs
+  double *mnz = nullptr;   // [p] compacted nonzero magnitudes
+  double *mfs = nullptr;   // {max |w|, nnz}
+  double *mvhat = nullptr, *mx = nullptr;  // [p] proposal before / after the prox step
 };
 
 namespace {
@@ -85,7 +91,7 @@ void free_ctx(pr_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
-                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split};
+                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx};
   for (void *b : bb)
     if (b) (void)hipFree(b);
   if (c->h_bstate) (void)hipHostFree(c->h_bstate);
@@ -669,6 +675,157 @@ int pr_time_batch_gemm(pr_ctx *c, int32_t m, int32_t reps, double *ms_fwd, doubl
     PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
     *outs[w] = (double)ms / reps;
   }
+  return PR_OK;
+}
+
+namespace {
+
+int ensure_mlp(pr_ctx *c) {
+  if (c->mF) return PR_OK;
+  const int64_t p = c->P.p;
+  bool ok = dalloc(&c->mF, (size_t)p * 8) == hipSuccess && dalloc(&c->mout, (size_t)p) == hipSuccess;
+  ok = ok && dalloc(&c->mnz, (size_t)p) == hipSuccess && dalloc(&c->mfs, 2) == hipSuccess;
+  ok = ok && dalloc(&c->mvhat, (size_t)p) == hipSuccess && dalloc(&c->mx, (size_t)p) == hipSuccess;
+  return ok ? PR_OK : PR_ENOMEM;
+}
+
+FeatScalars feat_scalars(const pr_node *node, const std::vector<int8_t> &st, int32_t kbar) {
+  FeatScalars sc;
+  sc.lambda2 = node->lambda2;
+  sc.k = node->k;
+  sc.n0 = sc.n1 = 0;
+  for (int8_t v : st) {
+    sc.n0 += v == kZero;
+    sc.n1 += v == kOne;
+  }
+  sc.kbar = kbar;
+  return sc;
+}
+
+// Status of the node in c->d_status and w = X^T zeta, zeta = -grad F(X beta),
+// in c->d_w: the inputs of the feature kernel.
+int grad_image(pr_ctx *c, const std::vector<int8_t> &st, const double *beta) {
+  const int64_t n = c->P.n, p = c->P.p;
+  hipStream_t s = c->stream;
+  PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, s));
+  if (launch_spfwd(c->P, c->B, c->iota, beta, c->d_np, kSpPlain, nullptr, c->d_u, s) != hipSuccess)
+    return PR_EDEVICE;
+  PR_TRY(launch_loss_terms(c->P.loss, c->d_u, c->P.y, n, c->B.gm, c->d_scal, s));
+  PR_TRY(launch_gemv_t(c->P, c->B.gm, nullptr, c->d_w, nullptr, nullptr, s));
+  return PR_OK;
+}
+
+}  // namespace
+
+int pr_mlp_features(pr_ctx *c, const pr_node *nodes, int32_t m, const double *Bparent, const double *Bchild,
+                    uint16_t *F, float *T) {
+  if (!c || !nodes || m < 0 || !Bparent || !F || (Bchild && !T) || ((uintptr_t)F) % 16) return PR_EINVAL;
+  const int64_t p = c->P.p;
+  std::vector<std::vector<int8_t>> sts((size_t)m);
+  std::vector<int32_t> kbars((size_t)m);
+  for (int32_t i = 0; i < m; i++) {
+    int64_t n1, pbar;
+    bool inf;
+    int rc = build_status(&nodes[i], p, sts[(size_t)i], n1, pbar, kbars[(size_t)i], inf);
+    if (rc != PR_OK) return rc;
+    if (inf) kbars[(size_t)i] = 0;
+  }
+  int rc = ensure_mlp(c);
+  if (rc != PR_OK) return rc;
+  hipStream_t s = c->stream;
+  for (int32_t i = 0; i < m; i++) {
+    const double *bp = Bparent + (int64_t)i * p;
+    rc = grad_image(c, sts[(size_t)i], bp);
+    if (rc != PR_OK) return rc;
+    PR_TRY(launch_features(bp, c->d_w, c->d_status, p, c->mnz, c->mfs,
+                           feat_scalars(&nodes[i], sts[(size_t)i], kbars[(size_t)i]),
+                           Bchild ? Bchild + (int64_t)i * p : nullptr, F + (int64_t)i * p * 8,
+                           T ? T + (int64_t)i * p : nullptr, s));
+  }
+  PR_TRY(hipStreamSynchronize(s));
+  return PR_OK;
+}
+
+int64_t pr_mlp_workspace(int64_t rows) {
+  if (rows < 1) return 0;
+  int cpb;
+  return (int64_t)mlp_grid(rows, &cpb) * kMlpPartStride;
+}
+
+int pr_mlp_forward(void *stream, const float *params, const uint16_t *F, int64_t rows, float *out) {
+  if (!params || !F || !out || rows < 0 || ((uintptr_t)F) % 16) return PR_EINVAL;
+  if (rows == 0) return PR_OK;
+  PR_TRY(launch_mlp_forward(params, F, rows, out, (hipStream_t)stream));
+  return PR_OK;
+}
+
+int pr_mlp_grad(void *stream, const float *params, const uint16_t *F, const float *T, int64_t rows, float *work,
+                float *grad) {
+  if (!params || !F || !T || !work || !grad || rows < 1 || ((uintptr_t)F) % 16) return PR_EINVAL;
+  PR_TRY(launch_mlp_grad(params, F, T, rows, work, grad, (hipStream_t)stream));
+  return PR_OK;
+}
+
+int pr_mlp_adam(void *stream, float *params, const float *grad, float *m1, float *m2, int32_t step, double lr,
+                double beta1, double beta2, double eps) {
+  if (!params || !grad || !m1 || !m2 || step < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+      !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return PR_EINVAL;
+  const double c1 = 1.0 / (1.0 - pow(beta1, step)), c2 = 1.0 / (1.0 - pow(beta2, step));
+  PR_TRY(launch_mlp_adam(params, grad, m1, m2, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                         (float)c2, (hipStream_t)stream));
+  return PR_OK;
+}
+
+int pr_mlp_warm_start(pr_ctx *c, const pr_node *nodes, int32_t m, const float *params, const double *Bparent,
+                      double *B0, int32_t *choice, double *gaps) {
+  if (!c || !nodes || m < 0 || !params || !Bparent || !B0) return PR_EINVAL;
+  const int64_t p = c->P.p;
+  std::vector<std::vector<int8_t>> sts((size_t)m);
+  std::vector<int32_t> kbars((size_t)m);
+  std::vector<char> infeas((size_t)m);
+  for (int32_t i = 0; i < m; i++) {
+    int64_t n1, pbar;
+    bool inf;
+    int rc = build_status(&nodes[i], p, sts[(size_t)i], n1, pbar, kbars[(size_t)i], inf);
+    if (rc != PR_OK) return rc;
+    infeas[(size_t)i] = inf;
+  }
+  int rc = ensure_mlp(c);
+  if (rc != PR_OK) return rc;
+  hipStream_t s = c->stream;
+  const double L = 1.01 * curvature(c->P.loss) * c->norm2;
+  for (int32_t i = 0; i < m; i++) {
+    const double *bp = Bparent + (int64_t)i * p;
+    double *x0 = B0 + (int64_t)i * p;
+    double gp = INFINITY, gm = INFINITY;
+    int use = 0;
+    if (!infeas[(size_t)i]) {
+      double lb, ub;
+      rc = pr_dual_bound(c, &nodes[i], nullptr, bp, &lb, &ub);  // leaves d_status and d_w = X^T zeta(beta)
+      if (rc != PR_OK) return rc;
+      gp = ub - lb;
+      PR_TRY(launch_features(bp, c->d_w, c->d_status, p, c->mnz, c->mfs,
+                             feat_scalars(&nodes[i], sts[(size_t)i], kbars[(size_t)i]), nullptr, c->mF, nullptr,
+                             s));
+      PR_TRY(launch_mlp_forward(params, c->mF, p, c->mout, s));
+      PR_TRY(launch_mlp_propose(bp, c->mout, p, c->mvhat, s));
+      const double rho = 2.0 * nodes[i].lambda2 / L;
+      PR_TRY(launch_prox(c->mvhat, c->mx, p, rho, kbars[(size_t)i], nodes[i].M, c->d_status, c->d_regscratch,
+                         nullptr, s));
+      rc = pr_dual_bound(c, &nodes[i], nullptr, c->mx, &lb, &ub);
+      if (rc != PR_OK) return rc;
+      gm = ub - lb;
+      use = gm < gp;
+    }
+    PR_TRY(hipMemcpyAsync(x0, use ? c->mx : bp, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    if (choice) choice[i] = use;
+    if (gaps) {
+      gaps[2 * i] = gp;
+      gaps[2 * i + 1] = gm;
+    }
+  }
+  PR_TRY(hipStreamSynchronize(s));
   return PR_OK;
 }
 

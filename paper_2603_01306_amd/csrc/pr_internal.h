@@ -116,6 +116,22 @@ hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int6
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int ksf, int fmaxf, int kst,
                                int fmaxt, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
+// learned warm start
+constexpr int kMlpPartStride = 4804;  // floats per block partial: 4801 gradient entries, loss, pad
+struct FeatScalars {
+  double lambda2;
+  int32_t k, n0, n1, kbar;
+};
+int mlp_grid(int64_t rows, int *cpb);
+hipError_t launch_mlp_forward(const float *P, const uint16_t *F, int64_t rows, float *out, hipStream_t s);
+hipError_t launch_mlp_grad(const float *P, const uint16_t *F, const float *T, int64_t rows, float *part,
+                           float *grad, hipStream_t s);
+hipError_t launch_mlp_adam(float *P, const float *g, float *m1, float *m2, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_features(const double *beta, const double *w, const int8_t *st, int64_t p, double *nzv,
+                           double *fs, FeatScalars sc, const double *beta_child, uint16_t *F, float *T,
+                           hipStream_t s);
+hipError_t launch_mlp_propose(const double *beta, const float *out, int64_t p, double *vhat, hipStream_t s);
 hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t loss, int64_t n,
                               hipStream_t s);
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,
