@@ -20,6 +20,7 @@ roofline.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
+  python bench.py --learned [--pairs N] [--epochs E]   # learned warm start experiment
 """
 import argparse
 import hashlib
@@ -178,6 +179,83 @@ def batch_bench(dev, steps, n_single=16):
     return out
 
 
+def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
+    """The learned warm start on the 16384 x 8192 design (BF16): training pairs
+    from the seeded branching process (256 children per batched solve), Adam
+    training of the network, and 512 held-out children solved from the parent
+    solutions and from the judged network starts, all to a 1e-6 FP64 gap."""
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    from paper_2603_01306_amd import learned
+    from workloads import config_instance, CONFIGS
+    cfg = CONFIGS[BATCH_WORKLOAD]
+    dev = torch.device("cuda:0")
+    inst = config_instance(BATCH_WORKLOAD)
+    X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    ctx = pr.Context(X, torch.from_numpy(inst.y).to(dev), pr.LSQ, max_batch=256)
+    rng = np.random.default_rng(seed)
+    root = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
+    t0 = time.perf_counter()
+    pool = learned.BranchingPool(ctx, root, capacity=n_pairs + 1, rel_gap_tol=cfg["tol"])
+
+    def gen_progress(done, total):
+        if done % (256 * 8) == 0 or done == total:
+            print(json.dumps({"progress": "pairs", "done": done, "of": total,
+                              "s": round(time.perf_counter() - t0, 1)}), flush=True)
+
+    F, T, gen_iters = learned.generate_pairs(pool, n_pairs, 256, rng, progress=gen_progress)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    params = learned.init_params(seed + 1, dev)
+    t1 = time.perf_counter()
+
+    def train_progress(ep, loss):
+        print(json.dumps({"progress": "epoch", "epoch": ep, "loss": loss, "s": round(time.perf_counter() - t1, 2)}),
+              flush=True)
+
+    batch_rows = 1 << 20          # 128 nodes' rows per Adam step
+    losses = learned.train(params, F, T, epochs, batch_rows, lr=2e-3, seed=seed + 2, progress=train_progress)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    # gradient kernel alone on one minibatch, HIP-event timed on the current stream
+    work = torch.empty(pr.mlp_workspace(batch_rows), dtype=torch.float32, device=dev)
+    grad = torch.empty(pr.MLP_NPARAM + 1, dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pr.mlp_grad(params, F[:batch_rows], T[:batch_rows], work, grad)
+    e0.record()
+    for _ in range(20):
+        pr.mlp_grad(params, F[:batch_rows], T[:batch_rows], work, grad)
+    e1.record()
+    torch.cuda.synchronize()
+    grad_ms = e0.elapsed_time(e1) / 20
+    flop_row = 3 * 2 * (8 * 64 + 64 * 64 + 64)       # forward + backward, MFMA-shaped work
+    del F, T
+    # held-out children: parents from the same pool, new random branchings
+    ch, bp = [], []
+    while len(ch) < n_eval:
+        c, Bp, _, _ = pool.grow(min(256, n_eval - len(ch)), rng, keep=False)
+        ch.extend(c)
+        bp.append(Bp)
+    Bp = torch.cat(bp)
+    ev = learned.evaluate(ctx, params, ch, Bp, rel_gap_tol=cfg["tol"])
+    arrays = {k: ev.pop(k) for k in ("iters_parent", "iters_learned", "choice", "gaps")}
+    ip, im = arrays["iters_parent"], arrays["iters_learned"]
+    out = {"metric": "learned warm start: iterations and time to 1e-6 FP64 gap vs parent warm start",
+           "workload": BATCH_WORKLOAD, "n": inst.n, "p": inst.p, "k": cfg["k"], "lambda2": cfg["lambda2"],
+           "pairs": n_pairs, "rows": n_pairs * inst.p, "generation_s": round(gen_s, 1),
+           "generation_child_iters_mean": round(float(gen_iters.mean()), 1),
+           "epochs": epochs, "train_s": round(train_s, 2), "epoch_losses": [float(f"{x:.4g}") for x in losses],
+           "grad_kernel_rows": batch_rows, "grad_kernel_ms": round(grad_ms, 4),
+           "grad_rows_per_s": round(batch_rows / (grad_ms * 1e-3)),
+           "grad_tflops_mfma_shaped": round(flop_row * batch_rows / (grad_ms * 1e-3) / 1e12, 2),
+           "eval": ev,
+           "eval_iters_saved_fraction": round(float(1.0 - im.sum() / max(ip.sum(), 1)), 4),
+           "eval_children_fewer_iters": int((im < ip).sum()), "eval_children_more_iters": int((im > ip).sum())}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +264,9 @@ def main():
     ap.add_argument("--kernel-probe", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
+    ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
+    ap.add_argument("--pairs", type=int, default=50000)
+    ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -193,6 +274,9 @@ def main():
         sys.exit(2)
     if args.kernel_probe:
         kernel_probe()
+        return
+    if args.learned:
+        learned_bench(args.pairs, args.epochs)
         return
     import torch
     dev = torch.device("cuda:0")
