@@ -20,16 +20,42 @@ typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// One DPP move of a double (two 32-bit halves); lanes outside row_mask, or
+// reading outside their row, receive `idb` (the identity's bit pattern).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v, long long idb) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(idb & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xf,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(idb >> 32), (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave reductions on the VALU cross-lane (DPP) network: pairs and quads by
+// quad permutations, 8 and 16 lanes by the half-row and row mirrors, then row
+// broadcasts of lane 15 and lane 31 leave the total in lane 63, which every
+// lane reads.  The order of the additions is fixed, so the result is
+// reproducible.
+template <class OP>
+__device__ __forceinline__ double wave_reduce(double v, long long idb, OP op) {
+  v = op(v, dpp_f64<0xb1, 0xf>(v, idb));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_f64<0x4e, 0xf>(v, idb));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_f64<0x141, 0xf>(v, idb));  // row_half_mirror
+  v = op(v, dpp_f64<0x140, 0xf>(v, idb));  // row_mirror
+  v = op(v, dpp_f64<0x142, 0xa>(v, idb));  // row_bcast:15 into rows 1 and 3
+  v = op(v, dpp_f64<0x143, 0xc>(v, idb));  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return wave_reduce(v, 0ll, [](double a, double b) { return a + b; });
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  return wave_reduce(v, (long long)0xfff0000000000000ull, [](double a, double b) { return fmax(a, b); });
 }
 
 // Sum of K values over a workgroup of NTH threads.  Every thread adds the

@@ -1015,27 +1015,26 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const double L = S->L;
   PackedStatus<EPT> sv;
   sv.load(prm->st, p);
+  // loss sums of the finalize blocks: lane-parallel loads, fixed-order wave sums
   double Fk = 0.0, negconj = 0.0;
-  for (int i = 0; i < B.nfin; i++) {
+  for (int i = lane_id(); i < B.nfin; i += 64) {
     Fk += B.rbsum[2 * i];
     negconj += B.rbsum[2 * i + 1];
   }
+  Fk = wave_sum(Fk);
+  negconj = wave_sum(negconj);
   // dual value at x^k: w = X^T zeta / (2 lambda2)
   const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
-  double x[EPT];
+  double x[EPT];  // h = B.h1 here, the gradient-step point v below, then x^{k+1}
   double sj1[1] = {0.0};
 #pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    x[e] = 0.0;
-    const int s = sv(e);
-    if (s != 3) {
-      x[e] = B.h1[tid + (int64_t)e * NT] * wscale;
-      if (s == kOne) sj1[0] += huber(x[e], M);
-    }
-  }
+  for (int e = 0; e < EPT; e++) x[e] = sv(e) != 3 ? B.h1[tid + (int64_t)e * NT] : 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; e++)
+    if (sv(e) == kOne) sj1[0] += huber(x[e] * wscale, M);
   block_sum<NT, 1>(sj1, lds.red);
-  auto aval = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
-  const double topsum = topsum_huber_f<EPT>(aval, kbar, M, lds.sel, lds.red);
+  auto wabs = [&](int e) { return sv(e) == kFree ? fabs(x[e] * wscale) : -1.0; };
+  const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
   const double psi = negconj - 2.0 * lam2 * (sj1[0] + topsum);
   const double phi = S->indom ? Fk + 2.0 * lam2 * S->gval : INFINITY;
   if (tid == 0) {
@@ -1104,39 +1103,48 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     lds.bci[2] = ub_improved;
   }
   __syncthreads();
-  double *__restrict__ xc = parity ? nb.x1 : nb.x0;
+  const double *__restrict__ xc = parity ? nb.x1 : nb.x0;
   double *__restrict__ xn = parity ? nb.x0 : nb.x1;  // holds x^{k-1}, receives x^{k+1}
-  if (lds.bci[2]) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.xbest[tid + (int64_t)e * NT] = xc[tid + (int64_t)e * NT];
-  }
-  if (lds.bci[0]) return;
+  const bool done = lds.bci[0] != 0;
   const double m = lds.bcd[0];
   const int restart = lds.bci[1];
   const double invL = 1.0 / L;
+  // every load of the step first, then the arithmetic, then the stores
+  double xk[EPT], xq[EPT], g2[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int64_t j = tid + (int64_t)e * NT;
+    const bool in = sv(e) != 3;
+    xk[e] = in ? xc[j] : 0.0;
+    xq[e] = (in && !done) ? xn[j] : 0.0;
+    g2[e] = (in && !done && (loss == kLsq || !restart)) ? (loss == kLsq ? nb.hprev[j] : B.h2[j]) : 0.0;
+  }
+  if (lds.bci[2]) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) nb.xbest[tid + (int64_t)e * NT] = xk[e];
+  }
+  if (done) return;
   // gradient step at the momentum point; x[] now holds v
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
-    x[e] = 0.0;
-    if (sv(e) != 3) {
-      const int64_t j = tid + (int64_t)e * NT;
-      const double xk = xc[j], xq = xn[j];
-      const double yj = xk + m * (xk - xq);
-      double gj;
-      if (loss == kLsq) {
-        const double h = B.h1[j], hp = nb.hprev[j];
-        gj = -2.0 * ((1.0 + m) * h - m * hp);
-        nb.hprev[j] = h;
-      } else {
-        gj = restart ? -B.h1[j] : B.h2[j];
-      }
-      x[e] = yj - gj * invL;
-    }
+    const double h = x[e];
+    const double yj = xk[e] + m * (xk[e] - xq[e]);
+    double gj;
+    if (loss == kLsq) gj = -2.0 * ((1.0 + m) * h - m * g2[e]);
+    else gj = restart ? -h : g2[e];
+    x[e] = sv(e) != 3 ? yj - gj * invL : 0.0;
+    g2[e] = h;
+  }
+  if (loss == kLsq) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) nb.hprev[tid + (int64_t)e * NT] = g2[e];
   }
   const double rho = 2.0 * lam2 * invL;
   int evals = 0;
-  const double tau = solve_tau_f<EPT>(aval, kbar, rho, M, S->tau, lds.red, &evals);
+  auto vabs = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
+  const double tau = solve_tau_f<EPT>(vabs, kbar, rho, M, S->tau, lds.red, &evals);
   const double inv1p = 1.0 / (1.0 + rho);
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
@@ -1236,37 +1244,37 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   const double lam2 = prm->lambda2, M = prm->M;
   const int parity = S->parity;
   const double L = S->L;
-  double *__restrict__ xc = (parity ? bb.x1 : bb.x0) + off;
+  const double *__restrict__ xc = (parity ? bb.x1 : bb.x0) + off;
   double *__restrict__ xn = (parity ? bb.x0 : bb.x1) + off;
   PackedStatus<EPT> sv;
   sv.load(prm->st, p);
+  // loss sums of the residual blocks: lane-parallel loads, fixed-order wave sums
   double Fk = 0.0, negconj = 0.0;
-  for (int i = 0; i < bb.nfb; i++) {
+  for (int i = lane_id(); i < bb.nfb; i += 64) {
     Fk += bb.fsum[2 * ((int64_t)node * bb.nfb + i)];
     negconj += bb.fsum[2 * ((int64_t)node * bb.nfb + i) + 1];
   }
+  Fk = wave_sum(Fk);
+  negconj = wave_sum(negconj);
   // h = X^T r from the GEMM split partials; w = h / lambda2 (= X^T zeta / (2 lambda2))
   const int64_t stride = (int64_t)bb.Nr * p;
   const int KS = *bb.ksp;
   const double *__restrict__ Hn = bb.CT + off;
+  const double wscale = 1.0 / lam2;
   double h[EPT];
-  double acc[2] = {0.0, 0.0};  // sum_{J1} H_M(w_j), w^T x
 #pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    h[e] = 0.0;
-    const int s = sv(e);
-    if (s != 3) {
-      const int64_t j = tid + (int64_t)e * NT;
-      double hv = 0.0;
-      for (int z = 0; z < KS; z++) hv += Hn[z * stride + j];
-      h[e] = hv;
-      const double wv = hv / lam2;
-      if (s == kOne) acc[0] += huber(wv, M);
-      acc[1] += wv * xc[j];
-    }
+  for (int e = 0; e < EPT; e++) h[e] = sv(e) != 3 ? Hn[tid + (int64_t)e * NT] : 0.0;
+  for (int z = 1; z < KS; z++) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) h[e] += Hn[z * stride + tid + (int64_t)e * NT];
   }
-  block_sum<NT, 2>(acc, lds.red);
-  auto wabs = [&](int e) { return sv(e) == kFree ? fabs(h[e] / lam2) : -1.0; };
+  double acc[1] = {0.0};  // sum_{J1} H_M(w_j)
+#pragma unroll
+  for (int e = 0; e < EPT; e++)
+    if (sv(e) == kOne) acc[0] += huber(h[e] * wscale, M);
+  block_sum<NT, 1>(acc, lds.red);
+  auto wabs = [&](int e) { return sv(e) == kFree ? fabs(h[e] * wscale) : -1.0; };
   const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
   const double gstar = acc[0] + topsum;
   // Psi(zeta) and Phi(x) from the FP64 products of this pass
@@ -1327,29 +1335,37 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     lds.bci[0] = done;
   }
   __syncthreads();
-  if (lds.bci[0]) {
+  const bool done = lds.bci[0] != 0;
+  double *__restrict__ hp = bb.hprev + off;
+  // every load of the step first, then the arithmetic, then the stores
+  double xk[EPT], xq[EPT], hq[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int64_t j = tid + (int64_t)e * NT;
+    const bool in = sv(e) != 3;
+    xk[e] = in ? xc[j] : 0.0;
+    xq[e] = (in && !done) ? xn[j] : 0.0;
+    hq[e] = (in && !done) ? hp[j] : 0.0;
+  }
+  if (done) {
     // the certified point is the iterate whose gap passed the test
 #pragma unroll
     for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xc[tid + (int64_t)e * NT];
+      if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xk[e];
     return;
   }
   const double m = lds.bcd[0];
   const double invL = 1.0 / L;
-  double *__restrict__ hp = bb.hprev + off;
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
-    double v = 0.0;
-    if (sv(e) != 3) {
-      const int64_t j = tid + (int64_t)e * NT;
-      const double xk = xc[j], xq = xn[j];
-      const double yj = xk + m * (xk - xq);
-      const double gj = -2.0 * ((1.0 + m) * h[e] - m * hp[j]);
-      hp[j] = h[e];
-      v = yj - gj * invL;
-    }
-    h[e] = v;  // h[] now holds v
+    const double yj = xk[e] + m * (xk[e] - xq[e]);
+    const double gj = -2.0 * ((1.0 + m) * h[e] - m * hq[e]);
+    hq[e] = h[e];
+    h[e] = sv(e) != 3 ? yj - gj * invL : 0.0;  // h[] now holds v
   }
+#pragma unroll
+  for (int e = 0; e < EPT; e++)
+    if (sv(e) != 3) hp[tid + (int64_t)e * NT] = hq[e];
   const double rho = 2.0 * lam2 * invL;
   int evals = 0;
   auto vabs = [&](int e) { return sv(e) == kFree ? fabs(h[e]) : -1.0; };
