@@ -160,12 +160,15 @@ def batch_bench(dev, steps, n_single=16):
     dt_s = time.perf_counter() - t0
     ok_s = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in single)
     ms_f, ms_t = ctx.time_batch_gemm(m, reps=10)
+    tiles = (m + 63) // 64
+    tf, tt = ctx.batch_tuning(tiles)
     nr = (m + 63) // 64 * 64
     flop = 2.0 * inst.n * inst.p * nr
     ach = flop / (ms_t * 1e-3) / 1e12
     out = {"workload": BATCH_WORKLOAD, "nodes": m, "x_storage": "bf16", "rel_gap_tol": cfg["tol"],
            "value": round(m * steps / dt_b, 3), "unit": "node relaxations/s", "steps": steps,
            "ms_per_step": round(1e3 * dt_b / steps, 2), "all_converged": ok_b,
+           "autotuned_splits": {"active_row_tiles": list(range(1, tiles + 1)), "forward": tf, "transpose": tt},
            "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 1),
            "single_path": {"value": round(n_single / dt_s, 3), "unit": "node relaxations/s",
                            "nodes": n_single, "all_converged": ok_s,

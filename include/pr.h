@@ -169,21 +169,28 @@ int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *
  * context stream; *ms_avg = elapsed / reps.  r device n, h device p. */
 int pr_time_gemv_t(pr_ctx *ctx, const double *r, double *h, int32_t reps, double *ms_avg);
 
+/* Splits chosen by the context's batched-GEMM autotuner (run at context
+ * creation): for i = 0 .. len-1, the number of reduction splits of the forward
+ * and of the transpose GEMM when i+1 tiles of 64 rows are active (host arrays
+ * of len entries).  PR_EINVAL if the context has no batched path. */
+int pr_batch_tuning(pr_ctx *ctx, int32_t len, int32_t *ksf_out, int32_t *kst_out);
+
 /* Time `reps` back-to-back launches of each of the two GEMMs of one
  * pr_solve_batch iteration for a batch of m nodes (forward U = Xit X^T, then
- * transpose H = R X), in the launch configuration the solve uses, with HIP
- * events on the context stream; *ms_fwd, *ms_t = elapsed / reps.  The
- * operands are the context's batch buffers (contents irrelevant to timing).
- * PR_EINVAL unless the context was created with max_batch >= m. */
+ * transpose H = R X) with all m rows active, in the launch configuration the
+ * solve uses (split count, persistent grid, tile counter reset before each
+ * launch), with HIP events on the context stream; *ms_fwd, *ms_t = elapsed /
+ * reps.  The operands are the context's batch buffers (contents irrelevant to
+ * timing).  PR_EINVAL unless the context was created with max_batch >= m. */
 int pr_time_batch_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms_fwd, double *ms_t);
 
 /* FP64 MFMA product used by pr_solve_batch for both of its matrix products
  * (test and measurement entry point): C[z][r][c] = sum over k in split z of
  * A[c][k] * B[r][k].  A is Mc x K, row-major BF16 bit patterns (uint16,
- * converted exactly), leading dimension lda (multiple of 4); B is Nr x K,
+ * converted exactly), leading dimension lda (multiple of 8); B is Nr x K,
  * row-major FP64, leading dimension ldb (even); FP64 accumulation, output C
  * FP64, KS x Nr x Mc (one plane per split of the reduction dimension into KS
- * equal parts).  Requires Mc a multiple of 128, Nr of 64, K of 16*KS; A 8-byte,
+ * equal parts).  Requires Mc a multiple of 128, Nr of 64, K of 32*KS; A and
  * B 16-byte aligned.  A, B, C device; the launch is enqueued on `stream`
  * (hipStream_t or NULL) and not waited for.  PR_EINVAL on a violated
  * requirement (nothing is launched). */

@@ -20,7 +20,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
+           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
            "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
@@ -94,6 +94,8 @@ def load():
         L.pr_solve_batch.restype = ctypes.c_int
         L.pr_solve_batch.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, ctypes.POINTER(PrOpts),
                                      P, P, ctypes.POINTER(PrResult)]
+        L.pr_batch_tuning.restype = ctypes.c_int
+        L.pr_batch_tuning.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.pr_time_batch_gemm.restype = ctypes.c_int
         L.pr_time_batch_gemm.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -261,6 +263,13 @@ class Context:
         _check(load().pr_solve_batch(self.h, arr, m, ctypes.byref(o), _dptr(B0), _dptr(Bout), res),
                "pr_solve_batch")
         return [r.as_dict() for r in res], Bout
+
+    def batch_tuning(self, tiles):
+        """Autotuned (forward, transpose) split counts for 1 .. tiles active 64-row tiles."""
+        a = (ctypes.c_int32 * tiles)()
+        b = (ctypes.c_int32 * tiles)()
+        _check(load().pr_batch_tuning(self.h, int(tiles), a, b), "pr_batch_tuning")
+        return list(a), list(b)
 
     def time_batch_gemm(self, m, reps=20):
         """(ms forward GEMM, ms transpose GEMM) per launch for a batch of m nodes."""

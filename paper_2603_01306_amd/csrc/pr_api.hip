@@ -72,7 +72,9 @@ struct pr_ctx {
   NodeState *h_bstate = nullptr;  // pinned, cap
   int32_t *d_active = nullptr;
   int32_t *d_rowmap = nullptr;    // [cap padded] slots of the nodes still iterating
-  int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split}
+  int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split, -, tile counters x2}
+  int32_t *d_ftab = nullptr;      // [2][kTuneMax] tuned split factors per active row-tile count
+  int32_t h_ftab[2 * kTuneMax] = {};
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
@@ -91,7 +93,7 @@ void free_ctx(pr_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
-                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx};
+                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx};
   for (void *b : bb)
     if (b) (void)hipFree(b);
   if (c->h_bstate) (void)hipHostFree(c->h_bstate);
@@ -237,6 +239,64 @@ int power_norm2(pr_ctx *c) {
 
 int nr_of(int32_t m) { return (m + 63) / 64 * 64; }
 
+// Autotuner of the batched GEMMs (run once per context).  For every count of
+// active 64-row tiles, each extra split factor f of each GEMM (a tile's extent
+// along the reduction dimension is K / (base * f)) is timed with HIP events in
+// the solve's launch configuration (persistent grid, row map, tile counter);
+// the chosen f minimises the measured time plus the modelled cost of the
+// split partial planes that the next kernel reads (bytes / kTunePlaneBW).
+// The table goes to the device, where the per-iteration row-map kernel reads
+// it.
+int tune_batch(pr_ctx *c) {
+  const int64_t n = c->P.n, p = c->P.p;
+  const int NrMax = nr_of(c->max_batch);
+  const int ntmax = NrMax / 64 < kTuneMax - 1 ? NrMax / 64 : kTuneMax - 1;
+  hipStream_t s = c->stream;
+  PR_TRY(launch_iota(c->d_rowmap, NrMax, s));
+  int32_t *cnt = c->d_split + 4;
+  for (int g = 0; g < 2; g++) {
+    const bool fwd = g == 0;
+    const int base = fwd ? c->KSF : c->KS, fmax = fwd ? c->fmaxF : c->fmaxT;
+    const double plane_bytes = 8.0 * (double)(fwd ? n : p);  // per row and split plane
+    for (int nta = 1; nta <= ntmax; nta++) {
+      const int32_t nrow = nta * 64 < c->max_batch ? nta * 64 : c->max_batch;
+      double best = INFINITY;
+      int bestf = 1;
+      for (int f = 1; f <= fmax; f *= 2) {
+        const int32_t sp[3] = {nrow, base * f, base * f};
+        PR_TRY(hipMemcpyAsync(c->d_split, sp, sizeof(sp), hipMemcpyHostToDevice, s));
+        auto launch = [&]() -> hipError_t {
+          hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
+          if (e != hipSuccess) return e;
+          if (fwd)
+            return launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, NrMax, p, base, nullptr, c->d_rowmap, c->d_split,
+                                   c->d_split + 1, base * fmax, cnt, s);
+          return launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, NrMax, n, base, nullptr,
+                                 c->d_rowmap, c->d_split, c->d_split + 2, base * fmax, cnt, s);
+        };
+        PR_TRY(launch());
+        PR_TRY(hipEventRecord(c->tev[0], s));
+        for (int r = 0; r < kTuneReps; r++) PR_TRY(launch());
+        PR_TRY(hipEventRecord(c->tev[1], s));
+        PR_TRY(hipEventSynchronize(c->tev[1]));
+        float ms = 0.0f;
+        PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+        const double cost = ms / kTuneReps + 1e3 * (double)(base * f) * nrow * plane_bytes / kTunePlaneBW;
+        if (cost < best) {
+          best = cost;
+          bestf = f;
+        }
+      }
+      c->h_ftab[g * kTuneMax + nta] = bestf;
+    }
+    for (int nta = ntmax + 1; nta < kTuneMax; nta++) c->h_ftab[g * kTuneMax + nta] = c->h_ftab[g * kTuneMax + ntmax];
+    c->h_ftab[g * kTuneMax] = 1;
+  }
+  PR_TRY(hipMemcpyAsync(c->d_ftab, c->h_ftab, sizeof(c->h_ftab), hipMemcpyHostToDevice, s));
+  PR_TRY(hipStreamSynchronize(s));
+  return PR_OK;
+}
+
 int alloc_batch(pr_ctx *c) {
   const int64_t n = c->P.n, p = c->P.p;
   const int cap = c->max_batch;
@@ -244,14 +304,15 @@ int alloc_batch(pr_ctx *c) {
   // split the reductions so that each GEMM has >= ~1024 workgroups at full batch
   const int tiles_t = (int)(p / 128) * (NrMax / 64);
   int KS = 1;
-  while (KS < 16 && tiles_t * KS < 512 && (n / (2 * KS)) % 16 == 0) KS *= 2;
+  while (KS < 16 && tiles_t * KS < 512 && (n / (2 * KS)) % 32 == 0) KS *= 2;
   const int tiles_f = (int)(n / 128) * (NrMax / 64);
   int KSF = 1;
-  while (KSF < 16 && tiles_f * KSF < 512 && (p / (2 * KSF)) % 16 == 0) KSF *= 2;
-  // as nodes finish the splits grow by up to NrMax / 64 (fewer row tiles)
+  while (KSF < 16 && tiles_f * KSF < 512 && (p / (2 * KSF)) % 32 == 0) KSF *= 2;
+  // extra split factors of the two GEMMs (chosen per iteration from the
+  // number of active row tiles), up to 16 while the split stays a multiple of 32
   int fF = 1, fT = 1;
-  while (2 * fF <= NrMax / 64 && (p / (2 * fF * KSF)) % 16 == 0) fF *= 2;
-  while (2 * fT <= NrMax / 64 && (n / (2 * fT * KS)) % 16 == 0) fT *= 2;
+  while (2 * fF <= 16 && (p / (2 * fF * KSF)) % 32 == 0 && p % (2 * fF * KSF) == 0) fF *= 2;
+  while (2 * fT <= 16 && (n / (2 * fT * KS)) % 32 == 0 && n % (2 * fT * KS) == 0) fT *= 2;
   c->KS = KS;
   c->KSF = KSF;
   c->fmaxF = fF;
@@ -269,7 +330,8 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && dalloc(&c->bstatus, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->d_bprm, cap) == hipSuccess && dalloc(&c->d_bstate, cap) == hipSuccess;
   ok = ok && dalloc(&c->d_active, 2) == hipSuccess;
-  ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 4) == hipSuccess;
+  ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 8) == hipSuccess;
+  ok = ok && dalloc(&c->d_ftab, 2 * kTuneMax) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_bstate, sizeof(NodeState) * cap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   if (!ok) return PR_ENOMEM;
@@ -278,6 +340,8 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && launch_transpose_bf16((const uint16_t *)c->P.X, c->Xrow, n, p, c->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) return PR_EDEVICE;
+  int rc = tune_batch(c);
+  if (rc != PR_OK) return rc;
   c->batch_ok = true;
   return PR_OK;
 }
@@ -306,15 +370,16 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
 hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
   const int64_t n = c->P.n, p = c->P.p;
   const int Nr = nr_of(m);
-  hipError_t e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->KSF, c->fmaxF, c->KS, c->fmaxT, s);
+  hipError_t e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF,
+                                     c->KS, s);
   if (e != hipSuccess) return e;
   e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
-                      c->d_split + 1, c->KSF * c->fmaxF, s);
+                      c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
   if (e != hipSuccess) return e;
   e = launch_batch_resid(c->CF, c->d_split + 1, n, m, Nr, c->P.y, c->Rd, c->fsum, c->d_bstate, s);
   if (e != hipSuccess) return e;
   e = launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, c->d_active, c->d_rowmap,
-                      c->d_split, c->d_split + 2, c->KS * c->fmaxT, s);
+                      c->d_split, c->d_split + 2, c->KS * c->fmaxT, c->d_split + 5, s);
   if (e != hipSuccess) return e;
   return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
 }
@@ -554,12 +619,12 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
 
 int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
             int64_t Nr, int64_t K, int32_t KS) {
-  if (!A || !B || !C || Mc < 128 || Nr < 64 || K < 16 || KS < 1 || Mc % 128 || Nr % 64 ||
-      K % (16 * (int64_t)KS) || lda < K || ldb < K || lda % 4 || ldb % 2)
+  if (!A || !B || !C || Mc < 128 || Nr < 64 || K < 32 || KS < 1 || Mc % 128 || Nr % 64 ||
+      K % (32 * (int64_t)KS) || lda < K || ldb < K || lda % 8 || ldb % 2)
     return PR_EINVAL;
-  if (((uintptr_t)A) % 8 || ((uintptr_t)B) % 16 || ((uintptr_t)C) % 8) return PR_EINVAL;
+  if (((uintptr_t)A) % 16 || ((uintptr_t)B) % 16 || ((uintptr_t)C) % 8) return PR_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  PR_TRY(launch_gemm_f64(A, lda, B, ldb, C, Mc, Nr, K, KS, nullptr, nullptr, nullptr, nullptr, 0, s));
+  PR_TRY(launch_gemm_f64(A, lda, B, ldb, C, Mc, Nr, K, KS, nullptr, nullptr, nullptr, nullptr, 0, nullptr, s));
   return PR_OK;
 }
 
@@ -652,17 +717,36 @@ int pr_time_gemv_t(pr_ctx *c, const double *r, double *h, int32_t reps, double *
   return PR_OK;
 }
 
+int pr_batch_tuning(pr_ctx *c, int32_t len, int32_t *ksf_out, int32_t *kst_out) {
+  if (!c || !c->batch_ok || len < 1 || !ksf_out || !kst_out) return PR_EINVAL;
+  for (int32_t i = 0; i < len; i++) {
+    const int t = i + 1 < kTuneMax ? i + 1 : kTuneMax - 1;
+    ksf_out[i] = c->KSF * c->h_ftab[t];
+    kst_out[i] = c->KS * c->h_ftab[kTuneMax + t];
+  }
+  return PR_OK;
+}
+
 int pr_time_batch_gemm(pr_ctx *c, int32_t m, int32_t reps, double *ms_fwd, double *ms_t) {
   if (!c || !c->batch_ok || m < 1 || m > c->max_batch || reps < 1 || !ms_fwd || !ms_t) return PR_EINVAL;
   const int64_t n = c->P.n, p = c->P.p;
   const int Nr = nr_of(m);
   hipStream_t s = c->stream;
+  // the split the batched iteration uses with all m rows active
+  int nta = (m + 63) / 64;
+  if (nta >= kTuneMax) nta = kTuneMax - 1;
+  const int ksf = c->KSF * c->h_ftab[nta], kst = c->KS * c->h_ftab[kTuneMax + nta];
+  int32_t *cnt = c->d_split + 4;
   auto fwd = [&]() {
-    return launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, nullptr, nullptr, nullptr, nullptr, 0, s);
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    return launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, ksf, nullptr, nullptr, nullptr, nullptr, 0, cnt, s);
   };
   auto trn = [&]() {
-    return launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, nullptr, nullptr,
-                           nullptr, nullptr, 0, s);
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    return launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, kst, nullptr, nullptr, nullptr,
+                           nullptr, 0, cnt, s);
   };
   double *outs[2] = {ms_fwd, ms_t};
   for (int w = 0; w < 2; w++) {

@@ -24,55 +24,38 @@ using namespace dev;
 
 typedef double d2v_t __attribute__((ext_vector_type(2)));
 typedef double d4v_t __attribute__((ext_vector_type(4)));
-typedef unsigned short us4_t __attribute__((ext_vector_type(4)));
+constexpr int kPipe = 2;       // reduction steps of operands held per wave in k_gemm_f64
+constexpr int kGemmGrid = 512;   // persistent grid of k_gemm_f64: two workgroups per CU
+typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 
 // C[z][r][c] = sum_{k in split z} A[c][k] * B[r][k], A BF16 (upcast exactly),
 // B FP64, FP64 MFMA.  Block = 4 waves, block tile 128 (c) x 64 (r), wave tile
-// 64 x 32 = 4 x 2 MFMA tiles of 16 x 16.  Within a reduction step of 16 the
-// lanes of quarter q take the 4 consecutive indices 4q..4q+3 (one 8-byte A load,
-// one 32-byte B load per tile) and MFMA s combines index 4q+s of every quarter.
-//
-// Row compaction: with rowmap != NULL only the first *nrow rows are computed,
-// local row l reading B row rowmap[l] and writing C row rowmap[l]; r tiles
-// past *nrow exit at once.  Rows of finished nodes thus cost nothing.
-// The split count may also come from the device (ksp != NULL): the grid is
-// sized for the largest count and the groups past MT * (*ksp) exit.
-__global__ __launch_bounds__(256) void k_gemm_f64(const uint16_t *__restrict__ A, int64_t lda,
-                                                  const double *__restrict__ B, int64_t ldb, double *__restrict__ C,
-                                                  int64_t Mc, int64_t Nr, int64_t K, int MT, int NT, int KS,
-                                                  const int32_t *__restrict__ active,
-                                                  const int32_t *__restrict__ rowmap,
-                                                  const int32_t *__restrict__ nrow,
-                                                  const int32_t *__restrict__ ksp) {
-  if (active && *active == 0) return;
-  if (ksp) KS = *ksp;
-  const int64_t Kc = K / KS;
-  const int b = blockIdx.x;
-  const int x = b & 7, qq = b >> 3;
-  const int g = qq / NT, nt = qq - g * NT;
-  const int G = g * 8 + x;
-  if (G >= MT * KS) return;
-  const int mt = G % MT, z = G / MT;
+// 64 x 32 = 4 x 2 MFMA tiles of 16 x 16.  The reduction runs in steps of 32:
+// the lanes of quarter q own the 8 consecutive indices 8q .. 8q+7 of a step
+// (one 16-byte A load per tile, four 16-byte B loads per tile), so a wave
+// reads 64 contiguous bytes of each A row per step and the next step reads the
+// rest of the same cache line; MFMA s of the step combines index 8q + s of
+// every quarter.  Operands are loaded kPipe - 1 steps ahead of the MFMAs.
+__device__ __forceinline__ void gemm_tile(const uint16_t *__restrict__ A, int64_t lda, const double *__restrict__ B,
+                                          int64_t ldb, double *__restrict__ C, int64_t Mc, int64_t Nr, int64_t Kc,
+                                          int mt, int z, int nt, int nr, const int32_t *__restrict__ rowmap) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane >> 4, rr = lane & 15;
   const int64_t c0 = (int64_t)mt * 128 + (w & 1) * 64;
   const int64_t r0 = (int64_t)nt * 64 + (w >> 1) * 32;
-  const int64_t k0 = (int64_t)z * Kc + 4 * q;
+  const int64_t k0 = (int64_t)z * Kc + 8 * q;
   // B row of each of the lane's two r positions, and the C row it is stored
   // to (-1: past the compacted rows, read a valid row and store nothing)
   int64_t brow[2], orow[2];
-  if (rowmap) {
-    const int nr = *nrow;
-    if ((int64_t)nt * 64 >= nr) return;  // so nr >= 1 below
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
-      const int64_t l = r0 + 16 * u + rr;
+  for (int u = 0; u < 2; u++) {
+    const int64_t l = r0 + 16 * u + rr;
+    if (rowmap) {
       orow[u] = l < nr ? rowmap[l] : -1;
       brow[u] = l < nr ? orow[u] : rowmap[0];
+    } else {
+      orow[u] = brow[u] = l;
     }
-  } else {
-#pragma unroll
-    for (int u = 0; u < 2; u++) orow[u] = brow[u] = r0 + 16 * u + rr;
   }
   const uint16_t *pa[4];
   const double *pb[2];
@@ -85,27 +68,41 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const uint16_t *__restrict__ A
   for (int t = 0; t < 4; t++)
 #pragma unroll
     for (int u = 0; u < 2; u++) acc[t][u] = d4v_t{0.0, 0.0, 0.0, 0.0};
-  for (int64_t kk = 0; kk < Kc; kk += 16) {
-    us4_t ar[4];
-    d2v_t br[2][2];
+  const int64_t nsteps = Kc / 32;
+  us8_t ar[kPipe][4];
+  d2v_t br[kPipe][2][4];
+  auto load = [&](int64_t st, us8_t (&a)[4], d2v_t (&bb)[2][4]) {
+    const int64_t kk = st * 32;
 #pragma unroll
-    for (int t = 0; t < 4; t++) ar[t] = *reinterpret_cast<const us4_t *>(pa[t] + kk);
+    for (int t = 0; t < 4; t++) a[t] = *reinterpret_cast<const us8_t *>(pa[t] + kk);
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
-      br[u][0] = *reinterpret_cast<const d2v_t *>(pb[u] + kk);
-      br[u][1] = *reinterpret_cast<const d2v_t *>(pb[u] + kk + 2);
-    }
+    for (int u = 0; u < 2; u++)
 #pragma unroll
-    for (int s4 = 0; s4 < 4; s4++) {
+      for (int v = 0; v < 4; v++) bb[u][v] = *reinterpret_cast<const d2v_t *>(pb[u] + kk + 2 * v);
+  };
+  auto step = [&](const us8_t (&a)[4], const d2v_t (&bb)[2][4]) {
+#pragma unroll
+    for (int s8 = 0; s8 < 8; s8++) {
       double av[4], bv[2];
 #pragma unroll
-      for (int t = 0; t < 4; t++) av[t] = (double)__uint_as_float(((unsigned int)ar[t][s4]) << 16);
+      for (int t = 0; t < 4; t++) av[t] = (double)__uint_as_float(((unsigned int)a[t][s8]) << 16);
 #pragma unroll
-      for (int u = 0; u < 2; u++) bv[u] = br[u][s4 >> 1][s4 & 1];
+      for (int u = 0; u < 2; u++) bv[u] = bb[u][s8 >> 1][s8 & 1];
 #pragma unroll
       for (int t = 0; t < 4; t++)
 #pragma unroll
         for (int u = 0; u < 2; u++) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < kPipe - 1; d++)
+    if (d < nsteps) load(d, ar[d], br[d]);
+  for (int64_t s0 = 0; s0 < nsteps; s0 += kPipe) {
+#pragma unroll
+    for (int d = 0; d < kPipe; d++) {
+      const int64_t sp = s0 + d + kPipe - 1;
+      if (sp < nsteps) load(sp, ar[(d + kPipe - 1) % kPipe], br[(d + kPipe - 1) % kPipe]);
+      if (s0 + d < nsteps) step(ar[d], br[d]);
     }
   }
   // MFMA output: register v of lane l is (c = 4v + l/16, r = l%16)
@@ -120,15 +117,60 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const uint16_t *__restrict__ A
   }
 }
 
+// Persistent launch: the grid (at most two workgroups per CU) walks the tile
+// list.  Row compaction: with rowmap != NULL only the first *nrow rows are
+// computed, local row l reading B row rowmap[l] and writing C row rowmap[l],
+// so rows of finished nodes cost nothing.  The split count may come from the
+// device (ksp != NULL).  Tile order is XCD-aware: consecutive workgroups go
+// round-robin over the 8 XCDs, item i goes to workgroup i mod grid (a
+// multiple of 8), and item i is (c tile, split) group (i / 8 / nta) * 8 + i % 8,
+// r tile (i / 8) % nta: the r tiles sharing an A tile run on one XCD and read
+// it from HBM once per XCD L2.
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const uint16_t *__restrict__ A, int64_t lda,
+                                                  const double *__restrict__ B, int64_t ldb, double *__restrict__ C,
+                                                  int64_t Mc, int64_t Nr, int64_t K, int MT, int NT, int KS,
+                                                  const int32_t *__restrict__ active,
+                                                  const int32_t *__restrict__ rowmap,
+                                                  const int32_t *__restrict__ nrow,
+                                                  const int32_t *__restrict__ ksp,
+                                                  int32_t *__restrict__ counter) {
+  if (active && *active == 0) return;
+  if (ksp) KS = *ksp;
+  const int nr = rowmap ? *nrow : (int)Nr;
+  const int nta = rowmap ? (nr + 63) / 64 : NT;
+  const int groups = MT * KS;
+  const int nitems = ((groups + 7) / 8) * 8 * nta;
+  const int64_t Kc = K / KS;
+  __shared__ int next;
+  // items in order: the workgroup's own first item, then (with a counter)
+  // whichever item is next when it finishes
+  int item = blockIdx.x;
+  while (item < nitems) {
+    const int x = item & 7, qq = item >> 3;
+    const int g = qq / nta, nt = qq - g * nta;
+    const int G = g * 8 + x;
+    if (G < groups) gemm_tile(A, lda, B, ldb, C, Mc, Nr, Kc, G % MT, G / MT, nt, nr, rowmap);
+    if (counter) {
+      __syncthreads();
+      if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(counter, 1);
+      __syncthreads();
+      item = next;
+    } else {
+      item += gridDim.x;
+    }
+  }
+}
+
 // Compacted row list of the batch: rowmap[0..nrow) = the slots of the nodes
 // that are still iterating, in increasing order, and the reduction split of
-// each GEMM for this iteration: the base split times the largest power of two
-// f <= min(fmax, NT / ceil(nrow / 64)), so the number of busy workgroups stays
-// near that of the full batch.  sp = {nrow, forward split, transpose split}.
-// One block of 256 threads.
+// each GEMM for this iteration: the base split times the factor the autotuner
+// chose for this many active 64-row tiles (ftab[0][nta], ftab[1][nta]).
+// sp = {nrow, forward split, transpose split, -}; the two tile counters of the
+// GEMMs are reset.  One block of 256 threads.
 __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restrict__ S, int m,
                                                       int32_t *__restrict__ rowmap, int32_t *__restrict__ sp,
-                                                      int NT, int ksf, int fmaxf, int kst, int fmaxt) {
+                                                      int32_t *__restrict__ counters, const int32_t *__restrict__ ftab,
+                                                      int ksf, int kst) {
   __shared__ int base;
   __shared__ int wsum[4];
   if (threadIdx.x == 0) base = 0;
@@ -149,14 +191,13 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int nta = (base + 63) / 64;
-    const int room = nta > 0 ? NT / nta : 1;
-    int ff = 1, ft = 1;
-    while (2 * ff <= fmaxf && 2 * ff <= room) ff *= 2;
-    while (2 * ft <= fmaxt && 2 * ft <= room) ft *= 2;
+    int nta = (base + 63) / 64;
+    if (nta >= kTuneMax) nta = kTuneMax - 1;
     sp[0] = base;
-    sp[1] = ksf * ff;
-    sp[2] = kst * ft;
+    sp[1] = ksf * ftab[nta];
+    sp[2] = kst * ftab[kTuneMax + nta];
+    counters[0] = 0;
+    counters[1] = 0;
   }
 }
 
@@ -221,19 +262,19 @@ __global__ void k_batch_zeta(const double *__restrict__ R, int64_t n, int node, 
 
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
                            int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
-                           const int32_t *nrow, const int32_t *ksp, int ks_max, hipStream_t s) {
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s) {
   const int MT = (int)(Mc / 128), NT = (int)(Nr / 64);
   const int groups = MT * (ksp ? ks_max : KS);
-  const int gpad = (groups + 7) / 8 * 8;
-  k_gemm_f64<<<(unsigned)(gpad * NT), 256, 0, s>>>(A, lda, B, ldb, C, Mc, Nr, K, MT, NT, KS, active, rowmap, nrow,
-                                                    ksp);
+  const int items = (groups + 7) / 8 * 8 * NT;
+  const int grid = items < kGemmGrid ? (items + 7) / 8 * 8 : kGemmGrid;
+  k_gemm_f64<<<(unsigned)grid, 256, 0, s>>>(A, lda, B, ldb, C, Mc, Nr, K, MT, NT, KS, active, rowmap, nrow, ksp,
+                                            counter);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int ksf, int fmaxf, int kst,
-                               int fmaxt, hipStream_t s) {
-  const int NT = (m + 63) / 64;
-  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, NT, ksf, fmaxf, kst, fmaxt);
+hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
+                               const int32_t *ftab, int ksf, int kst, hipStream_t s) {
+  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst);
   return hipGetLastError();
 }
 

@@ -112,10 +112,15 @@ hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, in
                               double *R, double *fsum, const NodeState *S, hipStream_t s);
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
                            int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
-                           const int32_t *nrow, const int32_t *ksp, int ks_max, hipStream_t s);
-hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int ksf, int fmaxf, int kst,
-                               int fmaxt, hipStream_t s);
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
+hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
+                               const int32_t *ftab, int ksf, int kst, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
+// batched-GEMM autotuner: split factors per count of active 64-row tiles
+constexpr int kTuneMax = 64;            // table entries (row-tile counts 1 .. 63)
+constexpr int kTuneReps = 2;            // timed launches per candidate
+constexpr double kTunePlaneBW = 5.0e12; // B/s assumed for reading the split partial planes
+
 // learned warm start
 constexpr int kMlpPartStride = 4804;  // floats per block partial: 4801 gradient entries, loss, pad
 struct FeatScalars {

@@ -105,7 +105,8 @@ def test_batch_full_size_256_nodes(dev):
     ctx.close()
 
 
-@pytest.mark.parametrize("Mc,Nr,K,KS", [(128, 64, 16, 1), (256, 192, 1024, 2), (1024, 512, 4096, 4), (384, 128, 96, 3)])
+@pytest.mark.parametrize("Mc,Nr,K,KS", [(128, 64, 32, 1), (256, 192, 1024, 2), (1024, 512, 4096, 4), (384, 128, 96, 3),
+                                         (128, 64, 160, 5)])
 def test_gemm_matches_float64_reference(dev, Mc, Nr, K, KS):
     """FP64 MFMA product over a BF16 A: within FP64 summation error of the
     exact product, |C - C_ref| <= 2 K 2^-53 (|B| |A|^T) per split."""
@@ -133,4 +134,4 @@ def test_gemm_rejects_bad_shapes(dev):
         pr.gemm(A, B)           # Mc not a multiple of 128
     A = torch.zeros(128, 64, dtype=torch.bfloat16, device=dev)
     with pytest.raises(pr.PrError):
-        pr.gemm(A, B, KS=3)     # K not a multiple of 16 * KS
+        pr.gemm(A, B, KS=3)     # K not a multiple of 32 * KS
