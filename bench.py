@@ -21,6 +21,7 @@ roofline.
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
   python bench.py --learned [--pairs N] [--epochs E]   # learned warm start experiment
+  python bench.py --e1               # g_N and prox evaluation times at the paper's microbenchmark shapes
 """
 import argparse
 import hashlib
@@ -259,6 +260,38 @@ def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
     ctx.close()
 
 
+def e1_bench(reps=20, seeds=5):
+    """Times of one prox_{rho g_N}(gamma) evaluation and one g_N evaluation at
+    beta = prox(gamma) on the GPU, at the root node, for gamma ~ N(0, I_p),
+    p = 100 * 2^i (i = 0..10), k = 10, M = 1, rho = 1 (the paper's
+    microbenchmark of its prox and g_N subroutines); mean over 5 seeds of the
+    HIP-event time per launch.  The paper reports ~1e-2 s (prox) and ~1e-3 s
+    (g_N) at p = 102,400 for its CPU implementation."""
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    dev = torch.device("cuda:0")
+    rows = []
+    for i in range(11):
+        p = 100 * 2 ** i
+        tp, tg = [], []
+        st = torch.zeros(p, dtype=torch.int8, device=dev)
+        for seed in range(seeds):
+            gamma = torch.from_numpy(np.random.default_rng(seed).standard_normal(p)).to(dev)
+            _, msp, msg = pr.time_prox(gamma, 1.0, 10, 1.0, st, reps=reps)
+            tp.append(msp)
+            tg.append(msg)
+        rows.append({"p": p, "prox_ms": round(float(np.mean(tp)), 4), "prox_ms_std": round(float(np.std(tp)), 4),
+                     "g_ms": round(float(np.mean(tg)), 4), "g_ms_std": round(float(np.std(tg)), 4)})
+        print(json.dumps({"progress": "e1", **rows[-1]}), flush=True)
+    big = rows[-1]
+    print(json.dumps({"metric": "prox and g_N evaluation time, root node, gamma ~ N(0, I_p), k=10, M=1, rho=1",
+                      "unit": "ms per evaluation (HIP events, mean of 5 seeds)", "rows": rows,
+                      "paper_cpu_p102400": {"prox_s": 1e-2, "g_s": 1e-3},
+                      "speedup_vs_paper_cpu_p102400": {"prox": round(1e-2 / (big["prox_ms"] * 1e-3), 1),
+                                                       "g": round(1e-3 / (big["g_ms"] * 1e-3), 1)}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +301,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
     ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
+    ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args()
@@ -280,6 +314,9 @@ def main():
         return
     if args.learned:
         learned_bench(args.pairs, args.epochs)
+        return
+    if args.e1:
+        e1_bench()
         return
     import torch
     dev = torch.device("cuda:0")

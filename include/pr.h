@@ -164,6 +164,14 @@ int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
 int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *opts,
                    const double *B0, double *B_out, pr_result *out);
 
+/* Time the prox of g_N (as pr_prox) and the value g_N at its output (as
+ * pr_regularizer) with HIP events on `stream`: one untimed launch, then `reps`
+ * back-to-back launches of each; *ms_prox, *ms_g = elapsed / reps.  out
+ * (device, p) receives prox_{rho g_N}(v).  The workspace is allocated before
+ * and freed after the timed launches.  Arguments and errors as pr_prox. */
+int pr_time_prox(void *stream, const double *v, int64_t p, double rho, int32_t k, double M, const int8_t *status,
+                 double *out, int32_t reps, double *ms_prox, double *ms_g);
+
 /* Time `reps` back-to-back launches of the X^T r kernel (the solver's
  * dominant kernel, same launch configuration) with HIP events on the
  * context stream; *ms_avg = elapsed / reps.  r device n, h device p. */

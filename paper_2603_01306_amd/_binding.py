@@ -20,7 +20,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
+           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
            "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
@@ -94,6 +94,9 @@ def load():
         L.pr_solve_batch.restype = ctypes.c_int
         L.pr_solve_batch.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, ctypes.POINTER(PrOpts),
                                      P, P, ctypes.POINTER(PrResult)]
+        L.pr_time_prox.restype = ctypes.c_int
+        L.pr_time_prox.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double, P, P,
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.pr_batch_tuning.restype = ctypes.c_int
         L.pr_batch_tuning.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.pr_time_batch_gemm.restype = ctypes.c_int
@@ -347,6 +350,18 @@ def prox(v, rho, k, M, status):
     _check(load().pr_prox(_stream_ptr(), _dptr(v.contiguous()), v.numel(), float(rho), int(k), float(M),
                           _dptr(status.contiguous()), _dptr(out)), "pr_prox")
     return out
+
+
+def time_prox(v, rho, k, M, status, reps=20):
+    """(prox output, ms per prox launch, ms per g_N launch) on the device."""
+    import torch
+    out = torch.empty_like(v)
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(load().pr_time_prox(_stream_ptr(), _dptr(v.contiguous()), v.numel(), float(rho), int(k), float(M),
+                               _dptr(status.contiguous()), _dptr(out), int(reps), ctypes.byref(a), ctypes.byref(b)),
+           "pr_time_prox")
+    return out, a.value, b.value
 
 
 def gemm(A, B, KS=1):

@@ -654,6 +654,57 @@ int pr_prox(void *stream, const double *v, int64_t p, double rho, int32_t k, dou
   return e == hipSuccess ? PR_OK : PR_EDEVICE;
 }
 
+int pr_time_prox(void *stream, const double *v, int64_t p, double rho, int32_t k, double M, const int8_t *status,
+                 double *out, int32_t reps, double *ms_prox, double *ms_g) {
+  if (!v || !out || !status || p < 1 || p >= ((int64_t)1 << 31) || !(rho > 0.0) || !isfinite(rho) ||
+      !(M > 0.0) || k < 1 || reps < 1 || !ms_prox || !ms_g)
+    return PR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int8_t> st((size_t)p);
+  PR_TRY(hipMemcpyAsync(st.data(), status, (size_t)p, hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  int64_t n1 = 0, nf = 0;
+  for (int64_t j = 0; j < p; j++) {
+    if (st[(size_t)j] == kOne) n1++;
+    else if (st[(size_t)j] == kFree) nf++;
+    else if (st[(size_t)j] != kZero) return PR_EINVAL;
+  }
+  if (n1 > k) return PR_EINVAL;
+  int64_t kb = (int64_t)k - n1;
+  if (kb > nf) kb = nf;
+  double *abuf = nullptr, *g2 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc((void **)&abuf, sizeof(double) * 3 * p) != hipSuccess) return PR_ENOMEM;
+  if (hipMalloc((void **)&g2, sizeof(double) * 2) != hipSuccess) {
+    (void)hipFree(abuf);
+    return PR_ENOMEM;
+  }
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float ms = 0.0f;
+  // prox: one untimed launch, then `reps` timed ones
+  if (e == hipSuccess) e = launch_prox(v, out, p, rho, (int32_t)kb, M, status, abuf, nullptr, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int32_t i = 0; i < reps && e == hipSuccess; i++) e = launch_prox(v, out, p, rho, (int32_t)kb, M, status, abuf, nullptr, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess) *ms_prox = (double)ms / reps;
+  // g_N at the prox output (a point of dom g_N)
+  if (e == hipSuccess) e = launch_regularizer(out, nullptr, p, (int32_t)kb, M, status, abuf, g2, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int32_t i = 0; i < reps && e == hipSuccess; i++) e = launch_regularizer(out, nullptr, p, (int32_t)kb, M, status, abuf, g2, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess) *ms_g = (double)ms / reps;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(g2);
+  (void)hipFree(abuf);
+  return e == hipSuccess ? PR_OK : PR_EDEVICE;
+}
+
 int pr_regularizer(void *stream, const double *beta, const double *alpha, int64_t p, int32_t k,
                    double M, const int8_t *status, double *g_out, double *gstar_out) {
   if ((!beta && !alpha) || !status || p < 1 || p >= ((int64_t)1 << 31) || !(M > 0.0) || k < 1)

@@ -176,3 +176,22 @@ def test_norm2_matches_oracle_power_iteration(dev):
     lam = np.linalg.eigvalsh(inst.X64() @ inst.X64().T).max()
     assert abs(ctx.norm2() - lam) <= 1e-6 * lam
     ctx.close()
+
+
+@pytest.mark.parametrize("p", [100, 6400, 102400])
+def test_prox_and_g_at_microbenchmark_shapes(dev, p):
+    """The paper's subroutine benchmark: gamma ~ N(0, I_p), root node, k = 10,
+    M = 1, rho = 1; prox within 1e-12 of Algorithm 2 + Moreau (oracle) and
+    g_N at beta = prox(gamma) within 1e-12 of Algorithm 1 (oracle)."""
+    import torch
+    import paper_2603_01306_amd as pr
+    gamma = np.random.default_rng(p).standard_normal(p)
+    st = torch.zeros(p, dtype=torch.int8, device=dev)
+    out, ms_prox, ms_g = pr.time_prox(torch.from_numpy(gamma).to(dev), 1.0, 10, 1.0, st, reps=2)
+    beta = out.cpu().numpy()
+    ref = oracle.prox_g(gamma, 1.0, 10, 1.0)
+    assert np.max(np.abs(beta - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    g_gpu, _ = pr.regularizer(out, None, 10, 1.0, st)
+    g_ref = oracle.g(ref, 10)
+    assert abs(g_gpu - g_ref) <= 1e-12 * max(1.0, abs(g_ref))
+    assert ms_prox > 0 and ms_g > 0
