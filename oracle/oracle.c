@@ -385,6 +385,8 @@ double orc_dual(const void *X, int xdt, const double *y, int64_t n, int64_t p, i
   return v;
 }
 
+enum { ORC_FISTA_GAP = 0, ORC_FISTA = 1, ORC_FISTA_FV = 2, ORC_PGD = 3 };
+
 /* ------------------------------------------------------------ solver */
 
 /* FISTA (fixed step 1/L, Beck-Teboulle momentum) with the duality-gap
@@ -395,14 +397,23 @@ double orc_dual(const void *X, int xdt, const double *y, int64_t n, int64_t p, i
  * satisfy (UB - LB) / |UB| <= tol.  Dynamic termination against an incumbent
  * value (Section 5.3): Psi >= cutoff prunes, Phi <= cutoff branches.
  *
+ * method selects the iteration compared in Section 5.2's convergence study:
+ *   ORC_FISTA_GAP   FISTA with the duality-gap restart (the method above)
+ *   ORC_FISTA       FISTA without restarts
+ *   ORC_FISTA_FV    FISTA restarted whenever Phi increases (function-value
+ *                   restart of O'Donoghue and Candes): t <- 1, y <- x
+ *   ORC_PGD         proximal gradient, x <- prox(x - grad / L) (no momentum)
+ * Every variant evaluates the same bounds and stopping test.
+ *
  * res[0..7] = {LB, UB, rel_gap, L, iters, restarts, status, 0}.
  * trace (optional, length trace_cap) receives Phi - Psi at iterates 0, 1, ...
+ * and phi_trace (optional, same length) Phi at those iterates.
  * zeta_out receives the dual vector that attains LB.
  */
 int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int loss, double lambda2,
               double M, int32_t k, const int8_t *st, double L, double tol, double eta, int64_t max_iter,
               double cutoff, const double *beta0, double *beta_out, double *zeta_out, double *res,
-              double *trace, int64_t trace_cap) {
+              double *trace, int64_t trace_cap, int method, double *phi_trace) {
   int64_t pbar, kbar;
   for (int i = 0; i < 8; i++) res[i] = 0.0;
   if (orc_node_dims(st, p, k, &pbar, &kbar) < 0) {
@@ -445,6 +456,8 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
   double LB = Psi, UB = Phi, gap_ref = Phi - Psi;
   memcpy(zeta_out, zeta, sizeof(double) * (size_t)n);
   if (trace && trace_cap > 0) trace[0] = Phi - Psi;
+  if (phi_trace && trace_cap > 0) phi_trace[0] = Phi;
+  double Phi_prev = Phi;
   int64_t it = 0, restarts = 0;
   int status = ORC_MAXITER;
   double rel = (UB - LB) / fmax(fabs(UB), 1e-300);
@@ -460,7 +473,7 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
     for (int64_t j = 0; j < p; j++) gp[j] = yv[j] - gp[j] / L;
     orc_prox_g(gp, st, p, 2.0 * lambda2 / L, k, M, xn);
     double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-    double mom = (t - 1.0) / tn;
+    double mom = (method == ORC_PGD) ? 0.0 : (t - 1.0) / tn;
     for (int64_t j = 0; j < p; j++) {
       yv[j] = xn[j] + mom * (xn[j] - x[j]);
       x[j] = xn[j];
@@ -474,6 +487,7 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
     if (Phi < UB) UB = Phi;
     double gap = Phi - Psi;
     if (trace && it < trace_cap) trace[it] = gap;
+    if (phi_trace && it < trace_cap) phi_trace[it] = Phi;
     rel = (UB - LB) / fmax(fabs(UB), 1e-300);
     if (rel <= tol) {
       status = ORC_CONVERGED;
@@ -487,12 +501,19 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
       status = ORC_CUTOFF_BRANCH;
       break;
     }
-    if (gap <= gap_ref / eta) {
+    int restart = 0;
+    if (method == ORC_FISTA_GAP && gap <= gap_ref / eta) {
+      gap_ref = gap;
+      restart = 1;
+    } else if (method == ORC_FISTA_FV && Phi > Phi_prev) {
+      restart = 1;
+    }
+    if (restart) {
       memcpy(yv, x, sizeof(double) * (size_t)p);
       t = 1.0;
-      gap_ref = gap;
       restarts++;
     }
+    Phi_prev = Phi;
   }
 #undef ORC_EVAL
   memcpy(beta_out, x, sizeof(double) * (size_t)p);
