@@ -81,6 +81,16 @@ typedef struct {
   int64_t n1;
 } pr_node;
 
+/* Iteration variants (pr_opts.method), as compared in the paper's
+ * convergence study (Section 5.2): FISTA with the duality-gap restart of
+ * Section 3.3 (the method; default), FISTA without restarts, FISTA restarted
+ * whenever Phi increases (function-value restart), proximal gradient.  All
+ * evaluate the same bounds and stopping test. */
+#define PR_FISTA_GAP 0
+#define PR_FISTA 1
+#define PR_FISTA_FV 2
+#define PR_PGD 3
+
 typedef struct {
   double rel_gap_tol; /* stop when (UB - LB) / |UB| <= tol; default 1e-6 */
   double eta;         /* restart factor (> 1); default e^3 */
@@ -88,6 +98,10 @@ typedef struct {
   double L;           /* step 1/L; 0 = 1.01 * loss curvature * ||X||^2 estimate */
   int32_t max_iter;   /* default 100000 */
   int32_t check_every; /* iterations per captured graph launch; default 32 */
+  int32_t method;      /* iteration variant, PR_FISTA_GAP (default) .. PR_PGD */
+  int32_t pad0;
+  double *trace;       /* pr_solve only, optional device array of 2 * (max_iter + 1)
+                          doubles: (Phi, Psi) of iterates 0, 1, ..., iters */
 } pr_opts;
 
 typedef struct {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpr.so")
 PR_OK, PR_EINVAL, PR_EOVERLAP, PR_EDEVICE, PR_ENOMEM = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
+FISTA_GAP, FISTA, FISTA_FV, PGD = 0, 1, 2, 3
 LSQ, LOGISTIC = 0, 1
 F64, F32, BF16 = 0, 1, 2
 
@@ -40,7 +41,8 @@ class PrNode(ctypes.Structure):
 class PrOpts(ctypes.Structure):
     _fields_ = [("rel_gap_tol", ctypes.c_double), ("eta", ctypes.c_double),
                 ("cutoff", ctypes.c_double), ("L", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("pad0", ctypes.c_int32), ("trace", ctypes.c_void_p)]
 
 
 class PrResult(ctypes.Structure):
@@ -151,6 +153,8 @@ def default_opts(**kw):
     for k, v in kw.items():
         if v is None:
             continue
+        if k == "trace":
+            v = v.data_ptr()  # a float64 CUDA tensor of 2 * (max_iter + 1) entries
         setattr(o, k, v)
     return o
 

@@ -151,7 +151,7 @@ int build_status(const pr_node *node, int64_t p, std::vector<int8_t> &st, int64_
 int check_opts(const pr_opts *o) {
   if (!o) return PR_OK;
   if (!(o->rel_gap_tol >= 0.0) || !(o->eta > 1.0) || o->max_iter < 0 || o->check_every < 1 ||
-      !(o->L >= 0.0) || !isfinite(o->L))
+      !(o->L >= 0.0) || !isfinite(o->L) || o->method < kFistaGap || o->method > kPgd)
     return PR_EINVAL;
   return PR_OK;
 }
@@ -422,6 +422,9 @@ void pr_opts_default(pr_opts *o) {
   o->L = 0.0;
   o->max_iter = 100000;
   o->check_every = 32;
+  o->method = PR_FISTA_GAP;
+  o->pad0 = 0;
+  o->trace = nullptr;
 }
 
 const char *pr_strerror(int code) {
@@ -569,6 +572,8 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   prm.tol = opts.rel_gap_tol;
   prm.cutoff = opts.cutoff;
   prm.max_iter = opts.max_iter;
+  prm.method = opts.method;
+  prm.trace = opts.trace;
   PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, c->stream));
   PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
   PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, p, c->stream));
@@ -1067,6 +1072,8 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     pp.tol = opts.rel_gap_tol;
     pp.cutoff = NAN;
     pp.max_iter = opts.max_iter;
+    pp.method = opts.method;
+    pp.trace = nullptr;
     PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
     if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
                                   hipMemcpyDeviceToDevice, s));

@@ -142,6 +142,39 @@ __device__ __forceinline__ double softplus(double z) { return fmax(z, 0.0) + log
 
 __device__ __forceinline__ double fista_next_t(double t) { return 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t)); }
 
+// Restart decision after the evaluation of iterate `it` (gap = Phi - Psi at
+// it, phi_prev = Phi at it - 1): the first iterate always starts an epoch;
+// then the duality-gap restart of Section 3.3 (gap fell by the factor eta
+// since the epoch start), the function-value restart (Phi increased), no
+// restart (plain FISTA), or a restart every step (proximal gradient: zero
+// momentum; not counted as a restart).
+__device__ __forceinline__ int decide_restart(const NodeParams *prm, int it, double gap, double phi, double phi_prev,
+                                              double &gap_ref, int &restarts) {
+  if (it == 0) {
+    gap_ref = gap;
+    return 1;
+  }
+  switch (prm->method) {
+    case kFistaGap:
+      if (gap <= gap_ref / prm->eta) {
+        gap_ref = gap;
+        restarts++;
+        return 1;
+      }
+      return 0;
+    case kFistaFv:
+      if (phi > phi_prev) {
+        restarts++;
+        return 1;
+      }
+      return 0;
+    case kPgd:
+      return 1;
+    default:
+      return 0;
+  }
+}
+
 template <typename T>
 struct XLoad;
 

@@ -17,12 +17,16 @@ enum : int32_t { kF64 = 0, kF32 = 1, kBF16 = 2 };
 enum : int32_t { kConverged = 1, kMaxIter = 2, kInfeasible = 3, kCutoffPrune = 4, kCutoffBranch = 5 };
 
 // Per-node constants, device resident (written by the host before a solve).
+// iteration variants (pr_opts.method)
+enum { kFistaGap = 0, kFista = 1, kFistaFv = 2, kPgd = 3 };
+
 struct NodeParams {
   const int8_t *st;   // status, p entries
   int64_t p, pbar;
   int32_t kbar, loss;
   double lambda2, M, eta, tol, cutoff;  // cutoff NaN = off
-  int32_t max_iter, pad;
+  int32_t max_iter, method;             // method: kFistaGap .. kPgd
+  double *trace;                        // optional: (Phi, Psi) of iterates 0 .. max_iter
 };
 
 // Per-node iteration state, device resident.

@@ -432,6 +432,10 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
 
   if (tid == 0) {
     const int it = S->iter;
+    if (prm->trace && it <= prm->max_iter) {
+      prm->trace[2 * it] = phi;
+      prm->trace[2 * it + 1] = psi;
+    }
     const double gap = phi - psi;
     double lb = S->lb, ub = S->ub;
     int improved = 0;
@@ -462,14 +466,7 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
     double m = 0.0, t = S->t, gap_ref = S->gap_ref;
     int restart = 0, restarts = S->restarts;
     if (!done) {
-      if (it == 0) {
-        restart = 1;
-        gap_ref = gap;
-      } else if (gap <= gap_ref / prm->eta) {
-        restart = 1;
-        gap_ref = gap;
-        restarts++;
-      }
+      restart = decide_restart(prm, it, gap, phi, S->phi, gap_ref, restarts);
       if (restart) {
         m = 0.0;
         t = 1.0;
@@ -1039,6 +1036,10 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const double phi = S->indom ? Fk + 2.0 * lam2 * S->gval : INFINITY;
   if (tid == 0) {
     const int it = S->iter;
+    if (prm->trace && it <= prm->max_iter) {
+      prm->trace[2 * it] = phi;
+      prm->trace[2 * it + 1] = psi;
+    }
     const double gap = phi - psi;
     double lb = S->lb, ub = S->ub;
     int improved = 0, ub_improved = 0;
@@ -1068,14 +1069,7 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     double m = 0.0, t = S->t, gap_ref = S->gap_ref;
     int restart = 0, restarts = S->restarts;
     if (!done) {
-      if (it == 0) {
-        restart = 1;
-        gap_ref = gap;
-      } else if (gap <= gap_ref / prm->eta) {
-        restart = 1;
-        gap_ref = gap;
-        restarts++;
-      }
+      restart = decide_restart(prm, it, gap, phi, S->phi, gap_ref, restarts);
       if (restart) {
         m = 0.0;
         t = 1.0;
@@ -1283,6 +1277,10 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   const double gap = phi - psi;
   if (tid == 0) {
     const int it = S->iter;
+    if (prm->trace && it <= prm->max_iter) {
+      prm->trace[2 * it] = phi;
+      prm->trace[2 * it + 1] = psi;
+    }
     double lb = S->lb, ub = S->ub;
     if (psi > lb) lb = psi;
     if (phi < ub) ub = phi;
@@ -1300,14 +1298,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     double m = 0.0, t = S->t, gap_ref = S->gap_ref;
     int restart = 0, restarts = S->restarts;
     if (!done) {
-      if (it == 0) {
-        restart = 1;
-        gap_ref = gap;
-      } else if (gap <= gap_ref / prm->eta) {
-        restart = 1;
-        gap_ref = gap;
-        restarts++;
-      }
+      restart = decide_restart(prm, it, gap, phi, S->phi, gap_ref, restarts);
       if (restart) {
         m = 0.0;
         t = 1.0;

@@ -37,9 +37,27 @@ def test_strerror_and_defaults_without_device():
     assert o.rel_gap_tol == 1e-6 and abs(o.eta - 20.085536923187668) < 1e-12 and o.max_iter > 0
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and every field offset of the header's structs, as a C compiler
+    lays them out, equal the ctypes mirrors of the binding."""
+    import subprocess
     import paper_2603_01306_amd._binding as b
-    assert ctypes.sizeof(b.PrProblem) == 40
-    assert ctypes.sizeof(b.PrNode) == 56
-    assert ctypes.sizeof(b.PrOpts) == 40
-    assert ctypes.sizeof(b.PrResult) == 48
+    structs = {"pr_problem": b.PrProblem, "pr_node": b.PrNode, "pr_opts": b.PrOpts, "pr_result": b.PrResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pr.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, f, v = line.split()
+        got[(a, f)] = int(v)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
