@@ -22,6 +22,7 @@ roofline.
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
   python bench.py --learned [--pairs N] [--epochs E]   # learned warm start experiment
   python bench.py --e1               # g_N and prox evaluation times at the paper's microbenchmark shapes
+  python bench.py --e3               # convergence of the iteration variants (gap restart vs others)
 """
 import argparse
 import hashlib
@@ -292,6 +293,60 @@ def e1_bench(reps=20, seeds=5):
                                                        "g": round(1e-3 / (big["g_ms"] * 1e-3), 1)}}), flush=True)
 
 
+def e3_bench(max_iter=20000):
+    """Convergence of the iteration variants on the bench workload (and the
+    logistic workload): FISTA with the duality-gap restart at eta = e^3 and
+    eta = e (the paper's convergence-study setting), FISTA without restart,
+    FISTA with function-value restart, proximal gradient.  Per-iterate
+    (Phi, Psi) traces from the GPU; reported: iterations to reach relative
+    gaps 1e-2 .. 1e-6 (best-so-far bounds) and the fitted log-gap slope."""
+    import math
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import config_instance, CONFIGS
+    dev = torch.device("cuda:0")
+    out = {"metric": "iterations to relative duality gap, by iteration variant", "workloads": {}}
+    for wl, loss in ((WORKLOAD, pr.LSQ), ("logistic_root_n32768_p16384_f32", pr.LOGISTIC)):
+        cfg = CONFIGS[wl]
+        inst = config_instance(wl)
+        ctx = pr.Context(torch.from_numpy(inst.Xcm).to(dev), torch.from_numpy(inst.y).to(dev), loss)
+        node = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
+        cap = max_iter if loss == pr.LSQ else max_iter // 4
+        res = {}
+        for name, meth, eta in (("fista_gap_restart_e3", pr.FISTA_GAP, math.exp(3.0)),
+                                ("fista_gap_restart_e", pr.FISTA_GAP, math.e),
+                                ("fista_no_restart", pr.FISTA, math.exp(3.0)),
+                                ("fista_function_value_restart", pr.FISTA_FV, math.exp(3.0)),
+                                ("proximal_gradient", pr.PGD, math.exp(3.0))):
+            tr = torch.full((2 * (cap + 1),), float("nan"), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"], max_iter=cap, method=meth, eta=eta, trace=tr)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t = tr.cpu().numpy().reshape(-1, 2)[: r["iters"] + 1]
+            phi, psi = t[:, 0], t[:, 1]
+            ub = np.minimum.accumulate(np.where(np.isfinite(phi), phi, np.inf))
+            lb = np.maximum.accumulate(psi)
+            rel = (ub - lb) / np.abs(ub)
+            reach = {}
+            for lvl in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+                hit = np.flatnonzero(rel <= lvl)
+                reach[f"{lvl:.0e}"] = int(hit[0]) if hit.size else None
+            ok = np.isfinite(rel) & (rel > 0)
+            k = np.flatnonzero(ok)
+            k = k[k >= k.size // 5] if k.size > 10 else k
+            slope = float(np.polyfit(k, np.log10(rel[k]), 1)[0]) if k.size > 2 else None
+            res[name] = {"status": r["status"], "iters": r["iters"], "restarts": r["restarts"], "seconds": round(dt, 3),
+                         "final_rel_gap": r["rel_gap"], "iterations_to_rel_gap": reach,
+                         "log10_gap_per_iteration": None if slope is None else round(slope, 5)}
+            print(json.dumps({"progress": "e3", "workload": wl, "variant": name, **res[name]}), flush=True)
+        out["workloads"][wl] = {"cap": cap, "variants": res}
+        ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +357,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
     ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
+    ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args()
@@ -317,6 +373,9 @@ def main():
         return
     if args.e1:
         e1_bench()
+        return
+    if args.e3:
+        e3_bench()
         return
     import torch
     dev = torch.device("cuda:0")
