@@ -173,8 +173,16 @@ int pr_dual_bound(pr_ctx *ctx, const pr_node *node, const double *zeta, const do
 int pr_gemv(pr_ctx *ctx, const double *b, double *u);
 int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
 
-/* Solve m nodes that share X (m <= max_batch).  B0 device p*m (column i =
- * warm start of node i) or NULL; B_out device p*m or NULL; out host m. */
+/* Solve m nodes that share X (m <= max_batch), each as pr_solve would:
+ * same bounds, stopping test, iteration variant and dynamic termination
+ * (cutoff).  With a BF16 least-squares problem (n, p multiples of 128) the
+ * nodes iterate together on FP64 MFMA products; every stopped node's Phi and
+ * Psi are then recomputed over the stored X, and a node whose decision
+ * (converged / prune / branch) is not confirmed continues alone on the
+ * pr_solve path.  Other problems run pr_solve node by node.  Traces
+ * (opts->trace) are not recorded.
+ *   B0 device m x p (row i = warm start of node i) or NULL; B_out device
+ *   m x p (row i receives node i's iterate) or NULL; out host m. */
 int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *opts,
                    const double *B0, double *B_out, pr_result *out);
 
@@ -218,6 +226,44 @@ int pr_time_batch_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms_fwd, dou
  * requirement (nothing is launched). */
 int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
             int64_t Nr, int64_t K, int32_t KS);
+
+/* ---- Branch and bound -------------------------------------------------
+ * Best-first branch and bound for problem (1) with least-squares loss, built
+ * on pr_solve_batch: every node bound is the certified FP64 bound of its
+ * perspective relaxation, solved with dynamic termination against the
+ * incumbent (Section 5.3).  Branching on the free coordinate with the largest
+ * |beta_j| of the node's relaxation solution (children: fixed to one, fixed to
+ * zero), children warm-started from the parent's solution.  Incumbents: ridge
+ * fit on J1 + the kbar largest free |beta_j| of each relaxation solution,
+ * clipped to the box (supports of at most 32 coordinates). */
+#define PR_BNB_OPTIMAL 1     /* (UB - LB) / |UB| <= rel_gap_tol */
+#define PR_BNB_NODE_LIMIT 2
+#define PR_BNB_TIME_LIMIT 3
+
+typedef struct {
+  double rel_gap_tol;   /* stop when (UB - LB) / |UB| <= this; default 1e-4 */
+  double time_limit_s;  /* wall-clock limit; default +inf */
+  int32_t max_nodes;    /* node relaxations solved at most; default 100000 */
+  int32_t batch;        /* nodes per pr_solve_batch call; 0 = the context's max_batch */
+  pr_opts node_opts;    /* options of every node relaxation (cutoff and trace are set by pr_bnb) */
+} pr_bnb_opts;
+
+typedef struct {
+  double lower_bound;   /* certified: min over open nodes (= upper_bound when the tree is closed) */
+  double upper_bound;   /* objective of the incumbent (a feasible k-sparse point) */
+  double rel_gap;
+  double seconds;       /* wall clock of the call */
+  double relaxation_seconds; /* of which inside pr_solve_batch */
+  int64_t nodes_solved, nodes_pruned, nodes_open;
+  int32_t max_depth, status; /* PR_BNB_OPTIMAL / PR_BNB_NODE_LIMIT / PR_BNB_TIME_LIMIT */
+} pr_bnb_result;
+
+void pr_bnb_opts_default(pr_bnb_opts *opts);
+
+/* Run branch and bound from `root` (its J0 / J1 are kept in every node).
+ * beta_best: device p or NULL, receives the incumbent.  out: host.  PR_EINVAL
+ * for a logistic problem or bad options; node errors as pr_solve. */
+int pr_bnb(pr_ctx *ctx, const pr_node *root, const pr_bnb_opts *opts, double *beta_best, pr_bnb_result *out);
 
 /* ---- Learned warm start for child nodes --------------------------------
  * Not part of the paper's method (which warm-starts a child from its

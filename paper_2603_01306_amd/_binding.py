@@ -16,13 +16,14 @@ PR_OK, PR_EINVAL, PR_EOVERLAP, PR_EDEVICE, PR_ENOMEM = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
 FISTA_GAP, FISTA, FISTA_FV, PGD = 0, 1, 2, 3
+BNB_OPTIMAL, BNB_NODE_LIMIT, BNB_TIME_LIMIT = 1, 2, 3
 LSQ, LOGISTIC = 0, 1
 F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
            "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
-           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_strerror"]
+           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
 
@@ -43,6 +44,18 @@ class PrOpts(ctypes.Structure):
                 ("cutoff", ctypes.c_double), ("L", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("pad0", ctypes.c_int32), ("trace", ctypes.c_void_p)]
+
+
+class PrBnbOpts(ctypes.Structure):
+    _fields_ = [("rel_gap_tol", ctypes.c_double), ("time_limit_s", ctypes.c_double), ("max_nodes", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("node_opts", PrOpts)]
+
+
+class PrBnbResult(ctypes.Structure):
+    _fields_ = [("lower_bound", ctypes.c_double), ("upper_bound", ctypes.c_double), ("rel_gap", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("relaxation_seconds", ctypes.c_double),
+                ("nodes_solved", ctypes.c_int64), ("nodes_pruned", ctypes.c_int64), ("nodes_open", ctypes.c_int64),
+                ("max_depth", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
 class PrResult(ctypes.Structure):
@@ -121,6 +134,10 @@ def load():
         L.pr_mlp_warm_start.restype = ctypes.c_int
         L.pr_mlp_warm_start.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, P, P, P,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+        L.pr_bnb_opts_default.restype = None
+        L.pr_bnb_opts_default.argtypes = [ctypes.POINTER(PrBnbOpts)]
+        L.pr_bnb.restype = ctypes.c_int
+        L.pr_bnb.argtypes = [P, ctypes.POINTER(PrNode), ctypes.POINTER(PrBnbOpts), P, ctypes.POINTER(PrBnbResult)]
         L.pr_strerror.restype = ctypes.c_char_p
         L.pr_strerror.argtypes = [ctypes.c_int]
         _lib = L
@@ -285,6 +302,22 @@ class Context:
         _check(load().pr_time_batch_gemm(self.h, int(m), int(reps), ctypes.byref(a), ctypes.byref(b)),
                "pr_time_batch_gemm")
         return a.value, b.value
+
+    def bnb(self, root, node_opts=None, **opts):
+        """Branch and bound from `root`; returns (result dict, incumbent (p,) float64)."""
+        import torch
+        o = PrBnbOpts()
+        load().pr_bnb_opts_default(ctypes.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        if node_opts:
+            o.node_opts = default_opts(**node_opts)
+        beta = torch.zeros(self.p, dtype=torch.float64, device=self.X.device)
+        res = PrBnbResult()
+        nd = root.c()
+        _check(load().pr_bnb(self.h, ctypes.byref(nd), ctypes.byref(o), _dptr(beta), ctypes.byref(res)), "pr_bnb")
+        out = {f: getattr(res, f) for f, _ in PrBnbResult._fields_}
+        return out, beta
 
     def mlp_features(self, nodes, Bparent, Bchild=None):
         """Feature rows (m*p, 8) bfloat16 of child nodes from their parents'

@@ -113,9 +113,11 @@ void free_ctx(pr_ctx *c) {
   delete c;
 }
 
+}  // namespace
+
 // Validate a node and build its status vector.  Returns PR_OK, or an error;
 // *infeasible is set when |J1| > k.
-int build_status(const pr_node *node, int64_t p, std::vector<int8_t> &st, int64_t &n1, int64_t &pbar,
+int pr::build_status(const pr_node *node, int64_t p, std::vector<int8_t> &st, int64_t &n1, int64_t &pbar,
                  int32_t &kbar, bool &infeasible) {
   if (!node) return PR_EINVAL;
   if (node->k < 1 || !(node->lambda2 > 0.0) || !isfinite(node->lambda2) || !(node->M > 0.0))
@@ -147,6 +149,12 @@ int build_status(const pr_node *node, int64_t p, std::vector<int8_t> &st, int64_
   kbar = (int32_t)kb;
   return PR_OK;
 }
+
+const Problem &pr::ctx_problem(const pr_ctx *c) { return c->P; }
+hipStream_t pr::ctx_stream(const pr_ctx *c) { return c->stream; }
+int32_t pr::ctx_max_batch(const pr_ctx *c) { return c->max_batch; }
+
+namespace {
 
 int check_opts(const pr_opts *o) {
   if (!o) return PR_OK;
@@ -1029,7 +1037,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (rc != PR_OK) return rc;
     infeas[(size_t)i] = inf;
   }
-  if (!c->batch_ok || !isnan(opts.cutoff)) {
+  if (!c->batch_ok) {
     for (int32_t i = 0; i < m; i++) {
       int rc = pr_solve(c, &nodes[i], &opts, B0 ? B0 + (int64_t)i * p : nullptr,
                         B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);
@@ -1070,7 +1078,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     pp.M = nodes[i].M;
     pp.eta = opts.eta;
     pp.tol = opts.rel_gap_tol;
-    pp.cutoff = NAN;
+    pp.cutoff = opts.cutoff;
     pp.max_iter = opts.max_iter;
     pp.method = opts.method;
     pp.trace = nullptr;
@@ -1108,12 +1116,16 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   }
   PR_TRY(hipStreamSynchronize(s));
   PR_TRY(hipMemcpy(c->h_bstate, c->d_bstate, sizeof(NodeState) * mb, hipMemcpyDeviceToHost));
-  // FP64 certification of every node over the stored X, at the iterate whose
-  // gap passed; nodes that do not certify continue on the single-node path.
+  // FP64 certification of every node over the stored X, at the iterate that
+  // stopped it: the decision of the batched step (converged, prune, branch)
+  // stands if Phi(x) and Psi(zeta) recomputed over X confirm it; otherwise the
+  // node continues on the single-node path.  A node stopped by the iteration
+  // limit reports its (valid) recomputed bounds.
   for (int32_t q = 0; q < mb; q++) {
     const int32_t i = slot_of[(size_t)q];
     const NodeState &hs = c->h_bstate[q];
     double *xq = c->bxbest + (int64_t)q * p;
+    const int st = hs.done ? hs.status : kMaxIter;
     if (!hs.done) {
       // the graph loop stopped at the iteration limit before this node did
       PR_TRY(hipMemcpyAsync(xq, (hs.parity ? c->bx1 : c->bx0) + (int64_t)q * p, sizeof(double) * p,
@@ -1126,15 +1138,20 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     rc = pr_dual_bound(c, &nodes[i], c->B.zbest, xq, &lb, &ub);
     if (rc != PR_OK) return rc;
     const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
+    bool confirmed = false;
+    if (st == kConverged) confirmed = rel <= opts.rel_gap_tol;
+    else if (st == kCutoffPrune) confirmed = lb >= opts.cutoff;
+    else if (st == kCutoffBranch) confirmed = ub <= opts.cutoff;
+    else confirmed = true;  // iteration limit
     pr_result &r = out[i];
-    if (rel <= opts.rel_gap_tol) {
+    if (confirmed) {
       r.lower_bound = lb;
       r.primal = ub;
       r.rel_gap = rel;
       r.L = L;
       r.iters = hs.iter;
       r.restarts = hs.restarts;
-      r.status = PR_CONVERGED;
+      r.status = st;
       if (B_out) PR_TRY(hipMemcpyAsync(B_out + (int64_t)i * p, xq, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     } else {
       pr_opts o2 = opts;  // a fresh iteration budget on the single-node FP64 path

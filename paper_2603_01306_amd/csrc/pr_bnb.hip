@@ -1,0 +1,444 @@
+// Branch and bound for the k-sparse problem (1) on top of the batched node
+// relaxations: every node's certified FP64 lower bound comes from
+// pr_solve_batch (perspective relaxation, FISTA with the duality-gap restart,
+// dynamic termination against the incumbent as in Section 5.3); this file
+// holds the search around it and the incumbent heuristic.
+//
+// Search: best first over open nodes keyed by their parents' bound; each round
+// solves up to max_batch nodes together, warm-started from their parents'
+// solutions.  A solved node is fathomed when its bound reaches the incumbent
+// (within the relative tolerance); otherwise it branches on the free
+// coordinate with the largest |beta_j| of its relaxation solution (children:
+// j fixed to one, j fixed to zero).
+//
+// Incumbent: the support J1 + the kbar largest |beta_j| over the free
+// coordinates of each node's relaxation solution; on that support the ridge
+// problem min ||y - X_S b||^2 + lambda2 ||b||^2 is solved (Cholesky of
+// X_S^T X_S + lambda2 I) and b is clipped to the box [-M, M], which keeps it
+// feasible; its objective, computed exactly from X_S^T X_S, X_S^T y and y^T y,
+// is an upper bound on the optimum of (1).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <queue>
+#include <vector>
+
+#include "pr_device.h"
+#include "pr_internal.h"
+
+#define PR_TRY(expr)                          \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return PR_EDEVICE;  \
+  } while (0)
+
+namespace pr {
+namespace {
+
+constexpr int kSubMax = 32;  // largest support the incumbent kernel handles
+
+// out[a * (m + 1) + b] = X[:, S[a]] . X[:, S[b]] (b < m), out[a * (m + 1) + m]
+// = X[:, S[a]] . y; block a computes row a, FP64 accumulation over the stored X.
+template <typename T>
+__global__ __launch_bounds__(256) void k_subgram(const T *__restrict__ X, int64_t n, const int32_t *__restrict__ S,
+                                                 int m, const double *__restrict__ y, double *__restrict__ out) {
+  __shared__ double red[4][kSubMax + 1];
+  const int a = blockIdx.x;
+  const T *__restrict__ xa = X + (int64_t)S[a] * n;
+  double acc[kSubMax + 1];
+#pragma unroll
+  for (int b = 0; b <= kSubMax; b++) acc[b] = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double va = (double)xa[i];
+#pragma unroll
+    for (int b = 0; b < kSubMax; b++)
+      if (b < m) acc[b] += va * (double)X[(int64_t)S[b] * n + i];
+    acc[kSubMax] += va * y[i];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b <= kSubMax; b++) {
+    const double v = dev::wave_sum(acc[b]);
+    if (lane == 0) red[w][b] = v;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b <= m; b += blockDim.x) {
+    const int src = b < m ? b : kSubMax;
+    out[(int64_t)a * (m + 1) + b] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_subgram_bf16(const uint16_t *__restrict__ X, int64_t n,
+                                                      const int32_t *__restrict__ S, int m,
+                                                      const double *__restrict__ y, double *__restrict__ out) {
+  __shared__ double red[4][kSubMax + 1];
+  const int a = blockIdx.x;
+  const uint16_t *__restrict__ xa = X + (int64_t)S[a] * n;
+  double acc[kSubMax + 1];
+#pragma unroll
+  for (int b = 0; b <= kSubMax; b++) acc[b] = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double va = (double)__uint_as_float(((unsigned int)xa[i]) << 16);
+#pragma unroll
+    for (int b = 0; b < kSubMax; b++)
+      if (b < m) acc[b] += va * (double)__uint_as_float(((unsigned int)X[(int64_t)S[b] * n + i]) << 16);
+    acc[kSubMax] += va * y[i];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b <= kSubMax; b++) {
+    const double v = dev::wave_sum(acc[b]);
+    if (lane == 0) red[w][b] = v;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b <= m; b += blockDim.x) {
+    const int src = b < m ? b : kSubMax;
+    out[(int64_t)a * (m + 1) + b] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+  }
+}
+
+hipError_t launch_subgram(const Problem &P, const int32_t *S, int m, double *out, hipStream_t s) {
+  switch (P.xdt) {
+    case kF64: k_subgram<double><<<m, 256, 0, s>>>((const double *)P.X, P.n, S, m, P.y, out); break;
+    case kF32: k_subgram<float><<<m, 256, 0, s>>>((const float *)P.X, P.n, S, m, P.y, out); break;
+    default: k_subgram_bf16<<<m, 256, 0, s>>>((const uint16_t *)P.X, P.n, S, m, P.y, out); break;
+  }
+  return hipGetLastError();
+}
+
+// Cholesky solve of (G + lam I) b = c, G m x m row-major; false if not SPD.
+bool ridge_solve(const std::vector<double> &G, const std::vector<double> &c, int m, double lam, std::vector<double> &b) {
+  std::vector<double> Lw((size_t)m * m, 0.0);
+  for (int i = 0; i < m; i++) {
+    for (int j = 0; j <= i; j++) {
+      double sum = G[(size_t)i * m + j] + (i == j ? lam : 0.0);
+      for (int q = 0; q < j; q++) sum -= Lw[(size_t)i * m + q] * Lw[(size_t)j * m + q];
+      if (i == j) {
+        if (!(sum > 0.0)) return false;
+        Lw[(size_t)i * m + i] = std::sqrt(sum);
+      } else {
+        Lw[(size_t)i * m + j] = sum / Lw[(size_t)j * m + j];
+      }
+    }
+  }
+  std::vector<double> z((size_t)m);
+  for (int i = 0; i < m; i++) {
+    double sum = c[(size_t)i];
+    for (int q = 0; q < i; q++) sum -= Lw[(size_t)i * m + q] * z[(size_t)q];
+    z[(size_t)i] = sum / Lw[(size_t)i * m + i];
+  }
+  b.assign((size_t)m, 0.0);
+  for (int i = m - 1; i >= 0; i--) {
+    double sum = z[(size_t)i];
+    for (int q = i + 1; q < m; q++) sum -= Lw[(size_t)q * m + i] * b[(size_t)q];
+    b[(size_t)i] = sum / Lw[(size_t)i * m + i];
+  }
+  return true;
+}
+
+struct Open {
+  double bound;
+  int32_t depth;
+  int32_t slot;  // arena slot of the parent's solution (-1: cold start)
+  std::vector<int32_t> J0, J1;
+};
+struct OpenCmp {
+  bool operator()(const Open &a, const Open &b) const { return a.bound > b.bound; }
+};
+
+}  // namespace
+
+struct BnbState {
+  pr_ctx *c;
+  Problem P;
+  hipStream_t s;
+  int64_t n, p;
+  double yy = 0.0;
+  int32_t *d_S = nullptr;
+  double *d_sub = nullptr;
+  double *arena = nullptr;  // [slots][p] parent solutions
+  int32_t slots = 0;
+  std::vector<int32_t> free_slots, refs;
+  double *d_B0 = nullptr, *d_Bout = nullptr;
+  double ub = INFINITY;
+  std::vector<double> best;  // dense incumbent (host)
+};
+
+// Incumbent candidate from a relaxation solution (host copy beta); updates
+// st.ub / st.best when it improves.
+static int try_incumbent(BnbState &st, const pr_node &node, const std::vector<int8_t> &status,
+                         const std::vector<double> &beta, double lam2, double M) {
+  const int64_t p = st.p;
+  std::vector<int32_t> S;
+  int32_t kbar = node.k;
+  for (int64_t j = 0; j < p; j++)
+    if (status[(size_t)j] == kOne) {
+      S.push_back((int32_t)j);
+      kbar--;
+    }
+  std::vector<std::pair<double, int32_t>> fr;
+  for (int64_t j = 0; j < p; j++)
+    if (status[(size_t)j] == kFree && beta[(size_t)j] != 0.0) fr.push_back({-std::fabs(beta[(size_t)j]), (int32_t)j});
+  const size_t take = std::min<size_t>(fr.size(), (size_t)std::max(kbar, 0));
+  std::partial_sort(fr.begin(), fr.begin() + take, fr.end());
+  for (size_t q = 0; q < take; q++) S.push_back(fr[q].second);
+  const int m = (int)S.size();
+  if (m == 0 || m > kSubMax) return PR_OK;
+  std::sort(S.begin(), S.end());
+  PR_TRY(hipMemcpyAsync(st.d_S, S.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st.s));
+  PR_TRY(launch_subgram(st.P, st.d_S, m, st.d_sub, st.s));
+  std::vector<double> sub((size_t)m * (m + 1));
+  PR_TRY(hipMemcpyAsync(sub.data(), st.d_sub, sizeof(double) * sub.size(), hipMemcpyDeviceToHost, st.s));
+  PR_TRY(hipStreamSynchronize(st.s));
+  std::vector<double> G((size_t)m * m), cv((size_t)m), b;
+  for (int a = 0; a < m; a++) {
+    for (int q = 0; q < m; q++) G[(size_t)a * m + q] = sub[(size_t)a * (m + 1) + q];
+    cv[(size_t)a] = sub[(size_t)a * (m + 1) + m];
+  }
+  if (!ridge_solve(G, cv, m, lam2, b)) return PR_OK;
+  for (double &v : b) v = std::min(M, std::max(-M, v));
+  double f = st.yy;
+  for (int a = 0; a < m; a++) {
+    double gb = 0.0;
+    for (int q = 0; q < m; q++) gb += G[(size_t)a * m + q] * b[(size_t)q];
+    f += b[(size_t)a] * (gb - 2.0 * cv[(size_t)a]) + lam2 * b[(size_t)a] * b[(size_t)a];
+  }
+  if (f < st.ub) {
+    st.ub = f;
+    st.best.assign((size_t)p, 0.0);
+    for (int a = 0; a < m; a++) st.best[(size_t)S[(size_t)a]] = b[(size_t)a];
+  }
+  return PR_OK;
+}
+
+}  // namespace pr
+
+using namespace pr;
+
+extern "C" {
+
+void pr_bnb_opts_default(pr_bnb_opts *o) {
+  if (!o) return;
+  o->rel_gap_tol = 1e-4;
+  o->time_limit_s = INFINITY;
+  o->max_nodes = 100000;
+  o->batch = 0;
+  pr_opts_default(&o->node_opts);
+}
+
+int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *beta_best, pr_bnb_result *out) {
+  if (!c || !root || !out) return PR_EINVAL;
+  pr_bnb_opts o;
+  pr_bnb_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  if (!(o.rel_gap_tol >= 0.0) || o.max_nodes < 1 || o.batch < 0 || !(o.time_limit_s > 0.0)) return PR_EINVAL;
+  const Problem &P = ctx_problem(c);
+  if (P.loss != kLsq) return PR_EINVAL;  // the incumbent heuristic is for least squares
+  const auto t0 = std::chrono::steady_clock::now();
+  auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+  {
+    std::vector<int8_t> st0;
+    int64_t n1, pbar;
+    int32_t kbar;
+    bool inf;
+    int rc = build_status(root, P.p, st0, n1, pbar, kbar, inf);
+    if (rc != PR_OK) return rc;
+  }
+  BnbState st;
+  st.c = c;
+  st.P = P;
+  st.s = ctx_stream(c);
+  st.n = P.n;
+  st.p = P.p;
+  const int32_t B = o.batch > 0 ? std::min(o.batch, ctx_max_batch(c)) : ctx_max_batch(c);
+  st.slots = std::min<int32_t>(o.max_nodes + 1, 4 * 4096);
+  memset(out, 0, sizeof(*out));
+  int rc = PR_OK;
+  bool ok = hipMalloc((void **)&st.d_S, sizeof(int32_t) * kSubMax) == hipSuccess;
+  ok = ok && hipMalloc((void **)&st.d_sub, sizeof(double) * kSubMax * (kSubMax + 1)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&st.arena, sizeof(double) * st.slots * P.p) == hipSuccess;
+  ok = ok && hipMalloc((void **)&st.d_B0, sizeof(double) * B * P.p) == hipSuccess;
+  ok = ok && hipMalloc((void **)&st.d_Bout, sizeof(double) * B * P.p) == hipSuccess;
+  auto cleanup = [&]() {
+    void *bufs[] = {st.d_S, st.d_sub, st.arena, st.d_B0, st.d_Bout};
+    for (void *q : bufs)
+      if (q) (void)hipFree(q);
+  };
+  if (!ok) {
+    cleanup();
+    return PR_ENOMEM;
+  }
+  {
+    std::vector<double> yh((size_t)P.n);
+    if (hipMemcpy(yh.data(), P.y, sizeof(double) * P.n, hipMemcpyDeviceToHost) != hipSuccess) {
+      cleanup();
+      return PR_EDEVICE;
+    }
+    for (double v : yh) st.yy += v * v;
+  }
+  st.refs.assign((size_t)st.slots, 0);
+  for (int32_t q = st.slots - 1; q >= 0; q--) st.free_slots.push_back(q);
+
+  std::priority_queue<Open, std::vector<Open>, OpenCmp> open;
+  {
+    Open r;
+    r.bound = -INFINITY;
+    r.depth = 0;
+    r.slot = -1;
+    if (root->n0) r.J0.assign(root->J0, root->J0 + root->n0);
+    if (root->n1) r.J1.assign(root->J1, root->J1 + root->n1);
+    open.push(r);
+  }
+  int64_t solved = 0, pruned = 0;
+  int32_t maxdepth = 0;
+  double relax_s = 0.0;
+  const double lam2 = root->lambda2, M = root->M;
+  std::vector<double> bh((size_t)P.p);
+  int status = PR_BNB_OPTIMAL;
+  auto gap_closed = [&](double lb) { return std::isfinite(st.ub) && st.ub - lb <= o.rel_gap_tol * std::fabs(st.ub); };
+  while (!open.empty()) {
+    if (gap_closed(open.top().bound)) break;
+    if (solved >= o.max_nodes) {
+      status = PR_BNB_NODE_LIMIT;
+      break;
+    }
+    if (elapsed() >= o.time_limit_s) {
+      status = PR_BNB_TIME_LIMIT;
+      break;
+    }
+    // next round: up to B open nodes, best bound first
+    std::vector<Open> round;
+    while (!open.empty() && (int32_t)round.size() < B && solved + (int64_t)round.size() < o.max_nodes) {
+      Open nd = open.top();
+      open.pop();
+      if (gap_closed(nd.bound)) {
+        pruned++;
+        if (nd.slot >= 0 && --st.refs[(size_t)nd.slot] == 0) st.free_slots.push_back(nd.slot);
+        continue;
+      }
+      round.push_back(std::move(nd));
+    }
+    if (round.empty()) continue;
+    const int32_t m = (int32_t)round.size();
+    std::vector<pr_node> nodes((size_t)m);
+    for (int32_t i = 0; i < m; i++) {
+      pr_node &q = nodes[(size_t)i];
+      q = *root;
+      q.J0 = round[(size_t)i].J0.empty() ? nullptr : round[(size_t)i].J0.data();
+      q.n0 = (int64_t)round[(size_t)i].J0.size();
+      q.J1 = round[(size_t)i].J1.empty() ? nullptr : round[(size_t)i].J1.data();
+      q.n1 = (int64_t)round[(size_t)i].J1.size();
+      double *dst = st.d_B0 + (int64_t)i * P.p;
+      if (round[(size_t)i].slot >= 0) {
+        if (hipMemcpyAsync(dst, st.arena + (int64_t)round[(size_t)i].slot * P.p, sizeof(double) * P.p,
+                           hipMemcpyDeviceToDevice, st.s) != hipSuccess) {
+          rc = PR_EDEVICE;
+          break;
+        }
+      } else if (hipMemsetAsync(dst, 0, sizeof(double) * P.p, st.s) != hipSuccess) {
+        rc = PR_EDEVICE;
+        break;
+      }
+    }
+    if (rc != PR_OK) break;
+    pr_opts no = o.node_opts;
+    no.cutoff = std::isfinite(st.ub) ? st.ub * (1.0 - o.rel_gap_tol) : NAN;
+    no.trace = nullptr;
+    std::vector<pr_result> res((size_t)m);
+    const double ts = elapsed();
+    rc = pr_solve_batch(c, nodes.data(), m, &no, st.d_B0, st.d_Bout, res.data());
+    relax_s += elapsed() - ts;
+    if (rc != PR_OK) break;
+    solved += m;
+    for (int32_t i = 0; i < m; i++) {
+      Open &nd = round[(size_t)i];
+      if (nd.slot >= 0 && --st.refs[(size_t)nd.slot] == 0) st.free_slots.push_back(nd.slot);
+      maxdepth = std::max(maxdepth, nd.depth);
+      const pr_result &r = res[(size_t)i];
+      if (r.status == PR_INFEASIBLE || r.status == PR_CUTOFF_PRUNE) {
+        pruned++;
+        continue;
+      }
+      const double bound = std::max(nd.bound, r.lower_bound);
+      std::vector<int8_t> sv;
+      int64_t n1, pbar;
+      int32_t kbar;
+      bool inf;
+      rc = build_status(&nodes[(size_t)i], P.p, sv, n1, pbar, kbar, inf);
+      if (rc != PR_OK) break;
+      if (hipMemcpyAsync(bh.data(), st.d_Bout + (int64_t)i * P.p, sizeof(double) * P.p, hipMemcpyDeviceToHost,
+                         st.s) != hipSuccess ||
+          hipStreamSynchronize(st.s) != hipSuccess) {
+        rc = PR_EDEVICE;
+        break;
+      }
+      rc = try_incumbent(st, nodes[(size_t)i], sv, bh, lam2, M);
+      if (rc != PR_OK) break;
+      if (gap_closed(bound)) {
+        pruned++;
+        continue;
+      }
+      // branch on the free coordinate with the largest |beta_j|
+      int32_t jb = -1;
+      double amax = -1.0;
+      for (int64_t j = 0; j < P.p; j++)
+        if (sv[(size_t)j] == kFree && std::fabs(bh[(size_t)j]) > amax) {
+          amax = std::fabs(bh[(size_t)j]);
+          jb = (int32_t)j;
+        }
+      if (jb < 0 || kbar <= 0) {  // nothing left to decide: the relaxation is the restricted problem
+        pruned++;
+        continue;
+      }
+      int32_t slot = -1;
+      if (!st.free_slots.empty()) {
+        slot = st.free_slots.back();
+        st.free_slots.pop_back();
+        st.refs[(size_t)slot] = 2;
+        if (hipMemcpyAsync(st.arena + (int64_t)slot * P.p, st.d_Bout + (int64_t)i * P.p, sizeof(double) * P.p,
+                           hipMemcpyDeviceToDevice, st.s) != hipSuccess) {
+          rc = PR_EDEVICE;
+          break;
+        }
+      }
+      Open a, b2;
+      a.bound = b2.bound = bound;
+      a.depth = b2.depth = nd.depth + 1;
+      a.slot = b2.slot = slot;
+      a.J0 = nd.J0;
+      a.J1 = nd.J1;
+      a.J1.push_back(jb);
+      b2.J0 = nd.J0;
+      b2.J0.push_back(jb);
+      b2.J1 = nd.J1;
+      open.push(std::move(a));
+      open.push(std::move(b2));
+    }
+    if (rc != PR_OK) break;
+  }
+  if (rc == PR_OK) {
+    double lb = open.empty() ? st.ub : std::min(st.ub, open.top().bound);
+    if (open.empty() && status == PR_BNB_OPTIMAL) lb = st.ub;
+    out->lower_bound = lb;
+    out->upper_bound = st.ub;
+    out->rel_gap = (st.ub - lb) / std::fmax(std::fabs(st.ub), 1e-300);
+    if (status == PR_BNB_OPTIMAL && !(out->rel_gap <= o.rel_gap_tol)) status = PR_BNB_NODE_LIMIT;
+    out->nodes_solved = solved;
+    out->nodes_pruned = pruned;
+    out->nodes_open = (int64_t)open.size();
+    out->max_depth = maxdepth;
+    out->status = status;
+    out->seconds = elapsed();
+    out->relaxation_seconds = relax_s;
+    if (beta_best) {
+      if (st.best.empty()) st.best.assign((size_t)P.p, 0.0);
+      if (hipMemcpy(beta_best, st.best.data(), sizeof(double) * P.p, hipMemcpyHostToDevice) != hipSuccess)
+        rc = PR_EDEVICE;
+    }
+  }
+  cleanup();
+  return rc;
+}
+
+}  // extern "C"

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
+#include "../../include/pr.h"
+
 namespace pr {
 
 constexpr int kNodeThreads = 512;    // threads of a per-node workgroup
@@ -93,7 +97,15 @@ struct Problem {
   int64_t n, p;
 };
 
-// ---- launchers (pr_kernels.hip) ----
+// ---- host helpers (pr_api.hip) ----
+// Validate a node and build its status vector; *infeasible when |J1| > k.
+int build_status(const pr_node *node, int64_t p, std::vector<int8_t> &st, int64_t &n1, int64_t &pbar,
+                 int32_t &kbar, bool &infeasible);
+const Problem &ctx_problem(const pr_ctx *c);
+hipStream_t ctx_stream(const pr_ctx *c);
+int32_t ctx_max_batch(const pr_ctx *c);
+
+// ---- kernel launchers ----
 hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
                          const int32_t *done, hipStream_t s);
 // u_partials / finalize: generic column-list GEMV u = sum_t X[:, idx[t]] * val[t]

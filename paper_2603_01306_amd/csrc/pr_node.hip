@@ -1291,6 +1291,12 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     if (rel <= bb.gap_factor * prm->tol) {
       done = 1;
       status = kConverged;
+    } else if (!isnan(prm->cutoff) && psi >= prm->cutoff) {
+      done = 1;
+      status = kCutoffPrune;
+    } else if (!isnan(prm->cutoff) && phi <= prm->cutoff) {
+      done = 1;
+      status = kCutoffBranch;
     } else if (it >= prm->max_iter) {
       done = 1;
       status = kMaxIter;

@@ -1,0 +1,89 @@
+"""Branch and bound on the GPU (pr_bnb) and the batched dynamic termination
+it relies on: the certified lower bound never exceeds the exact k-sparse
+optimum found by enumeration, the incumbent's objective is exact and reaches
+that optimum when the tree closes, and batched prune / branch decisions agree
+with the single-node path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.ksparse import ksparse_bruteforce
+from workloads import make_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(inst, dev, max_batch):
+    import torch
+    import paper_2603_01306_amd as pr
+    if inst.storage == "bf16":
+        X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        X = torch.from_numpy(inst.Xcm).to(dev)
+    return pr.Context(X, torch.from_numpy(inst.y).to(dev), 0, max_batch=max_batch)
+
+
+def _objective(X, y, b, lam2):
+    return float(np.sum((y - X @ b) ** 2) + lam2 * b @ b)
+
+
+@pytest.mark.parametrize("seed,k,lam2,J0,J1", [(3, 4, 0.5, (), ()), (4, 3, 1.0, (2,), (7,)), (5, 5, 0.2, (), ())])
+def test_bnb_matches_enumeration(dev, seed, k, lam2, J0, J1):
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=120, p=14, corr=0.5, k_true=4, snr=4.0, loss=0, seed=seed, storage="f64")
+    X, y = inst.X64().T, inst.y
+    ctx = _ctx(inst, dev, 8)
+    res, beta = ctx.bnb(pr.Node(k, lam2, 2.0, J0=J0, J1=J1), rel_gap_tol=1e-7,
+                        node_opts=dict(rel_gap_tol=1e-9, max_iter=200000))
+    opt, S, _ = ksparse_bruteforce(X, y, k, lam2, 2.0, J0=J0, J1=J1)
+    print(seed, res, opt, flush=True)
+    assert res["status"] == pr.BNB_OPTIMAL
+    assert res["lower_bound"] <= opt * (1 + 1e-9)
+    assert res["upper_bound"] >= opt * (1 - 1e-9)
+    assert res["upper_bound"] - opt <= 2e-7 * opt
+    b = beta.cpu().numpy()
+    assert np.count_nonzero(b) <= k and np.all(np.abs(b) <= 2.0) and np.all(b[list(J0)] == 0)
+    assert abs(_objective(X, y, b, lam2) - res["upper_bound"]) <= 1e-10 * res["upper_bound"]
+    ctx.close()
+
+
+def test_bnb_on_the_batched_path(dev):
+    """BF16 design on the batched path: bounds ordered, incumbent objective
+    exact, node accounting consistent."""
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=0, seed=9, storage="bf16")
+    X, y = inst.X64().T, inst.y
+    ctx = _ctx(inst, dev, 32)
+    res, beta = ctx.bnb(pr.Node(6, 0.5, 2.0), rel_gap_tol=1e-4, max_nodes=400)
+    print(res, flush=True)
+    assert res["lower_bound"] <= res["upper_bound"] * (1 + 1e-12)
+    b = beta.cpu().numpy()
+    assert np.count_nonzero(b) <= 6
+    assert abs(_objective(X, y, b, 0.5) - res["upper_bound"]) <= 1e-10 * res["upper_bound"]
+    root = oracle.solve(inst.Xcm, inst.y, 0, 0.5, 2.0, 6, tol=1e-9)
+    assert res["lower_bound"] >= root["lb"] * (1 - 1e-6)      # never below the root bound
+    assert res["nodes_solved"] >= 1 and res["nodes_pruned"] + res["nodes_open"] <= 2 * res["nodes_solved"] + 1
+    ctx.close()
+
+
+def test_batched_cutoff_decisions_match_single_path(dev):
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=0, seed=10, storage="bf16")
+    ctx = _ctx(inst, dev, 16)
+    rng = np.random.default_rng(0)
+    nodes = [pr.Node(6, 0.5, 2.0, J0=rng.choice(512, 20, replace=False)) for _ in range(8)]
+    free, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-9)
+    vals = sorted(r["lower_bound"] for r in free)
+    cutoff = 0.5 * (vals[3] + vals[4])                        # half the nodes prune, half branch
+    res, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-9, cutoff=cutoff)
+    for nd, r, f in zip(nodes, res, free):
+        assert r["status"] in (pr.CUTOFF_PRUNE, pr.CUTOFF_BRANCH, pr.CONVERGED)
+        if r["status"] == pr.CUTOFF_PRUNE:
+            assert r["lower_bound"] >= cutoff and f["lower_bound"] >= cutoff * (1 - 1e-9)
+        if r["status"] == pr.CUTOFF_BRANCH:
+            assert r["primal"] <= cutoff and f["lower_bound"] <= cutoff * (1 + 1e-9)
+        s = ctx.solve(nd, rel_gap_tol=1e-9, cutoff=cutoff)
+        assert (s["status"] == pr.CUTOFF_PRUNE) == (r["status"] == pr.CUTOFF_PRUNE)
+    ctx.close()
