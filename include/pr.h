@@ -130,6 +130,20 @@ int pr_ctx_destroy(pr_ctx *ctx);
 /* Cached estimate of ||X||_2^2 (largest eigenvalue of X^T X). */
 int pr_ctx_norm2(pr_ctx *ctx, double *norm2_out);
 
+/* Least squares from the Gram matrix.  Precomputes G = X^T X (p x p, FP64
+ * MFMA over the stored X, kept in device memory: 8 p^2 bytes), b = X^T y and
+ * y^T y, and from then on runs every pr_solve of the context as
+ *   h = b - G_S x_S  (a column-list product over the support of x)
+ * in place of the two matrix-vector products X x and X^T r: F(X x) =
+ * y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F for zeta =
+ * 2 (y - X x), the same iteration in exact arithmetic.  At the end of each
+ * solve the reported bounds are recomputed over the stored X (pr_dual_bound)
+ * and a decision they do not confirm is redone on the matrix-vector path.
+ * Requires least squares, p a multiple of 128 and at most 16384, n a multiple
+ * of 32; PR_EINVAL otherwise, PR_ENOMEM if G does not fit.  pr_solve_batch is
+ * not affected. */
+int pr_ctx_enable_gram(pr_ctx *ctx);
+
 /* Solve one node relaxation (Sections 3.3 and 4): FISTA steps
  * x = prox_{(2 lambda2 / L) g_N}(y - grad/L) with the Algorithm 2 prox,
  * Phi with the Algorithm 1 value of g_N, Psi with the closed-form conjugate

@@ -20,7 +20,7 @@ BNB_OPTIMAL, BNB_NODE_LIMIT, BNB_TIME_LIMIT = 1, 2, 3
 LSQ, LOGISTIC = 0, 1
 F64, F32, BF16 = 0, 1, 2
 
-EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_solve",
+EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
            "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
            "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_strerror"]
@@ -134,6 +134,8 @@ def load():
         L.pr_mlp_warm_start.restype = ctypes.c_int
         L.pr_mlp_warm_start.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, P, P, P,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+        L.pr_ctx_enable_gram.restype = ctypes.c_int
+        L.pr_ctx_enable_gram.argtypes = [P]
         L.pr_bnb_opts_default.restype = None
         L.pr_bnb_opts_default.argtypes = [ctypes.POINTER(PrBnbOpts)]
         L.pr_bnb.restype = ctypes.c_int
@@ -251,6 +253,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def enable_gram(self):
+        """Switch the context's least-squares solves to the Gram form h = b - G x."""
+        _check(load().pr_ctx_enable_gram(self.h), "pr_ctx_enable_gram")
 
     def norm2(self):
         v = ctypes.c_double()

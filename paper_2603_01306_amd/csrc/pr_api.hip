@@ -78,6 +78,13 @@ struct pr_ctx {
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
+  // least squares from the Gram matrix (pr_ctx_enable_gram)
+  bool gram = false;
+  double *G = nullptr;   // [p][p] X^T X over the stored X, FP64
+  double *gb = nullptr;  // [p] X^T y
+  double gyy = 0.0;      // y^T y
+  Problem PG{};          // G viewed as the "design" of the column-list GEMV (n = p, y = b)
+  ProbBufs BG{};         // its partial sums; h goes to B.h1
   // learned warm start (allocated on first use)
   uint16_t *mF = nullptr;  // [p][8] features of one node
   float *mout = nullptr;   // [p] network outputs
@@ -93,7 +100,7 @@ void free_ctx(pr_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
-                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx};
+                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb};
   for (void *b : bb)
     if (b) (void)hipFree(b);
   if (c->h_bstate) (void)hipHostFree(c->h_bstate);
@@ -168,6 +175,13 @@ double curvature(int loss) { return loss == kLsq ? 2.0 : 0.25; }
 
 // One iteration unit: column-list GEMV + loss epilogue, X^T pass, node step.
 hipError_t enqueue_unit(pr_ctx *c, hipStream_t s) {
+  if (c->gram) {
+    // h = b - G x over the support of x, then the node step
+    hipError_t e = launch_spfwd(c->PG, c->BG, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, kSpGram, c->d_state,
+                                nullptr, s);
+    if (e != hipSuccess) return e;
+    return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s);
+  }
   const int mode = c->P.loss == kLsq ? kSpLsq : kSpLogistic;
   hipError_t e = launch_spfwd(c->P, c->B, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, mode, c->d_state,
                               nullptr, s);
@@ -480,7 +494,7 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   ok = ok && hipHostMalloc((void **)&c->h_state, 2 * sizeof(NodeState), hipHostMallocDefault) == hipSuccess;
   ok = ok && dalloc(&c->d_status, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.x0, p) == hipSuccess && dalloc(&c->nb.x1, p) == hipSuccess;
-  ok = ok && dalloc(&c->nb.xbest, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.xbest, p) == hipSuccess && dalloc(&c->nb.xlb, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.hprev, p) == hipSuccess && dalloc(&c->nb.vbuf, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.abuf, p) == hipSuccess && dalloc(&c->nb.sidx, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.sval, p) == hipSuccess;
@@ -543,6 +557,101 @@ int pr_ctx_norm2(pr_ctx *c, double *out) {
   return PR_OK;
 }
 
+int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const double *beta0, double *beta_out,
+             double *zeta_out, pr_result *out);
+
+// End of a Gram-mode solve: the bounds the iteration computed from G are
+// recomputed over the stored X (pr_dual_bound): Psi at the dual vectors of the
+// iterate with the best Psi and of the iterate with the best Phi, and Phi at
+// the latter.  A decision (converged / prune / branch) these values do not
+// confirm is redone on the matrix-vector path from the best iterate.
+static int gram_certify(pr_ctx *c, const pr_node *node, const pr_opts *opts, const NodeState &hs, double *beta_out,
+                        double *zeta_out, pr_result *out) {
+  const int64_t n = c->P.n, p = c->P.p;
+  hipStream_t s = c->stream;
+  double lb1 = -INFINITY, ub1 = INFINITY, lb2 = -INFINITY, ub2 = INFINITY;
+  int rc = pr_dual_bound(c, node, nullptr, c->nb.xlb, &lb1, &ub1);  // leaves zeta(x_lb) in B.gm
+  if (rc != PR_OK) return rc;
+  if (zeta_out) PR_TRY(hipMemcpyAsync(zeta_out, c->B.gm, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  rc = pr_dual_bound(c, node, nullptr, c->nb.xbest, &lb2, &ub2);
+  if (rc != PR_OK) return rc;
+  if (zeta_out && lb2 > lb1) PR_TRY(hipMemcpyAsync(zeta_out, c->B.gm, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const double lb = lb2 > lb1 ? lb2 : lb1, ub = ub2;
+  const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
+  const int st = hs.done ? hs.status : kMaxIter;
+  bool confirmed = true;
+  if (st == kConverged) confirmed = rel <= opts->rel_gap_tol;
+  else if (st == kCutoffPrune) confirmed = lb >= opts->cutoff;
+  else if (st == kCutoffBranch) confirmed = ub <= opts->cutoff;
+  if (!confirmed) {
+    // rare: redo on the matrix-vector path, warm-started from the best iterate
+    PR_TRY(hipMemcpyAsync(c->nb.vbuf, c->nb.xbest, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    c->gram = false;
+    pr_opts o2 = *opts;
+    rc = pr_solve(c, node, &o2, c->nb.vbuf, beta_out, zeta_out, out);
+    c->gram = true;
+    if (rc == PR_OK) {
+      if (out->lower_bound < lb) out->lower_bound = lb;
+      out->iters += hs.iter;
+      out->restarts += hs.restarts;
+    }
+    return rc;
+  }
+  if (beta_out) PR_TRY(hipMemcpyAsync(beta_out, c->nb.xbest, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+  PR_TRY(hipStreamSynchronize(s));
+  out->lower_bound = lb;
+  out->primal = ub;
+  out->rel_gap = rel;
+  out->L = hs.L;
+  out->iters = hs.iter;
+  out->restarts = hs.restarts;
+  out->status = st;
+  return PR_OK;
+}
+
+int pr_ctx_enable_gram(pr_ctx *c) {
+  if (!c) return PR_EINVAL;
+  const int64_t n = c->P.n, p = c->P.p;
+  if (c->P.loss != kLsq || p % 128 != 0 || n % 32 != 0 || p > 16384) return PR_EINVAL;
+  if (c->gram) return PR_OK;
+  hipStream_t s = c->stream;
+  bool ok = dalloc(&c->G, (size_t)p * p) == hipSuccess && dalloc(&c->gb, (size_t)p) == hipSuccess;
+  c->PG.X = c->G;
+  c->PG.xdt = kF64;
+  c->PG.loss = kLsq;
+  c->PG.y = c->gb;
+  c->PG.n = p;
+  c->PG.p = p;
+  c->BG = c->B;
+  c->BG.rows = kSpThreads * 2;  // FP64 "design": 2 rows per 16-byte load
+  c->BG.rb = (int32_t)((p + c->BG.rows - 1) / c->BG.rows);
+  int nch = 512 / c->BG.rb;
+  if (nch < 1) nch = 1;
+  if (nch > 64) nch = 64;
+  c->BG.nch = nch;
+  c->BG.nfin = spfwd_final_blocks(p);
+  c->BG.part = nullptr;
+  ok = ok && dalloc(&c->BG.part, (size_t)nch * p) == hipSuccess;
+  if (!ok) return PR_ENOMEM;
+  // G = X^T X on FP64 MFMA (operands converted exactly, FP64 sums); b = X^T y
+  PR_TRY(launch_gemm_any(c->P.xdt, c->P.X, n, c->P.xdt, c->P.X, n, c->G, p, p, n, 1, nullptr, nullptr, nullptr,
+                         nullptr, 0, nullptr, s));
+  PR_TRY(launch_gemv_t(c->P, c->P.y, nullptr, c->gb, nullptr, nullptr, s));
+  std::vector<double> yh((size_t)n);
+  PR_TRY(hipMemcpyAsync(yh.data(), c->P.y, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  double yy = 0.0;
+  for (double v : yh) yy += v * v;
+  c->gyy = yy;
+  c->gram = true;
+  if (c->gexec) {  // the captured iteration changes
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_units = 0;
+  }
+  return PR_OK;
+}
+
 int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const double *beta0,
              double *beta_out, double *zeta_out, pr_result *out) {
   if (!c || !out) return PR_EINVAL;
@@ -582,6 +691,8 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   prm.max_iter = opts.max_iter;
   prm.method = opts.method;
   prm.trace = opts.trace;
+  prm.gram_b = c->gram ? c->gb : nullptr;
+  prm.gram_yy = c->gyy;
   PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, c->stream));
   PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
   PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, p, c->stream));
@@ -611,8 +722,13 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
     launched++;
   }
   PR_TRY(hipStreamSynchronize(c->stream));
-  PR_TRY(launch_zbest_final(c->d_state, c->B, c->P.loss, n, c->stream));
   NodeState hs;
+  if (c->gram) {
+    PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
+    PR_TRY(hipStreamSynchronize(c->stream));
+    return gram_certify(c, node, &opts, hs, beta_out, zeta_out, out);
+  }
+  PR_TRY(launch_zbest_final(c->d_state, c->B, c->P.loss, n, c->stream));
   PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
   PR_TRY(hipStreamSynchronize(c->stream));
   if (beta_out)

@@ -27,16 +27,47 @@ typedef double d4v_t __attribute__((ext_vector_type(4)));
 constexpr int kPipe = 2;       // reduction steps of operands held per wave in k_gemm_f64
 constexpr int kGemmGrid = 512;   // persistent grid of k_gemm_f64: two workgroups per CU
 typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
+typedef float f4v_t __attribute__((ext_vector_type(4)));
 
-// C[z][r][c] = sum_{k in split z} A[c][k] * B[r][k], A BF16 (upcast exactly),
-// B FP64, FP64 MFMA.  Block = 4 waves, block tile 128 (c) x 64 (r), wave tile
-// 64 x 32 = 4 x 2 MFMA tiles of 16 x 16.  The reduction runs in steps of 32:
-// the lanes of quarter q own the 8 consecutive indices 8q .. 8q+7 of a step
-// (one 16-byte A load per tile, four 16-byte B loads per tile), so a wave
-// reads 64 contiguous bytes of each A row per step and the next step reads the
-// rest of the same cache line; MFMA s of the step combines index 8q + s of
-// every quarter.  Operands are loaded kPipe - 1 steps ahead of the MFMAs.
-__device__ __forceinline__ void gemm_tile(const uint16_t *__restrict__ A, int64_t lda, const double *__restrict__ B,
+// Eight consecutive operand elements of one lane (one reduction step of a
+// lane quarter), loaded with 16-byte loads and read back as FP64: BF16 bit
+// patterns and FP32 values convert exactly.
+template <typename T>
+struct Lane8;
+template <>
+struct Lane8<uint16_t> {
+  us8_t v;
+  __device__ __forceinline__ void load(const uint16_t *p) { v = *reinterpret_cast<const us8_t *>(p); }
+  __device__ __forceinline__ double get(int s) const { return (double)__uint_as_float(((unsigned int)v[s]) << 16); }
+};
+template <>
+struct Lane8<float> {
+  f4v_t v[2];
+  __device__ __forceinline__ void load(const float *p) {
+    v[0] = *reinterpret_cast<const f4v_t *>(p);
+    v[1] = *reinterpret_cast<const f4v_t *>(p + 4);
+  }
+  __device__ __forceinline__ double get(int s) const { return (double)v[s >> 2][s & 3]; }
+};
+template <>
+struct Lane8<double> {
+  d2v_t v[4];
+  __device__ __forceinline__ void load(const double *p) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) v[i] = *reinterpret_cast<const d2v_t *>(p + 2 * i);
+  }
+  __device__ __forceinline__ double get(int s) const { return v[s >> 1][s & 1]; }
+};
+
+// C[z][r][c] = sum_{k in split z} A[c][k] * B[r][k] on FP64 MFMA, operands
+// BF16 / FP32 / FP64 (converted exactly).  Block = 4 waves, block tile 128 (c)
+// x 64 (r), wave tile 64 x 32 = 4 x 2 MFMA tiles of 16 x 16.  The reduction
+// runs in steps of 32: the lanes of quarter q own the 8 consecutive indices
+// 8q .. 8q+7 of a step (16-byte loads; a wave reads whole cache lines of each
+// row over consecutive steps); MFMA s of the step combines index 8q + s of
+// every quarter.  Operands are loaded PIPE - 1 steps ahead of the MFMAs.
+template <typename TA, typename TB, int PIPE>
+__device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B,
                                           int64_t ldb, double *__restrict__ C, int64_t Mc, int64_t Nr, int64_t Kc,
                                           int mt, int z, int nt, int nr, const int32_t *__restrict__ rowmap) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -57,8 +88,8 @@ __device__ __forceinline__ void gemm_tile(const uint16_t *__restrict__ A, int64_
       orow[u] = brow[u] = l;
     }
   }
-  const uint16_t *pa[4];
-  const double *pb[2];
+  const TA *pa[4];
+  const TB *pb[2];
 #pragma unroll
   for (int t = 0; t < 4; t++) pa[t] = A + (c0 + 16 * t + rr) * lda + k0;
 #pragma unroll
@@ -69,25 +100,23 @@ __device__ __forceinline__ void gemm_tile(const uint16_t *__restrict__ A, int64_
 #pragma unroll
     for (int u = 0; u < 2; u++) acc[t][u] = d4v_t{0.0, 0.0, 0.0, 0.0};
   const int64_t nsteps = Kc / 32;
-  us8_t ar[kPipe][4];
-  d2v_t br[kPipe][2][4];
-  auto load = [&](int64_t st, us8_t (&a)[4], d2v_t (&bb)[2][4]) {
+  Lane8<TA> ar[PIPE][4];
+  Lane8<TB> br[PIPE][2];
+  auto load = [&](int64_t st, Lane8<TA>(&a)[4], Lane8<TB>(&bb)[2]) {
     const int64_t kk = st * 32;
 #pragma unroll
-    for (int t = 0; t < 4; t++) a[t] = *reinterpret_cast<const us8_t *>(pa[t] + kk);
+    for (int t = 0; t < 4; t++) a[t].load(pa[t] + kk);
 #pragma unroll
-    for (int u = 0; u < 2; u++)
-#pragma unroll
-      for (int v = 0; v < 4; v++) bb[u][v] = *reinterpret_cast<const d2v_t *>(pb[u] + kk + 2 * v);
+    for (int u = 0; u < 2; u++) bb[u].load(pb[u] + kk);
   };
-  auto step = [&](const us8_t (&a)[4], const d2v_t (&bb)[2][4]) {
+  auto step = [&](const Lane8<TA>(&a)[4], const Lane8<TB>(&bb)[2]) {
 #pragma unroll
     for (int s8 = 0; s8 < 8; s8++) {
       double av[4], bv[2];
 #pragma unroll
-      for (int t = 0; t < 4; t++) av[t] = (double)__uint_as_float(((unsigned int)a[t][s8]) << 16);
+      for (int t = 0; t < 4; t++) av[t] = a[t].get(s8);
 #pragma unroll
-      for (int u = 0; u < 2; u++) bv[u] = bb[u][s8 >> 1][s8 & 1];
+      for (int u = 0; u < 2; u++) bv[u] = bb[u].get(s8);
 #pragma unroll
       for (int t = 0; t < 4; t++)
 #pragma unroll
@@ -95,14 +124,17 @@ __device__ __forceinline__ void gemm_tile(const uint16_t *__restrict__ A, int64_
     }
   };
 #pragma unroll
-  for (int d = 0; d < kPipe - 1; d++)
+  for (int d = 0; d < PIPE - 1; d++)
     if (d < nsteps) load(d, ar[d], br[d]);
-  for (int64_t s0 = 0; s0 < nsteps; s0 += kPipe) {
+  for (int64_t s0 = 0; s0 < nsteps; s0 += PIPE) {
 #pragma unroll
-    for (int d = 0; d < kPipe; d++) {
-      const int64_t sp = s0 + d + kPipe - 1;
-      if (sp < nsteps) load(sp, ar[(d + kPipe - 1) % kPipe], br[(d + kPipe - 1) % kPipe]);
-      if (s0 + d < nsteps) step(ar[d], br[d]);
+    for (int d = 0; d < PIPE; d++) {
+      const int64_t sp = s0 + d + PIPE - 1;
+      if (PIPE > 1 && sp < nsteps) load(sp, ar[(d + PIPE - 1) % PIPE], br[(d + PIPE - 1) % PIPE]);
+      if (s0 + d < nsteps) {
+        if (PIPE == 1) load(s0 + d, ar[0], br[0]);
+        step(ar[d], br[d]);
+      }
     }
   }
   // MFMA output: register v of lane l is (c = 4v + l/16, r = l%16)
@@ -126,14 +158,14 @@ __device__ __forceinline__ void gemm_tile(const uint16_t *__restrict__ A, int64_
 // multiple of 8), and item i is (c tile, split) group (i / 8 / nta) * 8 + i % 8,
 // r tile (i / 8) % nta: the r tiles sharing an A tile run on one XCD and read
 // it from HBM once per XCD L2.
-__global__ __launch_bounds__(256, 2) void k_gemm_f64(const uint16_t *__restrict__ A, int64_t lda,
-                                                  const double *__restrict__ B, int64_t ldb, double *__restrict__ C,
-                                                  int64_t Mc, int64_t Nr, int64_t K, int MT, int NT, int KS,
-                                                  const int32_t *__restrict__ active,
-                                                  const int32_t *__restrict__ rowmap,
-                                                  const int32_t *__restrict__ nrow,
-                                                  const int32_t *__restrict__ ksp,
-                                                  int32_t *__restrict__ counter) {
+template <typename TA, typename TB, int PIPE>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B,
+                                                     int64_t ldb, double *__restrict__ C, int64_t Mc, int64_t Nr,
+                                                     int64_t K, int MT, int NT, int KS,
+                                                     const int32_t *__restrict__ active,
+                                                     const int32_t *__restrict__ rowmap,
+                                                     const int32_t *__restrict__ nrow,
+                                                     const int32_t *__restrict__ ksp, int32_t *__restrict__ counter) {
   if (active && *active == 0) return;
   if (ksp) KS = *ksp;
   const int nr = rowmap ? *nrow : (int)Nr;
@@ -149,7 +181,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const uint16_t *__restrict_
     const int x = item & 7, qq = item >> 3;
     const int g = qq / nta, nt = qq - g * nta;
     const int G = g * 8 + x;
-    if (G < groups) gemm_tile(A, lda, B, ldb, C, Mc, Nr, Kc, G % MT, G / MT, nt, nr, rowmap);
+    if (G < groups) gemm_tile<TA, TB, PIPE>(A, lda, B, ldb, C, Mc, Nr, Kc, G % MT, G / MT, nt, nr, rowmap);
     if (counter) {
       __syncthreads();
       if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(counter, 1);
@@ -260,16 +292,38 @@ __global__ void k_batch_zeta(const double *__restrict__ R, int64_t n, int node, 
 
 }  // namespace
 
-hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
-                           int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
-                           const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s) {
+template <typename TA, typename TB, int PIPE>
+hipError_t launch_gemm_t(const TA *A, int64_t lda, const TB *B, int64_t ldb, double *C, int64_t Mc, int64_t Nr,
+                         int64_t K, int KS, const int32_t *active, const int32_t *rowmap, const int32_t *nrow,
+                         const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s) {
   const int MT = (int)(Mc / 128), NT = (int)(Nr / 64);
   const int groups = MT * (ksp ? ks_max : KS);
   const int items = (groups + 7) / 8 * 8 * NT;
   const int grid = items < kGemmGrid ? (items + 7) / 8 * 8 : kGemmGrid;
-  k_gemm_f64<<<(unsigned)grid, 256, 0, s>>>(A, lda, B, ldb, C, Mc, Nr, K, MT, NT, KS, active, rowmap, nrow, ksp,
-                                            counter);
+  k_gemm_f64<TA, TB, PIPE><<<(unsigned)grid, 256, 0, s>>>(A, lda, B, ldb, C, Mc, Nr, K, MT, NT, KS, active, rowmap,
+                                                          nrow, ksp, counter);
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
+                           int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s) {
+  return launch_gemm_t<uint16_t, double, kPipe>(A, lda, B, ldb, C, Mc, Nr, K, KS, active, rowmap, nrow, ksp, ks_max,
+                                                counter, s);
+}
+
+hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const void *B, int64_t ldb, double *C,
+                           int64_t Mc, int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s) {
+#define PR_GEMM_CASE(A_T, B_T, PIPE_)                                                                              \
+  return launch_gemm_t<A_T, B_T, PIPE_>((const A_T *)A, lda, (const B_T *)B, ldb, C, Mc, Nr, K, KS, active, rowmap, \
+                                        nrow, ksp, ks_max, counter, s)
+  if (adt == kBF16 && bdt == kF64) PR_GEMM_CASE(uint16_t, double, kPipe);
+  if (adt == kBF16 && bdt == kBF16) PR_GEMM_CASE(uint16_t, uint16_t, kPipe);
+  if (adt == kF32 && bdt == kF32) PR_GEMM_CASE(float, float, kPipe);
+  if (adt == kF64 && bdt == kF64) PR_GEMM_CASE(double, double, 1);  // two stages would spill
+#undef PR_GEMM_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,

@@ -31,6 +31,10 @@ struct NodeParams {
   double lambda2, M, eta, tol, cutoff;  // cutoff NaN = off
   int32_t max_iter, method;             // method: kFistaGap .. kPgd
   double *trace;                        // optional: (Phi, Psi) of iterates 0 .. max_iter
+  // least squares from the Gram matrix (NULL: from the matrix-vector products):
+  // b = X^T y, yy = y^T y; h = b - G x arrives in place of X^T r
+  const double *gram_b;
+  double gram_yy;
 };
 
 // Per-node iteration state, device resident.
@@ -62,6 +66,7 @@ struct NodeBufs {
   double *abuf;        // magnitudes scratch (negative = not free)
   int32_t *sidx;       // support list of the current iterate
   double *sval;
+  double *xlb;         // Gram mode: iterate whose dual vector attains the best Psi
 };
 
 // Shared per-problem vectors of a single-node solve.
@@ -110,7 +115,7 @@ hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, d
                          const int32_t *done, hipStream_t s);
 // u_partials / finalize: generic column-list GEMV u = sum_t X[:, idx[t]] * val[t]
 // followed by the per-row-block epilogue selected by `mode`.
-enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2 };
+enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2, kSpGram = 3 };
 hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx, const double *val,
                         const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
                         hipStream_t s);
@@ -128,6 +133,11 @@ hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, in
                               double *R, double *fsum, const NodeState *S, hipStream_t s);
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
                            int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
+                           const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
+// Same product with operand types adt, bdt in {kBF16, kF32, kF64}: supported
+// pairs (BF16, FP64), (BF16, BF16), (FP32, FP32), (FP64, FP64).
+hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const void *B, int64_t ldb, double *C,
+                           int64_t Mc, int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
                            const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
                                const int32_t *ftab, int ksf, int kst, hipStream_t s);

@@ -1012,24 +1012,45 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const double L = S->L;
   PackedStatus<EPT> sv;
   sv.load(prm->st, p);
+  const double *__restrict__ gb = prm->gram_b;
   // loss sums of the finalize blocks: lane-parallel loads, fixed-order wave sums
   double Fk = 0.0, negconj = 0.0;
-  for (int i = lane_id(); i < B.nfin; i += 64) {
-    Fk += B.rbsum[2 * i];
-    negconj += B.rbsum[2 * i + 1];
+  if (!gb) {
+    for (int i = lane_id(); i < B.nfin; i += 64) {
+      Fk += B.rbsum[2 * i];
+      negconj += B.rbsum[2 * i + 1];
+    }
+    Fk = wave_sum(Fk);
+    negconj = wave_sum(negconj);
   }
-  Fk = wave_sum(Fk);
-  negconj = wave_sum(negconj);
   // dual value at x^k: w = X^T zeta / (2 lambda2)
   const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
   double x[EPT];  // h = B.h1 here, the gradient-step point v below, then x^{k+1}
-  double sj1[1] = {0.0};
+  double sj1[3] = {0.0, 0.0, 0.0};  // sum_{J1} H_M(w_j); Gram mode: x^T (b + h), b^T x
 #pragma unroll
   for (int e = 0; e < EPT; e++) x[e] = sv(e) != 3 ? B.h1[tid + (int64_t)e * NT] : 0.0;
 #pragma unroll
   for (int e = 0; e < EPT; e++)
     if (sv(e) == kOne) sj1[0] += huber(x[e] * wscale, M);
-  block_sum<NT, 1>(sj1, lds.red);
+  if (gb) {
+    const double *__restrict__ xcur = parity ? nb.x1 : nb.x0;
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      if (sv(e) == 3) continue;
+      const int64_t j = tid + (int64_t)e * NT;
+      const double xv = xcur[j], bv = gb[j];
+      sj1[1] += xv * (bv + x[e]);
+      sj1[2] += bv * xv;
+    }
+  }
+  block_sum<NT, 3>(sj1, lds.red);
+  if (gb) {
+    // F(X x) = y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F, as
+    // h = b - G x: both from the Gram quantities, no pass over X
+    const double yy = prm->gram_yy;
+    Fk = yy - sj1[1];
+    negconj = 2.0 * (yy - sj1[2]) - Fk;
+  }
   auto wabs = [&](int e) { return sv(e) == kFree ? fabs(x[e] * wscale) : -1.0; };
   const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
   const double psi = negconj - 2.0 * lam2 * (sj1[0] + topsum);
@@ -1095,6 +1116,7 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     lds.bci[0] = done;
     lds.bci[1] = restart;
     lds.bci[2] = ub_improved;
+    lds.bci[3] = improved;
   }
   __syncthreads();
   const double *__restrict__ xc = parity ? nb.x1 : nb.x0;
@@ -1117,6 +1139,11 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
 #pragma unroll
     for (int e = 0; e < EPT; e++)
       if (sv(e) != 3) nb.xbest[tid + (int64_t)e * NT] = xk[e];
+  }
+  if (gb && lds.bci[3]) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) nb.xlb[tid + (int64_t)e * NT] = xk[e];
   }
   if (done) return;
   // gradient step at the momentum point; x[] now holds v

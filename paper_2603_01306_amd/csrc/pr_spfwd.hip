@@ -11,7 +11,9 @@
 //               result does not depend on scheduling) and runs the epilogue:
 //   least squares: r = y - u, F = ||r||^2, -F*(-zeta) = 2 r^T y - ||r||^2;
 //   logistic:      zeta = y sigma(-y u), F, binary entropies, and the gradient
-//                  at the momentum point (1+m)u - m u_prev.
+//                  at the momentum point (1+m)u - m u_prev;
+//   Gram (least squares with X^T X held in memory): the "matrix" is G = X^T X
+//                  and y holds b = X^T y, so the kernel writes h = b - G x.
 // Bytes per launch pair: |list| * n * sizeof(X) + 16 * nch * n (partials)
 // + the epilogue vectors.
 #include "pr_device.h"
@@ -128,6 +130,13 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
     if (active)
 #pragma unroll
       for (int e = 0; e < VEC; e++) u_out[row0 + e] = u[e];
+    return;
+  }
+  if (mode == kSpGram) {
+    // the product is G x over the Gram matrix and y holds b = X^T y: h = b - G x
+    if (active)
+#pragma unroll
+      for (int e = 0; e < VEC; e++) B.h1[row0 + e] = y[row0 + e] - u[e];
     return;
   }
   const int improved = S->improved;

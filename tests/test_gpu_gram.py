@@ -1,0 +1,79 @@
+"""Least squares from the Gram matrix (pr_ctx_enable_gram): h = b - G x in
+place of X x and X^T r.  The per-iterate (Phi, Psi) trace equals the
+matrix-vector path's and the oracle's, bounds match the oracle, and the
+reported bound is recomputed over the stored X."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(inst, dev, gram):
+    import torch
+    import paper_2603_01306_amd as pr
+    if inst.storage == "bf16":
+        X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        X = torch.from_numpy(inst.Xcm).to(dev)
+    c = pr.Context(X, torch.from_numpy(inst.y).to(dev), 0)
+    if gram:
+        c.enable_gram()
+    return c
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f64"])
+def test_gram_trace_matches_oracle_and_matvec_path(dev, storage):
+    import torch
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=512, corr=0.7, k_true=8, snr=5.0, loss=0, seed=12, storage=storage)
+    L = 2.02 * float(np.linalg.eigvalsh(inst.X64() @ inst.X64().T).max())
+    node = pr.Node(8, 0.3, 2.0, J0=[1, 9], J1=[4])
+    its = 60
+    traces = []
+    for gram in (False, True):
+        c = _ctx(inst, dev, gram)
+        tr = torch.full((2 * (its + 1),), float("nan"), dtype=torch.float64, device=dev)
+        c.solve(node, rel_gap_tol=0.0, max_iter=its, L=L, trace=tr)
+        traces.append(tr.cpu().numpy().reshape(-1, 2))
+        c.close()
+    ref = oracle.solve(inst.Xcm, inst.y, 0, 0.3, 2.0, 8, status=node.status(inst.p), L=L, tol=0.0,
+                       max_iter=its, trace_cap=its + 1)
+    ophi = ref["phi_trace"]
+    fin = np.isfinite(ophi)
+    for t in traces:
+        assert np.array_equal(np.isfinite(t[:, 0]), fin)
+        assert np.all(np.abs(t[fin, 0] - ophi[fin]) <= 1e-10 * np.abs(ophi[fin]))
+        assert np.all(np.abs(t[:, 1] - (ophi - ref["trace"])) <= 1e-10 * abs(ophi[-1]))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_gram_bound_is_certified_over_x(dev, storage):
+    import torch
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=2048, p=1024, corr=0.8, k_true=10, snr=5.0, loss=0, seed=13, storage=storage)
+    c = _ctx(inst, dev, True)
+    node = pr.Node(10, 0.2, 2.0, J0=[0, 5, 77], J1=[100])
+    r = c.solve(node, rel_gap_tol=1e-7, want_zeta=True)
+    ref = oracle.solve(inst.Xcm, inst.y, 0, 0.2, 2.0, 10, status=node.status(inst.p), tol=1e-10)
+    assert r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-7
+    assert abs(r["lower_bound"] - ref["lb"]) <= 2e-7 * abs(ref["ub"])
+    st = node.status(inst.p)
+    zeta = r["zeta"].cpu().numpy()
+    psi = oracle.dual(inst.Xcm, inst.y, zeta, 0, 0.2, 2.0, 10, status=st)
+    assert abs(psi - r["lower_bound"]) <= 1e-11 * abs(psi)            # the reported bound is Psi(zeta) over X
+    phi = oracle.primal(inst.Xcm, inst.y, r["beta"].cpu().numpy(), 0, 0.2, 2.0, 10, status=st)
+    assert abs(phi - r["primal"]) <= 1e-11 * abs(phi)
+    c.close()
+
+
+def test_gram_rejects_unsupported_shapes(dev):
+    import torch
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=300, p=200, corr=0.5, k_true=5, snr=5.0, loss=0, seed=1, storage="f64")
+    c = _ctx(inst, dev, False)
+    with pytest.raises(pr.PrError):
+        c.enable_gram()                       # p not a multiple of 128
+    c.close()
