@@ -18,6 +18,10 @@ together by pr_solve_batch to the same 1e-6 FP64 gap, against the single-node
 path on the first nodes of the same list; its GEMMs against the FP64 MFMA
 roofline.
 
+"gram": the same root solve with the least-squares Gram mode on (G = X^T X
+formed once per design, timed apart; each iteration then reads only the Gram
+columns of the current support), with the number of solves that repay G.
+
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
   python bench.py --learned [--pairs N] [--epochs E]   # learned warm start experiment
@@ -183,6 +187,36 @@ def batch_bench(dev, steps, n_single=16):
     out["speedup_vs_single"] = round(out["value"] / out["single_path"]["value"], 2)
     ctx.close()
     return out
+
+
+def gram_bench(ctx, node, cfg, steps, ref):
+    """The same root solves with the least-squares Gram mode on: G = X^T X is
+    formed once per design (timed apart, like ||X||^2) and each iteration reads
+    only the Gram columns of the current support.  Same iterates up to
+    rounding, same certified bound (recomputed over X before it is returned)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.enable_gram()
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    ctx.solve(node, want_beta=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [ctx.solve(node, want_beta=False) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(r["iters"] for r in res)
+    lb = res[-1]["lower_bound"]
+    t_mv = 1.0 / ref["value"]
+    t_g = dt / steps
+    return {"value": round(steps / dt, 3), "unit": "node relaxations/s", "steps": steps,
+            "ms_per_step": round(1e3 * t_g, 3), "iters_per_solve": iters / steps,
+            "us_per_iter": round(1e6 * dt / iters, 2),
+            "all_converged": all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in res),
+            "gram_setup_s": round(setup, 4),
+            "break_even_solves": round(setup / max(t_mv - t_g, 1e-12), 1),
+            "lower_bound": lb, "lower_bound_rel_diff_vs_matvec": abs(lb - ref["lower_bound"]) / abs(lb)}
 
 
 def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
@@ -391,6 +425,7 @@ def main():
     ap.add_argument("--kernel-probe", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
+    ap.add_argument("--gram-steps", type=int, default=10, help="timed root solves in Gram mode (0 skips them)")
     ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
@@ -450,6 +485,8 @@ def main():
             "all_converged": ok, "lower_bound": results[-1]["lower_bound"],
             "setup_s_per_matrix": round(setup_s, 3),
             "roofline": roof}
+    if args.gram_steps > 0:
+        line["gram"] = gram_bench(ctx, node, cfg, args.gram_steps, line)
     ctx.close()
     if args.batch_steps > 0:
         line["batch"] = batch_bench(dev, args.batch_steps)

@@ -40,6 +40,8 @@ struct pr_ctx {
   NodeState *d_state = nullptr;
   NodeState *h_state = nullptr;  // pinned, 2 slots
   int8_t *d_status = nullptr;
+  uint32_t *d_stp = nullptr;     // the status packed 2 bits per entry (NodeParams::stp)
+  std::vector<uint32_t> h_stp;
   NodeBufs nb{};
   ProbBufs B{};
   int32_t *iota = nullptr;
@@ -95,6 +97,22 @@ struct pr_ctx {
 
 namespace {
 
+// Status in the packed layout of NodeParams::stp (3 = beyond p).
+void pack_status(const std::vector<int8_t> &st, std::vector<uint32_t> &w) {
+  const int64_t p = (int64_t)st.size();
+  const int64_t T = kNodeThreads;
+  for (size_t k = 0; k < w.size(); k++) {
+    const int64_t q = (int64_t)k / T, t = (int64_t)k % T;
+    uint32_t v = 0u;
+    for (int i = 0; i < 16; i++) {
+      const int64_t j = t + (16 * q + i) * T;
+      const uint32_t code = (j < p) ? (uint32_t)st[(size_t)j] : 3u;
+      v |= code << (2 * i);
+    }
+    w[k] = v;
+  }
+}
+
 void free_ctx(pr_ctx *c) {
   if (!c) return;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -110,7 +128,7 @@ void free_ctx(pr_ctx *c) {
     if (c->tev[i]) (void)hipEventDestroy(c->tev[i]);
   }
   if (c->cap) (void)hipStreamDestroy(c->cap);
-  void *bufs[] = {c->d_prm, c->d_state, c->d_status, c->nb.x0, c->nb.x1, c->nb.xbest, c->nb.hprev, c->nb.vbuf,
+  void *bufs[] = {c->d_prm, c->d_state, c->d_status, c->d_stp, c->nb.x0, c->nb.x1, c->nb.xbest, c->nb.hprev, c->nb.vbuf,
                   c->nb.abuf, c->nb.sidx, c->nb.sval, c->B.r, c->B.gm, c->B.ucur, c->B.uprev,
                   c->B.zbest, c->B.h1, c->B.h2, c->B.part, c->B.rbsum, c->iota,
                   c->d_np, c->d_u, c->d_v, c->d_w, c->d_scal, c->d_lam, c->d_regscratch};
@@ -174,13 +192,16 @@ int check_opts(const pr_opts *o) {
 double curvature(int loss) { return loss == kLsq ? 2.0 : 0.25; }
 
 // One iteration unit: column-list GEMV + loss epilogue, X^T pass, node step.
-hipError_t enqueue_unit(pr_ctx *c, hipStream_t s) {
+// `unit` is the unit's position in the captured graph (its parity selects the
+// x buffers; see StepArgs).
+hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
+  const StepArgs a{c->P.p, c->d_stp, c->gram ? c->gb : nullptr, unit & 1};
   if (c->gram) {
     // h = b - G x over the support of x, then the node step
     hipError_t e = launch_spfwd(c->PG, c->BG, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, kSpGram, c->d_state,
                                 nullptr, s);
     if (e != hipSuccess) return e;
-    return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s);
+    return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s, &a);
   }
   const int mode = c->P.loss == kLsq ? kSpLsq : kSpLogistic;
   hipError_t e = launch_spfwd(c->P, c->B, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, mode, c->d_state,
@@ -189,10 +210,14 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s) {
   e = launch_gemv_t(c->P, c->B.r, c->P.loss == kLsq ? nullptr : c->B.gm, c->B.h1, c->B.h2,
                     &c->d_state->done, s);
   if (e != hipSuccess) return e;
-  return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s);
+  return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s, &a);
 }
 
+// The iteration graph: `units` iterations rounded up to an even count, so that
+// every launch starts with x^k in the first buffer (iterations after the node
+// is done exit at once).
 int ensure_graph(pr_ctx *c, int32_t units) {
+  units += units & 1;
   if (c->gexec && c->graph_units == units) return PR_OK;
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
@@ -201,7 +226,7 @@ int ensure_graph(pr_ctx *c, int32_t units) {
   hipGraph_t g = nullptr;
   PR_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int i = 0; i < units && e == hipSuccess; i++) e = enqueue_unit(c, c->cap);
+  for (int i = 0; i < units && e == hipSuccess; i++) e = enqueue_unit(c, c->cap, i);
   hipError_t e2 = hipStreamEndCapture(c->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -493,6 +518,8 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   ok = ok && dalloc(&c->d_prm, 1) == hipSuccess && dalloc(&c->d_state, 1) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_state, 2 * sizeof(NodeState), hipHostMallocDefault) == hipSuccess;
   ok = ok && dalloc(&c->d_status, p) == hipSuccess;
+  c->h_stp.assign((size_t)kNodeThreads * (size_t)((p + 16 * kNodeThreads - 1) / (16 * kNodeThreads)), 0u);
+  ok = ok && dalloc(&c->d_stp, c->h_stp.size()) == hipSuccess;
   ok = ok && dalloc(&c->nb.x0, p) == hipSuccess && dalloc(&c->nb.x1, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.xbest, p) == hipSuccess && dalloc(&c->nb.xlb, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.hprev, p) == hipSuccess && dalloc(&c->nb.vbuf, p) == hipSuccess;
@@ -693,7 +720,11 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   prm.trace = opts.trace;
   prm.gram_b = c->gram ? c->gb : nullptr;
   prm.gram_yy = c->gyy;
+  prm.stp = c->d_stp;
+  pack_status(st, c->h_stp);
   PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, c->stream));
+  PR_TRY(hipMemcpyAsync(c->d_stp, c->h_stp.data(), sizeof(uint32_t) * c->h_stp.size(), hipMemcpyHostToDevice,
+                        c->stream));
   PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
   PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, p, c->stream));
   rc = ensure_graph(c, opts.check_every);

@@ -20,6 +20,13 @@ typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations and meets the other waves, but leaves its global stores in
+// flight (a full __syncthreads also waits for every outstanding global
+// access).  Only for code whose threads do not read each other's global
+// writes within the kernel.
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // One DPP move of a double (two 32-bit halves); lanes outside row_mask, or
 // reading outside their row, receive `idb` (the identity's bit pattern).
 template <int CTRL, int ROWMASK>

@@ -26,6 +26,10 @@ enum { kFistaGap = 0, kFista = 1, kFistaFv = 2, kPgd = 3 };
 
 struct NodeParams {
   const int8_t *st;   // status, p entries
+  // the same status packed 2 bits per entry for the register-resident step:
+  // word q * kNodeThreads + t holds entries j = t + (16 q + i) * kNodeThreads,
+  // i = 0 .. 15, in bits 2i, 2i + 1 (3 = beyond p)
+  const uint32_t *stp;
   int64_t p, pbar;
   int32_t kbar, loss;
   double lambda2, M, eta, tol, cutoff;  // cutoff NaN = off
@@ -55,6 +59,8 @@ struct NodeState {
   int32_t indom;   // current iterate lies in dom g_N
   int32_t tau_iters; // evaluations used by the last threshold search
   int32_t pad[3];
+  double tk;       // kbar-th largest free |w| of the dual at the last iterate (<= 0: none)
+  double tkw;      // relative half-width of the selection window around tk
 };
 
 // Node-local vectors.
@@ -122,8 +128,18 @@ hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx,
 int spfwd_final_blocks(int64_t n);
 hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, const double *beta0,
                             double L, int64_t p, hipStream_t s);
+// Per-context constants of the single-node step, fixed when the iteration
+// graph is captured: p, the packed status (NodeParams::stp), Gram mode's b
+// (NULL: matrix-vector mode) and which x buffer holds x^k in this unit (every
+// graph launch runs an even number of units and starts at parity 0).
+struct StepArgs {
+  int64_t p;
+  const uint32_t *stp;
+  const double *gb;
+  int32_t parity;
+};
 hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
-                            int64_t p, hipStream_t s);
+                            int64_t p, hipStream_t s, const StepArgs *a = nullptr);
 hipError_t launch_batch_init(const NodeParams *prm, NodeState *S, BatchBufs bb, const double *B0, double L,
                              int64_t p, hipStream_t s);
 hipError_t launch_batch_step(const NodeParams *prm, NodeState *S, BatchBufs bb, int64_t p, hipStream_t s);

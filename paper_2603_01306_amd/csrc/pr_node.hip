@@ -992,6 +992,8 @@ __global__ __launch_bounds__(NT) void k_node_init_r(const NodeParams *__restrict
     s.rel_gap = INFINITY;
     s.gval = is.gval;
     s.tau = -1.0;
+    s.tk = -1.0;
+    s.tkw = 0.25;
     s.status = kMaxIter;
     s.nsupp = is.nsupp;
     s.indom = is.indom;
@@ -999,20 +1001,308 @@ __global__ __launch_bounds__(NT) void k_node_init_r(const NodeParams *__restrict
   }
 }
 
+// ---- single-node step, latency-ordered
+//
+// One workgroup owns the node.  Every global load of the step is issued in
+// the prologue (status as packed 2-bit words, X^T r, the two last iterates,
+// the previous gradient), the reductions take one barrier each (two
+// alternating LDS slots), and the dual's top-kbar selection first tries a
+// window around the previous iteration's kbar-th value: when the window
+// brackets the new kbar-th value and holds at most kWinCap entries, one wave
+// sorts them and no radix pass is needed.
+
+// Workgroup sums (and maxima) with one barrier: reduction i writes slot i % 2
+// before its barrier and reads it after.  A thread writes for reduction i + 1
+// only after it has read reduction i's slot, and slot i % 2 is written again
+// by reduction i + 2 only after every thread has passed barrier i + 1, so no
+// second barrier is needed.  Every thread must run the same sequence.
+struct Red2 {
+  double *buf;  // 2 * NW * 8 doubles of LDS
+  int ph;
+  template <int KS, int KM>
+  __device__ __forceinline__ void run(double *s, double *m) {
+    constexpr int K = KS + KM;
+    static_assert(K >= 1 && K <= 8, "at most 8 values per reduction");
+#pragma unroll
+    for (int k = 0; k < KS; k++) s[k] = wave_sum(s[k]);
+#pragma unroll
+    for (int k = 0; k < KM; k++) m[k] = wave_max(m[k]);
+    double *r = buf + ph * (NW * 8);
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int k = 0; k < KS; k++) r[wave_id() * K + k] = s[k];
+#pragma unroll
+      for (int k = 0; k < KM; k++) r[wave_id() * K + KS + k] = m[k];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < KS; k++) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; w++) acc += r[w * K + k];
+      s[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < KM; k++) {
+      double acc = r[KS + k];
+      for (int w = 1; w < NW; w++) acc = fmax(acc, r[w * K + KS + k]);
+      m[k] = acc;
+    }
+    ph ^= 1;
+  }
+  template <int KS>
+  __device__ __forceinline__ void sum(double (&s)[KS]) {
+    run<KS, 0>(s, nullptr);
+  }
+  template <int KS, int KM>
+  __device__ __forceinline__ void summax(double (&s)[KS], double (&m)[KM]) {
+    run<KS, KM>(s, m);
+  }
+};
+
+constexpr int kWinCap = 64;  // window entries one wave sorts
+
+template <int EPT>
+struct StepLds {
+  double red[2 * NW * 8];
+  SelLds sel;
+  int cnt[EPT * NW];       // support entries per (e, wave) group
+  int ofs[NW][EPT * NW];   // each wave's copy of their exclusive prefix
+  double bcd[4];
+  int bci[4];
+};
+
+template <int EPT>
+__device__ __forceinline__ void load_packed_status(PackedStatus<EPT> &sv, const uint32_t *__restrict__ stp) {
+#pragma unroll
+  for (int q = 0; q < (EPT + 15) / 16; q++) sv.w[q] = stp[q * NT + threadIdx.x];
+}
+
+template <int EPT, class F>
+__device__ __forceinline__ double solve_tau_2(F aval, int kbar, double rho, double M, double warm, Red2 &R, int *evals) {
+  double st[2] = {0.0, 0.0};
+  double mx[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const double x = aval(e);
+    if (x > 0.0) {
+      st[0] += 1.0;
+      st[1] += x;
+      mx[0] = fmax(mx[0], x);
+    }
+  }
+  R.summax(st, mx);
+  const double amax = mx[0];
+  *evals = 0;
+  if (kbar <= 0) return INFINITY;
+  const double K = (double)kbar;
+  if (st[0] <= K) return 0.0;
+  const bool finM = isfinite(M);
+  auto Dof = [&](double t) { return finM ? fmin(t / rho, M) : t / rho; };
+  auto froot = [&](double h, double nb, double sB) -> double {
+    if (nb <= 0.0) return NAN;
+    if (finM) {
+      const double Sf = h + (sB - nb * rho * M) / M;
+      if (Sf >= K) return (sB - M * (K - h)) / nb;
+    }
+    return rho * sB / (K - h + rho * nb);
+  };
+  double lo = 0.0, hi = amax;
+  double tau = (warm > lo && warm < hi) ? warm : froot(0.0, st[0], st[1]);
+  if (!(tau > lo && tau < hi)) tau = 0.5 * (lo + hi);
+  bool from_root = false;
+  double ph = -1.0, pb = -1.0;
+  int nsteps = 0;
+  double wref = hi - lo;
+  for (int it = 0; it < 200; it++) {
+    const double D = Dof(tau);
+    double v[3] = {0.0, 0.0, 0.0};
+    const double top = tau + D;
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double x = aval(e);
+      if (x > tau) {
+        v[1] += 1.0;
+        if (x > top) v[0] += 1.0;
+        else v[2] += x;
+      }
+    }
+    R.sum(v);
+    *evals = it + 1;
+    if (from_root && v[0] == ph && v[1] == pb) return tau;
+    const double S = v[0] + (v[2] - (v[1] - v[0]) * tau) / D;
+    if (S > K) lo = tau;
+    else if (S < K) hi = tau;
+    else return tau;
+    double c = froot(v[0], v[1] - v[0], v[2]);
+    if (c == tau) return tau;
+    if (nsteps >= 2 && hi - lo > 0.5 * wref) {
+      nsteps = 0;
+      wref = hi - lo;
+      c = NAN;
+    }
+    if (c > lo && c < hi) {
+      from_root = true;
+      nsteps++;
+    } else {
+      c = 0.5 * (lo + hi);
+      from_root = false;
+      nsteps = 0;
+      wref = hi - lo;
+    }
+    ph = v[0];
+    pb = v[1];
+    if (!(c > lo && c < hi)) return c;
+    tau = c;
+  }
+  return tau;
+}
+
+template <int EPT, class F>
+__device__ __forceinline__ double alg1_2(F aval, int kbar, double theta, Red2 &R) {
+  if (kbar <= 0 || !(theta > 0.0)) return 0.0;
+  const double K = (double)kbar;
+  double s = theta / K;
+  double prevK = 0.0;
+  for (int it = 0; it <= kbar + 1; it++) {
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double x = aval(e);
+      if (x >= 0.0) {
+        if (x > s) {
+          v[0] += 1.0;
+          v[2] += x * x;
+        } else {
+          v[1] += x;
+        }
+      }
+    }
+    R.sum(v);
+    if (v[0] == prevK || v[0] >= K) return 0.5 * (v[2] + (K - v[0]) * s * s);
+    prevK = v[0];
+    s = fmin(s, v[1] / (K - v[0]));
+  }
+  return NAN;
+}
+
+// Support list (ascending j), Algorithm 1 value and dom test of the iterate x
+// held in registers.  Groups (e, wave) come in j order o = e * NW + w; after
+// one barrier every wave scans all group counts itself.
+template <int EPT>
+__device__ __forceinline__ IterStats finish_2(const double (&x)[EPT], const PackedStatus<EPT> &sv, int kbar, double M,
+                              int32_t *__restrict__ sidx, double *__restrict__ sval, StepLds<EPT> &L, Red2 &R) {
+  constexpr int NO = EPT * NW;
+  constexpr int C = (NO + 63) / 64;
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+  double sm[2] = {0.0, 0.0};       // theta, sum_{J1} x^2
+  double mx[3] = {0.0, 0.0, 0.0};  // max |x|, over J0, over the box coordinates
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    const double xj = x[e];
+    const double ax = fabs(xj);
+    if (s != 3) {
+      mx[0] = fmax(mx[0], ax);
+      if (s == kZero) mx[1] = fmax(mx[1], ax);
+      else mx[2] = fmax(mx[2], ax);
+      if (s == kFree) sm[0] += ax;
+      else if (s == kOne) sm[1] += xj * xj;
+    }
+    const unsigned long long mk = __ballot(s != 3 && xj != 0.0);
+    if (lane == 0) L.cnt[e * NW + w] = __popcll(mk);
+  }
+  lds_barrier();
+  int c[C];
+  int loc = 0;
+#pragma unroll
+  for (int q = 0; q < C; q++) {
+    const int o = lane * C + q;
+    c[q] = (o < NO) ? L.cnt[o] : 0;
+    loc += c[q];
+  }
+  int incl = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int tot = __shfl(incl, 63, 64);
+  int run = incl - loc;
+#pragma unroll
+  for (int q = 0; q < C; q++) {
+    const int o = lane * C + q;
+    if (o < NO) L.ofs[w][o] = run;
+    run += c[q];
+  }
+  __asm__ volatile("" ::: "memory");  // this wave's LDS writes stay ahead of its reads
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const bool nz = sv(e) != 3 && x[e] != 0.0;
+    const unsigned long long mk = __ballot(nz);
+    if (nz) {
+      const uint32_t pos = (uint32_t)(L.ofs[w][e * NW + w] + __popcll(mk & below));
+      sidx[pos] = (int32_t)(tid + e * NT);
+      sval[pos] = x[e];
+    }
+  }
+  R.summax(sm, mx);
+  const double gA = mx[0], g0 = mx[1], gB = mx[2];
+  const double zt = 1e-9 * fmax(1.0, gA);
+  int ok = (g0 <= zt);
+  if (isfinite(M) && gB > M * (1.0 + 1e-9)) ok = 0;
+  if (kbar == 0) {
+    if (sm[0] > zt) ok = 0;
+  } else if (isfinite(M) && sm[0] > M * (double)kbar * (1.0 + 1e-9)) {
+    ok = 0;
+  }
+  auto aval = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
+  const double gv = 0.5 * sm[1] + alg1_2<EPT>(aval, kbar, sm[0], R);
+  return IterStats{gv, ok, tot};
+}
+
 template <int EPT>
 __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict__ prm, NodeState *S,
-                                                    NodeBufs nb, ProbBufs B) {
-  __shared__ NodeLds lds;
-  if (S->done) return;
+                                                    NodeBufs nb, ProbBufs B, StepArgs A) {
+  __shared__ StepLds<EPT> lds;
   const int tid = threadIdx.x;
-  const int64_t p = prm->p;
+  const int64_t p = A.p;
+  const double *__restrict__ gb = A.gb;
+  const int parity = A.parity;
+  // scalar state and parameters: independent loads, issued together with the
+  // vector loads below; the done test waits for them only after those
+  const int done0 = S->done, indom0 = S->indom;
+  const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw;
   const int kbar = prm->kbar, loss = prm->loss;
   const double lam2 = prm->lambda2, M = prm->M;
-  const int parity = S->parity;
-  const double L = S->L;
+  const double *__restrict__ xc = parity ? nb.x1 : nb.x0;
+  double *__restrict__ xn = parity ? nb.x0 : nb.x1;  // holds x^{k-1}, receives x^{k+1}
+  // the loads of the step: X^T r (Gram mode: b - G x), x^k and b first; the
+  // operands of the gradient step (x^{k-1}, previous gradient) are issued
+  // once b has been consumed and arrive during the dual evaluation (with 16
+  // or more entries per thread they are loaded at the gradient step instead,
+  // which keeps the selection passes out of scratch memory)
+  constexpr bool kPre = EPT <= 8;
   PackedStatus<EPT> sv;
-  sv.load(prm->st, p);
-  const double *__restrict__ gb = prm->gram_b;
+  load_packed_status<EPT>(sv, A.stp);
+  double x[EPT], xk[EPT], xq[EPT], g2[EPT];
+  double r1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  {
+    double bv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      const bool in = j < (uint32_t)p;
+      x[e] = in ? B.h1[j] : 0.0;
+      xk[e] = in ? xc[j] : 0.0;
+      bv[e] = (in && gb) ? gb[j] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      r1[1] += xk[e] * (bv[e] + x[e]);
+      r1[2] += bv[e] * xk[e];
+    }
+  }
   // loss sums of the finalize blocks: lane-parallel loads, fixed-order wave sums
   double Fk = 0.0, negconj = 0.0;
   if (!gb) {
@@ -1020,42 +1310,90 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
       Fk += B.rbsum[2 * i];
       negconj += B.rbsum[2 * i + 1];
     }
+  }
+  if (done0) return;
+  const double *__restrict__ gp = (loss == kLsq) ? nb.hprev : B.h2;
+  if (kPre) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      const bool in = j < (uint32_t)p;
+      xq[e] = in ? xn[j] : 0.0;
+      g2[e] = in ? gp[j] : 0.0;
+    }
+  }
+  Red2 R;
+  R.buf = lds.red;
+  R.ph = 0;
+  if (tid == 0) lds.sel.ngat = 0;
+  if (!gb) {
     Fk = wave_sum(Fk);
     negconj = wave_sum(negconj);
   }
-  // dual value at x^k: w = X^T zeta / (2 lambda2)
+  // dual value at x^k: w = X^T zeta / (2 lambda2); the top-kbar window of
+  // free |w| around the previous kbar-th value
   const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
-  double x[EPT];  // h = B.h1 here, the gradient-step point v below, then x^{k+1}
-  double sj1[3] = {0.0, 0.0, 0.0};  // sum_{J1} H_M(w_j); Gram mode: x^T (b + h), b^T x
+  const bool wv = tkp > 0.0 && kbar > 0;
+  const double wa = wv ? tkp * (1.0 - dlt) : INFINITY, wb = wv ? tkp * (1.0 + dlt) : INFINITY;
+  // r1: sum_{J1} H_M(w_j); Gram: x^T (b + h), b^T x; #{w > wb}, #{w >= wa}, sum_{w > wb} H_M(w)
 #pragma unroll
-  for (int e = 0; e < EPT; e++) x[e] = sv(e) != 3 ? B.h1[tid + (int64_t)e * NT] : 0.0;
-#pragma unroll
-  for (int e = 0; e < EPT; e++)
-    if (sv(e) == kOne) sj1[0] += huber(x[e] * wscale, M);
-  if (gb) {
-    const double *__restrict__ xcur = parity ? nb.x1 : nb.x0;
-#pragma unroll
-    for (int e = 0; e < EPT; e++) {
-      if (sv(e) == 3) continue;
-      const int64_t j = tid + (int64_t)e * NT;
-      const double xv = xcur[j], bv = gb[j];
-      sj1[1] += xv * (bv + x[e]);
-      sj1[2] += bv * xv;
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    if (s == 3) continue;
+    const double w = x[e] * wscale;
+    if (s == kOne) r1[0] += huber(w, M);
+    if (s == kFree) {
+      const double aw = fabs(w);
+      if (aw > wb) {
+        r1[3] += 1.0;
+        r1[5] += huber(aw, M);
+      }
+      if (aw >= wa) r1[4] += 1.0;
     }
   }
-  block_sum<NT, 3>(sj1, lds.red);
+  R.sum(r1);
   if (gb) {
     // F(X x) = y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F, as
     // h = b - G x: both from the Gram quantities, no pass over X
     const double yy = prm->gram_yy;
-    Fk = yy - sj1[1];
-    negconj = 2.0 * (yy - sj1[2]) - Fk;
+    Fk = yy - r1[1];
+    negconj = 2.0 * (yy - r1[2]) - Fk;
   }
   auto wabs = [&](int e) { return sv(e) == kFree ? fabs(x[e] * wscale) : -1.0; };
-  const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
-  const double psi = negconj - 2.0 * lam2 * (sj1[0] + topsum);
-  const double phi = S->indom ? Fk + 2.0 * lam2 * S->gval : INFINITY;
+  const double cgt = r1[3], cge = r1[4];
+  const bool fast = wv && cgt < (double)kbar && (double)kbar <= cge && cge - cgt <= (double)kWinCap;
+  double topsum = 0.0, tkn = -1.0;
+  if (kbar > 0 && fast) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double aw = wabs(e);
+      if (aw >= wa && aw <= wb) lds.sel.gat[atomicAdd(&lds.sel.ngat, 1)] = aw;
+    }
+    lds_barrier();
+    if (wave_id() == 0) {
+      const int lane = lane_id();
+      const int cw = (int)(cge - cgt);
+      const int mm = kbar - (int)cgt;  // 1 <= mm <= cw
+      double v = (lane < cw) ? lds.sel.gat[lane] : -1.0;
+      v = wave_sort_desc(v);
+      tkn = __shfl(v, mm - 1, 64);
+      topsum = r1[5] + wave_sum(lane < mm ? huber(v, M) : 0.0);
+    }
+  } else if (kbar > 0) {
+    tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+    const double Ht = huber(tkn, M);
+    double v1[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double aw = wabs(e);
+      if (aw >= 0.0) v1[0] += fmax(huber(aw, M) - Ht, 0.0);
+    }
+    R.sum(v1);
+    topsum = (double)kbar * Ht + v1[0];
+  }
   if (tid == 0) {
+    const double psi = negconj - 2.0 * lam2 * (r1[0] + topsum);
+    const double phi = indom0 ? Fk + 2.0 * lam2 * gval0 : INFINITY;
     const int it = S->iter;
     if (prm->trace && it <= prm->max_iter) {
       prm->trace[2 * it] = phi;
@@ -1100,6 +1438,11 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
         t = tn;
       }
     }
+    // next window: twice the relative move of the kbar-th value, narrowed when
+    // the window held the value but had too many entries
+    double tw = 0.25;
+    if (wv && tkn > 0.0) tw = fmin(0.25, fmax(1e-12, 2.0 * fabs(tkn - tkp) / tkn));
+    if (wv && !fast && cgt < (double)kbar && (double)kbar <= cge) tw = fmin(tw, 0.25 * dlt);
     S->phi = phi;
     S->psi = psi;
     S->lb = lb;
@@ -1111,6 +1454,8 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     S->gap_ref = gap_ref;
     S->restarts = restarts;
     S->mom = m;
+    S->tk = tkn;
+    S->tkw = tw;
     if (done) S->done = 1;
     lds.bcd[0] = m;
     lds.bci[0] = done;
@@ -1118,34 +1463,31 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     lds.bci[2] = ub_improved;
     lds.bci[3] = improved;
   }
-  __syncthreads();
-  const double *__restrict__ xc = parity ? nb.x1 : nb.x0;
-  double *__restrict__ xn = parity ? nb.x0 : nb.x1;  // holds x^{k-1}, receives x^{k+1}
+  lds_barrier();
   const bool done = lds.bci[0] != 0;
   const double m = lds.bcd[0];
   const int restart = lds.bci[1];
   const double invL = 1.0 / L;
-  // every load of the step first, then the arithmetic, then the stores
-  double xk[EPT], xq[EPT], g2[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const int64_t j = tid + (int64_t)e * NT;
-    const bool in = sv(e) != 3;
-    xk[e] = in ? xc[j] : 0.0;
-    xq[e] = (in && !done) ? xn[j] : 0.0;
-    g2[e] = (in && !done && (loss == kLsq || !restart)) ? (loss == kLsq ? nb.hprev[j] : B.h2[j]) : 0.0;
-  }
   if (lds.bci[2]) {
 #pragma unroll
     for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.xbest[tid + (int64_t)e * NT] = xk[e];
+      if (sv(e) != 3) nb.xbest[(uint32_t)(tid + e * NT)] = xk[e];
   }
   if (gb && lds.bci[3]) {
 #pragma unroll
     for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.xlb[tid + (int64_t)e * NT] = xk[e];
+      if (sv(e) != 3) nb.xlb[(uint32_t)(tid + e * NT)] = xk[e];
   }
   if (done) return;
+  if (!kPre) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      const bool in = j < (uint32_t)p;
+      xq[e] = in ? xn[j] : 0.0;
+      g2[e] = in ? gp[j] : 0.0;
+    }
+  }
   // gradient step at the momentum point; x[] now holds v
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
@@ -1160,12 +1502,12 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   if (loss == kLsq) {
 #pragma unroll
     for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.hprev[tid + (int64_t)e * NT] = g2[e];
+      if (sv(e) != 3) nb.hprev[(uint32_t)(tid + e * NT)] = g2[e];
   }
   const double rho = 2.0 * lam2 * invL;
   int evals = 0;
   auto vabs = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
-  const double tau = solve_tau_f<EPT>(vabs, kbar, rho, M, S->tau, lds.red, &evals);
+  const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
   const double inv1p = 1.0 / (1.0 + rho);
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
@@ -1178,11 +1520,11 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
         if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
         xv = (r == 0.0) ? 0.0 : copysign(r, x[e]);
       }
-      xn[tid + (int64_t)e * NT] = xv;
+      xn[(uint32_t)(tid + e * NT)] = xv;
     }
     x[e] = xv;
   }
-  IterStats is = finish_r<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds);
+  IterStats is = finish_2<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds, R);
   if (tid == 0) {
     S->gval = is.gval;
     S->indom = is.indom;
@@ -1244,6 +1586,8 @@ __global__ __launch_bounds__(NT) void k_batch_init(const NodeParams *__restrict_
     s.rel_gap = INFINITY;
     s.gval = is.gval;
     s.tau = -1.0;
+    s.tk = -1.0;
+    s.tkw = 0.25;
     s.status = kMaxIter;
     s.nsupp = is.nsupp;
     s.indom = is.indom;
@@ -1447,14 +1791,16 @@ hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, co
 }
 
 hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
-                            int64_t p, hipStream_t s) {
-  switch (node_ept(p)) {
-    case 1: k_node_step_r<1><<<1, NT, 0, s>>>(prm, S, nb, B); break;
-    case 2: k_node_step_r<2><<<1, NT, 0, s>>>(prm, S, nb, B); break;
-    case 4: k_node_step_r<4><<<1, NT, 0, s>>>(prm, S, nb, B); break;
-    case 8: k_node_step_r<8><<<1, NT, 0, s>>>(prm, S, nb, B); break;
-    case 16: k_node_step_r<16><<<1, NT, 0, s>>>(prm, S, nb, B); break;
-    case 32: k_node_step_r<32><<<1, NT, 0, s>>>(prm, S, nb, B); break;
+                            int64_t p, hipStream_t s, const StepArgs *a) {
+  const int ept = node_ept(p);
+  if (ept != 0 && !a) return hipErrorInvalidValue;
+  switch (ept) {
+    case 1: k_node_step_r<1><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
+    case 2: k_node_step_r<2><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
+    case 4: k_node_step_r<4><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
+    case 8: k_node_step_r<8><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
+    case 16: k_node_step_r<16><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
+    case 32: k_node_step_r<32><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
     default: k_node_step<<<1, NT, 0, s>>>(prm, S, nb, B); break;
   }
   return hipGetLastError();
