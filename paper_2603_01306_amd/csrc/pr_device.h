@@ -232,22 +232,18 @@ __device__ __forceinline__ void load_rhs(const double *__restrict__ r, int64_t i
   }
 }
 
-// Deterministic transpose-reduction of 4 per-lane partial sums (one per
-// column) over the 64 lanes: afterwards lane 16*c holds the total of column c.
-__device__ __forceinline__ double reduce4(double (&v)[4]) {
-  const int lane = lane_id();
-  const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
-  double s0 = b5 ? v[0] : v[2], s1 = b5 ? v[1] : v[3];
-  double k0 = b5 ? v[2] : v[0], k1 = b5 ? v[3] : v[1];
-  k0 += __shfl_xor(s0, 32, 64);
-  k1 += __shfl_xor(s1, 32, 64);
-  double s = b4 ? k0 : k1;
-  double k = b4 ? k1 : k0;
-  k += __shfl_xor(s, 16, 64);
+// Deterministic transpose-reduction of 2 per-lane partial sums (one per
+// column) over the 64 lanes: afterwards lane 32*c holds the total of column c.
+__device__ __forceinline__ double reduce2(double (&v)[2]) {
+  const bool b5 = (lane_id() & 32) != 0;
+  const double s = b5 ? v[0] : v[1];
+  double k = b5 ? v[1] : v[0];
+  k += __shfl_xor(s, 32, 64);
 #pragma unroll
-  for (int o = 8; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+  for (int o = 16; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
   return k;
 }
+
 
 
 }  // namespace dev

@@ -1,13 +1,15 @@
 // X^T r on gfx950: h = X^T r (one or two right-hand sides) for column-major X
 // stored FP32 / BF16 / FP64, accumulated in FP64.
 //
-// One wave per 4 adjacent columns streams the full column length: each lane
-// loads 16 bytes of every column per step with non-temporal loads (X is read
-// once per launch and should not displace the L2-resident right-hand side),
-// one row step per lane in flight (4 loads; a measured sweep over 1, 2, 4
-// steps on MI355X favoured 1, which leaves the most waves resident), then a deterministic in-wave transpose reduction
-// leaves column c's total in lane 16c.  Algorithmic bytes per launch:
-// n*p*sizeof(X) + 8n per right-hand side + 8p per output.
+// One wave per kColsPerWave adjacent columns streams the full column length:
+// each lane loads 16 bytes of every column per step with non-temporal loads
+// (X is read once per launch and should not displace the L2-resident
+// right-hand side), one row step per lane in flight (a measured sweep over
+// 1, 2, 4 steps on MI355X favoured 1), then a deterministic in-wave transpose
+// reduction leaves column c's total in lane 32c.  Two columns per wave (a
+// sweep over 1, 2, 4, 8) give twice the waves of four, which the HBM stream
+// needs to stay full.  Algorithmic bytes per launch: n*p*sizeof(X) + 8n per
+// right-hand side + 8p per output.
 #include "pr_device.h"
 
 namespace pr {
@@ -30,26 +32,27 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
   const int lane = lane_id();
   const int64_t col0 = ((int64_t)blockIdx.x * (kGemvThreads / 64) + wave_id()) * kColsPerWave;
   if (col0 >= p) return;
-  const T *c[4];
+  constexpr int C = kColsPerWave;
+  const T *c[C];
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
+  for (int q = 0; q < C; q++) {
     const int64_t cj = (col0 + q < p) ? col0 + q : p - 1;
     c[q] = X + cj * n;
   }
-  double acc[NRHS][4];
+  double acc[NRHS][C];
 #pragma unroll
   for (int h = 0; h < NRHS; h++)
 #pragma unroll
-    for (int q = 0; q < 4; q++) acc[h][q] = 0.0;
+    for (int q = 0; q < C; q++) acc[h][q] = 0.0;
   const int64_t step = 64 * VEC;
   int64_t i = (int64_t)lane * VEC;
   for (; i + (U - 1) * step + VEC <= n; i += U * step) {
-    double xv[U][4][VEC];
+    double xv[U][C][VEC];
     double rv[U][NRHS][VEC];
 #pragma unroll
     for (int u = 0; u < U; u++) {
 #pragma unroll
-      for (int q = 0; q < 4; q++) XLoad<T>::load(c[q] + i + u * step, xv[u][q]);
+      for (int q = 0; q < C; q++) XLoad<T>::load(c[q] + i + u * step, xv[u][q]);
       load_rhs<VEC>(r1, i + u * step, rv[u][0]);
       if (NRHS > 1) load_rhs<VEC>(r2, i + u * step, rv[u][NRHS - 1]);
     }
@@ -58,32 +61,32 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 #pragma unroll
       for (int h = 0; h < NRHS; h++)
 #pragma unroll
-        for (int q = 0; q < 4; q++)
+        for (int q = 0; q < C; q++)
 #pragma unroll
           for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[u][q][e], rv[u][h][e], acc[h][q]);
   }
   for (; i + VEC <= n; i += step) {
-    double xv[4][VEC];
+    double xv[C][VEC];
     double rv[NRHS][VEC];
 #pragma unroll
-    for (int q = 0; q < 4; q++) XLoad<T>::load(c[q] + i, xv[q]);
+    for (int q = 0; q < C; q++) XLoad<T>::load(c[q] + i, xv[q]);
     load_rhs<VEC>(r1, i, rv[0]);
     if (NRHS > 1) load_rhs<VEC>(r2, i, rv[NRHS - 1]);
 #pragma unroll
     for (int h = 0; h < NRHS; h++)
 #pragma unroll
-      for (int q = 0; q < 4; q++)
+      for (int q = 0; q < C; q++)
 #pragma unroll
         for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[q][e], rv[h][e], acc[h][q]);
   }
-  const int64_t col = col0 + (lane >> 4);
-  const bool writer = (lane & 15) == 0 && col < p;
+  const int64_t col = col0 + (lane >> 5);
+  const bool writer = (lane & 31) == 0 && col < p;
   {
-    double t = reduce4(acc[0]);
+    double t = reduce2(acc[0]);
     if (writer) h1[col] = t;
   }
   if (NRHS > 1) {
-    double t = reduce4(acc[NRHS - 1]);
+    double t = reduce2(acc[NRHS - 1]);
     if (writer) h2[col] = t;
   }
 }
