@@ -16,7 +16,8 @@ CPU oracle on a bounded sample of the same workload.
 sets of sizes 0-64 / 0-19) sharing a BF16 copy of the same design, solved
 together by pr_solve_batch to the same 1e-6 FP64 gap, against the single-node
 path on the first nodes of the same list; its GEMMs against the FP64 MFMA
-roofline.
+roofline; "batch.gram": the same batch in Gram mode (one product G X_it per
+iteration instead of two products with X).
 
 "gram": the same root solve with the least-squares Gram mode on (G = X^T X
 formed once per design, timed apart; each iteration then reads only the Gram
@@ -185,6 +186,32 @@ def batch_bench(dev, steps, n_single=16):
                         "flop_per_launch": flop, "avg_launch_ms": round(ms_t, 4),
                         "forward_avg_launch_ms": round(ms_f, 4)}}
     out["speedup_vs_single"] = round(out["value"] / out["single_path"]["value"], 2)
+    # the same nodes in batched Gram mode: one product G X_it per iteration
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.enable_gram()
+    torch.cuda.synchronize()
+    setup_g = time.perf_counter() - t0
+    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])      # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gruns = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt_g = time.perf_counter() - t0
+    ok_g = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for run in gruns for r in run)
+    lbd = max(abs(a["lower_bound"] - b["lower_bound"]) / abs(b["primal"]) for a, b in zip(gruns[-1], res))
+    ms_g = ctx.time_gram_gemm(m, reps=10)
+    flop_g = 2.0 * inst.p * inst.p * nr
+    ach_g = flop_g / (ms_g * 1e-3) / 1e12
+    git = np.array([r["iters"] for r in gruns[-1]])
+    out["gram"] = {"value": round(m * steps / dt_g, 3), "unit": "node relaxations/s", "steps": steps,
+                   "ms_per_step": round(1e3 * dt_g / steps, 2), "all_converged": ok_g,
+                   "setup_s": round(setup_g, 4), "iters_mean": round(float(git.mean()), 1),
+                   "max_rel_bound_diff_vs_matvec_batch": lbd,
+                   "roofline": {"bound": "mfma", "achieved": round(ach_g, 2), "peak": FP64_MFMA_PEAK_TFS,
+                                "unit": "TFLOP/s", "frac": round(ach_g / FP64_MFMA_PEAK_TFS, 4), "traffic": None,
+                                "kernel": "k_gemm_f64<double,double> (G X_it)", "flop_per_launch": flop_g,
+                                "avg_launch_ms": round(ms_g, 4)}}
     ctx.close()
     return out
 

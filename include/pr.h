@@ -139,9 +139,12 @@ int pr_ctx_norm2(pr_ctx *ctx, double *norm2_out);
  * 2 (y - X x), the same iteration in exact arithmetic.  At the end of each
  * solve the reported bounds are recomputed over the stored X (pr_dual_bound)
  * and a decision they do not confirm is redone on the matrix-vector path.
+ * On a context with the batched path, pr_solve_batch then runs one product
+ * U = G X_it per iteration (FP64 MFMA over the m current iterates; its
+ * reduction split is autotuned here) in place of its two products with X, and
+ * h = b - U; every stopped node is still recertified over the stored X.
  * Requires least squares, p a multiple of 128 and at most 16384, n a multiple
- * of 32; PR_EINVAL otherwise, PR_ENOMEM if G does not fit.  pr_solve_batch is
- * not affected. */
+ * of 32; PR_EINVAL otherwise, PR_ENOMEM if G does not fit. */
 int pr_ctx_enable_gram(pr_ctx *ctx);
 
 /* Solve one node relaxation (Sections 3.3 and 4): FISTA steps
@@ -227,6 +230,15 @@ int pr_batch_tuning(pr_ctx *ctx, int32_t len, int32_t *ksf_out, int32_t *kst_out
  * reps.  The operands are the context's batch buffers (contents irrelevant to
  * timing).  PR_EINVAL unless the context was created with max_batch >= m. */
 int pr_time_batch_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms_fwd, double *ms_t);
+
+/* Batched Gram mode (pr_solve_batch after pr_ctx_enable_gram on a context
+ * with the batched path): each iteration's one product U = G X_it (FP64 MFMA,
+ * X_it the m current iterates) replaces the two products with X.  Time `reps`
+ * back-to-back launches of that product for m active rows in the solve's
+ * configuration (autotuned split, persistent grid), HIP events on the context
+ * stream; *ms = elapsed / reps.  PR_EINVAL unless Gram mode is on, the
+ * context has the batched path and max_batch >= m. */
+int pr_time_gram_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms);
 
 /* FP64 MFMA product used by pr_solve_batch for both of its matrix products
  * (test and measurement entry point): C[z][r][c] = sum over k in split z of

@@ -75,8 +75,12 @@ struct pr_ctx {
   int32_t *d_active = nullptr;
   int32_t *d_rowmap = nullptr;    // [cap padded] slots of the nodes still iterating
   int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split, -, tile counters x2}
-  int32_t *d_ftab = nullptr;      // [2][kTuneMax] tuned split factors per active row-tile count
-  int32_t h_ftab[2 * kTuneMax] = {};
+  int32_t *d_ftab = nullptr;      // [kTuneTables][kTuneMax] tuned split factors per active row-tile count
+  int32_t h_ftab[kTuneTables * kTuneMax] = {};
+  // batched Gram mode: U = G X_it planes [KSG * f][cap padded][p] (CT's storage when it is large enough)
+  int32_t KSG = 1, fmaxG = 1;
+  double *CG = nullptr;
+  bool cg_own = false, gram_batch_ok = false;
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
@@ -117,6 +121,7 @@ void free_ctx(pr_ctx *c) {
   if (!c) return;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
+  if (c->cg_own && c->CG) (void)hipFree(c->CG);
   void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
                 c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb};
   for (void *b : bb)
@@ -378,7 +383,7 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && dalloc(&c->d_bprm, cap) == hipSuccess && dalloc(&c->d_bstate, cap) == hipSuccess;
   ok = ok && dalloc(&c->d_active, 2) == hipSuccess;
   ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 8) == hipSuccess;
-  ok = ok && dalloc(&c->d_ftab, 2 * kTuneMax) == hipSuccess;
+  ok = ok && dalloc(&c->d_ftab, kTuneTables * kTuneMax) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_bstate, sizeof(NodeState) * cap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   if (!ok) return PR_ENOMEM;
@@ -390,6 +395,68 @@ int alloc_batch(pr_ctx *c) {
   int rc = tune_batch(c);
   if (rc != PR_OK) return rc;
   c->batch_ok = true;
+  return PR_OK;
+}
+
+// Batched Gram mode (least squares, after pr_ctx_enable_gram): one product
+// U = G X_it per iteration in place of the two products with X.  Its base
+// split, plane storage and autotuned split table (ftab row 2, same cost model
+// as tune_batch).
+int tune_gram_batch(pr_ctx *c) {
+  const int64_t p = c->P.p;
+  const int NrMax = nr_of(c->max_batch);
+  const int tiles = (int)(p / 128) * (NrMax / 64);
+  int KSG = 1;
+  while (KSG < 16 && tiles * KSG < 512 && (p / (2 * KSG)) % 32 == 0) KSG *= 2;
+  int fG = 1;
+  while (2 * fG <= 16 && (p / (2 * fG * KSG)) % 32 == 0 && p % (2 * fG * KSG) == 0) fG *= 2;
+  c->KSG = KSG;
+  c->fmaxG = fG;
+  if (KSG * fG <= c->KS * c->fmaxT) {
+    c->CG = c->CT;
+    c->cg_own = false;
+  } else {
+    if (dalloc(&c->CG, (size_t)KSG * fG * NrMax * p) != hipSuccess) return PR_ENOMEM;
+    c->cg_own = true;
+  }
+  const int ntmax = NrMax / 64 < kTuneMax - 1 ? NrMax / 64 : kTuneMax - 1;
+  hipStream_t s = c->stream;
+  PR_TRY(launch_iota(c->d_rowmap, NrMax, s));
+  int32_t *cnt = c->d_split + 4;
+  const double plane_bytes = 8.0 * (double)p;
+  for (int nta = 1; nta <= ntmax; nta++) {
+    const int32_t nrow = nta * 64 < c->max_batch ? nta * 64 : c->max_batch;
+    double best = INFINITY;
+    int bestf = 1;
+    for (int f = 1; f <= fG; f *= 2) {
+      const int32_t sp[3] = {nrow, KSG * f, KSG * f};
+      PR_TRY(hipMemcpyAsync(c->d_split, sp, sizeof(sp), hipMemcpyHostToDevice, s));
+      auto launch = [&]() -> hipError_t {
+        hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
+        if (e != hipSuccess) return e;
+        return launch_gemm_any(kF64, c->G, p, kF64, c->Bx, p, c->CG, p, NrMax, p, KSG, nullptr, c->d_rowmap,
+                               c->d_split, c->d_split + 2, KSG * fG, cnt, s);
+      };
+      PR_TRY(launch());
+      PR_TRY(hipEventRecord(c->tev[0], s));
+      for (int r = 0; r < kTuneReps; r++) PR_TRY(launch());
+      PR_TRY(hipEventRecord(c->tev[1], s));
+      PR_TRY(hipEventSynchronize(c->tev[1]));
+      float ms = 0.0f;
+      PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+      const double cost = ms / kTuneReps + 1e3 * (double)(KSG * f) * nrow * plane_bytes / kTunePlaneBW;
+      if (cost < best) {
+        best = cost;
+        bestf = f;
+      }
+    }
+    c->h_ftab[2 * kTuneMax + nta] = bestf;
+  }
+  for (int nta = ntmax + 1; nta < kTuneMax; nta++) c->h_ftab[2 * kTuneMax + nta] = c->h_ftab[2 * kTuneMax + ntmax];
+  c->h_ftab[2 * kTuneMax] = 1;
+  PR_TRY(hipMemcpyAsync(c->d_ftab, c->h_ftab, sizeof(c->h_ftab), hipMemcpyHostToDevice, s));
+  PR_TRY(hipStreamSynchronize(s));
+  c->gram_batch_ok = true;
   return PR_OK;
 }
 
@@ -405,7 +472,7 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   bb.hprev = c->bhprev;
   bb.sidx = c->bsidx;
   bb.sval = c->bsval;
-  bb.CT = c->CT;
+  bb.CT = c->gram ? c->CG : c->CT;
   bb.fsum = c->fsum;
   bb.Bx = c->Bx;
   bb.active = c->d_active;
@@ -413,12 +480,22 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   return bb;
 }
 
-// One batched iteration: forward GEMM, residual split, X^T R GEMM, node steps.
+// One batched iteration: forward GEMM, residual split, X^T R GEMM, node steps
+// (Gram mode: the product G X_it, node steps).
 hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
   const int64_t n = c->P.n, p = c->P.p;
   const int Nr = nr_of(m);
-  hipError_t e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF,
-                                     c->KS, s);
+  hipError_t e;
+  if (c->gram) {
+    e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KSG, 2,
+                            s);
+    if (e != hipSuccess) return e;
+    e = launch_gemm_any(kF64, c->G, p, kF64, c->Bx, p, c->CG, p, Nr, p, c->KSG, c->d_active, c->d_rowmap,
+                        c->d_split, c->d_split + 2, c->KSG * c->fmaxG, c->d_split + 4, s);
+    if (e != hipSuccess) return e;
+    return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
+  }
+  e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KS, 1, s);
   if (e != hipSuccess) return e;
   e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
                       c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
@@ -670,11 +747,20 @@ int pr_ctx_enable_gram(pr_ctx *c) {
   double yy = 0.0;
   for (double v : yh) yy += v * v;
   c->gyy = yy;
+  if (c->batch_ok) {
+    const int rc = tune_gram_batch(c);
+    if (rc != PR_OK) return rc;
+  }
   c->gram = true;
-  if (c->gexec) {  // the captured iteration changes
+  if (c->gexec) {  // the captured iterations change
     (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->graph_units = 0;
+  }
+  if (c->bgexec) {
+    (void)hipGraphExecDestroy(c->bgexec);
+    c->bgexec = nullptr;
+    c->bgraph_units = 0;
   }
   return PR_OK;
 }
@@ -935,6 +1021,32 @@ int pr_batch_tuning(pr_ctx *c, int32_t len, int32_t *ksf_out, int32_t *kst_out) 
     ksf_out[i] = c->KSF * c->h_ftab[t];
     kst_out[i] = c->KS * c->h_ftab[kTuneMax + t];
   }
+  return PR_OK;
+}
+
+int pr_time_gram_gemm(pr_ctx *c, int32_t m, int32_t reps, double *ms) {
+  if (!c || !c->gram_batch_ok || m < 1 || m > c->max_batch || reps < 1 || !ms) return PR_EINVAL;
+  const int64_t p = c->P.p;
+  const int Nr = nr_of(m);
+  hipStream_t s = c->stream;
+  int nta = (m + 63) / 64;
+  if (nta >= kTuneMax) nta = kTuneMax - 1;
+  const int ksg = c->KSG * c->h_ftab[2 * kTuneMax + nta];
+  int32_t *cnt = c->d_split + 4;
+  auto gemm = [&]() {
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    return launch_gemm_any(kF64, c->G, p, kF64, c->Bx, p, c->CG, p, Nr, p, ksg, nullptr, nullptr, nullptr, nullptr, 0,
+                           cnt, s);
+  };
+  PR_TRY(gemm());
+  PR_TRY(hipEventRecord(c->tev[0], s));
+  for (int i = 0; i < reps; i++) PR_TRY(gemm());
+  PR_TRY(hipEventRecord(c->tev[1], s));
+  PR_TRY(hipEventSynchronize(c->tev[1]));
+  float e = 0.0f;
+  PR_TRY(hipEventElapsedTime(&e, c->tev[0], c->tev[1]));
+  *ms = (double)e / reps;
   return PR_OK;
 }
 
@@ -1229,6 +1341,8 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     pp.max_iter = opts.max_iter;
     pp.method = opts.method;
     pp.trace = nullptr;
+    pp.gram_b = c->gram ? c->gb : nullptr;
+    pp.gram_yy = c->gyy;
     PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
     if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
                                   hipMemcpyDeviceToDevice, s));
@@ -1281,8 +1395,13 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     // certify with the dual vector of the stopping iterate, zeta = 2 (y - X x),
     // by Phi(x) and Psi(zeta) recomputed over the stored X
     double lb = -INFINITY, ub = INFINITY;
-    PR_TRY(launch_batch_zeta(c->Rd, n, q, c->B.zbest, s));
-    rc = pr_dual_bound(c, &nodes[i], c->B.zbest, xq, &lb, &ub);
+    if (c->gram) {
+      // Gram mode keeps no residuals: zeta(x) = 2 (y - X x) is formed over X
+      rc = pr_dual_bound(c, &nodes[i], nullptr, xq, &lb, &ub);
+    } else {
+      PR_TRY(launch_batch_zeta(c->Rd, n, q, c->B.zbest, s));
+      rc = pr_dual_bound(c, &nodes[i], c->B.zbest, xq, &lb, &ub);
+    }
     if (rc != PR_OK) return rc;
     const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
     bool confirmed = false;

@@ -196,13 +196,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, i
 // Compacted row list of the batch: rowmap[0..nrow) = the slots of the nodes
 // that are still iterating, in increasing order, and the reduction split of
 // each GEMM for this iteration: the base split times the factor the autotuner
-// chose for this many active 64-row tiles (ftab[0][nta], ftab[1][nta]).
-// sp = {nrow, forward split, transpose split, -}; the two tile counters of the
+// chose for this many active 64-row tiles (ftab[0][nta] for the forward
+// product, ftab[trow][nta] for the product whose planes the node step reads:
+// trow = 1 for X^T R, 2 for the Gram product G X_it).
+// sp = {nrow, forward split, second split, -}; the two tile counters of the
 // GEMMs are reset.  One block of 256 threads.
 __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restrict__ S, int m,
                                                       int32_t *__restrict__ rowmap, int32_t *__restrict__ sp,
                                                       int32_t *__restrict__ counters, const int32_t *__restrict__ ftab,
-                                                      int ksf, int kst) {
+                                                      int ksf, int kst, int trow) {
   __shared__ int base;
   __shared__ int wsum[4];
   if (threadIdx.x == 0) base = 0;
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
     if (nta >= kTuneMax) nta = kTuneMax - 1;
     sp[0] = base;
     sp[1] = ksf * ftab[nta];
-    sp[2] = kst * ftab[kTuneMax + nta];
+    sp[2] = kst * ftab[trow * kTuneMax + nta];
     counters[0] = 0;
     counters[1] = 0;
   }
@@ -327,8 +329,8 @@ hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const v
 }
 
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
-                               const int32_t *ftab, int ksf, int kst, hipStream_t s) {
-  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst);
+                               const int32_t *ftab, int ksf, int kst, int trow, hipStream_t s) {
+  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst, trow);
   return hipGetLastError();
 }
 

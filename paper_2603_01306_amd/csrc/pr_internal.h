@@ -94,7 +94,7 @@ struct BatchBufs {
   double *x0, *x1, *xbest, *hprev;
   int32_t *sidx;
   double *sval;
-  const double *CT;   // [*ksp][Nr][p] partial products X^T r
+  const double *CT;   // [*ksp][Nr][p] partial products X^T r (Gram mode: G x)
   const double *fsum; // [m][nfb][2] partial sums of r^2 and 2 r^T y - r^T r
   double *Bx;         // [Nr][p] current iterates (rows of the forward GEMM)
   int32_t *active;    // number of nodes not yet done
@@ -156,10 +156,12 @@ hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const v
                            int64_t Mc, int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
                            const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
-                               const int32_t *ftab, int ksf, int kst, hipStream_t s);
+                               const int32_t *ftab, int ksf, int kst, int trow, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
-// batched-GEMM autotuner: split factors per count of active 64-row tiles
+// batched-GEMM autotuner: split factors per count of active 64-row tiles,
+// one table per product (forward, X^T R, Gram)
 constexpr int kTuneMax = 64;            // table entries (row-tile counts 1 .. 63)
+constexpr int kTuneTables = 3;
 constexpr int kTuneReps = 2;            // timed launches per candidate
 constexpr double kTunePlaneBW = 5.0e12; // B/s assumed for reading the split partial planes
 

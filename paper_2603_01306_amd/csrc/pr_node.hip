@@ -1613,15 +1613,19 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   double *__restrict__ xn = (parity ? bb.x0 : bb.x1) + off;
   PackedStatus<EPT> sv;
   sv.load(prm->st, p);
+  const double *__restrict__ gb = prm->gram_b;
   // loss sums of the residual blocks: lane-parallel loads, fixed-order wave sums
   double Fk = 0.0, negconj = 0.0;
-  for (int i = lane_id(); i < bb.nfb; i += 64) {
-    Fk += bb.fsum[2 * ((int64_t)node * bb.nfb + i)];
-    negconj += bb.fsum[2 * ((int64_t)node * bb.nfb + i) + 1];
+  if (!gb) {
+    for (int i = lane_id(); i < bb.nfb; i += 64) {
+      Fk += bb.fsum[2 * ((int64_t)node * bb.nfb + i)];
+      negconj += bb.fsum[2 * ((int64_t)node * bb.nfb + i) + 1];
+    }
+    Fk = wave_sum(Fk);
+    negconj = wave_sum(negconj);
   }
-  Fk = wave_sum(Fk);
-  negconj = wave_sum(negconj);
-  // h = X^T r from the GEMM split partials; w = h / lambda2 (= X^T zeta / (2 lambda2))
+  // h = X^T r from the GEMM split partials (Gram mode: h = b - G x from the
+  // split partials of G x); w = h / lambda2 (= X^T zeta / (2 lambda2))
   const int64_t stride = (int64_t)bb.Nr * p;
   const int KS = *bb.ksp;
   const double *__restrict__ Hn = bb.CT + off;
@@ -1634,11 +1638,29 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     for (int e = 0; e < EPT; e++)
       if (sv(e) != 3) h[e] += Hn[z * stride + tid + (int64_t)e * NT];
   }
-  double acc[1] = {0.0};  // sum_{J1} H_M(w_j)
+  // sum_{J1} H_M(w_j); Gram mode: x^T (b + h), b^T x
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (gb) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      if (sv(e) == 3) continue;
+      const int64_t j = tid + (int64_t)e * NT;
+      const double bj = gb[j], xj = xc[j];
+      h[e] = bj - h[e];
+      acc[1] += xj * (bj + h[e]);
+      acc[2] += bj * xj;
+    }
+  }
 #pragma unroll
   for (int e = 0; e < EPT; e++)
     if (sv(e) == kOne) acc[0] += huber(h[e] * wscale, M);
-  block_sum<NT, 1>(acc, lds.red);
+  block_sum<NT, 3>(acc, lds.red);
+  if (gb) {
+    // F(X x) = y^T y - x^T (b + h), -F*(-zeta) = 2 (y^T y - b^T x) - F
+    const double yy = prm->gram_yy;
+    Fk = yy - acc[1];
+    negconj = 2.0 * (yy - acc[2]) - Fk;
+  }
   auto wabs = [&](int e) { return sv(e) == kFree ? fabs(h[e] * wscale) : -1.0; };
   const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
   const double gstar = acc[0] + topsum;

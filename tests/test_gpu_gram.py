@@ -77,3 +77,58 @@ def test_gram_rejects_unsupported_shapes(dev):
     with pytest.raises(pr.PrError):
         c.enable_gram()                       # p not a multiple of 128
     c.close()
+
+
+def _bctx(inst, dev, gram, m):
+    import torch
+    import paper_2603_01306_amd as pr
+    X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    c = pr.Context(X, torch.from_numpy(inst.y).to(dev), 0, max_batch=m)
+    if gram:
+        c.enable_gram()
+    return c
+
+
+def test_batched_gram_bounds_match_matvec_batch_and_oracle(dev):
+    """The batch in Gram mode (one product G X_it per iteration) certifies the
+    same bounds as the batch over X and as the oracle, node by node."""
+    import paper_2603_01306_amd as pr
+    from workloads import make_nodes
+    inst = make_instance(n=2048, p=512, corr=0.7, k_true=8, snr=5.0, loss=0, seed=21, storage="bf16")
+    raw = make_nodes(inst.p, 12, seed=3, max_j0=20, max_j1=5)
+    nodes = [pr.Node(8, 0.3, 2.0, J0=a, J1=b) for a, b in raw]
+    res = {}
+    for gram in (False, True):
+        c = _bctx(inst, dev, gram, 16)
+        r, B = c.solve_batch(nodes, rel_gap_tol=1e-7)
+        res[gram] = (r, B.cpu().numpy())
+        c.close()
+    for q, nd in enumerate(nodes):
+        rg, rm = res[True][0][q], res[False][0][q]
+        assert rg["status"] == pr.CONVERGED and rg["rel_gap"] <= 1e-7, rg
+        assert abs(rg["lower_bound"] - rm["lower_bound"]) <= 2e-7 * abs(rm["primal"])
+        ref = oracle.solve(inst.Xcm, inst.y, 0, 0.3, 2.0, 8, status=nd.status(inst.p), tol=1e-10)
+        assert rg["lower_bound"] <= ref["ub"] * (1 + 1e-12)
+        assert abs(rg["lower_bound"] - ref["lb"]) <= 2e-7 * abs(ref["ub"])
+        # the returned beta attains the reported primal value over the stored X
+        phi = oracle.primal(inst.Xcm, inst.y, res[True][1][q], 0, 0.3, 2.0, 8, status=nd.status(inst.p))
+        assert abs(phi - rg["primal"]) <= 1e-11 * abs(phi)
+
+
+def test_batched_gram_cutoff_decisions(dev):
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=0, seed=10, storage="bf16")
+    c = _bctx(inst, dev, True, 16)
+    rng = np.random.default_rng(0)
+    nodes = [pr.Node(6, 0.5, 2.0, J0=rng.choice(512, 20, replace=False)) for _ in range(8)]
+    free, _ = c.solve_batch(nodes, rel_gap_tol=1e-9)
+    vals = sorted(r["lower_bound"] for r in free)
+    cutoff = 0.5 * (vals[3] + vals[4])
+    res, _ = c.solve_batch(nodes, rel_gap_tol=1e-9, cutoff=cutoff)
+    for r, f in zip(res, free):
+        assert r["status"] in (pr.CUTOFF_PRUNE, pr.CUTOFF_BRANCH, pr.CONVERGED)
+        if r["status"] == pr.CUTOFF_PRUNE:
+            assert r["lower_bound"] >= cutoff and f["lower_bound"] >= cutoff * (1 - 1e-9)
+        if r["status"] == pr.CUTOFF_BRANCH:
+            assert r["primal"] <= cutoff and f["lower_bound"] <= cutoff * (1 + 1e-9)
+    c.close()
