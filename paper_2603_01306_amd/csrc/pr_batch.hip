@@ -16,6 +16,8 @@
 // XCDs, so block b is given the (c tile, split) group (b / 8 / NT) * 8 + b % 8
 // and r tile (b / 8) % NT: the NT blocks sharing an A tile run on one XCD and
 // read it from HBM once per XCD L2.
+#include <type_traits>
+
 #include "pr_device.h"
 
 namespace pr {
@@ -149,6 +151,102 @@ __device__ __forceinline__ void gemm_tile(const TA *__restrict__ A, int64_t lda,
   }
 }
 
+// The same block tile for FP64 A and B, staged through LDS.  With 8-byte
+// operands the direct loads above fetch each A row twice and each B row twice
+// per block (two waves share every row), which the per-CU load bandwidth
+// cannot feed; here the block loads its 128 x 16 A and 64 x 16 B slices of a
+// reduction step once (coalesced 16-byte loads, 8 threads per 128-byte row)
+// into one of two LDS buffers while the MFMAs consume the other.  Rows are
+// padded to 18 doubles against bank conflicts.  Lane quarter q owns reduction
+// indices 4q .. 4q+3 of a step; MFMA j combines index 4q + j of every quarter.
+constexpr int kLdsRow = 18;
+constexpr int kLdsStage = (128 + 64) * kLdsRow;  // doubles per buffer
+
+__device__ __forceinline__ void gemm_tile_f64_lds(const double *__restrict__ A, int64_t lda,
+                                                  const double *__restrict__ B, int64_t ldb, double *__restrict__ C,
+                                                  int64_t Mc, int64_t Nr, int64_t Kc, int mt, int z, int nt, int nr,
+                                                  const int32_t *__restrict__ rowmap, double *lds) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = lane >> 4, rr = lane & 15;
+  // cooperative loads: A chunk id = tid + 256 i (i < 4), B chunk id = tid + 256 i (i < 2);
+  // row = id / 8, 16-byte part = id % 8
+  const int part = tid & 7;
+  const double *ga[4];
+  const double *gbp[2];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int row = (tid >> 3) + 32 * i;
+    ga[i] = A + ((int64_t)mt * 128 + row) * lda + (int64_t)z * Kc + 2 * part;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const int row = (tid >> 3) + 32 * i;
+    const int l = nt * 64 + row;
+    const int64_t br = rowmap ? (l < nr ? rowmap[l] : rowmap[0]) : l;
+    gbp[i] = B + br * ldb + (int64_t)z * Kc + 2 * part;
+  }
+  // C rows of the lane's two r positions (-1: past the compacted rows)
+  const int64_t c0 = (int64_t)mt * 128 + (w & 1) * 64;
+  const int lr0 = nt * 64 + (w >> 1) * 32;
+  int64_t orow[2];
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    const int l = lr0 + 16 * u + rr;
+    orow[u] = rowmap ? (l < nr ? rowmap[l] : -1) : l;
+  }
+  d4v_t acc[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int u = 0; u < 2; u++) acc[t][u] = d4v_t{0.0, 0.0, 0.0, 0.0};
+  const int64_t nsteps = Kc / 16;
+  d2v_t ra[4], rb[2];
+  auto gload = [&](int64_t st) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) ra[i] = *reinterpret_cast<const d2v_t *>(ga[i] + st * 16);
+#pragma unroll
+    for (int i = 0; i < 2; i++) rb[i] = *reinterpret_cast<const d2v_t *>(gbp[i] + st * 16);
+  };
+  auto lstore = [&](double *buf) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) *reinterpret_cast<d2v_t *>(buf + ((tid >> 3) + 32 * i) * kLdsRow + 2 * part) = ra[i];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+      *reinterpret_cast<d2v_t *>(buf + (128 + (tid >> 3) + 32 * i) * kLdsRow + 2 * part) = rb[i];
+  };
+  gload(0);
+  lstore(lds);
+  __syncthreads();
+  const int arow = (w & 1) * 64 + rr, brow = 128 + (w >> 1) * 32 + rr;
+  for (int64_t st = 0; st < nsteps; st++) {
+    double *cur = lds + (st & 1) * kLdsStage;
+    if (st + 1 < nsteps) gload(st + 1);
+    d4v_t fa[4], fb[2];
+#pragma unroll
+    for (int t = 0; t < 4; t++) fa[t] = *reinterpret_cast<const d4v_t *>(cur + (arow + 16 * t) * kLdsRow + 4 * q);
+#pragma unroll
+    for (int u = 0; u < 2; u++) fb[u] = *reinterpret_cast<const d4v_t *>(cur + (brow + 16 * u) * kLdsRow + 4 * q);
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[t][j], fb[u][j], acc[t][u], 0, 0, 0);
+    if (st + 1 < nsteps) lstore(lds + ((st + 1) & 1) * kLdsStage);
+    __syncthreads();
+  }
+  double *Cz = C + (int64_t)z * Nr * Mc;
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    if (orow[u] < 0) continue;
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) Cz[orow[u] * Mc + c0 + 16 * t + 4 * v + q] = acc[t][u][v];
+  }
+}
+
 // Persistent launch: the grid (at most two workgroups per CU) walks the tile
 // list.  Row compaction: with rowmap != NULL only the first *nrow rows are
 // computed, local row l reading B row rowmap[l] and writing C row rowmap[l],
@@ -174,6 +272,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, i
   const int nitems = ((groups + 7) / 8) * 8 * nta;
   const int64_t Kc = K / KS;
   __shared__ int next;
+  constexpr bool kLds = std::is_same<TA, double>::value && std::is_same<TB, double>::value;
+  __shared__ double stage[kLds ? 2 * kLdsStage : 1];
   // items in order: the workgroup's own first item, then (with a counter)
   // whichever item is next when it finishes
   int item = blockIdx.x;
@@ -181,7 +281,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, i
     const int x = item & 7, qq = item >> 3;
     const int g = qq / nta, nt = qq - g * nta;
     const int G = g * 8 + x;
-    if (G < groups) gemm_tile<TA, TB, PIPE>(A, lda, B, ldb, C, Mc, Nr, Kc, G % MT, G / MT, nt, nr, rowmap);
+    if (G < groups) {
+      if constexpr (std::is_same<TA, double>::value && std::is_same<TB, double>::value)
+        gemm_tile_f64_lds(A, lda, B, ldb, C, Mc, Nr, Kc, G % MT, G / MT, nt, nr, rowmap, stage);
+      else
+        gemm_tile<TA, TB, PIPE>(A, lda, B, ldb, C, Mc, Nr, Kc, G % MT, G / MT, nt, nr, rowmap);
+    }
     if (counter) {
       __syncthreads();
       if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(counter, 1);
