@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/pr.h"
@@ -81,6 +82,8 @@ struct pr_ctx {
   int32_t KSG = 1, fmaxG = 1;
   double *CG = nullptr;
   bool cg_own = false, gram_batch_ok = false;
+  uint32_t *bstp = nullptr;        // [cap][stpw] packed node status of the batch
+  std::vector<uint32_t> h_bstp;
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
@@ -122,7 +125,7 @@ void free_ctx(pr_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   if (c->cg_own && c->CG) (void)hipFree(c->CG);
-  void *bb[] = {c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
+  void *bb[] = {c->bstp, c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
                 c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb};
   for (void *b : bb)
     if (b) (void)hipFree(b);
@@ -380,6 +383,7 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && dalloc(&c->bxbest, (size_t)cap * p) == hipSuccess && dalloc(&c->bhprev, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->bsval, (size_t)cap * p) == hipSuccess && dalloc(&c->bsidx, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->bstatus, (size_t)cap * p) == hipSuccess;
+  ok = ok && dalloc(&c->bstp, (size_t)cap * c->h_stp.size()) == hipSuccess;
   ok = ok && dalloc(&c->d_bprm, cap) == hipSuccess && dalloc(&c->d_bstate, cap) == hipSuccess;
   ok = ok && dalloc(&c->d_active, 2) == hipSuccess;
   ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 8) == hipSuccess;
@@ -477,6 +481,11 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   bb.Bx = c->Bx;
   bb.active = c->d_active;
   bb.gap_factor = 0.99;
+  bb.p = c->P.p;
+  bb.stp = c->bstp;
+  bb.stpw = (int64_t)c->h_stp.size();
+  bb.gb = c->gram ? c->gb : nullptr;
+  bb.gyy = c->gyy;
   return bb;
 }
 
@@ -1346,6 +1355,17 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
     if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
                                   hipMemcpyDeviceToDevice, s));
+  }
+  {
+    const size_t W = c->h_stp.size();
+    c->h_bstp.assign((size_t)mb * W, 0u);
+    std::vector<uint32_t> w(W);
+    for (int32_t q = 0; q < mb; q++) {
+      pack_status(sts[(size_t)slot_of[(size_t)q]], w);
+      std::copy(w.begin(), w.end(), c->h_bstp.begin() + (size_t)q * W);
+    }
+    PR_TRY(hipMemcpyAsync(c->bstp, c->h_bstp.data(), sizeof(uint32_t) * c->h_bstp.size(), hipMemcpyHostToDevice,
+                          s));
   }
   PR_TRY(hipMemcpyAsync(c->d_bprm, prm.data(), sizeof(NodeParams) * mb, hipMemcpyHostToDevice, s));
   int32_t act = mb;

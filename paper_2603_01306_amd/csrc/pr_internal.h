@@ -99,6 +99,11 @@ struct BatchBufs {
   double *Bx;         // [Nr][p] current iterates (rows of the forward GEMM)
   int32_t *active;    // number of nodes not yet done
   double gap_factor;  // stop when Phi - Psi <= gap_factor * tol * |Phi| (margin for the host re-check)
+  int64_t p;
+  const uint32_t *stp;  // packed status of the nodes (NodeParams::stp layout), stpw words per node
+  int64_t stpw;
+  const double *gb;     // Gram mode: b = X^T y (NULL: products over X); gyy = y^T y
+  double gyy;
 };
 
 struct Problem {

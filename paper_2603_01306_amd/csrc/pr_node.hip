@@ -1597,23 +1597,43 @@ __global__ __launch_bounds__(NT) void k_batch_init(const NodeParams *__restrict_
 
 template <int EPT>
 __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict__ prmA, NodeState *SA, BatchBufs bb) {
-  __shared__ NodeLds lds;
+  __shared__ StepLds<EPT> lds;
   const int node = blockIdx.x;
   const NodeParams *prm = prmA + node;
   NodeState *S = SA + node;
-  if (S->done) return;
   const int tid = threadIdx.x;
-  const int64_t p = prm->p;
+  const int64_t p = bb.p;
   const int64_t off = (int64_t)node * p;
+  const double *__restrict__ gb = bb.gb;
+  // scalar state: independent loads, issued with the vector loads below
+  const int done0 = S->done, parity = S->parity, indom0 = S->indom;
+  const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw;
   const int kbar = prm->kbar;
   const double lam2 = prm->lambda2, M = prm->M;
-  const int parity = S->parity;
-  const double L = S->L;
   const double *__restrict__ xc = (parity ? bb.x1 : bb.x0) + off;
   double *__restrict__ xn = (parity ? bb.x0 : bb.x1) + off;
   PackedStatus<EPT> sv;
-  sv.load(prm->st, p);
-  const double *__restrict__ gb = prm->gram_b;
+  load_packed_status<EPT>(sv, bb.stp + (int64_t)node * bb.stpw);
+  // h = X^T r from the GEMM split partials (Gram mode: G x, turned into
+  // h = b - G x below); x^k
+  const int64_t stride = (int64_t)bb.Nr * p;
+  const int KS = *bb.ksp;
+  const double *__restrict__ Hn = bb.CT + off;
+  double h[EPT], xk[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const uint32_t j = (uint32_t)(tid + e * NT);
+    const bool in = j < (uint32_t)p;
+    h[e] = in ? Hn[j] : 0.0;
+    xk[e] = in ? xc[j] : 0.0;
+  }
+  for (int z = 1; z < KS; z++) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      if (j < (uint32_t)p) h[e] += Hn[z * stride + j];
+    }
+  }
   // loss sums of the residual blocks: lane-parallel loads, fixed-order wave sums
   double Fk = 0.0, negconj = 0.0;
   if (!gb) {
@@ -1621,54 +1641,87 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
       Fk += bb.fsum[2 * ((int64_t)node * bb.nfb + i)];
       negconj += bb.fsum[2 * ((int64_t)node * bb.nfb + i) + 1];
     }
+  }
+  if (done0) return;
+  Red2 R;
+  R.buf = lds.red;
+  R.ph = 0;
+  if (tid == 0) lds.sel.ngat = 0;
+  if (!gb) {
     Fk = wave_sum(Fk);
     negconj = wave_sum(negconj);
   }
-  // h = X^T r from the GEMM split partials (Gram mode: h = b - G x from the
-  // split partials of G x); w = h / lambda2 (= X^T zeta / (2 lambda2))
-  const int64_t stride = (int64_t)bb.Nr * p;
-  const int KS = *bb.ksp;
-  const double *__restrict__ Hn = bb.CT + off;
+  // dual at x^k: w = h / lambda2 (= X^T zeta / (2 lambda2)); the top-kbar window
+  // of free |w| around the previous kbar-th value (as in the single-node step)
   const double wscale = 1.0 / lam2;
-  double h[EPT];
+  const bool wv = tkp > 0.0 && kbar > 0;
+  const double wa = wv ? tkp * (1.0 - dlt) : INFINITY, wb = wv ? tkp * (1.0 + dlt) : INFINITY;
+  // r1: sum_{J1} H_M(w_j); Gram: x^T (b + h), b^T x; #{w > wb}, #{w >= wa}, sum_{w > wb} H_M(w)
+  double r1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int e = 0; e < EPT; e++) h[e] = sv(e) != 3 ? Hn[tid + (int64_t)e * NT] : 0.0;
-  for (int z = 1; z < KS; z++) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) h[e] += Hn[z * stride + tid + (int64_t)e * NT];
-  }
-  // sum_{J1} H_M(w_j); Gram mode: x^T (b + h), b^T x
-  double acc[3] = {0.0, 0.0, 0.0};
-  if (gb) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++) {
-      if (sv(e) == 3) continue;
-      const int64_t j = tid + (int64_t)e * NT;
-      const double bj = gb[j], xj = xc[j];
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    if (s == 3) continue;
+    if (gb) {
+      const double bj = gb[tid + (int64_t)e * NT];
       h[e] = bj - h[e];
-      acc[1] += xj * (bj + h[e]);
-      acc[2] += bj * xj;
+      r1[1] += xk[e] * (bj + h[e]);
+      r1[2] += bj * xk[e];
+    }
+    const double w = h[e] * wscale;
+    if (s == kOne) r1[0] += huber(w, M);
+    if (s == kFree) {
+      const double aw = fabs(w);
+      if (aw > wb) {
+        r1[3] += 1.0;
+        r1[5] += huber(aw, M);
+      }
+      if (aw >= wa) r1[4] += 1.0;
     }
   }
-#pragma unroll
-  for (int e = 0; e < EPT; e++)
-    if (sv(e) == kOne) acc[0] += huber(h[e] * wscale, M);
-  block_sum<NT, 3>(acc, lds.red);
+  R.sum(r1);
   if (gb) {
     // F(X x) = y^T y - x^T (b + h), -F*(-zeta) = 2 (y^T y - b^T x) - F
-    const double yy = prm->gram_yy;
-    Fk = yy - acc[1];
-    negconj = 2.0 * (yy - acc[2]) - Fk;
+    Fk = bb.gyy - r1[1];
+    negconj = 2.0 * (bb.gyy - r1[2]) - Fk;
   }
   auto wabs = [&](int e) { return sv(e) == kFree ? fabs(h[e] * wscale) : -1.0; };
-  const double topsum = topsum_huber_f<EPT>(wabs, kbar, M, lds.sel, lds.red);
-  const double gstar = acc[0] + topsum;
-  // Psi(zeta) and Phi(x) from the FP64 products of this pass
-  const double psi = negconj - 2.0 * lam2 * gstar;
-  const double phi = S->indom ? Fk + 2.0 * lam2 * S->gval : INFINITY;
-  const double gap = phi - psi;
+  const double cgt = r1[3], cge = r1[4];
+  const bool fast = wv && cgt < (double)kbar && (double)kbar <= cge && cge - cgt <= (double)kWinCap;
+  double topsum = 0.0, tkn = -1.0;
+  if (kbar > 0 && fast) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double aw = wabs(e);
+      if (aw >= wa && aw <= wb) lds.sel.gat[atomicAdd(&lds.sel.ngat, 1)] = aw;
+    }
+    lds_barrier();
+    if (wave_id() == 0) {
+      const int lane = lane_id();
+      const int cw = (int)(cge - cgt);
+      const int mm = kbar - (int)cgt;  // 1 <= mm <= cw
+      double v = (lane < cw) ? lds.sel.gat[lane] : -1.0;
+      v = wave_sort_desc(v);
+      tkn = __shfl(v, mm - 1, 64);
+      topsum = r1[5] + wave_sum(lane < mm ? huber(v, M) : 0.0);
+    }
+  } else if (kbar > 0) {
+    tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+    const double Ht = huber(tkn, M);
+    double v1[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const double aw = wabs(e);
+      if (aw >= 0.0) v1[0] += fmax(huber(aw, M) - Ht, 0.0);
+    }
+    R.sum(v1);
+    topsum = (double)kbar * Ht + v1[0];
+  }
   if (tid == 0) {
+    // Psi(zeta) and Phi(x) from the FP64 products of this pass
+    const double psi = negconj - 2.0 * lam2 * (r1[0] + topsum);
+    const double phi = indom0 ? Fk + 2.0 * lam2 * gval0 : INFINITY;
+    const double gap = phi - psi;
     const int it = S->iter;
     if (prm->trace && it <= prm->max_iter) {
       prm->trace[2 * it] = phi;
@@ -1707,6 +1760,9 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
         t = tn;
       }
     }
+    double tw = 0.25;
+    if (wv && tkn > 0.0) tw = fmin(0.25, fmax(1e-12, 2.0 * fabs(tkn - tkp) / tkn));
+    if (wv && !fast && cgt < (double)kbar && (double)kbar <= cge) tw = fmin(tw, 0.25 * dlt);
     S->phi = phi;
     S->psi = psi;
     S->lb = lb;
@@ -1717,6 +1773,8 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     S->gap_ref = gap_ref;
     S->restarts = restarts;
     S->mom = m;
+    S->tk = tkn;
+    S->tkw = tw;
     if (done) {
       S->done = 1;
       atomicSub(bb.active, 1);
@@ -1724,25 +1782,23 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     lds.bcd[0] = m;
     lds.bci[0] = done;
   }
-  __syncthreads();
+  lds_barrier();
   const bool done = lds.bci[0] != 0;
-  double *__restrict__ hp = bb.hprev + off;
-  // every load of the step first, then the arithmetic, then the stores
-  double xk[EPT], xq[EPT], hq[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const int64_t j = tid + (int64_t)e * NT;
-    const bool in = sv(e) != 3;
-    xk[e] = in ? xc[j] : 0.0;
-    xq[e] = (in && !done) ? xn[j] : 0.0;
-    hq[e] = (in && !done) ? hp[j] : 0.0;
-  }
   if (done) {
     // the certified point is the iterate whose gap passed the test
 #pragma unroll
     for (int e = 0; e < EPT; e++)
       if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xk[e];
     return;
+  }
+  double *__restrict__ hp = bb.hprev + off;
+  double xq[EPT], hq[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const uint32_t j = (uint32_t)(tid + e * NT);
+    const bool in = j < (uint32_t)p;
+    xq[e] = in ? xn[j] : 0.0;
+    hq[e] = in ? hp[j] : 0.0;
   }
   const double m = lds.bcd[0];
   const double invL = 1.0 / L;
@@ -1755,11 +1811,11 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   }
 #pragma unroll
   for (int e = 0; e < EPT; e++)
-    if (sv(e) != 3) hp[tid + (int64_t)e * NT] = hq[e];
+    if (sv(e) != 3) hp[(uint32_t)(tid + e * NT)] = hq[e];
   const double rho = 2.0 * lam2 * invL;
   int evals = 0;
   auto vabs = [&](int e) { return sv(e) == kFree ? fabs(h[e]) : -1.0; };
-  const double tau = solve_tau_f<EPT>(vabs, kbar, rho, M, S->tau, lds.red, &evals);
+  const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
   const double inv1p = 1.0 / (1.0 + rho);
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
@@ -1772,13 +1828,13 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
         if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
         xv = (r == 0.0) ? 0.0 : copysign(r, h[e]);
       }
-      const int64_t j = tid + (int64_t)e * NT;
+      const uint32_t j = (uint32_t)(tid + e * NT);
       xn[j] = xv;
       bb.Bx[off + j] = xv;
     }
     h[e] = xv;
   }
-  IterStats is = finish_r<EPT>(h, sv, kbar, M, bb.sidx + off, bb.sval + off, lds);
+  IterStats is = finish_2<EPT>(h, sv, kbar, M, bb.sidx + off, bb.sval + off, lds, R);
   if (tid == 0) {
     S->gval = is.gval;
     S->indom = is.indom;
