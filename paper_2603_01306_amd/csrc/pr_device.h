@@ -232,19 +232,6 @@ __device__ __forceinline__ void load_rhs(const double *__restrict__ r, int64_t i
   }
 }
 
-// Deterministic transpose-reduction of 2 per-lane partial sums (one per
-// column) over the 64 lanes: afterwards lane 32*c holds the total of column c.
-__device__ __forceinline__ double reduce2(double (&v)[2]) {
-  const bool b5 = (lane_id() & 32) != 0;
-  const double s = b5 ? v[0] : v[1];
-  double k = b5 ? v[1] : v[0];
-  k += __shfl_xor(s, 32, 64);
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
-  return k;
-}
-
-
 
 }  // namespace dev
 }  // namespace pr

@@ -1,20 +1,53 @@
 // X^T r on gfx950: h = X^T r (one or two right-hand sides) for column-major X
 // stored FP32 / BF16 / FP64, accumulated in FP64.
 //
-// One wave per kColsPerWave adjacent columns streams the full column length:
-// each lane loads 16 bytes of every column per step with non-temporal loads
-// (X is read once per launch and should not displace the L2-resident
-// right-hand side), one row step per lane in flight (a measured sweep over
-// 1, 2, 4 steps on MI355X favoured 1), then a deterministic in-wave transpose
-// reduction leaves column c's total in lane 32c.  Two columns per wave (a
-// sweep over 1, 2, 4, 8) give twice the waves of four, which the HBM stream
-// needs to stay full.  Algorithmic bytes per launch: n*p*sizeof(X) + 8n per
-// right-hand side + 8p per output.
+// One wave per C adjacent columns streams the full column length: each lane
+// loads 16 bytes of every column per step with non-temporal loads (X is read
+// once per launch and should not displace the L2-resident right-hand side),
+// one row step per lane in flight (a measured sweep over 1, 2, 4 steps on
+// MI355X favoured 1), then a deterministic in-wave transpose reduction leaves
+// column c's total in lane (64 / C) c.  With one right-hand side, C = 2 (a
+// sweep over 1, 2, 4, 8 columns per wave): twice the waves of C = 4, which the
+// HBM stream needs to stay full.  With two, C = 8: every wave re-reads both
+// right-hand sides from L2 for its columns, and at small C that L2 traffic
+// (at C = 2 twice the bytes of X) becomes the limit (logistic 32768 x 16384:
+// 585 / 537 / 504 / 498 us per iteration at C = 2 / 4 / 8 / 16; 16 needs 254
+// VGPRs).  Algorithmic bytes per launch: n*p*sizeof(X) + 8n per right-hand
+// side + 8p per output.
 #include "pr_device.h"
 
 namespace pr {
 namespace {
 using namespace dev;
+
+constexpr int gemv_cols(int nrhs) { return nrhs == 1 ? 2 : 8; }
+
+// Deterministic transpose reduction of C per-lane partial sums (one per
+// column) over the 64 lanes: at each exchange over lane bit s (32, 16, ...)
+// the lanes with that bit set keep the upper half of their columns and add
+// their partner's, the others the lower half; once one column is left the
+// plain butterfly finishes.  Column c's total ends in lane (64 / C) c.
+template <int C>
+__device__ __forceinline__ double reduce_cols(double (&v)[C]) {
+  const int lane = lane_id();
+  double cur[C];
+#pragma unroll
+  for (int i = 0; i < C; i++) cur[i] = v[i];
+  int s = 32;
+#pragma unroll
+  for (int w = C; w > 1; w >>= 1, s >>= 1) {
+    const bool hi = (lane & s) != 0;
+#pragma unroll
+    for (int i = 0; i < w / 2; i++) {
+      const double send = hi ? cur[i] : cur[i + w / 2];
+      const double keep = hi ? cur[i + w / 2] : cur[i];
+      cur[i] = keep + __shfl_xor(send, s, 64);
+    }
+  }
+#pragma unroll
+  for (; s > 0; s >>= 1) cur[0] += __shfl_xor(cur[0], s, 64);
+  return cur[0];
+}
 
 template <typename T, int NRHS>
 __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X, int64_t n, int64_t p,
@@ -30,9 +63,9 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 #endif
   constexpr int U = PR_GEMVT_STEPS;  // row steps in flight
   const int lane = lane_id();
-  const int64_t col0 = ((int64_t)blockIdx.x * (kGemvThreads / 64) + wave_id()) * kColsPerWave;
+  constexpr int C = gemv_cols(NRHS);
+  const int64_t col0 = ((int64_t)blockIdx.x * (kGemvThreads / 64) + wave_id()) * C;
   if (col0 >= p) return;
-  constexpr int C = kColsPerWave;
   const T *c[C];
 #pragma unroll
   for (int q = 0; q < C; q++) {
@@ -79,14 +112,15 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 #pragma unroll
         for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[q][e], rv[h][e], acc[h][q]);
   }
-  const int64_t col = col0 + (lane >> 5);
-  const bool writer = (lane & 31) == 0 && col < p;
+  constexpr int LPC = 64 / C;  // lanes per column after the reduction
+  const int64_t col = col0 + lane / LPC;
+  const bool writer = (lane % LPC) == 0 && col < p;
   {
-    double t = reduce2(acc[0]);
+    double t = reduce_cols(acc[0]);
     if (writer) h1[col] = t;
   }
   if (NRHS > 1) {
-    double t = reduce2(acc[NRHS - 1]);
+    double t = reduce_cols(acc[NRHS - 1]);
     if (writer) h2[col] = t;
   }
 }
@@ -95,10 +129,10 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 
 hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
                          const int32_t *done, hipStream_t s) {
-  const int cols_per_block = (kGemvThreads / 64) * kColsPerWave;
+  const bool two = (r2 != nullptr);
+  const int cols_per_block = (kGemvThreads / 64) * gemv_cols(two ? 2 : 1);
   dim3 grid((unsigned)((P.p + cols_per_block - 1) / cols_per_block));
   dim3 block(kGemvThreads);
-  const bool two = (r2 != nullptr);
   switch (P.xdt) {
     case kF32:
       if (two) k_gemv_t<float, 2><<<grid, block, 0, s>>>((const float *)P.X, P.n, P.p, r1, r2, h1, h2, done);

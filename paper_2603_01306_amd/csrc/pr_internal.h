@@ -11,8 +11,7 @@
 namespace pr {
 
 constexpr int kNodeThreads = 512;    // threads of a per-node workgroup
-constexpr int kGemvThreads = 256;    // 4 waves, 2 columns per wave
-constexpr int kColsPerWave = 2;
+constexpr int kGemvThreads = 256;    // 4 waves of the X^T r kernel
 constexpr int kSpThreads = 256;      // column-list GEMV workgroup
 
 enum : int32_t { kFree = 0, kZero = 1, kOne = 2 };
