@@ -1265,6 +1265,10 @@ template <int EPT>
 __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict__ prm, NodeState *S,
                                                     NodeBufs nb, ProbBufs B, StepArgs A) {
   __shared__ StepLds<EPT> lds;
+  // with 32 entries per thread the radix selection reads the magnitudes from
+  // LDS (the register-resident passes would not stay in registers)
+  constexpr bool kSelLds = EPT > 16;
+  __shared__ double wl[kSelLds ? EPT * NT : 1];
   const int tid = threadIdx.x;
   const int64_t p = A.p;
   const double *__restrict__ gb = A.gb;
@@ -1281,13 +1285,16 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // operands of the gradient step (x^{k-1}, previous gradient) are issued
   // once b has been consumed and arrive during the dual evaluation (with 16
   // or more entries per thread they are loaded at the gradient step instead,
-  // which keeps the selection passes out of scratch memory)
+  // which keeps the selection passes out of scratch memory; with 32 entries
+  // x^k is not held either: the gradient step loads its operands in halves)
   constexpr bool kPre = EPT <= 8;
+  constexpr bool kHoldXk = EPT <= 16;
+  constexpr int EK = kHoldXk ? EPT : 1;
   PackedStatus<EPT> sv;
   load_packed_status<EPT>(sv, A.stp);
-  double x[EPT], xk[EPT], xq[EPT], g2[EPT];
+  double x[EPT], xk[EK], xq[EK], g2[EK];
   double r1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  {
+  if constexpr (kHoldXk) {
     double bv[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; e++) {
@@ -1301,6 +1308,23 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     for (int e = 0; e < EPT; e++) {
       r1[1] += xk[e] * (bv[e] + x[e]);
       r1[2] += bv[e] * xk[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      x[e] = j < (uint32_t)p ? B.h1[j] : 0.0;
+    }
+    if (gb) {
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        if (j < (uint32_t)p) {
+          const double xv = xc[j], bj = gb[j];
+          r1[1] += xv * (bj + x[e]);
+          r1[2] += bj * xv;
+        }
+      }
     }
   }
   // loss sums of the finalize blocks: lane-parallel loads, fixed-order wave sums
@@ -1380,7 +1404,14 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
       topsum = r1[5] + wave_sum(lane < mm ? huber(v, M) : 0.0);
     }
   } else if (kbar > 0) {
-    tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+    if constexpr (kSelLds) {
+#pragma unroll
+      for (int e = 0; e < EPT; e++) wl[tid + e * NT] = wabs(e);
+      __syncthreads();
+      tkn = select_kth(wl, (int64_t)EPT * NT, kbar, lds.sel);
+    } else {
+      tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+    }
     const double Ht = huber(tkn, M);
     double v1[1] = {0.0};
 #pragma unroll
@@ -1468,41 +1499,68 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const double m = lds.bcd[0];
   const int restart = lds.bci[1];
   const double invL = 1.0 / L;
-  if (lds.bci[2]) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.xbest[(uint32_t)(tid + e * NT)] = xk[e];
-  }
-  if (gb && lds.bci[3]) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.xlb[(uint32_t)(tid + e * NT)] = xk[e];
-  }
-  if (done) return;
-  if (!kPre) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++) {
-      const uint32_t j = (uint32_t)(tid + e * NT);
-      const bool in = j < (uint32_t)p;
-      xq[e] = in ? xn[j] : 0.0;
-      g2[e] = in ? gp[j] : 0.0;
-    }
-  }
-  // gradient step at the momentum point; x[] now holds v
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
+  // gradient step at the momentum point on entries [e0, e1); x[] then holds v
+  auto grad = [&](int e, double xke, double xqe, double g2e) {
     const double h = x[e];
-    const double yj = xk[e] + m * (xk[e] - xq[e]);
+    const double yj = xke + m * (xke - xqe);
     double gj;
-    if (loss == kLsq) gj = -2.0 * ((1.0 + m) * h - m * g2[e]);
-    else gj = restart ? -h : g2[e];
+    if (loss == kLsq) gj = -2.0 * ((1.0 + m) * h - m * g2e);
+    else gj = restart ? -h : g2e;
     x[e] = sv(e) != 3 ? yj - gj * invL : 0.0;
-    g2[e] = h;
-  }
-  if (loss == kLsq) {
+    if (loss == kLsq && sv(e) != 3) nb.hprev[(uint32_t)(tid + e * NT)] = h;
+  };
+  if constexpr (kHoldXk) {
+    if (lds.bci[2]) {
 #pragma unroll
-    for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) nb.hprev[(uint32_t)(tid + e * NT)] = g2[e];
+      for (int e = 0; e < EPT; e++)
+        if (sv(e) != 3) nb.xbest[(uint32_t)(tid + e * NT)] = xk[e];
+    }
+    if (gb && lds.bci[3]) {
+#pragma unroll
+      for (int e = 0; e < EPT; e++)
+        if (sv(e) != 3) nb.xlb[(uint32_t)(tid + e * NT)] = xk[e];
+    }
+    if (done) return;
+    if (!kPre) {
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        const bool in = j < (uint32_t)p;
+        xq[e] = in ? xn[j] : 0.0;
+        g2[e] = in ? gp[j] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; e++) grad(e, xk[e], xq[e], g2[e]);
+  } else {
+    constexpr int HE = EPT / 2;
+#pragma unroll
+    for (int hh = 0; hh < 2; hh++) {
+      double xkh[HE], xqh[HE], g2h[HE];
+#pragma unroll
+      for (int i = 0; i < HE; i++) {
+        const uint32_t j = (uint32_t)(tid + (hh * HE + i) * NT);
+        const bool in = j < (uint32_t)p;
+        xkh[i] = in ? xc[j] : 0.0;
+        xqh[i] = (in && !done) ? xn[j] : 0.0;
+        g2h[i] = (in && !done) ? gp[j] : 0.0;
+      }
+      if (lds.bci[2]) {
+#pragma unroll
+        for (int i = 0; i < HE; i++)
+          if (sv(hh * HE + i) != 3) nb.xbest[(uint32_t)(tid + (hh * HE + i) * NT)] = xkh[i];
+      }
+      if (gb && lds.bci[3]) {
+#pragma unroll
+        for (int i = 0; i < HE; i++)
+          if (sv(hh * HE + i) != 3) nb.xlb[(uint32_t)(tid + (hh * HE + i) * NT)] = xkh[i];
+      }
+      if (!done) {
+#pragma unroll
+        for (int i = 0; i < HE; i++) grad(hh * HE + i, xkh[i], xqh[i], g2h[i]);
+      }
+    }
+    if (done) return;
   }
   const double rho = 2.0 * lam2 * invL;
   int evals = 0;
