@@ -768,101 +768,6 @@ __device__ double select_kth_f(F aval, int k, SelLds &sm) {
 }
 
 template <int EPT, class F>
-__device__ double topsum_huber_f(F aval, int kbar, double M, SelLds &sm, double *red) {
-  if (kbar <= 0) return 0.0;
-  const double t = select_kth_f<EPT>(aval, kbar, sm);
-  const double Ht = huber(t, M);
-  double v[1] = {0.0};
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const double x = aval(e);
-    if (x >= 0.0) v[0] += fmax(huber(x, M) - Ht, 0.0);
-  }
-  block_sum<NT, 1>(v, red);
-  return (double)kbar * Ht + v[0];
-}
-
-template <int EPT, class F>
-__device__ double solve_tau_f(F aval, int kbar, double rho, double M, double warm, double *red, int *evals) {
-  double st[2] = {0.0, 0.0};
-  double mx = 0.0;
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const double x = aval(e);
-    if (x > 0.0) {
-      st[0] += 1.0;
-      st[1] += x;
-      mx = fmax(mx, x);
-    }
-  }
-  block_sum<NT, 2>(st, red);
-  const double amax = block_max<NT>(mx, red);
-  *evals = 0;
-  if (kbar <= 0) return INFINITY;
-  const double K = (double)kbar;
-  if (st[0] <= K) return 0.0;
-  const bool finM = isfinite(M);
-  auto Dof = [&](double t) { return finM ? fmin(t / rho, M) : t / rho; };
-  auto froot = [&](double h, double nb, double sB) -> double {
-    if (nb <= 0.0) return NAN;
-    if (finM) {
-      const double Sf = h + (sB - nb * rho * M) / M;
-      if (Sf >= K) return (sB - M * (K - h)) / nb;
-    }
-    return rho * sB / (K - h + rho * nb);
-  };
-  double lo = 0.0, hi = amax;
-  double tau = (warm > lo && warm < hi) ? warm : froot(0.0, st[0], st[1]);
-  if (!(tau > lo && tau < hi)) tau = 0.5 * (lo + hi);
-  bool from_root = false;
-  double ph = -1.0, pb = -1.0;
-  int nsteps = 0;
-  double wref = hi - lo;
-  for (int it = 0; it < 200; it++) {
-    const double D = Dof(tau);
-    double v[3] = {0.0, 0.0, 0.0};
-    const double top = tau + D;
-#pragma unroll
-    for (int e = 0; e < EPT; e++) {
-      const double x = aval(e);
-      if (x > tau) {
-        v[1] += 1.0;
-        if (x > top) v[0] += 1.0;
-        else v[2] += x;
-      }
-    }
-    block_sum<NT, 3>(v, red);
-    *evals = it + 1;
-    if (from_root && v[0] == ph && v[1] == pb) return tau;
-    const double S = v[0] + (v[2] - (v[1] - v[0]) * tau) / D;
-    if (S > K) lo = tau;
-    else if (S < K) hi = tau;
-    else return tau;
-    double c = froot(v[0], v[1] - v[0], v[2]);
-    if (c == tau) return tau;
-    if (nsteps >= 2 && hi - lo > 0.5 * wref) {
-      nsteps = 0;
-      wref = hi - lo;
-      c = NAN;
-    }
-    if (c > lo && c < hi) {
-      from_root = true;
-      nsteps++;
-    } else {
-      c = 0.5 * (lo + hi);
-      from_root = false;
-      nsteps = 0;
-      wref = hi - lo;
-    }
-    ph = v[0];
-    pb = v[1];
-    if (!(c > lo && c < hi)) return c;
-    tau = c;
-  }
-  return tau;
-}
-
-template <int EPT, class F>
 __device__ double alg1_f(F aval, int kbar, double theta, double *red) {
   if (kbar <= 0 || !(theta > 0.0)) return 0.0;
   const double K = (double)kbar;
@@ -1077,6 +982,9 @@ __device__ __forceinline__ void load_packed_status(PackedStatus<EPT> &sv, const 
   for (int q = 0; q < (EPT + 15) / 16; q++) sv.w[q] = stp[q * NT + threadIdx.x];
 }
 
+// The prox threshold tau of the pooled-threshold form (same search as
+// solve_tau above) over the register-resident magnitudes aval(e), warm-started
+// from the previous iteration's tau, one-barrier reductions.
 template <int EPT, class F>
 __device__ __forceinline__ double solve_tau_2(F aval, int kbar, double rho, double M, double warm, Red2 &R, int *evals) {
   double st[2] = {0.0, 0.0};
