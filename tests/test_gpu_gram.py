@@ -132,3 +132,44 @@ def test_batched_gram_cutoff_decisions(dev):
         if r["status"] == pr.CUTOFF_BRANCH:
             assert r["primal"] <= cutoff and f["lower_bound"] <= cutoff * (1 + 1e-9)
     c.close()
+
+
+def test_gram_rejects_logistic(dev):
+    import torch
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=256, p=128, corr=0.5, k_true=4, snr=5.0, loss=1, seed=2, storage="f64")
+    c = pr.Context(torch.from_numpy(inst.Xcm).to(dev), torch.from_numpy(inst.y).to(dev), 1)
+    with pytest.raises(pr.PrError):
+        c.enable_gram()                       # the Gram identities hold for least squares only
+    c.close()
+
+
+def test_gram_cutoff_warm_start_and_iteration_limit(dev):
+    """Single-node Gram mode: cutoff decisions agree with the matrix-vector
+    path and are confirmed over X, a warm start reaches the same bound, and an
+    iteration limit reports a valid (recomputed) bound."""
+    import torch
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=512, corr=0.7, k_true=8, snr=5.0, loss=0, seed=31, storage="f32")
+    cg, cm = _ctx(inst, dev, True), _ctx(inst, dev, False)
+    node = pr.Node(8, 0.3, 2.0, J0=[2, 40], J1=[7])
+    free = cm.solve(node, rel_gap_tol=1e-9)
+    lb = free["lower_bound"]
+    for cutoff, want in ((lb * 0.99, pr.CUTOFF_PRUNE), (lb * 1.01, pr.CUTOFF_BRANCH)):
+        rg = cg.solve(node, rel_gap_tol=1e-9, cutoff=cutoff)
+        rm = cm.solve(node, rel_gap_tol=1e-9, cutoff=cutoff)
+        assert rg["status"] == rm["status"] == want, (rg, rm)
+        if want == pr.CUTOFF_PRUNE:
+            assert rg["lower_bound"] >= cutoff
+        else:
+            assert rg["primal"] <= cutoff
+    warm = cg.solve(node, beta0=free["beta"], rel_gap_tol=1e-8)
+    assert warm["status"] == pr.CONVERGED and warm["iters"] < free["iters"]
+    assert abs(warm["lower_bound"] - lb) <= 1e-8 * abs(free["primal"])
+    short = cg.solve(node, rel_gap_tol=0.0, max_iter=5, want_zeta=True)
+    assert short["status"] == pr.MAXITER and short["iters"] == 5
+    st = node.status(inst.p)
+    psi = oracle.dual(inst.Xcm, inst.y, short["zeta"].cpu().numpy(), 0, 0.3, 2.0, 8, status=st)
+    assert abs(psi - short["lower_bound"]) <= 1e-11 * abs(psi) and psi <= lb * (1 + 1e-12)
+    cg.close()
+    cm.close()
