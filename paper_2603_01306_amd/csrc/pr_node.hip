@@ -60,15 +60,14 @@ __device__ __forceinline__ void hist_locate(SelLds &sm, int above, int k) {
 // sorted by one wave.  Requires 1 <= k <= #{a[j] >= 0}.
 __device__ double select_kth(const double *__restrict__ a, int64_t p, int k, SelLds &sm) {
   const int tid = threadIdx.x;
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)tid * E, j1 = (j0 + E < p) ? j0 + E : p;
   unsigned long long prefix = 0ull;
   int above = 0, shift = 52, width = 11;
   for (;;) {
     for (int b = tid; b < 2048; b += NT) sm.hist[b] = 0u;
     __syncthreads();
     const unsigned long long mask = (1ull << width) - 1ull;
-    for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+    for (int64_t j = threadIdx.x; j < p; j += NT) {
       double x = a[j];
       if (x >= 0.0) {
         unsigned long long key = (unsigned long long)__double_as_longlong(x);
@@ -87,7 +86,8 @@ __device__ double select_kth(const double *__restrict__ a, int64_t p, int k, Sel
     if (cnt <= 64) {
       if (tid == 0) sm.ngat = 0;
       __syncthreads();
-      for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+      for (int64_t j = threadIdx.x; j < p; j += NT) {
         double x = a[j];
         if (x >= 0.0) {
           unsigned long long key = (unsigned long long)__double_as_longlong(x);
@@ -121,10 +121,9 @@ __device__ double topsum_huber(const double *__restrict__ a, int64_t p, int kbar
   if (kbar <= 0) return 0.0;
   const double t = select_kth(a, p, kbar, sm);
   const double Ht = huber(t, M);
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)threadIdx.x * E, j1 = (j0 + E < p) ? j0 + E : p;
   double v[1] = {0.0};
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     double x = a[j];
     if (x >= 0.0) v[0] += fmax(huber(x, M) - Ht, 0.0);
   }
@@ -156,11 +155,12 @@ struct TauEval {
   double h, b, sB;
 };
 
-__device__ __forceinline__ TauEval tau_eval(const double *__restrict__ a, int64_t j0, int64_t j1,
-                                            double tau, double D, double *red) {
+__device__ __forceinline__ TauEval tau_eval(const double *__restrict__ a, int64_t p, double tau, double D,
+                                            double *red) {
   double v[3] = {0.0, 0.0, 0.0};
   const double hi = tau + D;
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     double x = a[j];
     if (x > tau) {
       v[1] += 1.0;
@@ -174,11 +174,10 @@ __device__ __forceinline__ TauEval tau_eval(const double *__restrict__ a, int64_
 
 __device__ double solve_tau(const double *__restrict__ a, int64_t p, int kbar, double rho, double M,
                             double warm, double *red, int *evals) {
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)threadIdx.x * E, j1 = (j0 + E < p) ? j0 + E : p;
   double st[2] = {0.0, 0.0};
   double mx = 0.0;
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     double x = a[j];
     if (x > 0.0) {
       st[0] += 1.0;
@@ -211,7 +210,7 @@ __device__ double solve_tau(const double *__restrict__ a, int64_t p, int kbar, d
   double wref = hi - lo;
   for (int it = 0; it < 200; it++) {
     const double D = Dof(tau);
-    TauEval e = tau_eval(a, j0, j1, tau, D, red);
+    TauEval e = tau_eval(a, p, tau, D, red);
     *evals = it + 1;
     if (from_root && e.h == ph && e.b == pb) return tau;  // sets reproduced: exact root
     const double S = e.h + (e.sB - (e.b - e.h) * tau) / D;
@@ -255,14 +254,13 @@ __device__ double solve_tau(const double *__restrict__ a, int64_t p, int kbar, d
 __device__ double alg1_free(const double *__restrict__ a, int64_t p, int kbar, double theta,
                             double *red) {
   if (kbar <= 0 || !(theta > 0.0)) return 0.0;
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)threadIdx.x * E, j1 = (j0 + E < p) ? j0 + E : p;
   const double K = (double)kbar;
   double s = theta / K;
   double prevK = 0.0;
   for (int it = 0; it <= kbar + 1; it++) {
     double v[3] = {0.0, 0.0, 0.0};  // #{q > s}, sum_{q <= s} q, sum_{q > s} q^2
-    for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+    for (int64_t j = threadIdx.x; j < p; j += NT) {
       double x = a[j];
       if (x >= 0.0) {
         if (x > s) {
@@ -284,7 +282,8 @@ __device__ double alg1_free(const double *__restrict__ a, int64_t p, int kbar, d
 
 // Support compaction, Algorithm 1 value, and dom g_N test (relative slack
 // 1e-9, as the oracle) for the iterate x.  Writes |x_j| (free) or -1 into
-// abuf, and the support list in ascending index order.
+// abuf, and the support list in a fixed order: thread t owns j = t, t + 512,
+// ... (coalesced passes) and its entries follow those of threads 0 .. t-1.
 struct IterStats {
   double gval;
   int indom, nsupp;
@@ -294,12 +293,11 @@ __device__ IterStats finish_iterate(const double *__restrict__ x, const int8_t *
                                     int64_t p, int kbar, double M, double *__restrict__ abuf,
                                     int32_t *__restrict__ sidx, double *__restrict__ sval,
                                     double *red, int *scan) {
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)threadIdx.x * E, j1 = (j0 + E < p) ? j0 + E : p;
   double v[2] = {0.0, 0.0};  // theta, sum_{J1} x^2
   double amax = 0.0, j0max = 0.0, boxmax = 0.0;
   int cnt = 0;
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double xj = x[j];
     const int s = st[j];
     const double ax = fabs(xj);
@@ -313,7 +311,8 @@ __device__ IterStats finish_iterate(const double *__restrict__ x, const int8_t *
   }
   int tot;
   int off = block_excl_scan<NT>(cnt, scan, &tot);
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double xj = x[j];
     if (xj != 0.0) {
       sidx[off] = (int32_t)j;
@@ -346,6 +345,7 @@ __global__ __launch_bounds__(NT) void k_node_init(const NodeParams *__restrict__
   __shared__ double red[NW * 4];
   __shared__ int scan[NW];
   const int64_t p = prm->p;
+#pragma unroll 8
   for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double b = beta0 ? beta0[j] : 0.0;
     nb.x0[j] = b;
@@ -404,8 +404,6 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
   const int kbar = prm->kbar, loss = prm->loss;
   const double lam2 = prm->lambda2, M = prm->M;
   const int8_t *__restrict__ st = prm->st;
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)tid * E, j1 = (j0 + E < p) ? j0 + E : p;
   const int parity = S->parity;
   const double L = S->L;
 
@@ -418,7 +416,8 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
   // dual: w = X^T zeta / (2 lambda2)
   const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
   double sj1[1] = {0.0};
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double w = B.h1[j] * wscale;
     const int s = st[j];
     if (s == kOne) sj1[0] += huber(w, M);
@@ -496,15 +495,18 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
   __syncthreads();
   double *__restrict__ xc = parity ? nb.x1 : nb.x0;
   double *__restrict__ xn = parity ? nb.x0 : nb.x1;  // holds x^{k-1}, receives x^{k+1}
-  if (bci[2])
-    for (int64_t j = j0; j < j1; j++) nb.xbest[j] = xc[j];
+  if (bci[2]) {
+#pragma unroll 8
+    for (int64_t j = threadIdx.x; j < p; j += NT) nb.xbest[j] = xc[j];
+  }
   if (bci[0]) return;
   const double m = bcd[0];
   const int restart = bci[1];
 
   // gradient step at the momentum point
   const double invL = 1.0 / L;
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double xk = xc[j], xq = xn[j];
     const double yj = xk + m * (xk - xq);
     double gj;
@@ -524,7 +526,8 @@ __global__ __launch_bounds__(NT) void k_node_step(const NodeParams *__restrict__
   int evals = 0;
   const double tau = solve_tau(nb.abuf, p, kbar, rho, M, S->tau, red, &evals);
   const double inv1p = 1.0 / (1.0 + rho);
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double v = nb.vbuf[j];
     const int s = st[j];
     double x = 0.0;
@@ -562,14 +565,14 @@ __global__ __launch_bounds__(NT) void k_prox(const double *v, double *out, int64
                                              int kbar, double M, const int8_t *__restrict__ st,
                                              double *abuf) {
   __shared__ double red[NW * 4];
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)threadIdx.x * E, j1 = (j0 + E < p) ? j0 + E : p;
-  for (int64_t j = j0; j < j1; j++) abuf[j] = (st[j] == kFree) ? fabs(v[j]) : -1.0;
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) abuf[j] = (st[j] == kFree) ? fabs(v[j]) : -1.0;
   __syncthreads();
   int evals;
   const double tau = solve_tau(abuf, p, kbar, rho, M, -1.0, red, &evals);
   const double inv1p = 1.0 / (1.0 + rho);
-  for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
     const double vj = v[j];
     const int s = st[j];
     double x = 0.0;
@@ -591,8 +594,6 @@ __global__ __launch_bounds__(NT) void k_regularizer(const double *beta, const do
   __shared__ double red[NW * 4];
   __shared__ int scan[NW];
   __shared__ SelLds sel;
-  const int64_t E = (p + NT - 1) / NT;
-  const int64_t j0 = (int64_t)threadIdx.x * E, j1 = (j0 + E < p) ? j0 + E : p;
   if (beta) {
     IterStats is = finish_iterate(beta, st, p, kbar, M, abuf, sidx, sval, red, scan);
     if (threadIdx.x == 0) out2[0] = is.indom ? is.gval : INFINITY;
@@ -600,7 +601,8 @@ __global__ __launch_bounds__(NT) void k_regularizer(const double *beta, const do
   }
   if (alpha) {
     double s1[1] = {0.0};
-    for (int64_t j = j0; j < j1; j++) {
+#pragma unroll 8
+    for (int64_t j = threadIdx.x; j < p; j += NT) {
       const int s = st[j];
       if (s == kOne) s1[0] += huber(alpha[j], M);
       abuf[j] = (s == kFree) ? fabs(alpha[j]) : -1.0;
