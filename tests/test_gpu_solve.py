@@ -101,6 +101,36 @@ def test_small_nodes_lower_bound_parity(dev, loss, node_seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("p,n,lam2", [(1000, 256, 0.5), (1500, 256, 0.75), (3000, 256, 1.5), (17000, 128, 20.0)])
+@pytest.mark.parametrize("loss", [0, 1])
+def test_node_step_tiers_match_oracle(dev, p, n, lam2, loss):
+    """The per-node step keeps 2, 4 or 8 entries per thread in registers for
+    p <= 1024, 2048, 4096 and switches to the strided kernel over HBM vectors
+    beyond 16384 entries: first iterates and the converged bound agree with
+    the oracle on each tier, p ragged against the workgroup."""
+    inst = make_instance(n=n, p=p, corr=0.5, k_true=6, snr=5.0, loss=loss, seed=40 + loss, storage="f32")
+    ctx = _ctx(dev, inst)
+    pr = _pr()
+    J0, J1 = make_nodes(inst.p, 1, seed=p, max_j0=60, max_j1=4)[0]
+    node = pr.Node(6, lam2, 2.0, J0=J0, J1=J1)
+    st = node.status(inst.p)
+    lam = float(np.linalg.eigvalsh(inst.X64() @ inst.X64().T).max())
+    L = (2.0 if loss == 0 else 0.25) * lam * 1.01
+    few = ctx.solve(node, max_iter=3, L=L, rel_gap_tol=0.0)
+    ref3 = oracle.solve(inst.Xcm, inst.y, loss, lam2, 2.0, 6, status=st, L=L, tol=0.0, max_iter=3)
+    assert few["iters"] == 3
+    assert abs(few["lower_bound"] - ref3["lb"]) <= 1e-11 * abs(ref3["ub"])
+    assert abs(few["primal"] - ref3["ub"]) <= 1e-11 * abs(ref3["ub"])
+    res = ctx.solve(node, want_zeta=True, rel_gap_tol=1e-7, L=L)
+    ref = oracle.solve(inst.Xcm, inst.y, loss, lam2, 2.0, 6, status=st, L=L, tol=1e-8)
+    print(p, loss, res["iters"], ref["iters"], res["lower_bound"], ref["lb"])
+    assert res["status"] == pr.CONVERGED
+    assert abs(res["lower_bound"] - ref["lb"]) <= 1e-6 * abs(ref["ub"])
+    psi = oracle.dual(inst.Xcm, inst.y, res["zeta"].cpu().numpy(), loss, lam2, 2.0, 6, status=st)
+    assert abs(psi - res["lower_bound"]) <= 1e-11 * abs(psi)
+    ctx.close()
+
+
 def test_node_edge_cases(c1):
     inst, ctx, lam = c1
     pr = _pr()
