@@ -29,6 +29,7 @@ columns of the current support), with the number of solves that repay G.
   python bench.py --e1               # g_N and prox evaluation times at the paper's microbenchmark shapes
   python bench.py --e3               # convergence of the iteration variants (gap restart vs others)
   python bench.py --bnb              # branch and bound on the paper's synthetic setting
+  python bench.py --paper-shapes     # root solve times at the paper's n = p = 1000 ... 16000 shapes
 """
 import argparse
 import hashlib
@@ -444,6 +445,57 @@ def bnb_bench(n=16000, p=16000, corr=0.5, k=10, lambda2=1.0, M=2.0, seed=0, batc
     ctx.close()
 
 
+def paper_shapes_bench(sizes=(1000, 2000, 4000, 8000, 16000), seeds=(0, 1, 2, 3, 4)):
+    """Root relaxation solve times at the shapes of the paper's GPU-acceleration
+    tables (Section 5.2): n = p, rows N(0, Sigma) with Sigma_ij = 0.5^|i-j|,
+    k = 10 unit coefficients, SNR 5, lambda2 = 1, M = 2, relative gap 1e-6,
+    cold start, least squares and logistic, five seeds.  X is stored FP32.
+    Per seed: context setup (||X||^2 by power iteration, once per design),
+    the first solve (graph capture included) and a repeated solve."""
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import make_instance
+    dev = torch.device("cuda:0")
+    rows = []
+    for loss in (pr.LSQ, pr.LOGISTIC):
+        for p in sizes:
+            rec = {"setup_s": [], "first_solve_s": [], "solve_s": [], "iters": [], "converged": []}
+            for seed in seeds:
+                inst = make_instance(n=p, p=p, corr=0.5, k_true=10, snr=5.0, loss=loss, seed=seed, storage="f32")
+                X = torch.from_numpy(inst.Xcm).to(dev)
+                y = torch.from_numpy(inst.y).to(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx = pr.Context(X, y, loss)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                node = pr.Node(10, 1.0, 2.0)
+                r1 = ctx.solve(node, want_beta=False)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                r2 = ctx.solve(node, want_beta=False)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                assert r1["lower_bound"] == r2["lower_bound"]
+                rec["setup_s"].append(t1 - t0)
+                rec["first_solve_s"].append(t2 - t1)
+                rec["solve_s"].append(t3 - t2)
+                rec["iters"].append(r2["iters"])
+                rec["converged"].append(r2["status"] == pr.CONVERGED and r2["rel_gap"] <= 1e-6)
+                ctx.close()
+                del X, y, inst
+            row = {"loss": "least_squares" if loss == pr.LSQ else "logistic", "n": p, "p": p,
+                   "all_converged": all(rec["converged"]), "iters_mean": float(np.mean(rec["iters"]))}
+            for key in ("setup_s", "first_solve_s", "solve_s"):
+                row[key + "_mean"] = round(float(np.mean(rec[key])), 4)
+                row[key + "_std"] = round(float(np.std(rec[key])), 4)
+            rows.append(row)
+            print(json.dumps({"progress": "paper shapes", **row}), flush=True)
+    print(json.dumps({"metric": "root relaxation solve time to 1e-6 rel. gap at the paper's shapes",
+                      "x_storage": "f32", "seeds": len(seeds), "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -457,6 +509,7 @@ def main():
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
     ap.add_argument("--bnb", action="store_true", help="branch and bound on the paper's synthetic setting instead")
+    ap.add_argument("--paper-shapes", action="store_true", help="root solve times at the paper's table shapes instead")
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args()
@@ -478,6 +531,9 @@ def main():
         return
     if args.bnb:
         bnb_bench()
+        return
+    if args.paper_shapes:
+        paper_shapes_bench()
         return
     import torch
     dev = torch.device("cuda:0")

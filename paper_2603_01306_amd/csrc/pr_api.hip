@@ -28,6 +28,9 @@ hipError_t dalloc(T **p, size_t count) {
   return hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1));
 }
 
+constexpr int kLanczosMax = 512;   // Lanczos steps for ||X||_2^2 at most
+constexpr int kLanczosCheck = 8;   // steps between convergence checks on the host
+
 }  // namespace
 
 struct pr_ctx {
@@ -51,7 +54,8 @@ struct pr_ctx {
   double *d_v = nullptr;         // p
   double *d_w = nullptr;         // p
   double *d_scal = nullptr;      // small scalars
-  double *d_lam = nullptr;       // power-iteration history
+  double *d_lam = nullptr;       // Lanczos coefficients: alpha [kLanczosMax], beta [kLanczosMax]
+  double *d_vprev = nullptr;     // p: previous Lanczos vector
   double *d_regscratch = nullptr;  // 3p
   hipGraphExec_t gexec = nullptr;
   int32_t graph_units = 0;
@@ -139,7 +143,7 @@ void free_ctx(pr_ctx *c) {
   void *bufs[] = {c->d_prm, c->d_state, c->d_status, c->d_stp, c->nb.x0, c->nb.x1, c->nb.xbest, c->nb.hprev, c->nb.vbuf,
                   c->nb.abuf, c->nb.sidx, c->nb.sval, c->B.r, c->B.gm, c->B.ucur, c->B.uprev,
                   c->B.zbest, c->B.h1, c->B.h2, c->B.part, c->B.rbsum, c->iota,
-                  c->d_np, c->d_u, c->d_v, c->d_w, c->d_scal, c->d_lam, c->d_regscratch};
+                  c->d_np, c->d_u, c->d_v, c->d_w, c->d_scal, c->d_lam, c->d_vprev, c->d_regscratch};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_state) (void)hipHostFree(c->h_state);
@@ -250,45 +254,72 @@ int ensure_graph(pr_ctx *c, int32_t units) {
   return PR_OK;
 }
 
-// ||X||_2^2 by power iteration on X^T X with Rayleigh quotients ||X v||^2,
-// ||v|| = 1, from the all-ones direction; stops when two consecutive
-// quotients agree to 1e-10 relative (checked every 16 iterations) or after
-// 2000 iterations.
-int power_norm2(pr_ctx *c) {
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal
+// a[0..m) and off-diagonal b[0..m-1), by bisection on the Sturm count (the
+// number of negative pivots of T - x I = L D L^T is the number of eigenvalues
+// below x), started from the Gershgorin interval.  Returns the upper end of
+// the final interval.
+double tridiag_max_eig(const double *a, const double *b, int m) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; i++) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  hi += 1e-15 * fabs(hi) + 1e-300;
+  auto below = [&](double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; i++) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) cnt++;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 2e-16 * std::max(fabs(lo), fabs(hi)); it++) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) == m) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+// ||X||_2^2 = lambda_max(X^T X) by the Lanczos recurrence on X^T X from the
+// all-ones direction: each step is one product X v, one X^T u and one
+// single-workgroup update, with no host round trip; every kLanczosCheck steps
+// the host takes the top eigenvalue of the tridiagonal matrix of the
+// recurrence coefficients (a lower bound that rises to lambda_max) and stops
+// once it moved by at most 1e-13 relative over the last check interval, when
+// the recurrence breaks down (an invariant subspace: the value is exact), or
+// after min(p, kLanczosMax) steps.  Without reorthogonalisation the extreme
+// value still converges; lost orthogonality only repeats converged values.
+int lanczos_norm2(pr_ctx *c) {
   const int64_t n = c->P.n, p = c->P.p;
   std::vector<double> ones((size_t)p, 1.0 / sqrt((double)p));
   PR_TRY(hipMemcpyAsync(c->d_v, ones.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->stream));
-  const int maxit = 2000, chunk = 16;
-  std::vector<double> lam(chunk);
+  double *alpha = c->d_lam, *beta = c->d_lam + kLanczosMax;
+  std::vector<double> ha(kLanczosMax), hb(kLanczosMax);
+  const int mmax = (int)std::min<int64_t>(kLanczosMax, p);
   double prev = -1.0;
-  for (int it0 = 0; it0 < maxit; it0 += chunk) {
-    for (int q = 0; q < chunk; q++) {
-      if (launch_spfwd(c->P, c->B, c->iota, c->d_v, c->d_np, kSpPlain, nullptr, c->d_u, c->stream) !=
-          hipSuccess)
-        return PR_EDEVICE;
-      PR_TRY(launch_sumsq(c->d_u, n, c->d_lam + q, c->stream));
-      PR_TRY(launch_gemv_t(c->P, c->d_u, nullptr, c->d_w, nullptr, nullptr, c->stream));
-      PR_TRY(launch_sumsq(c->d_w, p, c->d_scal, c->stream));
-      PR_TRY(hipMemcpyAsync(lam.data(), c->d_lam, sizeof(double) * chunk, hipMemcpyDeviceToHost, c->stream));
-      // v = w / ||w|| needs the norm on the host only once per chunk: the
-      // device normalises with the value it just computed
-      double nw = 0.0;
-      PR_TRY(hipMemcpyAsync(&nw, c->d_scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      PR_TRY(hipStreamSynchronize(c->stream));
-      if (!(nw > 0.0)) {
-        c->norm2 = lam[q];
-        return PR_OK;
-      }
-      PR_TRY(launch_scale_copy(c->d_w, c->d_v, 1.0 / sqrt(nw), p, c->stream));
-      const double l = lam[q];
-      if (prev > 0.0 && fabs(l - prev) <= 1e-10 * l) {
-        c->norm2 = l;
-        return PR_OK;
-      }
-      prev = l;
-    }
+  for (int j = 0; j < mmax; j++) {
+    if (launch_spfwd(c->P, c->B, c->iota, c->d_v, c->d_np, kSpPlain, nullptr, c->d_u, c->stream) != hipSuccess)
+      return PR_EDEVICE;
+    PR_TRY(launch_sumsq(c->d_u, n, alpha + j, c->stream));
+    PR_TRY(launch_gemv_t(c->P, c->d_u, nullptr, c->d_w, nullptr, nullptr, c->stream));
+    PR_TRY(launch_lanczos(c->d_w, c->d_v, c->d_vprev, alpha + j, j > 0 ? beta + j - 1 : nullptr, beta + j, p,
+                          c->stream));
+    const int m = j + 1;
+    if (m % kLanczosCheck != 0 && m != mmax) continue;
+    PR_TRY(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
+    PR_TRY(hipMemcpyAsync(hb.data(), beta, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
+    PR_TRY(hipStreamSynchronize(c->stream));
+    const double th = tridiag_max_eig(ha.data(), hb.data(), m);
+    c->norm2 = th;
+    if (!(hb[(size_t)m - 1] > 1e-14 * th)) return PR_OK;
+    if (prev > 0.0 && th - prev <= 1e-13 * th) return PR_OK;
+    prev = th;
   }
-  c->norm2 = prev;
   return PR_OK;
 }
 
@@ -620,7 +651,8 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   ok = ok && dalloc(&c->iota, p) == hipSuccess && dalloc(&c->d_np, 1) == hipSuccess;
   ok = ok && dalloc(&c->d_u, n) == hipSuccess && dalloc(&c->d_v, p) == hipSuccess;
   ok = ok && dalloc(&c->d_w, p) == hipSuccess && dalloc(&c->d_scal, 8) == hipSuccess;
-  ok = ok && dalloc(&c->d_lam, 16) == hipSuccess && dalloc(&c->d_regscratch, 3 * (size_t)p) == hipSuccess;
+  ok = ok && dalloc(&c->d_lam, 2 * kLanczosMax) == hipSuccess && dalloc(&c->d_vprev, p) == hipSuccess;
+  ok = ok && dalloc(&c->d_regscratch, 3 * (size_t)p) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreate(&c->tev[0]) == hipSuccess && hipEventCreate(&c->tev[1]) == hipSuccess;
@@ -640,7 +672,7 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
     free_ctx(c);
     return PR_EDEVICE;
   }
-  int rc = power_norm2(c);
+  int rc = lanczos_norm2(c);
   if (rc != PR_OK) {
     free_ctx(c);
     return rc;

@@ -669,6 +669,7 @@ __global__ __launch_bounds__(NT) void k_zeta_terms(int32_t loss, const double *z
 __global__ __launch_bounds__(NT) void k_sumsq(const double *v, int64_t n, double *out) {
   __shared__ double red[NW * 4];
   double s[1] = {0.0};
+#pragma unroll 8
   for (int64_t i = threadIdx.x; i < n; i += NT) s[0] += v[i] * v[i];
   block_sum<NT, 1>(s, red);
   if (threadIdx.x == 0) *out = s[0];
@@ -678,6 +679,35 @@ __global__ void k_scale_copy(const double *src, double *dst, double a, int64_t n
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = a * src[i];
+}
+
+// One step of the Lanczos recurrence on A = X^T X.  On entry w = A v_j;
+// w <- w - alpha_j v_j - beta_{j-1} v_{j-1}, beta_j = ||w||, then
+// v_{j-1} <- v_j and v_j <- w / beta_j (zero when beta_j = 0).  alpha_j and
+// beta_{j-1} come from device memory (no beta_{j-1} at j = 0); beta_j is
+// written to beta_out.  Every thread owns the same indices in both passes.
+__global__ __launch_bounds__(NT) void k_lanczos(double *w, double *v, double *vprev, const double *alpha,
+                                                const double *beta_prev, double *beta_out, int64_t p) {
+  __shared__ double red[NW * 4];
+  const double a = *alpha;
+  const double b = beta_prev ? *beta_prev : 0.0;
+  double s[1] = {0.0};
+#pragma unroll 8
+  for (int64_t i = threadIdx.x; i < p; i += NT) {
+    double t = w[i] - a * v[i];
+    if (beta_prev) t -= b * vprev[i];
+    w[i] = t;
+    s[0] += t * t;
+  }
+  block_sum<NT, 1>(s, red);
+  const double nb = sqrt(s[0]);
+  if (threadIdx.x == 0) *beta_out = nb;
+  const double inv = nb > 0.0 ? 1.0 / nb : 0.0;
+#pragma unroll 8
+  for (int64_t i = threadIdx.x; i < p; i += NT) {
+    vprev[i] = v[i];
+    v[i] = w[i] * inv;
+  }
 }
 
 __global__ void k_iota(int32_t *idx, int64_t n) {
@@ -1923,6 +1953,12 @@ hipError_t launch_sumsq(const double *v, int64_t n, double *out, hipStream_t s) 
 
 hipError_t launch_scale_copy(const double *src, double *dst, double a, int64_t n, hipStream_t s) {
   k_scale_copy<<<256, 256, 0, s>>>(src, dst, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos(double *w, double *v, double *vprev, const double *alpha, const double *beta_prev,
+                          double *beta_out, int64_t p, hipStream_t s) {
+  k_lanczos<<<1, NT, 0, s>>>(w, v, vprev, alpha, beta_prev, beta_out, p);
   return hipGetLastError();
 }
 

@@ -167,11 +167,18 @@ def test_gemv_and_gemv_t_match_oracle(dev, storage, n, p):
     ctx.close()
 
 
-def test_norm2_matches_oracle_power_iteration(dev):
-    inst = make_instance(n=2048, p=512, corr=0.9, k_true=8, snr=5.0, loss=0, seed=2, storage="f32")
+@pytest.mark.parametrize("n,p,corr,storage", [(2048, 512, 0.9, "f32"), (64, 1000, 0.5, "f64"), (300, 1, 0.0, "f64"),
+                                               (1000, 3, 0.99, "f64"), (4096, 2048, 0.5, "bf16")])
+def test_norm2_matches_exact_eigenvalue(dev, n, p, corr, storage):
+    """||X||_2^2 of the context (Lanczos on X^T X) against the largest
+    eigenvalue of the smaller Gram matrix by a dense symmetric eigensolver:
+    tall, wide (rank n < p), one column, and a few strongly correlated
+    columns (the recurrence breaks down after p steps)."""
+    inst = make_instance(n=n, p=p, corr=corr, k_true=1, snr=5.0, loss=0, seed=2, storage=storage)
     ctx = _ctx_for(dev, inst.Xcm, inst.y)
-    lam = np.linalg.eigvalsh(inst.X64() @ inst.X64().T).max()
-    assert abs(ctx.norm2() - lam) <= 1e-6 * lam
+    X = inst.X64()
+    lam = np.linalg.eigvalsh(X @ X.T if p <= n else X.T @ X).max()
+    assert abs(ctx.norm2() - lam) <= 1e-10 * lam
     ctx.close()
 
 
