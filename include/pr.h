@@ -254,14 +254,17 @@ int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64
             int64_t Nr, int64_t K, int32_t KS);
 
 /* ---- Branch and bound -------------------------------------------------
- * Best-first branch and bound for problem (1) with least-squares loss, built
- * on pr_solve_batch: every node bound is the certified FP64 bound of its
+ * Best-first branch and bound for problem (1), least-squares or logistic
+ * loss, built on pr_solve_batch (one node at a time where the context has no
+ * batched path): every node bound is the certified FP64 bound of its
  * perspective relaxation, solved with dynamic termination against the
  * incumbent (Section 5.3).  Branching on the free coordinate with the largest
  * |beta_j| of the node's relaxation solution (children: fixed to one, fixed to
- * zero), children warm-started from the parent's solution.  Incumbents: ridge
- * fit on J1 + the kbar largest free |beta_j| of each relaxation solution,
- * clipped to the box (supports of at most 32 coordinates). */
+ * zero), children warm-started from the parent's solution.  Incumbents on the
+ * support S = J1 + the kbar largest free |beta_j| of each relaxation solution
+ * (at most 32 coordinates): least squares, the ridge fit on S clipped to the
+ * box; logistic, pr_solve on the leaf node J1 = S, J0 = the rest (there the
+ * relaxation is problem (1) restricted to S), each support once. */
 #define PR_BNB_OPTIMAL 1     /* (UB - LB) / |UB| <= rel_gap_tol */
 #define PR_BNB_NODE_LIMIT 2
 #define PR_BNB_TIME_LIMIT 3
@@ -288,7 +291,7 @@ void pr_bnb_opts_default(pr_bnb_opts *opts);
 
 /* Run branch and bound from `root` (its J0 / J1 are kept in every node).
  * beta_best: device p or NULL, receives the incumbent.  out: host.  PR_EINVAL
- * for a logistic problem or bad options; node errors as pr_solve. */
+ * for bad options; node errors as pr_solve. */
 int pr_bnb(pr_ctx *ctx, const pr_node *root, const pr_bnb_opts *opts, double *beta_best, pr_bnb_result *out);
 
 /* ---- Learned warm start for child nodes --------------------------------

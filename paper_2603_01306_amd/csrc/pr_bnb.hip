@@ -11,17 +11,23 @@
 // coordinate with the largest |beta_j| of its relaxation solution (children:
 // j fixed to one, j fixed to zero).
 //
-// Incumbent: the support J1 + the kbar largest |beta_j| over the free
-// coordinates of each node's relaxation solution; on that support the ridge
-// problem min ||y - X_S b||^2 + lambda2 ||b||^2 is solved (Cholesky of
+// Incumbent: the support S = J1 + the kbar largest |beta_j| over the free
+// coordinates of each node's relaxation solution.  Least squares: the ridge
+// problem min ||y - X_S b||^2 + lambda2 ||b||^2 is solved on S (Cholesky of
 // X_S^T X_S + lambda2 I) and b is clipped to the box [-M, M], which keeps it
 // feasible; its objective, computed exactly from X_S^T X_S, X_S^T y and y^T y,
-// is an upper bound on the optimum of (1).
+// is an upper bound on the optimum of (1).  Logistic: the leaf node J1 = S,
+// J0 = the rest has kbar = 0, where g_N is half the squared norm and the
+// relaxation is problem (1) restricted to S (Section 3); pr_solve on it
+// (warm-started from the node's solution) returns a feasible point whose
+// primal value, evaluated in FP64 over the stored X, is the objective of (1)
+// there.  Each support is tried once.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <queue>
+#include <set>
 #include <vector>
 
 #include "pr_device.h"
@@ -161,14 +167,16 @@ struct BnbState {
   int32_t slots = 0;
   std::vector<int32_t> free_slots, refs;
   double *d_B0 = nullptr, *d_Bout = nullptr;
+  double *d_cand = nullptr;  // p: logistic incumbent candidate
   double ub = INFINITY;
   std::vector<double> best;  // dense incumbent (host)
+  std::set<std::vector<int32_t>> tried;  // logistic supports already solved
 };
 
 // Incumbent candidate from a relaxation solution (host copy beta); updates
 // st.ub / st.best when it improves.
 static int try_incumbent(BnbState &st, const pr_node &node, const std::vector<int8_t> &status,
-                         const std::vector<double> &beta, double lam2, double M) {
+                         const std::vector<double> &beta, const double *d_beta, double lam2, double M) {
   const int64_t p = st.p;
   std::vector<int32_t> S;
   int32_t kbar = node.k;
@@ -186,6 +194,34 @@ static int try_incumbent(BnbState &st, const pr_node &node, const std::vector<in
   const int m = (int)S.size();
   if (m == 0 || m > kSubMax) return PR_OK;
   std::sort(S.begin(), S.end());
+  if (st.P.loss == kLogistic) {
+    if (!st.tried.insert(S).second) return PR_OK;
+    std::vector<int32_t> J0;
+    J0.reserve((size_t)(p - m));
+    size_t q = 0;
+    for (int64_t j = 0; j < p; j++) {
+      if (q < S.size() && S[q] == (int32_t)j) q++;
+      else J0.push_back((int32_t)j);
+    }
+    pr_node leaf = node;
+    leaf.J1 = S.data();
+    leaf.n1 = m;
+    leaf.J0 = J0.empty() ? nullptr : J0.data();
+    leaf.n0 = (int64_t)J0.size();
+    pr_opts lo;
+    pr_opts_default(&lo);
+    lo.rel_gap_tol = 1e-9;
+    pr_result r;
+    int rc = pr_solve(st.c, &leaf, &lo, d_beta, st.d_cand, nullptr, &r);
+    if (rc != PR_OK) return rc;
+    if (r.primal < st.ub) {
+      st.ub = r.primal;
+      st.best.assign((size_t)p, 0.0);
+      PR_TRY(hipMemcpyAsync(st.best.data(), st.d_cand, sizeof(double) * p, hipMemcpyDeviceToHost, st.s));
+      PR_TRY(hipStreamSynchronize(st.s));
+    }
+    return PR_OK;
+  }
   PR_TRY(hipMemcpyAsync(st.d_S, S.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st.s));
   PR_TRY(launch_subgram(st.P, st.d_S, m, st.d_sub, st.s));
   std::vector<double> sub((size_t)m * (m + 1));
@@ -234,7 +270,6 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
   if (opts_in) o = *opts_in;
   if (!(o.rel_gap_tol >= 0.0) || o.max_nodes < 1 || o.batch < 0 || !(o.time_limit_s > 0.0)) return PR_EINVAL;
   const Problem &P = ctx_problem(c);
-  if (P.loss != kLsq) return PR_EINVAL;  // the incumbent heuristic is for least squares
   const auto t0 = std::chrono::steady_clock::now();
   auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
   {
@@ -260,8 +295,9 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
   ok = ok && hipMalloc((void **)&st.arena, sizeof(double) * st.slots * P.p) == hipSuccess;
   ok = ok && hipMalloc((void **)&st.d_B0, sizeof(double) * B * P.p) == hipSuccess;
   ok = ok && hipMalloc((void **)&st.d_Bout, sizeof(double) * B * P.p) == hipSuccess;
+  ok = ok && hipMalloc((void **)&st.d_cand, sizeof(double) * P.p) == hipSuccess;
   auto cleanup = [&]() {
-    void *bufs[] = {st.d_S, st.d_sub, st.arena, st.d_B0, st.d_Bout};
+    void *bufs[] = {st.d_S, st.d_sub, st.arena, st.d_B0, st.d_Bout, st.d_cand};
     for (void *q : bufs)
       if (q) (void)hipFree(q);
   };
@@ -373,7 +409,7 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
         rc = PR_EDEVICE;
         break;
       }
-      rc = try_incumbent(st, nodes[(size_t)i], sv, bh, lam2, M);
+      rc = try_incumbent(st, nodes[(size_t)i], sv, bh, st.d_Bout + (int64_t)i * P.p, lam2, M);
       if (rc != PR_OK) break;
       if (gap_closed(bound)) {
         pruned++;

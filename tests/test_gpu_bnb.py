@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.ksparse import ksparse_bruteforce
+from oracle.ksparse import ksparse_bruteforce, ksparse_bruteforce_logistic
 from workloads import make_instance
 
 pytestmark = pytest.mark.gpu
@@ -22,7 +22,7 @@ def _ctx(inst, dev, max_batch):
         X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
     else:
         X = torch.from_numpy(inst.Xcm).to(dev)
-    return pr.Context(X, torch.from_numpy(inst.y).to(dev), 0, max_batch=max_batch)
+    return pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
 
 
 def _objective(X, y, b, lam2):
@@ -46,6 +46,31 @@ def test_bnb_matches_enumeration(dev, seed, k, lam2, J0, J1):
     b = beta.cpu().numpy()
     assert np.count_nonzero(b) <= k and np.all(np.abs(b) <= 2.0) and np.all(b[list(J0)] == 0)
     assert abs(_objective(X, y, b, lam2) - res["upper_bound"]) <= 1e-10 * res["upper_bound"]
+    ctx.close()
+
+
+@pytest.mark.parametrize("seed,k,lam2,J0,J1", [(6, 3, 0.3, (), ()), (7, 2, 0.5, (1,), (4,))])
+def test_bnb_logistic_matches_enumeration(dev, seed, k, lam2, J0, J1):
+    """Logistic loss: the tree closes on the optimum of problem (1) found by
+    enumerating every support (box-constrained logistic ridge per support);
+    the incumbent is a feasible k-sparse point whose objective is the
+    reported upper bound."""
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=120, p=12, corr=0.5, k_true=3, snr=4.0, loss=1, seed=seed, storage="f64")
+    X, y = inst.X64().T, inst.y
+    ctx = _ctx(inst, dev, 8)
+    res, beta = ctx.bnb(pr.Node(k, lam2, 2.0, J0=J0, J1=J1), rel_gap_tol=1e-7,
+                        node_opts=dict(rel_gap_tol=1e-9, max_iter=200000))
+    opt, S, _ = ksparse_bruteforce_logistic(X, y, k, lam2, 2.0, J0=J0, J1=J1)
+    print(seed, res, opt, S, flush=True)
+    assert res["status"] == pr.BNB_OPTIMAL
+    assert res["lower_bound"] <= opt * (1 + 1e-9)
+    assert res["upper_bound"] >= opt * (1 - 1e-9)
+    assert res["upper_bound"] - opt <= 2e-7 * opt
+    b = beta.cpu().numpy()
+    assert np.count_nonzero(b) <= k and np.all(np.abs(b) <= 2.0) and np.all(b[list(J0)] == 0)
+    obj = float(np.sum(np.logaddexp(0.0, -y * (X @ b))) + lam2 * b @ b)
+    assert abs(obj - res["upper_bound"]) <= 1e-10 * res["upper_bound"]
     ctx.close()
 
 
