@@ -240,6 +240,17 @@ int pr_time_batch_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms_fwd, dou
  * context has the batched path and max_batch >= m. */
 int pr_time_gram_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms);
 
+/* Support-union compaction of the batched Gram product: after the first
+ * graph launch of a batched Gram solve, the union U of the iterates' supports
+ * is taken; while its size padded to the GEMM's reduction granule (*kp) is at
+ * most 3/4 of p, each product runs as G[:, U] X_it[U, :] over kp reduction
+ * indices, plus the (few) nonzeros outside U added column by column, so the
+ * result is the full product up to summation order.  Reports |U| (*ku), *kp
+ * and the number of nonzeros outside U summed over the nodes' last iterates
+ * (*nout) of the last pr_solve_batch on this context, all 0 when it ran
+ * without the compaction.  ku, kp, nout: host. */
+int pr_batch_union_size(pr_ctx *ctx, int64_t *ku, int64_t *kp, int64_t *nout);
+
 /* FP64 MFMA product used by pr_solve_batch for both of its matrix products
  * (test and measurement entry point): C[z][r][c] = sum over k in split z of
  * A[c][k] * B[r][k].  A is Mc x K, row-major BF16 bit patterns (uint16,

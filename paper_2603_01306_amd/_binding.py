@@ -22,7 +22,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
+           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
            "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
@@ -119,6 +119,9 @@ def load():
                                          ctypes.POINTER(ctypes.c_double)]
         L.pr_time_gram_gemm.restype = ctypes.c_int
         L.pr_time_gram_gemm.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.pr_batch_union_size.restype = ctypes.c_int
+        L.pr_batch_union_size.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]
         L.pr_gemm.restype = ctypes.c_int
         L.pr_gemm.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
                               ctypes.c_int64, ctypes.c_int32]
@@ -316,6 +319,17 @@ class Context:
         a = ctypes.c_double()
         _check(load().pr_time_gram_gemm(self.h, int(m), int(reps), ctypes.byref(a)), "pr_time_gram_gemm")
         return a.value
+
+    def batch_union_size(self):
+        """(|U|, padded size, nonzeros outside U at the nodes' last iterates)
+        of the support union the last batched Gram solve compacted its product
+        to, (0, 0, 0) when it ran without."""
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        o = ctypes.c_int64()
+        _check(load().pr_batch_union_size(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(o)),
+               "pr_batch_union_size")
+        return a.value, b.value, o.value
 
     def bnb(self, root, node_opts=None, **opts):
         """Branch and bound from `root`; returns (result dict, incumbent (p,) float64)."""

@@ -30,6 +30,7 @@ hipError_t dalloc(T **p, size_t count) {
 
 constexpr int kLanczosMax = 512;   // Lanczos steps for ||X||_2^2 at most
 constexpr int kLanczosCheck = 8;   // steps between convergence checks on the host
+constexpr int kUnionRebuilds = 8;  // checks for new coordinates of the batched Gram union per solve
 
 }  // namespace
 
@@ -79,7 +80,7 @@ struct pr_ctx {
   NodeState *h_bstate = nullptr;  // pinned, cap
   int32_t *d_active = nullptr;
   int32_t *d_rowmap = nullptr;    // [cap padded] slots of the nodes still iterating
-  int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split, -, tile counters x2}
+  int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split, compacted Gram split, tile counters x2}
   int32_t *d_ftab = nullptr;      // [kTuneTables][kTuneMax] tuned split factors per active row-tile count
   int32_t h_ftab[kTuneTables * kTuneMax] = {};
   // batched Gram mode: U = G X_it planes [KSG * f][cap padded][p] (CT's storage when it is large enough)
@@ -91,6 +92,19 @@ struct pr_ctx {
   int32_t *h_active = nullptr;    // pinned, 2 slots
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
+  int64_t bgraph_kp = 0, bgraph_ku = 0;
+  // support-union compaction of the batched Gram product (built per pr_solve_batch)
+  bool union_on = false;
+  int64_t ku = 0, kp = 0;           // union size, padded to the GEMM's reduction granule
+  int64_t union_nout = 0;           // nonzeros outside the union at the nodes' last iterates
+  int32_t *d_umask = nullptr;       // [p]
+  int32_t *d_ulist = nullptr;       // [p] union coordinates, ascending
+  int32_t *d_olist = nullptr;       // [p] the other coordinates
+  int32_t *d_ocnt = nullptr;        // [cap padded] nonzeros outside the union per node
+  int32_t *d_oidx = nullptr;        // [cap padded][p]
+  double *d_oval = nullptr;         // [cap padded][p]
+  double *BxU = nullptr;            // [cap padded][kp max] compacted iterates
+  double *GU = nullptr;             // [p][kp max] union columns of G
   // least squares from the Gram matrix (pr_ctx_enable_gram)
   bool gram = false;
   double *G = nullptr;   // [p][p] X^T X over the stored X, FP64
@@ -129,6 +143,11 @@ void free_ctx(pr_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   if (c->cg_own && c->CG) (void)hipFree(c->CG);
+  {
+    void *ub[] = {c->d_umask, c->d_ulist, c->d_olist, c->d_ocnt, c->d_oidx, c->d_oval, c->BxU, c->GU};
+    for (void *b : ub)
+      if (b) (void)hipFree(b);
+  }
   void *bb[] = {c->bstp, c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
                 c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb};
   for (void *b : bb)
@@ -499,7 +518,7 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   BatchBufs bb{};
   bb.m = m;
   bb.Nr = nr_of(m);
-  bb.ksp = c->d_split + 2;
+  bb.ksp = c->d_split + (c->gram && c->union_on ? 3 : 2);  // planes of the product the step sums
   bb.nfb = c->nfb;
   bb.x0 = c->bx0;
   bb.x1 = c->bx1;
@@ -528,14 +547,26 @@ hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
   hipError_t e;
   if (c->gram) {
     e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KSG, 2,
-                            s);
+                            c->union_on ? c->kp : p, p, s);
     if (e != hipSuccess) return e;
-    e = launch_gemm_any(kF64, c->G, p, kF64, c->Bx, p, c->CG, p, Nr, p, c->KSG, c->d_active, c->d_rowmap,
-                        c->d_split, c->d_split + 2, c->KSG * c->fmaxG, c->d_split + 4, s);
+    if (c->union_on) {
+      e = launch_union_compact(c->Bx, p, c->d_rowmap, c->d_split, Nr, c->d_ulist, c->ku, c->kp, c->d_olist,
+                               p - c->ku, c->BxU, c->d_ocnt, c->d_oidx, c->d_oval, c->d_active, s);
+      if (e != hipSuccess) return e;
+      e = launch_gemm_any(kF64, c->GU, c->kp, kF64, c->BxU, c->kp, c->CG, p, Nr, c->kp, c->KSG, c->d_active,
+                          c->d_rowmap, c->d_split, c->d_split + 3, c->KSG * c->fmaxG, c->d_split + 4, s);
+      if (e != hipSuccess) return e;
+      e = launch_union_fix(c->G, p, c->d_rowmap, c->d_split, Nr, c->d_ocnt, c->d_oidx, c->d_oval, c->CG,
+                           c->d_active, s);
+    } else {
+      e = launch_gemm_any(kF64, c->G, p, kF64, c->Bx, p, c->CG, p, Nr, p, c->KSG, c->d_active, c->d_rowmap,
+                          c->d_split, c->d_split + 2, c->KSG * c->fmaxG, c->d_split + 4, s);
+    }
     if (e != hipSuccess) return e;
     return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
   }
-  e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KS, 1, s);
+  e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KS, 1, p, p,
+                          s);
   if (e != hipSuccess) return e;
   e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
                       c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
@@ -549,7 +580,10 @@ hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
 }
 
 int ensure_batch_graph(pr_ctx *c, int32_t m, int32_t units) {
-  if (c->bgexec && c->bgraph_units == units && c->bgraph_m == m) return PR_OK;
+  // the union sizes are kernel arguments of the captured launches
+  const int64_t kp = c->union_on ? c->kp : 0, ku = c->union_on ? c->ku : 0;
+  if (c->bgexec && c->bgraph_units == units && c->bgraph_m == m && c->bgraph_kp == kp && c->bgraph_ku == ku)
+    return PR_OK;
   if (c->bgexec) {
     (void)hipGraphExecDestroy(c->bgexec);
     c->bgexec = nullptr;
@@ -571,6 +605,59 @@ int ensure_batch_graph(pr_ctx *c, int32_t m, int32_t units) {
   }
   c->bgraph_units = units;
   c->bgraph_m = m;
+  c->bgraph_kp = kp;
+  c->bgraph_ku = ku;
+  return PR_OK;
+}
+
+// Support union of the batch's current iterates (rows 0..m-1 of Bx) for the
+// Gram product.  fresh: a new union, compaction on when its padded size is
+// at most 3/4 of p.  Otherwise the current iterates' supports are joined to
+// the union in use, unless the join would not fit (the union in use stays,
+// its misses go through the correction kernel).  *changed tells whether the
+// lists and G[:, U] were rebuilt.  Runs between graph launches, with nothing
+// else in flight.
+int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
+  const int64_t p = c->P.p;
+  const int NrMax = nr_of(c->max_batch);
+  // the FP64 tile steps 16 reduction indices; every split count the tuned
+  // table may pick (KSG * f, f <= fmaxG) must divide kp into such steps
+  const int64_t gran = 16LL * c->KSG * c->fmaxG;
+  const int64_t kpmax = (3 * p / 4) / gran * gran;
+  *changed = false;
+  if (fresh) c->union_on = false;
+  if (kpmax < gran) return PR_OK;
+  if (!c->d_umask) {
+    bool ok = dalloc(&c->d_umask, p) == hipSuccess && dalloc(&c->d_ulist, p) == hipSuccess;
+    ok = ok && dalloc(&c->d_olist, p) == hipSuccess && dalloc(&c->d_ocnt, NrMax) == hipSuccess;
+    ok = ok && dalloc(&c->d_oidx, (size_t)NrMax * p) == hipSuccess;
+    ok = ok && dalloc(&c->d_oval, (size_t)NrMax * p) == hipSuccess;
+    ok = ok && dalloc(&c->BxU, (size_t)NrMax * kpmax) == hipSuccess;
+    ok = ok && dalloc(&c->GU, (size_t)p * kpmax) == hipSuccess;
+    if (!ok) return PR_ENOMEM;
+  }
+  hipStream_t s = c->stream;
+  if (fresh) PR_TRY(hipMemsetAsync(c->d_umask, 0, sizeof(int32_t) * p, s));
+  PR_TRY(launch_union_mask(c->Bx, m, p, c->d_umask, s));
+  std::vector<int32_t> mask((size_t)p);
+  PR_TRY(hipMemcpyAsync(mask.data(), c->d_umask, sizeof(int32_t) * p, hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> ul, ol;
+  for (int64_t j = 0; j < p; j++) (mask[(size_t)j] ? ul : ol).push_back((int32_t)j);
+  const int64_t ku = (int64_t)ul.size();
+  const int64_t kp = (ku + gran - 1) / gran * gran;
+  if (ku == 0 || kp > kpmax) return PR_OK;
+  if (!fresh && ku == c->ku) return PR_OK;
+  PR_TRY(hipMemcpyAsync(c->d_ulist, ul.data(), sizeof(int32_t) * ku, hipMemcpyHostToDevice, s));
+  if (!ol.empty())
+    PR_TRY(hipMemcpyAsync(c->d_olist, ol.data(), sizeof(int32_t) * ol.size(), hipMemcpyHostToDevice, s));
+  PR_TRY(launch_gather_cols(c->G, p, c->d_ulist, ku, kp, c->GU, s));
+  if (fresh) PR_TRY(hipMemsetAsync(c->d_ocnt, 0, sizeof(int32_t) * NrMax, s));
+  PR_TRY(hipStreamSynchronize(s));  // the host lists go out of scope
+  c->ku = ku;
+  c->kp = kp;
+  c->union_on = true;
+  *changed = true;
   return PR_OK;
 }
 
@@ -1065,6 +1152,14 @@ int pr_batch_tuning(pr_ctx *c, int32_t len, int32_t *ksf_out, int32_t *kst_out) 
   return PR_OK;
 }
 
+int pr_batch_union_size(pr_ctx *c, int64_t *ku, int64_t *kp, int64_t *nout) {
+  if (!c || !ku || !kp || !nout) return PR_EINVAL;
+  *ku = c->union_on ? c->ku : 0;
+  *kp = c->union_on ? c->kp : 0;
+  *nout = c->union_on ? c->union_nout : 0;
+  return PR_OK;
+}
+
 int pr_time_gram_gemm(pr_ctx *c, int32_t m, int32_t reps, double *ms) {
   if (!c || !c->gram_batch_ok || m < 1 || m > c->max_batch || reps < 1 || !ms) return PR_EINVAL;
   const int64_t p = c->P.p;
@@ -1404,6 +1499,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   PR_TRY(hipMemcpyAsync(c->d_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
   BatchBufs bb = batch_bufs(c, mb);
   PR_TRY(launch_batch_init(c->d_bprm, c->d_bstate, bb, B0 ? c->bxbest : nullptr, L, p, s));
+  c->union_on = false;
   int rc = ensure_batch_graph(c, mb, opts.check_every);
   if (rc != PR_OK) return rc;
   auto issue = [&](int slot) -> hipError_t {
@@ -1417,18 +1513,61 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   int64_t launched = 0;
   PR_TRY(issue(0));
   launched++;
+  if (c->gram && launched < max_launches) {
+    // after the first launch the supports have settled: compact the Gram
+    // product to their union for the remaining launches
+    PR_TRY(hipEventSynchronize(c->ev[0]));
+    if (c->h_active[0] > 0) {
+      bool changed = false;
+      rc = build_union(c, mb, true, &changed);
+      if (rc != PR_OK) return rc;
+      if (changed) {
+        rc = ensure_batch_graph(c, mb, opts.check_every);
+        if (rc != PR_OK) return rc;
+      }
+    }
+  }
   PR_TRY(issue(1));
   launched++;
+  int rebuilds = 0;
   for (int64_t k = 0;; k++) {
     const int slot = (int)(k & 1);
     PR_TRY(hipEventSynchronize(c->ev[slot]));
     if (c->h_active[slot] <= 0) break;
     if (launched >= max_launches) break;
+    if (c->union_on && rebuilds < kUnionRebuilds) {
+      // supports still move in the first launches: once the other launch is
+      // done, join the coordinates that left the union when there are more
+      // than one per four nodes (each costs a column of G per iteration)
+      PR_TRY(hipStreamSynchronize(s));
+      std::vector<int32_t> oc((size_t)mb);
+      PR_TRY(hipMemcpy(oc.data(), c->d_ocnt, sizeof(int32_t) * mb, hipMemcpyDeviceToHost));
+      int64_t nout = 0;
+      for (int32_t v : oc) nout += v;
+      rebuilds++;
+      if (4 * nout > mb) {
+        bool changed = false;
+        rc = build_union(c, mb, false, &changed);
+        if (rc != PR_OK) return rc;
+        if (changed) {
+          rc = ensure_batch_graph(c, mb, opts.check_every);
+          if (rc != PR_OK) return rc;
+        } else {
+          rebuilds = kUnionRebuilds;  // nothing new fits: keep this union
+        }
+      }
+    }
     PR_TRY(issue(slot));
     launched++;
   }
   PR_TRY(hipStreamSynchronize(s));
   PR_TRY(hipMemcpy(c->h_bstate, c->d_bstate, sizeof(NodeState) * mb, hipMemcpyDeviceToHost));
+  c->union_nout = 0;
+  if (c->union_on) {
+    std::vector<int32_t> oc((size_t)mb);
+    PR_TRY(hipMemcpy(oc.data(), c->d_ocnt, sizeof(int32_t) * mb, hipMemcpyDeviceToHost));
+    for (int32_t v : oc) c->union_nout += v;
+  }
   // FP64 certification of every node over the stored X, at the iterate that
   // stopped it: the decision of the batched step (converged, prune, branch)
   // stands if Phi(x) and Psi(zeta) recomputed over X confirm it; otherwise the

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, i
 __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restrict__ S, int m,
                                                       int32_t *__restrict__ rowmap, int32_t *__restrict__ sp,
                                                       int32_t *__restrict__ counters, const int32_t *__restrict__ ftab,
-                                                      int ksf, int kst, int trow) {
+                                                      int ksf, int kst, int trow, int64_t kred, int64_t kfull) {
   __shared__ int base;
   __shared__ int wsum[4];
   if (threadIdx.x == 0) base = 0;
@@ -335,6 +335,11 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
     sp[0] = base;
     sp[1] = ksf * ftab[nta];
     sp[2] = kst * ftab[trow * kTuneMax + nta];
+    // split of a product over kred < kfull reduction indices: the tuned split
+    // scaled by kred / kfull, rounded down to a power of two (>= 1)
+    int ks3 = 1;
+    while (2 * ks3 <= (int)(((int64_t)sp[2] * kred) / kfull)) ks3 *= 2;
+    sp[3] = ks3;
     counters[0] = 0;
     counters[1] = 0;
   }
@@ -397,6 +402,126 @@ __global__ void k_batch_zeta(const double *__restrict__ R, int64_t n, int node, 
     zeta[i] = 2.0 * R[(int64_t)node * n + i];
 }
 
+
+// ---- Support-union compaction of the batched Gram product -------------------
+// The iterates of a batch are sparse and their supports overlap, so after the
+// first iterations the union U of the supports covers only part of the p
+// coordinates.  Then G X_it = G[:, U] X_it[U, :] + sum over the few nonzeros
+// outside U, and the GEMM runs over |U| (padded) reduction indices instead of p.
+
+// mask[j] = 1 where some row of Bx (m rows of length p) is nonzero; mask is
+// cleared beforehand.  Every writer stores the same value.
+__global__ __launch_bounds__(256) void k_union_mask(const double *__restrict__ Bx, int64_t p,
+                                                    int32_t *__restrict__ mask) {
+  const double *row = Bx + (int64_t)blockIdx.x * p;
+  for (int64_t j = threadIdx.x; j < p; j += 256)
+    if (row[j] != 0.0) mask[j] = 1;
+}
+
+// GU[c][q] = G[c][ulist[q]] for q < ku, 0 for ku <= q < kp; rows c < p.
+__global__ __launch_bounds__(256) void k_gather_cols(const double *__restrict__ G, int64_t p,
+                                                     const int32_t *__restrict__ ulist, int64_t ku, int64_t kp,
+                                                     double *__restrict__ GU) {
+  const int64_t c = blockIdx.x;
+  const double *row = G + c * p;
+  double *out = GU + c * kp;
+  for (int64_t q = threadIdx.x; q < kp; q += 256) out[q] = q < ku ? row[ulist[q]] : 0.0;
+}
+
+// For the first *nrow compacted rows (node = rowmap[r]): BxU[node][q] =
+// Bx[node][ulist[q]] (0 past ku), and the nonzeros of the node's row outside
+// the union (olist, no entries) listed in oidx / oval[node][...] with their
+// count in ocnt[node].
+__global__ __launch_bounds__(256) void k_union_compact(const double *__restrict__ Bx, int64_t p,
+                                                       const int32_t *__restrict__ rowmap,
+                                                       const int32_t *__restrict__ nrow,
+                                                       const int32_t *__restrict__ ulist, int64_t ku, int64_t kp,
+                                                       const int32_t *__restrict__ olist, int64_t no,
+                                                       double *__restrict__ BxU, int32_t *__restrict__ ocnt,
+                                                       int32_t *__restrict__ oidx, double *__restrict__ oval,
+                                                       const int32_t *__restrict__ active) {
+  if (active && *active == 0) return;
+  if ((int)blockIdx.x >= *nrow) return;
+  __shared__ int cnt;
+  const int64_t node = rowmap[blockIdx.x];
+  const double *row = Bx + node * p;
+  double *out = BxU + node * kp;
+  for (int64_t q = threadIdx.x; q < kp; q += 256) out[q] = q < ku ? row[ulist[q]] : 0.0;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < no; t += 256) {
+    const int32_t j = olist[t];
+    const double v = row[j];
+    if (v != 0.0) {
+      const int slot = atomicAdd(&cnt, 1);  // LDS counter
+      oidx[node * p + slot] = j;
+      oval[node * p + slot] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ocnt[node] = cnt;
+}
+
+// Plane 0 of the product, row node = rowmap[r]: C[node][c] += sum over the
+// node's nonzeros outside the union of G[c][j] x_j (column j of the
+// symmetric G read contiguously).  Thread i keeps its kFixC output entries
+// c = c0 + i + 256 e in registers and streams the columns past them, four
+// columns in flight.  Nothing to do for most rows.
+constexpr int kFixC = 8;
+__global__ __launch_bounds__(256) void k_union_fix(const double *__restrict__ G, int64_t p,
+                                                   const int32_t *__restrict__ rowmap,
+                                                   const int32_t *__restrict__ nrow,
+                                                   const int32_t *__restrict__ ocnt,
+                                                   const int32_t *__restrict__ oidx, const double *__restrict__ oval,
+                                                   double *__restrict__ C, const int32_t *__restrict__ active) {
+  if (active && *active == 0) return;
+  if ((int)blockIdx.x >= *nrow) return;
+  const int64_t node = rowmap[blockIdx.x];
+  const int cnt = ocnt[node];
+  if (cnt == 0) return;
+  const int32_t *ix = oidx + node * p;
+  const double *vx = oval + node * p;
+  double *crow = C + node * p;
+  for (int64_t c0 = 0; c0 < p; c0 += 256 * kFixC) {
+    double acc[kFixC];
+#pragma unroll
+    for (int e = 0; e < kFixC; e++) acc[e] = 0.0;
+    int t = 0;
+    for (; t + 4 <= cnt; t += 4) {
+      double g[4][kFixC];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const double *col = G + (int64_t)ix[t + u] * p + c0 + threadIdx.x;
+#pragma unroll
+        for (int e = 0; e < kFixC; e++) {
+          const int64_t c = c0 + threadIdx.x + 256 * e;
+          g[u][e] = c < p ? col[256 * e] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const double v = vx[t + u];
+#pragma unroll
+        for (int e = 0; e < kFixC; e++) acc[e] = fma(g[u][e], v, acc[e]);
+      }
+    }
+    for (; t < cnt; t++) {
+      const double *col = G + (int64_t)ix[t] * p + c0 + threadIdx.x;
+      const double v = vx[t];
+#pragma unroll
+      for (int e = 0; e < kFixC; e++) {
+        const int64_t c = c0 + threadIdx.x + 256 * e;
+        if (c < p) acc[e] = fma(col[256 * e], v, acc[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kFixC; e++) {
+      const int64_t c = c0 + threadIdx.x + 256 * e;
+      if (c < p) crow[c] += acc[e];
+    }
+  }
+}
+
 }  // namespace
 
 template <typename TA, typename TB, int PIPE>
@@ -434,14 +559,42 @@ hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const v
 }
 
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
-                               const int32_t *ftab, int ksf, int kst, int trow, hipStream_t s) {
-  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst, trow);
+                               const int32_t *ftab, int ksf, int kst, int trow, int64_t kred, int64_t kfull,
+                               hipStream_t s) {
+  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst, trow, kred, kfull);
   return hipGetLastError();
 }
 
 hipError_t launch_transpose_bf16(const uint16_t *in, uint16_t *out, int64_t n, int64_t p, hipStream_t s) {
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((p + 63) / 64));
   k_transpose_bf16<<<grid, 256, 0, s>>>(in, out, n, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_union_mask(const double *Bx, int m, int64_t p, int32_t *mask, hipStream_t s) {
+  k_union_mask<<<(unsigned)m, 256, 0, s>>>(Bx, p, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const double *G, int64_t p, const int32_t *ulist, int64_t ku, int64_t kp, double *GU,
+                              hipStream_t s) {
+  k_gather_cols<<<(unsigned)p, 256, 0, s>>>(G, p, ulist, ku, kp, GU);
+  return hipGetLastError();
+}
+
+hipError_t launch_union_compact(const double *Bx, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
+                                const int32_t *ulist, int64_t ku, int64_t kp, const int32_t *olist, int64_t no,
+                                double *BxU, int32_t *ocnt, int32_t *oidx, double *oval, const int32_t *active,
+                                hipStream_t s) {
+  k_union_compact<<<(unsigned)Nr, 256, 0, s>>>(Bx, p, rowmap, nrow, ulist, ku, kp, olist, no, BxU, ocnt, oidx, oval,
+                                               active);
+  return hipGetLastError();
+}
+
+hipError_t launch_union_fix(const double *G, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
+                            const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
+                            const int32_t *active, hipStream_t s) {
+  k_union_fix<<<(unsigned)Nr, 256, 0, s>>>(G, p, rowmap, nrow, ocnt, oidx, oval, C, active);
   return hipGetLastError();
 }
 

@@ -160,7 +160,18 @@ hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const v
                            int64_t Mc, int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
                            const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
-                               const int32_t *ftab, int ksf, int kst, int trow, hipStream_t s);
+                               const int32_t *ftab, int ksf, int kst, int trow, int64_t kred, int64_t kfull,
+                               hipStream_t s);
+hipError_t launch_union_mask(const double *Bx, int m, int64_t p, int32_t *mask, hipStream_t s);
+hipError_t launch_gather_cols(const double *G, int64_t p, const int32_t *ulist, int64_t ku, int64_t kp, double *GU,
+                              hipStream_t s);
+hipError_t launch_union_compact(const double *Bx, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
+                                const int32_t *ulist, int64_t ku, int64_t kp, const int32_t *olist, int64_t no,
+                                double *BxU, int32_t *ocnt, int32_t *oidx, double *oval, const int32_t *active,
+                                hipStream_t s);
+hipError_t launch_union_fix(const double *G, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
+                            const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
+                            const int32_t *active, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
 // batched-GEMM autotuner: split factors per count of active 64-row tiles,
 // one table per product (forward, X^T R, Gram)

@@ -115,6 +115,44 @@ def test_batched_gram_bounds_match_matvec_batch_and_oracle(dev):
         assert abs(phi - rg["primal"]) <= 1e-11 * abs(phi)
 
 
+@pytest.mark.parametrize("check_every", [8, 32])
+def test_batched_gram_union_compaction(dev, check_every):
+    """After the first graph launch the batched Gram product runs over the
+    union of the iterates' supports (plus the nonzeros that later fall outside
+    it, added column by column).  Built after 8 iterations the union misses
+    coordinates that enter later, which exercises that correction; after 32
+    it has mostly settled.  Bounds agree with the batch over X and with the
+    oracle."""
+    import paper_2603_01306_amd as pr
+    from workloads import make_nodes
+    inst = make_instance(n=2048, p=2048, corr=0.7, k_true=8, snr=5.0, loss=0, seed=23, storage="bf16")
+    raw = make_nodes(inst.p, 24, seed=5, max_j0=30, max_j1=4)
+    nodes = [pr.Node(8, 0.3, 2.0, J0=a, J1=b) for a, b in raw]
+    res = {}
+    for gram in (False, True):
+        c = _bctx(inst, dev, gram, 32)
+        r, B = c.solve_batch(nodes, rel_gap_tol=1e-7, check_every=check_every)
+        res[gram] = (r, B.cpu().numpy(), c.batch_union_size())
+        c.close()
+    ku, kp, nout = res[True][2]
+    print("union", ku, kp, "of", inst.p, "outside", nout, flush=True)
+    assert 0 < ku <= kp < inst.p and res[False][2] == (0, 0, 0)
+    if check_every == 8:
+        assert nout > 0
+    for q, nd in enumerate(nodes):
+        rg, rm = res[True][0][q], res[False][0][q]
+        assert rg["status"] == pr.CONVERGED and rg["rel_gap"] <= 1e-7, rg
+        assert abs(rg["lower_bound"] - rm["lower_bound"]) <= 2e-7 * abs(rm["primal"])
+        # the same iteration as the batch over X (a wrong product would stall
+        # the node until the FP64 check sends it to the single-node path)
+        assert abs(rg["iters"] - rm["iters"]) <= 3, (q, rg["iters"], rm["iters"])
+        if q < 4:
+            ref = oracle.solve(inst.Xcm, inst.y, 0, 0.3, 2.0, 8, status=nd.status(inst.p), tol=1e-10)
+            assert abs(rg["lower_bound"] - ref["lb"]) <= 2e-7 * abs(ref["ub"])
+            phi = oracle.primal(inst.Xcm, inst.y, res[True][1][q], 0, 0.3, 2.0, 8, status=nd.status(inst.p))
+            assert abs(phi - rg["primal"]) <= 1e-11 * abs(phi)
+
+
 def test_batched_gram_cutoff_decisions(dev):
     import paper_2603_01306_amd as pr
     inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=0, seed=10, storage="bf16")
