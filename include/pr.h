@@ -240,12 +240,13 @@ int pr_time_batch_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms_fwd, dou
  * context has the batched path and max_batch >= m. */
 int pr_time_gram_gemm(pr_ctx *ctx, int32_t m, int32_t reps, double *ms);
 
-/* Support-union compaction of the batched Gram product: after the first
- * graph launch of a batched Gram solve, the union U of the iterates' supports
- * is taken; while its size padded to the GEMM's reduction granule (*kp) is at
- * most 3/4 of p, each product runs as G[:, U] X_it[U, :] over kp reduction
- * indices, plus the (few) nonzeros outside U added column by column, so the
- * result is the full product up to summation order.  Reports |U| (*ku), *kp
+/* Support-union compaction of the batched product with the iterates (G X_it
+ * in Gram mode, X_it X^T otherwise): after the first graph launch of
+ * pr_solve_batch, the union U of the iterates' supports is taken; while its
+ * size padded to the GEMM's reduction granule (*kp) is at most 3/4 of p, each
+ * product runs over the kp columns of U only (G[:, U] X_it[U, :], X_it[:, U]
+ * X[:, U]^T), plus the (few) nonzeros outside U added column by column, so
+ * the result is the full product up to summation order.  Reports |U| (*ku), *kp
  * and the number of nonzeros outside U summed over the nodes' last iterates
  * (*nout) of the last pr_solve_batch on this context, all 0 when it ran
  * without the compaction.  ku, kp, nout: host. */

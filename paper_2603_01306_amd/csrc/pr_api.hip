@@ -30,7 +30,7 @@ hipError_t dalloc(T **p, size_t count) {
 
 constexpr int kLanczosMax = 512;   // Lanczos steps for ||X||_2^2 at most
 constexpr int kLanczosCheck = 8;   // steps between convergence checks on the host
-constexpr int kUnionRebuilds = 8;  // checks for new coordinates of the batched Gram union per solve
+constexpr int kUnionRebuilds = 16;  // checks for new coordinates of the batch's support union per solve
 
 }  // namespace
 
@@ -93,7 +93,7 @@ struct pr_ctx {
   hipGraphExec_t bgexec = nullptr;
   int32_t bgraph_units = 0, bgraph_m = 0;
   int64_t bgraph_kp = 0, bgraph_ku = 0;
-  // support-union compaction of the batched Gram product (built per pr_solve_batch)
+  // support-union compaction of the batched product with the iterates (built per pr_solve_batch)
   bool union_on = false;
   int64_t ku = 0, kp = 0;           // union size, padded to the GEMM's reduction granule
   int64_t union_nout = 0;           // nonzeros outside the union at the nodes' last iterates
@@ -104,7 +104,8 @@ struct pr_ctx {
   int32_t *d_oidx = nullptr;        // [cap padded][p]
   double *d_oval = nullptr;         // [cap padded][p]
   double *BxU = nullptr;            // [cap padded][kp max] compacted iterates
-  double *GU = nullptr;             // [p][kp max] union columns of G
+  double *GU = nullptr;             // [p][3p/4] union columns of G (Gram mode)
+  uint16_t *XrU = nullptr;          // [n][3p/4] union columns of the row-major X copy (products over X)
   // least squares from the Gram matrix (pr_ctx_enable_gram)
   bool gram = false;
   double *G = nullptr;   // [p][p] X^T X over the stored X, FP64
@@ -144,7 +145,7 @@ void free_ctx(pr_ctx *c) {
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   if (c->cg_own && c->CG) (void)hipFree(c->CG);
   {
-    void *ub[] = {c->d_umask, c->d_ulist, c->d_olist, c->d_ocnt, c->d_oidx, c->d_oval, c->BxU, c->GU};
+    void *ub[] = {c->d_umask, c->d_ulist, c->d_olist, c->d_ocnt, c->d_oidx, c->d_oval, c->BxU, c->GU, c->XrU};
     for (void *b : ub)
       if (b) (void)hipFree(b);
   }
@@ -565,13 +566,25 @@ hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
     if (e != hipSuccess) return e;
     return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
   }
-  e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KS, 1, p, p,
-                          s);
+  e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KS, 1,
+                          c->union_on ? c->kp : p, p, s);
   if (e != hipSuccess) return e;
-  e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
-                      c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
+  if (c->union_on) {
+    e = launch_union_compact(c->Bx, p, c->d_rowmap, c->d_split, Nr, c->d_ulist, c->ku, c->kp, c->d_olist, p - c->ku,
+                             c->BxU, c->d_ocnt, c->d_oidx, c->d_oval, c->d_active, s);
+    if (e != hipSuccess) return e;
+    e = launch_gemm_f64(c->XrU, c->kp, c->BxU, c->kp, c->CF, n, Nr, c->kp, c->KSF, c->d_active, c->d_rowmap,
+                        c->d_split, c->d_split + 3, c->KSF * c->fmaxF, c->d_split + 4, s);
+    if (e != hipSuccess) return e;
+    e = launch_union_fix_bf16((const uint16_t *)c->P.X, n, p, c->d_rowmap, c->d_split, Nr, c->d_ocnt, c->d_oidx,
+                              c->d_oval, c->CF, c->d_active, s);
+  } else {
+    e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
+                        c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
+  }
   if (e != hipSuccess) return e;
-  e = launch_batch_resid(c->CF, c->d_split + 1, n, m, Nr, c->P.y, c->Rd, c->fsum, c->d_bstate, s);
+  e = launch_batch_resid(c->CF, c->union_on ? c->d_split + 3 : c->d_split + 1, n, m, Nr, c->P.y, c->Rd, c->fsum,
+                         c->d_bstate, s);
   if (e != hipSuccess) return e;
   e = launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, c->d_active, c->d_rowmap,
                       c->d_split, c->d_split + 2, c->KS * c->fmaxT, c->d_split + 5, s);
@@ -611,18 +624,20 @@ int ensure_batch_graph(pr_ctx *c, int32_t m, int32_t units) {
 }
 
 // Support union of the batch's current iterates (rows 0..m-1 of Bx) for the
-// Gram product.  fresh: a new union, compaction on when its padded size is
-// at most 3/4 of p.  Otherwise the current iterates' supports are joined to
+// product with the iterates (G X_it in Gram mode, else the forward product
+// X_it X^T).  fresh: a new union, compaction on when its padded size is at
+// most 3/4 of p.  Otherwise the current iterates' supports are joined to
 // the union in use, unless the join would not fit (the union in use stays,
 // its misses go through the correction kernel).  *changed tells whether the
 // lists and G[:, U] were rebuilt.  Runs between graph launches, with nothing
 // else in flight.
 int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
-  const int64_t p = c->P.p;
+  const int64_t n = c->P.n, p = c->P.p;
   const int NrMax = nr_of(c->max_batch);
-  // the FP64 tile steps 16 reduction indices; every split count the tuned
-  // table may pick (KSG * f, f <= fmaxG) must divide kp into such steps
-  const int64_t gran = 16LL * c->KSG * c->fmaxG;
+  // every split count the tuned table may pick must divide kp into whole
+  // reduction steps of the tile: 16 indices (FP64 x FP64, Gram mode) with
+  // splits KSG * f, f <= fmaxG; 32 (BF16 x FP64) with KSF * f, f <= fmaxF
+  const int64_t gran = c->gram ? 16LL * c->KSG * c->fmaxG : 32LL * c->KSF * c->fmaxF;
   const int64_t kpmax = (3 * p / 4) / gran * gran;
   *changed = false;
   if (fresh) c->union_on = false;
@@ -632,10 +647,11 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
     ok = ok && dalloc(&c->d_olist, p) == hipSuccess && dalloc(&c->d_ocnt, NrMax) == hipSuccess;
     ok = ok && dalloc(&c->d_oidx, (size_t)NrMax * p) == hipSuccess;
     ok = ok && dalloc(&c->d_oval, (size_t)NrMax * p) == hipSuccess;
-    ok = ok && dalloc(&c->BxU, (size_t)NrMax * kpmax) == hipSuccess;
-    ok = ok && dalloc(&c->GU, (size_t)p * kpmax) == hipSuccess;
+    ok = ok && dalloc(&c->BxU, (size_t)NrMax * (3 * p / 4)) == hipSuccess;
     if (!ok) return PR_ENOMEM;
   }
+  if (c->gram && !c->GU && dalloc(&c->GU, (size_t)p * (3 * p / 4)) != hipSuccess) return PR_ENOMEM;
+  if (!c->gram && !c->XrU && dalloc(&c->XrU, (size_t)n * (3 * p / 4)) != hipSuccess) return PR_ENOMEM;
   hipStream_t s = c->stream;
   if (fresh) PR_TRY(hipMemsetAsync(c->d_umask, 0, sizeof(int32_t) * p, s));
   PR_TRY(launch_union_mask(c->Bx, m, p, c->d_umask, s));
@@ -651,7 +667,8 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
   PR_TRY(hipMemcpyAsync(c->d_ulist, ul.data(), sizeof(int32_t) * ku, hipMemcpyHostToDevice, s));
   if (!ol.empty())
     PR_TRY(hipMemcpyAsync(c->d_olist, ol.data(), sizeof(int32_t) * ol.size(), hipMemcpyHostToDevice, s));
-  PR_TRY(launch_gather_cols(c->G, p, c->d_ulist, ku, kp, c->GU, s));
+  if (c->gram) PR_TRY(launch_gather_cols(c->G, p, c->d_ulist, ku, kp, c->GU, s));
+  else PR_TRY(launch_gather_cols_bf16(c->Xrow, n, p, c->d_ulist, ku, kp, c->XrU, s));
   if (fresh) PR_TRY(hipMemsetAsync(c->d_ocnt, 0, sizeof(int32_t) * NrMax, s));
   PR_TRY(hipStreamSynchronize(s));  // the host lists go out of scope
   c->ku = ku;
@@ -1513,9 +1530,9 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   int64_t launched = 0;
   PR_TRY(issue(0));
   launched++;
-  if (c->gram && launched < max_launches) {
-    // after the first launch the supports have settled: compact the Gram
-    // product to their union for the remaining launches
+  if (launched < max_launches) {
+    // after the first launch the supports have settled: compact the product
+    // with the iterates to their union for the remaining launches
     PR_TRY(hipEventSynchronize(c->ev[0]));
     if (c->h_active[0] > 0) {
       bool changed = false;

@@ -335,10 +335,11 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
     sp[0] = base;
     sp[1] = ksf * ftab[nta];
     sp[2] = kst * ftab[trow * kTuneMax + nta];
-    // split of a product over kred < kfull reduction indices: the tuned split
-    // scaled by kred / kfull, rounded down to a power of two (>= 1)
+    // split of the compacted product over kred < kfull reduction indices: the
+    // tuned split scaled by kred / kfull, rounded down to a power of two (>= 1)
+    const int base = trow == 2 ? sp[2] : sp[1];  // the Gram product, else the forward product
     int ks3 = 1;
-    while (2 * ks3 <= (int)(((int64_t)sp[2] * kred) / kfull)) ks3 *= 2;
+    while (2 * ks3 <= (int)(((int64_t)base * kred) / kfull)) ks3 *= 2;
     sp[3] = ks3;
     counters[0] = 0;
     counters[1] = 0;
@@ -418,14 +419,16 @@ __global__ __launch_bounds__(256) void k_union_mask(const double *__restrict__ B
     if (row[j] != 0.0) mask[j] = 1;
 }
 
-// GU[c][q] = G[c][ulist[q]] for q < ku, 0 for ku <= q < kp; rows c < p.
-__global__ __launch_bounds__(256) void k_gather_cols(const double *__restrict__ G, int64_t p,
+// AU[c][q] = A[c][ulist[q]] for q < ku, 0 for ku <= q < kp, for the rows c
+// of a row-major A with p columns (G, or the row-major copy of X).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_cols(const T *__restrict__ A, int64_t p,
                                                      const int32_t *__restrict__ ulist, int64_t ku, int64_t kp,
-                                                     double *__restrict__ GU) {
+                                                     T *__restrict__ AU) {
   const int64_t c = blockIdx.x;
-  const double *row = G + c * p;
-  double *out = GU + c * kp;
-  for (int64_t q = threadIdx.x; q < kp; q += 256) out[q] = q < ku ? row[ulist[q]] : 0.0;
+  const T *row = A + c * p;
+  T *out = AU + c * kp;
+  for (int64_t q = threadIdx.x; q < kp; q += 256) out[q] = q < ku ? row[ulist[q]] : (T)0;
 }
 
 // For the first *nrow compacted rows (node = rowmap[r]): BxU[node][q] =
@@ -463,12 +466,32 @@ __global__ __launch_bounds__(256) void k_union_compact(const double *__restrict_
 }
 
 // Plane 0 of the product, row node = rowmap[r]: C[node][c] += sum over the
-// node's nonzeros outside the union of G[c][j] x_j (column j of the
-// symmetric G read contiguously).  Thread i keeps its kFixC output entries
-// c = c0 + i + 256 e in registers and streams the columns past them, four
-// columns in flight.  Nothing to do for most rows.
-constexpr int kFixC = 8;
-__global__ __launch_bounds__(256) void k_union_fix(const double *__restrict__ G, int64_t p,
+// node's nonzeros x_j outside the union of column j of the matrix (length L:
+// column j of the symmetric G, or of the column-major X; BF16 upcast
+// exactly), read contiguously.  grid = (rows, L / kFixSpan): a workgroup
+// covers kFixSpan output entries, thread i the 8 consecutive entries
+// c0 + 8 i .. c0 + 8 i + 7 (one or four 16-byte loads per column), four
+// columns in flight.  Nothing to do for most rows.  L is a multiple of 8.
+constexpr int kFixSpan = 2048;
+template <typename T>
+struct Fix8;
+template <>
+struct Fix8<double> {
+  d2v_t v[4];
+  __device__ __forceinline__ void load(const double *p) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) v[i] = *reinterpret_cast<const d2v_t *>(p + 2 * i);
+  }
+  __device__ __forceinline__ double get(int e) const { return v[e >> 1][e & 1]; }
+};
+template <>
+struct Fix8<uint16_t> {
+  us8_t v;
+  __device__ __forceinline__ void load(const uint16_t *p) { v = *reinterpret_cast<const us8_t *>(p); }
+  __device__ __forceinline__ double get(int e) const { return (double)__uint_as_float(((unsigned int)v[e]) << 16); }
+};
+template <typename T>
+__global__ __launch_bounds__(256) void k_union_fix(const T *__restrict__ Mat, int64_t L, int64_t p,
                                                    const int32_t *__restrict__ rowmap,
                                                    const int32_t *__restrict__ nrow,
                                                    const int32_t *__restrict__ ocnt,
@@ -479,47 +502,35 @@ __global__ __launch_bounds__(256) void k_union_fix(const double *__restrict__ G,
   const int64_t node = rowmap[blockIdx.x];
   const int cnt = ocnt[node];
   if (cnt == 0) return;
+  const int64_t c = (int64_t)blockIdx.y * kFixSpan + 8 * (int64_t)threadIdx.x;
+  if (c >= L) return;
   const int32_t *ix = oidx + node * p;
   const double *vx = oval + node * p;
-  double *crow = C + node * p;
-  for (int64_t c0 = 0; c0 < p; c0 += 256 * kFixC) {
-    double acc[kFixC];
+  double acc[8];
 #pragma unroll
-    for (int e = 0; e < kFixC; e++) acc[e] = 0.0;
-    int t = 0;
-    for (; t + 4 <= cnt; t += 4) {
-      double g[4][kFixC];
+  for (int e = 0; e < 8; e++) acc[e] = 0.0;
+  int t = 0;
+  for (; t + 4 <= cnt; t += 4) {
+    Fix8<T> g[4];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const double *col = G + (int64_t)ix[t + u] * p + c0 + threadIdx.x;
+    for (int u = 0; u < 4; u++) g[u].load(Mat + (int64_t)ix[t + u] * L + c);
 #pragma unroll
-        for (int e = 0; e < kFixC; e++) {
-          const int64_t c = c0 + threadIdx.x + 256 * e;
-          g[u][e] = c < p ? col[256 * e] : 0.0;
-        }
-      }
+    for (int u = 0; u < 4; u++) {
+      const double v = vx[t + u];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const double v = vx[t + u];
-#pragma unroll
-        for (int e = 0; e < kFixC; e++) acc[e] = fma(g[u][e], v, acc[e]);
-      }
-    }
-    for (; t < cnt; t++) {
-      const double *col = G + (int64_t)ix[t] * p + c0 + threadIdx.x;
-      const double v = vx[t];
-#pragma unroll
-      for (int e = 0; e < kFixC; e++) {
-        const int64_t c = c0 + threadIdx.x + 256 * e;
-        if (c < p) acc[e] = fma(col[256 * e], v, acc[e]);
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < kFixC; e++) {
-      const int64_t c = c0 + threadIdx.x + 256 * e;
-      if (c < p) crow[c] += acc[e];
+      for (int e = 0; e < 8; e++) acc[e] = fma(g[u].get(e), v, acc[e]);
     }
   }
+  for (; t < cnt; t++) {
+    Fix8<T> g;
+    g.load(Mat + (int64_t)ix[t] * L + c);
+    const double v = vx[t];
+#pragma unroll
+    for (int e = 0; e < 8; e++) acc[e] = fma(g.get(e), v, acc[e]);
+  }
+  double *crow = C + node * L + c;
+#pragma unroll
+  for (int e = 0; e < 8; e++) crow[e] += acc[e];
 }
 
 }  // namespace
@@ -578,7 +589,13 @@ hipError_t launch_union_mask(const double *Bx, int m, int64_t p, int32_t *mask, 
 
 hipError_t launch_gather_cols(const double *G, int64_t p, const int32_t *ulist, int64_t ku, int64_t kp, double *GU,
                               hipStream_t s) {
-  k_gather_cols<<<(unsigned)p, 256, 0, s>>>(G, p, ulist, ku, kp, GU);
+  k_gather_cols<double><<<(unsigned)p, 256, 0, s>>>(G, p, ulist, ku, kp, GU);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cols_bf16(const uint16_t *A, int64_t rows, int64_t p, const int32_t *ulist, int64_t ku,
+                                   int64_t kp, uint16_t *AU, hipStream_t s) {
+  k_gather_cols<uint16_t><<<(unsigned)rows, 256, 0, s>>>(A, p, ulist, ku, kp, AU);
   return hipGetLastError();
 }
 
@@ -594,7 +611,16 @@ hipError_t launch_union_compact(const double *Bx, int64_t p, const int32_t *rowm
 hipError_t launch_union_fix(const double *G, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
                             const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
                             const int32_t *active, hipStream_t s) {
-  k_union_fix<<<(unsigned)Nr, 256, 0, s>>>(G, p, rowmap, nrow, ocnt, oidx, oval, C, active);
+  dim3 grid((unsigned)Nr, (unsigned)((p + kFixSpan - 1) / kFixSpan));
+  k_union_fix<double><<<grid, 256, 0, s>>>(G, p, p, rowmap, nrow, ocnt, oidx, oval, C, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_union_fix_bf16(const uint16_t *X, int64_t n, int64_t p, const int32_t *rowmap, const int32_t *nrow,
+                                 int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
+                                 const int32_t *active, hipStream_t s) {
+  dim3 grid((unsigned)Nr, (unsigned)((n + kFixSpan - 1) / kFixSpan));
+  k_union_fix<uint16_t><<<grid, 256, 0, s>>>(X, n, p, rowmap, nrow, ocnt, oidx, oval, C, active);
   return hipGetLastError();
 }
 

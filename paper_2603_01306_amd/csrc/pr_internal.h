@@ -172,6 +172,11 @@ hipError_t launch_union_compact(const double *Bx, int64_t p, const int32_t *rowm
 hipError_t launch_union_fix(const double *G, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
                             const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
                             const int32_t *active, hipStream_t s);
+hipError_t launch_gather_cols_bf16(const uint16_t *A, int64_t rows, int64_t p, const int32_t *ulist, int64_t ku,
+                                   int64_t kp, uint16_t *AU, hipStream_t s);
+hipError_t launch_union_fix_bf16(const uint16_t *X, int64_t n, int64_t p, const int32_t *rowmap, const int32_t *nrow,
+                                 int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
+                                 const int32_t *active, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
 // batched-GEMM autotuner: split factors per count of active 64-row tiles,
 // one table per product (forward, X^T R, Gram)

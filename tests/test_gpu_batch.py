@@ -94,8 +94,14 @@ def test_batch_full_size_256_nodes(dev):
     raw = make_nodes(inst.p, 256, seed=1, max_j0=64, max_j1=19)
     nodes = [pr.Node(20, 0.1, 2.0, J0=a, J1=b) for a, b in raw]
     res, B = ctx.solve_batch(nodes, max_iter=4000)
-    print("iters", sorted(r["iters"] for r in res)[::32], flush=True)
+    ku, kp, nout = ctx.batch_union_size()
+    print("iters", sorted(r["iters"] for r in res)[::32], "union", ku, kp, nout, flush=True)
     assert all(r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-6 for r in res)
+    # the forward product ran compacted to the support union, and every node
+    # finished in the batched iteration (no fallback to the single-node path,
+    # which would take thousands of iterations)
+    assert 0 < ku <= kp < inst.p
+    assert max(r["iters"] for r in res) < 1000
     for i in np.random.default_rng(0).choice(256, 8, replace=False):
         st = nodes[i].status(inst.p)
         beta = B[i].cpu().numpy()
