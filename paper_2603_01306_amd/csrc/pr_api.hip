@@ -106,6 +106,8 @@ struct pr_ctx {
   double *BxU = nullptr;            // [cap padded][kp max] compacted iterates
   double *GU = nullptr;             // [p][3p/4] union columns of G (Gram mode)
   uint16_t *XrU = nullptr;          // [n][3p/4] union columns of the row-major X copy (products over X)
+  // batched certification: per-node scratch [cap padded][p] and {Psi, Phi} per node
+  double *cert_a = nullptr, *d_cert = nullptr;
   // least squares from the Gram matrix (pr_ctx_enable_gram)
   bool gram = false;
   double *G = nullptr;   // [p][p] X^T X over the stored X, FP64
@@ -145,7 +147,8 @@ void free_ctx(pr_ctx *c) {
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   if (c->cg_own && c->CG) (void)hipFree(c->CG);
   {
-    void *ub[] = {c->d_umask, c->d_ulist, c->d_olist, c->d_ocnt, c->d_oidx, c->d_oval, c->BxU, c->GU, c->XrU};
+    void *ub[] = {c->d_umask, c->d_ulist, c->d_olist, c->d_ocnt, c->d_oidx, c->d_oval, c->BxU, c->GU, c->XrU,
+                  c->cert_a, c->d_cert};
     for (void *b : ub)
       if (b) (void)hipFree(b);
   }
@@ -675,6 +678,46 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
   c->kp = kp;
   c->union_on = true;
   *changed = true;
+  return PR_OK;
+}
+
+// FP64 values of the m batched nodes at their stopping iterates (rows of
+// bxbest), over the stored X, for every node at once: the forward product
+// X_it X^T and the transposed product R X on the batch's FP64-accumulated
+// GEMMs (split as the iteration splits them), residual rows and loss sums,
+// then one workgroup per node for g_N(x) and g_N*(X^T zeta / (2 lambda2)).
+// lb[q] = Psi(zeta_q) with zeta_q = 2 (y - X x_q), ub[q] = Phi(x_q).
+int certify_batch(pr_ctx *c, int32_t m, std::vector<double> &lb, std::vector<double> &ub) {
+  const int64_t n = c->P.n, p = c->P.p;
+  const int NrMax = nr_of(c->max_batch), Nr = nr_of(m);
+  hipStream_t s = c->stream;
+  if (!c->cert_a) {
+    bool ok = dalloc(&c->cert_a, (size_t)NrMax * p) == hipSuccess && dalloc(&c->d_cert, 2 * (size_t)NrMax) == hipSuccess;
+    if (!ok) return PR_ENOMEM;
+  }
+  int nta = Nr / 64;
+  if (nta >= kTuneMax) nta = kTuneMax - 1;
+  static_assert(kTuneTables >= 2, "forward and transpose split tables");
+  const int32_t ksf = c->KSF * c->h_ftab[nta];
+  const int32_t kst = c->KS * c->h_ftab[kTuneMax + nta];
+  PR_TRY(hipMemcpyAsync(c->Bx, c->bxbest, sizeof(double) * m * p, hipMemcpyDeviceToDevice, s));
+  PR_TRY(hipMemcpyAsync(c->d_split + 6, &ksf, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  PR_TRY(launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, ksf, nullptr, nullptr, nullptr, nullptr, ksf, nullptr,
+                         s));
+  PR_TRY(launch_batch_resid(c->CF, c->d_split + 6, n, m, Nr, c->P.y, c->Rd, c->fsum, nullptr, s));
+  PR_TRY(launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, kst, nullptr, nullptr, nullptr,
+                         nullptr, kst, nullptr, s));
+  PR_TRY(launch_cert_batch(c->d_bprm, c->bxbest, c->CT, kst, Nr, c->fsum, c->nfb, p, c->cert_a, c->bsidx, c->bsval,
+                           c->d_cert, m, s));
+  std::vector<double> h((size_t)2 * m);
+  PR_TRY(hipMemcpyAsync(h.data(), c->d_cert, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s));
+  PR_TRY(hipStreamSynchronize(s));
+  lb.resize((size_t)m);
+  ub.resize((size_t)m);
+  for (int32_t q = 0; q < m; q++) {
+    lb[(size_t)q] = h[2 * (size_t)q];
+    ub[(size_t)q] = h[2 * (size_t)q + 1];
+  }
   return PR_OK;
 }
 
@@ -1591,26 +1634,22 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   // node continues on the single-node path.  A node stopped by the iteration
   // limit reports its (valid) recomputed bounds.
   for (int32_t q = 0; q < mb; q++) {
+    const NodeState &hs = c->h_bstate[q];
+    if (!hs.done)  // the graph loop stopped at the iteration limit before this node did
+      PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, (hs.parity ? c->bx1 : c->bx0) + (int64_t)q * p,
+                            sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+  }
+  // certify with the dual vector of each stopping iterate, zeta = 2 (y - X x),
+  // by Phi(x) and Psi(zeta) recomputed over the stored X, all nodes at once
+  std::vector<double> lbs, ubs;
+  rc = certify_batch(c, mb, lbs, ubs);
+  if (rc != PR_OK) return rc;
+  for (int32_t q = 0; q < mb; q++) {
     const int32_t i = slot_of[(size_t)q];
     const NodeState &hs = c->h_bstate[q];
     double *xq = c->bxbest + (int64_t)q * p;
     const int st = hs.done ? hs.status : kMaxIter;
-    if (!hs.done) {
-      // the graph loop stopped at the iteration limit before this node did
-      PR_TRY(hipMemcpyAsync(xq, (hs.parity ? c->bx1 : c->bx0) + (int64_t)q * p, sizeof(double) * p,
-                            hipMemcpyDeviceToDevice, s));
-    }
-    // certify with the dual vector of the stopping iterate, zeta = 2 (y - X x),
-    // by Phi(x) and Psi(zeta) recomputed over the stored X
-    double lb = -INFINITY, ub = INFINITY;
-    if (c->gram) {
-      // Gram mode keeps no residuals: zeta(x) = 2 (y - X x) is formed over X
-      rc = pr_dual_bound(c, &nodes[i], nullptr, xq, &lb, &ub);
-    } else {
-      PR_TRY(launch_batch_zeta(c->Rd, n, q, c->B.zbest, s));
-      rc = pr_dual_bound(c, &nodes[i], c->B.zbest, xq, &lb, &ub);
-    }
-    if (rc != PR_OK) return rc;
+    const double lb = lbs[(size_t)q], ub = ubs[(size_t)q];
     const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
     bool confirmed = false;
     if (st == kConverged) confirmed = rel <= opts.rel_gap_tol;

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ 
                                                      const NodeState *S) {
   __shared__ double red[4 * 4];
   const int node = blockIdx.y;
-  if (S[node].done) return;
+  if (S && S[node].done) return;  // S == NULL: every row (certification)
   const int KSF = *ksp;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   const int64_t plane = (int64_t)Nr * n;

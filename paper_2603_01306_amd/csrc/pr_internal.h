@@ -214,6 +214,9 @@ hipError_t launch_zeta_terms(int32_t loss, const double *zeta, const double *y, 
                              double *sums_out, hipStream_t s);
 hipError_t launch_sumsq(const double *v, int64_t n, double *out, hipStream_t s);
 hipError_t launch_scale_copy(const double *src, double *dst, double a, int64_t n, hipStream_t s);
+hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const double *H, int KS, int Nr,
+                             const double *fsum, int nfb, int64_t p, double *abuf, int32_t *sidx, double *sval,
+                             double *out, int m, hipStream_t s);
 hipError_t launch_lanczos(double *w, double *v, double *vprev, const double *alpha, const double *beta_prev,
                           double *beta_out, int64_t p, hipStream_t s);
 hipError_t launch_iota(int32_t *idx, int64_t n, hipStream_t s);

@@ -614,6 +614,54 @@ __global__ __launch_bounds__(NT) void k_regularizer(const double *beta, const do
   }
 }
 
+// Certified values of m batched least-squares nodes at their stopping
+// iterates x (rows of X_it), all over the stored X: workgroup q takes F(Xx)
+// = ||r||^2 and -F*(-zeta) = 2 r^T y - ||r||^2 (zeta = 2 r, r = y - X x) from
+// the per-block sums of its residual row in block order, w = X^T zeta /
+// (2 lambda2) = (X^T r) / lambda2 from the split planes of the transposed
+// product in plane order, and evaluates g_N(x) (Algorithm 1 with the domain
+// test) and g_N*(w) (sum of H_M over J1 + TopSum of H_M over the free
+// coordinates, eq. of g*): out[q] = {Psi(zeta), Phi(x)} (Phi = +inf off dom).
+__global__ __launch_bounds__(NT) void k_cert_batch(const NodeParams *__restrict__ prm, const double *__restrict__ Xit,
+                                                   const double *__restrict__ H, int KS, int Nr,
+                                                   const double *__restrict__ fsum, int nfb, int64_t p,
+                                                   double *__restrict__ abuf, int32_t *__restrict__ sidx,
+                                                   double *__restrict__ sval, double *__restrict__ out) {
+  __shared__ double red[NW * 4];
+  __shared__ int scan[NW];
+  __shared__ SelLds sel;
+  const int q = blockIdx.x;
+  const NodeParams P = prm[q];
+  const double *x = Xit + (int64_t)q * p;
+  double *a = abuf + (int64_t)q * p;
+  double F = 0.0, Fs = 0.0;  // every thread sums the same values in the same order
+  for (int b = 0; b < nfb; b++) {
+    F += fsum[2 * ((int64_t)q * nfb + b)];
+    Fs += fsum[2 * ((int64_t)q * nfb + b) + 1];
+  }
+  const IterStats is = finish_iterate(x, P.st, p, P.kbar, P.M, a, sidx + (int64_t)q * p, sval + (int64_t)q * p,
+                                      red, scan);
+  __syncthreads();
+  const int64_t plane = (int64_t)Nr * p;
+  const double inv = 1.0 / P.lambda2;
+  double s1[1] = {0.0};
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
+    double h = 0.0;
+    for (int z = 0; z < KS; z++) h += H[(int64_t)z * plane + (int64_t)q * p + j];
+    const double wj = h * inv;
+    const int sj = P.st[j];
+    if (sj == kOne) s1[0] += huber(wj, P.M);
+    a[j] = (sj == kFree) ? fabs(wj) : -1.0;
+  }
+  block_sum<NT, 1>(s1, red);
+  __syncthreads();
+  const double gs = s1[0] + topsum_huber(a, p, P.kbar, P.M, sel, red);
+  if (threadIdx.x == 0) {
+    out[2 * q] = Fs - 2.0 * P.lambda2 * gs;
+    out[2 * q + 1] = is.indom ? F + 2.0 * P.lambda2 * is.gval : INFINITY;
+  }
+}
+
 // F(u), zeta = -grad F(u) and -F*(-zeta) for an arbitrary u (dual bound of a
 // given beta).  sums_out = {F(u), -F*(-zeta)}.
 __global__ __launch_bounds__(NT) void k_loss_terms(int32_t loss, const double *u, const double *y,
@@ -1953,6 +2001,13 @@ hipError_t launch_sumsq(const double *v, int64_t n, double *out, hipStream_t s) 
 
 hipError_t launch_scale_copy(const double *src, double *dst, double a, int64_t n, hipStream_t s) {
   k_scale_copy<<<256, 256, 0, s>>>(src, dst, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const double *H, int KS, int Nr,
+                             const double *fsum, int nfb, int64_t p, double *abuf, int32_t *sidx, double *sval,
+                             double *out, int m, hipStream_t s) {
+  k_cert_batch<<<(unsigned)m, NT, 0, s>>>(prm, Xit, H, KS, Nr, fsum, nfb, p, abuf, sidx, sval, out);
   return hipGetLastError();
 }
 
