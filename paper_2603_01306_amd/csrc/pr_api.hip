@@ -1598,7 +1598,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (c->union_on && rebuilds < kUnionRebuilds) {
       // supports still move in the first launches: once the other launch is
       // done, join the coordinates that left the union when there are more
-      // than one per four nodes (each costs a column of G per iteration)
+      // than one per four nodes (each costs one matrix column per iteration)
       PR_TRY(hipStreamSynchronize(s));
       std::vector<int32_t> oc((size_t)mb);
       PR_TRY(hipMemcpy(oc.data(), c->d_ocnt, sizeof(int32_t) * mb, hipMemcpyDeviceToHost));

@@ -304,8 +304,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, i
 // chose for this many active 64-row tiles (ftab[0][nta] for the forward
 // product, ftab[trow][nta] for the product whose planes the node step reads:
 // trow = 1 for X^T R, 2 for the Gram product G X_it).
-// sp = {nrow, forward split, second split, -}; the two tile counters of the
-// GEMMs are reset.  One block of 256 threads.
+// sp = {nrow, forward split, second split, split of the product compacted to
+// kred of its kfull reduction indices}; the two tile counters of the GEMMs
+// are reset.  One block of 256 threads.
 __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restrict__ S, int m,
                                                       int32_t *__restrict__ rowmap, int32_t *__restrict__ sp,
                                                       int32_t *__restrict__ counters, const int32_t *__restrict__ ftab,
@@ -404,11 +405,12 @@ __global__ void k_batch_zeta(const double *__restrict__ R, int64_t n, int node, 
 }
 
 
-// ---- Support-union compaction of the batched Gram product -------------------
+// ---- Support-union compaction of the batch's product with the iterates -------
 // The iterates of a batch are sparse and their supports overlap, so after the
 // first iterations the union U of the supports covers only part of the p
-// coordinates.  Then G X_it = G[:, U] X_it[U, :] + sum over the few nonzeros
-// outside U, and the GEMM runs over |U| (padded) reduction indices instead of p.
+// coordinates.  Then G X_it = G[:, U] X_it[U, :] (Gram mode) and X_it X^T =
+// X_it[:, U] X[:, U]^T (products over X), each plus the few nonzeros outside
+// U, and the GEMM runs over |U| (padded) reduction indices instead of p.
 
 // mask[j] = 1 where some row of Bx (m rows of length p) is nonzero; mask is
 // cleared beforehand.  Every writer stores the same value.
