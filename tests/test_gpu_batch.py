@@ -85,6 +85,37 @@ def test_batch_warm_start_and_repeat(small):
         assert abs(a["lower_bound"] - b["lower_bound"]) <= 2e-7 * abs(a["primal"])
 
 
+@pytest.mark.parametrize("gram", [False, True])
+@pytest.mark.parametrize("max_iter", [1, 7, 40])
+def test_batch_iteration_limit_reports_certified_values(dev, gram, max_iter):
+    """Nodes stopped by the iteration limit (the graph loop ends before they
+    converge, so their iterate is taken from the working buffer of either
+    parity) report Phi of the returned beta and Psi of zeta = 2 (y - X beta),
+    both recomputed by the oracle over the stored X, and a bound no higher
+    than the relaxation's optimum."""
+    pr = _pr()
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=0, seed=21, storage="bf16")
+    ctx = _ctx(dev, inst, 16)
+    if gram:
+        ctx.enable_gram()
+    raw = make_nodes(inst.p, 10, seed=8, max_j0=30, max_j1=5)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-9, max_iter=max_iter, check_every=2)
+    B = B.cpu().numpy()
+    X64 = inst.X64()
+    for q, (nd, r) in enumerate(zip(nodes, res)):
+        st = nd.status(inst.p)
+        assert r["status"] in (pr.MAXITER, pr.CONVERGED), r
+        phi = oracle.primal(inst.Xcm, inst.y, B[q], 0, 0.2, 2.0, 8, status=st)
+        zeta = 2.0 * (inst.y - X64.T @ B[q])
+        psi = oracle.dual(inst.Xcm, inst.y, zeta, 0, 0.2, 2.0, 8, status=st)
+        assert abs(phi - r["primal"]) <= 1e-10 * abs(phi), (q, phi, r)
+        assert abs(psi - r["lower_bound"]) <= 1e-9 * abs(phi), (q, psi, r)
+        ref = oracle.solve(inst.Xcm, inst.y, 0, 0.2, 2.0, 8, status=st, tol=1e-10)
+        assert r["lower_bound"] <= ref["ub"] * (1 + 1e-12) and r["primal"] >= ref["lb"] * (1 - 1e-12)
+    ctx.close()
+
+
 def test_batch_full_size_256_nodes(dev):
     """256 nodes on the BF16 copy of the n=16384, p=8192 design; the oracle
     re-certifies 8 seeded nodes from the returned betas."""
