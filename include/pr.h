@@ -124,7 +124,8 @@ void pr_opts_default(pr_opts *opts);
  * NULL = the default stream) of the current device.  Estimates ||X||_2^2 by
  * the Lanczos recurrence on X^T X (used for the step 1/L, Section 5.2 FISTA)
  * and allocates a workspace for up to max_batch nodes (>= 1).  X and y are
- * not copied: they must outlive the context and must not change. */
+ * not copied: they must outlive the context and must not change.  PR_EINVAL
+ * for n < 1, p < 1, p >= 2^29 or max_batch < 1. */
 int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void *stream);
 int pr_ctx_destroy(pr_ctx *ctx);
 /* Cached estimate of ||X||_2^2 (largest eigenvalue of X^T X). */

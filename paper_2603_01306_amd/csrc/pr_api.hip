@@ -242,8 +242,12 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
   hipError_t e = launch_spfwd(c->P, c->B, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, mode, c->d_state,
                               nullptr, s);
   if (e != hipSuccess) return e;
+  // the register-resident node step leaves g_N of its new iterate to an extra
+  // workgroup of this product (the strided step evaluates it itself)
+  const bool reg = node_ept(c->P.p) != 0;
   e = launch_gemv_t(c->P, c->B.r, c->P.loss == kLsq ? nullptr : c->B.gm, c->B.h1, c->B.h2,
-                    &c->d_state->done, s);
+                    &c->d_state->done, s, reg ? c->d_prm : nullptr, c->d_state, c->nb.sidx, c->nb.sval,
+                    &c->d_state->nsupp);
   if (e != hipSuccess) return e;
   return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s, &a);
 }
@@ -750,7 +754,7 @@ const char *pr_strerror(int code) {
 }
 
 int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void *stream) {
-  if (!out || !prob || !prob->X || !prob->y || prob->n < 1 || prob->p < 1 || max_batch < 1)
+  if (!out || !prob || !prob->X || !prob->y || prob->n < 1 || prob->p < 1 || prob->p >= kJ0Flag || max_batch < 1)
     return PR_EINVAL;
   if (prob->xdtype < PR_F64 || prob->xdtype > PR_BF16) return PR_EINVAL;
   if (prob->loss != PR_LSQ && prob->loss != PR_LOGISTIC) return PR_EINVAL;

@@ -49,14 +49,112 @@ __device__ __forceinline__ double reduce_cols(double (&v)[C]) {
   return cur[0];
 }
 
+// g_N and the dom test of the iterate whose nonzeros (and only those) are
+// listed in idx / val (ns entries, J1 and J0 entries flagged with kJ1Flag /
+// kJ0Flag), for the node with parameters P: theta = sum of the free |x_j|,
+// the J1 sum of squares and the largest |x_j| off and on J0 in one block
+// reduction (the dom test of the node step), then Algorithm 1 over the free
+// magnitudes as the fixed point s <- (sum of the values <= s) / (kbar -
+// #{q > s}) from s = theta / kbar, one block reduction per round (zeros of
+// the free set change none of these sums).  Writes S->gval and S->indom.
+// Runs as one extra workgroup of the X^T r product, which follows the
+// column-list product of the same iterate and outlasts this evaluation.
+__device__ void list_values(const NodeParams *__restrict__ P, const int32_t *__restrict__ idx,
+                            const double *__restrict__ val, int ns, NodeState *S) {
+  constexpr int NWS = kGemvThreads / 64;
+  __shared__ double red[NWS * 4];
+  const int kbar = P->kbar;
+  const double M = P->M;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // theta, sum_{J1} x^2, max |x| off J0, max |x| on J0
+  for (int t = threadIdx.x; t < ns; t += kGemvThreads) {
+    const int32_t it = idx[t];
+    const double xj = val[t], ax = fabs(xj);
+    if (it & kJ0Flag) {
+      v[3] = fmax(v[3], ax);
+    } else {
+      if (it & kJ1Flag) v[1] += xj * xj;
+      else v[0] += ax;
+      v[2] = fmax(v[2], ax);
+    }
+  }
+  v[0] = wave_sum(v[0]);
+  v[1] = wave_sum(v[1]);
+  v[2] = wave_max(v[2]);
+  v[3] = wave_max(v[3]);
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) red[wave_id() * 4 + k] = v[k];
+  }
+  __syncthreads();
+  double theta = 0.0, sq = 0.0, gB = 0.0, g0 = 0.0;
+  for (int w = 0; w < NWS; w++) {
+    theta += red[w * 4];
+    sq += red[w * 4 + 1];
+    gB = fmax(gB, red[w * 4 + 2]);
+    g0 = fmax(g0, red[w * 4 + 3]);
+  }
+  const double zt = 1e-9 * fmax(1.0, fmax(gB, g0));
+  int ok = (g0 <= zt);
+  if (isfinite(M) && gB > M * (1.0 + 1e-9)) ok = 0;
+  if (kbar == 0) {
+    if (theta > zt) ok = 0;
+  } else if (isfinite(M) && theta > M * (double)kbar * (1.0 + 1e-9)) {
+    ok = 0;
+  }
+  double a1 = 0.0;
+  if (kbar > 0 && theta > 0.0) {
+    const double K = (double)kbar;
+    double sv = theta / K, prevK = 0.0;
+    a1 = NAN;
+    for (int it = 0; it <= kbar + 1; it++) {
+      double r[3] = {0.0, 0.0, 0.0};  // #{q > s}, sum of q <= s, sum of q^2 over q > s
+      for (int t = threadIdx.x; t < ns; t += kGemvThreads) {
+        if (idx[t] & (kJ1Flag | kJ0Flag)) continue;
+        const double q = fabs(val[t]);
+        if (q > sv) {
+          r[0] += 1.0;
+          r[2] += q * q;
+        } else {
+          r[1] += q;
+        }
+      }
+      block_sum<kGemvThreads, 3>(r, red);
+      if (r[0] == prevK || r[0] >= K) {
+        a1 = 0.5 * (r[2] + (K - r[0]) * sv * sv);
+        break;
+      }
+      prevK = r[0];
+      sv = fmin(sv, r[1] / (K - r[0]));
+    }
+  }
+  if (threadIdx.x == 0) {
+    S->gval = 0.5 * sq + a1;
+    S->indom = ok;
+  }
+}
+
 template <typename T, int NRHS>
 __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X, int64_t n, int64_t p,
                                                          const double *__restrict__ r1,
                                                          const double *__restrict__ r2,
                                                          double *__restrict__ h1,
                                                          double *__restrict__ h2,
-                                                         const int32_t *__restrict__ done) {
+                                                         const int32_t *__restrict__ done,
+                                                         const NodeParams *__restrict__ node, NodeState *S,
+                                                         const int32_t *__restrict__ sidx,
+                                                         const double *__restrict__ sval,
+                                                         const int32_t *__restrict__ nlist) {
   if (done && *done) return;
+  // with `node` the first workgroup (dispatched first) evaluates g_N of the
+  // listed iterate; the product's workgroups follow it
+  int bx = (int)blockIdx.x;
+  if (node) {
+    if (bx == 0) {
+      list_values(node, sidx, sval, *nlist, S);
+      return;
+    }
+    bx--;
+  }
   constexpr int VEC = XLoad<T>::VEC;
 #ifndef PR_GEMVT_STEPS
 #define PR_GEMVT_STEPS 1
@@ -64,7 +162,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
   constexpr int U = PR_GEMVT_STEPS;  // row steps in flight
   const int lane = lane_id();
   constexpr int C = gemv_cols(NRHS);
-  const int64_t col0 = ((int64_t)blockIdx.x * (kGemvThreads / 64) + wave_id()) * C;
+  const int64_t col0 = ((int64_t)bx * (kGemvThreads / 64) + wave_id()) * C;
   if (col0 >= p) return;
   const T *c[C];
 #pragma unroll
@@ -128,25 +226,31 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 }  // namespace
 
 hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
-                         const int32_t *done, hipStream_t s) {
+                         const int32_t *done, hipStream_t s, const NodeParams *node, NodeState *S,
+                         const int32_t *sidx, const double *sval, const int32_t *nlist) {
+  if (node && (!S || !sidx || !sval || !nlist)) return hipErrorInvalidValue;
   const bool two = (r2 != nullptr);
   const int cols_per_block = (kGemvThreads / 64) * gemv_cols(two ? 2 : 1);
-  dim3 grid((unsigned)((P.p + cols_per_block - 1) / cols_per_block));
+  dim3 grid((unsigned)((P.p + cols_per_block - 1) / cols_per_block) + (node ? 1u : 0u));
   dim3 block(kGemvThreads);
+#define PR_GEMVT(T, R)                                                                                   \
+  k_gemv_t<T, R><<<grid, block, 0, s>>>((const T *)P.X, P.n, P.p, r1, r2, h1, h2, done, node, S, sidx, sval, \
+                                        nlist)
   switch (P.xdt) {
     case kF32:
-      if (two) k_gemv_t<float, 2><<<grid, block, 0, s>>>((const float *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      else k_gemv_t<float, 1><<<grid, block, 0, s>>>((const float *)P.X, P.n, P.p, r1, r2, h1, h2, done);
+      if (two) PR_GEMVT(float, 2);
+      else PR_GEMVT(float, 1);
       break;
     case kF64:
-      if (two) k_gemv_t<double, 2><<<grid, block, 0, s>>>((const double *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      else k_gemv_t<double, 1><<<grid, block, 0, s>>>((const double *)P.X, P.n, P.p, r1, r2, h1, h2, done);
+      if (two) PR_GEMVT(double, 2);
+      else PR_GEMVT(double, 1);
       break;
     default:
-      if (two) k_gemv_t<uint16_t, 2><<<grid, block, 0, s>>>((const uint16_t *)P.X, P.n, P.p, r1, r2, h1, h2, done);
-      else k_gemv_t<uint16_t, 1><<<grid, block, 0, s>>>((const uint16_t *)P.X, P.n, P.p, r1, r2, h1, h2, done);
+      if (two) PR_GEMVT(uint16_t, 2);
+      else PR_GEMVT(uint16_t, 1);
       break;
   }
+#undef PR_GEMVT
   return hipGetLastError();
 }
 

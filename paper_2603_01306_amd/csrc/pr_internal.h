@@ -16,6 +16,12 @@ constexpr int kSpThreads = 256;      // column-list GEMV workgroup
 
 enum : int32_t { kFree = 0, kZero = 1, kOne = 2 };
 enum : int32_t { kLsq = 0, kLogistic = 1 };
+// Support lists of the register-resident node routines mark J1 and J0
+// entries with these bits of the coordinate index (p < 2^29); readers mask
+// them off.
+constexpr int32_t kJ1Flag = 1 << 30;
+constexpr int32_t kJ0Flag = 1 << 29;
+constexpr int32_t kIdxMask = kJ0Flag - 1;
 enum : int32_t { kF64 = 0, kF32 = 1, kBF16 = 2 };
 enum : int32_t { kConverged = 1, kMaxIter = 2, kInfeasible = 3, kCutoffPrune = 4, kCutoffBranch = 5 };
 
@@ -121,8 +127,13 @@ hipStream_t ctx_stream(const pr_ctx *c);
 int32_t ctx_max_batch(const pr_ctx *c);
 
 // ---- kernel launchers ----
+// With `node` (and S, the node's support list sidx / sval of length *nlist),
+// one extra workgroup evaluates g_N and the dom test of the listed iterate
+// into S->gval / S->indom beside the product.
 hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
-                         const int32_t *done, hipStream_t s);
+                         const int32_t *done, hipStream_t s, const NodeParams *node = nullptr,
+                         NodeState *S = nullptr, const int32_t *sidx = nullptr, const double *sval = nullptr,
+                         const int32_t *nlist = nullptr);
 // u_partials / finalize: generic column-list GEMV u = sum_t X[:, idx[t]] * val[t]
 // followed by the per-row-block epilogue selected by `mode`.
 enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2, kSpGram = 3 };
@@ -130,6 +141,7 @@ hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx,
                         const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
                         hipStream_t s);
 int spfwd_final_blocks(int64_t n);
+int node_ept(int64_t p);  // entries per thread of the register-resident node kernels (0: strided)
 hipError_t launch_node_init(const NodeParams *prm, NodeState *S, NodeBufs nb, const double *beta0,
                             double L, int64_t p, hipStream_t s);
 // Per-context constants of the single-node step, fixed when the iteration

@@ -921,7 +921,7 @@ __device__ IterStats finish_r(const double (&x)[EPT], const PackedStatus<EPT> &s
     const unsigned long long m = __ballot(nz);
     if (nz) {
       const int pos = L.cnt_ew[e * NW + w] + __popcll(m & below);
-      sidx[pos] = (int32_t)(tid + e * NT);
+      sidx[pos] = (int32_t)(tid + e * NT) | (sv(e) == kOne ? kJ1Flag : (sv(e) == kZero ? kJ0Flag : 0));
       sval[pos] = x[e];
     }
   }
@@ -1173,30 +1173,20 @@ __device__ __forceinline__ double alg1_2(F aval, int kbar, double theta, Red2 &R
   return NAN;
 }
 
-// Support list (ascending j), Algorithm 1 value and dom test of the iterate x
-// held in registers.  Groups (e, wave) come in j order o = e * NW + w; after
-// one barrier every wave scans all group counts itself.
+// Support list of the iterate x held in registers (ascending j, every nonzero;
+// J1 / J0 entries flagged with kJ1Flag / kJ0Flag).  Groups (e, wave) come in
+// j order o = e * NW + w; after one barrier every wave scans all group counts
+// itself.  Returns the list length.
 template <int EPT>
-__device__ __forceinline__ IterStats finish_2(const double (&x)[EPT], const PackedStatus<EPT> &sv, int kbar, double M,
-                              int32_t *__restrict__ sidx, double *__restrict__ sval, StepLds<EPT> &L, Red2 &R) {
+__device__ __forceinline__ int support_list_2(const double (&x)[EPT], const PackedStatus<EPT> &sv,
+                                              int32_t *__restrict__ sidx, double *__restrict__ sval,
+                                              StepLds<EPT> &L) {
   constexpr int NO = EPT * NW;
   constexpr int C = (NO + 63) / 64;
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-  double sm[2] = {0.0, 0.0};       // theta, sum_{J1} x^2
-  double mx[3] = {0.0, 0.0, 0.0};  // max |x|, over J0, over the box coordinates
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
-    const int s = sv(e);
-    const double xj = x[e];
-    const double ax = fabs(xj);
-    if (s != 3) {
-      mx[0] = fmax(mx[0], ax);
-      if (s == kZero) mx[1] = fmax(mx[1], ax);
-      else mx[2] = fmax(mx[2], ax);
-      if (s == kFree) sm[0] += ax;
-      else if (s == kOne) sm[1] += xj * xj;
-    }
-    const unsigned long long mk = __ballot(s != 3 && xj != 0.0);
+    const unsigned long long mk = __ballot(sv(e) != 3 && x[e] != 0.0);
     if (lane == 0) L.cnt[e * NW + w] = __popcll(mk);
   }
   lds_barrier();
@@ -1230,10 +1220,34 @@ __device__ __forceinline__ IterStats finish_2(const double (&x)[EPT], const Pack
     const unsigned long long mk = __ballot(nz);
     if (nz) {
       const uint32_t pos = (uint32_t)(L.ofs[w][e * NW + w] + __popcll(mk & below));
-      sidx[pos] = (int32_t)(tid + e * NT);
+      sidx[pos] = (int32_t)(tid + e * NT) | (sv(e) == kOne ? kJ1Flag : (sv(e) == kZero ? kJ0Flag : 0));
       sval[pos] = x[e];
     }
   }
+  return tot;
+}
+
+// Support list, Algorithm 1 value and dom test of the iterate x held in
+// registers.
+template <int EPT>
+__device__ __forceinline__ IterStats finish_2(const double (&x)[EPT], const PackedStatus<EPT> &sv, int kbar, double M,
+                              int32_t *__restrict__ sidx, double *__restrict__ sval, StepLds<EPT> &L, Red2 &R) {
+  double sm[2] = {0.0, 0.0};       // theta, sum_{J1} x^2
+  double mx[3] = {0.0, 0.0, 0.0};  // max |x|, over J0, over the box coordinates
+#pragma unroll
+  for (int e = 0; e < EPT; e++) {
+    const int s = sv(e);
+    const double xj = x[e];
+    const double ax = fabs(xj);
+    if (s != 3) {
+      mx[0] = fmax(mx[0], ax);
+      if (s == kZero) mx[1] = fmax(mx[1], ax);
+      else mx[2] = fmax(mx[2], ax);
+      if (s == kFree) sm[0] += ax;
+      else if (s == kOne) sm[1] += xj * xj;
+    }
+  }
+  const int tot = support_list_2<EPT>(x, sv, sidx, sval, L);
   R.summax(sm, mx);
   const double gA = mx[0], g0 = mx[1], gB = mx[2];
   const double zt = 1e-9 * fmax(1.0, gA);
@@ -1570,11 +1584,22 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     }
     x[e] = xv;
   }
-  IterStats is = finish_2<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds, R);
+  if (A.gb) {
+    // Gram mode: no X^T r product follows, so the step evaluates g_N of the
+    // new iterate and its dom test itself
+    IterStats is = finish_2<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds, R);
+    if (tid == 0) {
+      S->gval = is.gval;
+      S->indom = is.indom;
+      S->nsupp = is.nsupp;
+    }
+  } else {
+    // the extra workgroup of the next X^T r product evaluates them from this
+    // support list (S->gval / S->indom before the next step reads them)
+    const int nsupp = support_list_2<EPT>(x, sv, nb.sidx, nb.sval, lds);
+    if (tid == 0) S->nsupp = nsupp;
+  }
   if (tid == 0) {
-    S->gval = is.gval;
-    S->indom = is.indom;
-    S->nsupp = is.nsupp;
     S->tau = tau;
     S->tau_iters = evals;
     S->parity = parity ^ 1;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kSpThreads) void k_spfwd_part(const T *__restrict__
     u4_t raw[kSpInFlight];
 #pragma unroll
     for (int c = 0; c < kSpInFlight; c++) {
-      const T *col = X + (int64_t)idx[t + c] * n;   // wave-uniform column base
+      const T *col = X + (int64_t)(idx[t + c] & kIdxMask) * n;   // wave-uniform column base
       raw[c] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
     }
 #pragma unroll
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kSpThreads) void k_spfwd_part(const T *__restrict__
     }
   }
   for (; t < t1; t++) {
-    const T *col = X + (int64_t)idx[t] * n;
+    const T *col = X + (int64_t)(idx[t] & kIdxMask) * n;
     const u4_t raw = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
     const double w = val[t];
 #pragma unroll
