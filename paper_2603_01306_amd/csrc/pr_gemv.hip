@@ -49,32 +49,46 @@ __device__ __forceinline__ double reduce_cols(double (&v)[C]) {
   return cur[0];
 }
 
-// g_N and the dom test of the iterate whose nonzeros (and only those) are
-// listed in idx / val (ns entries, J1 and J0 entries flagged with kJ1Flag /
-// kJ0Flag), for the node with parameters P: theta = sum of the free |x_j|,
-// the J1 sum of squares and the largest |x_j| off and on J0 in one block
-// reduction (the dom test of the node step), then Algorithm 1 over the free
-// magnitudes as the fixed point s <- (sum of the values <= s) / (kbar -
-// #{q > s}) from s = theta / kbar, one block reduction per round (zeros of
-// the free set change none of these sums).  Writes S->gval and S->indom.
-// Runs as one extra workgroup of the X^T r product, which follows the
-// column-list product of the same iterate and outlasts this evaluation.
+// g_N and the dom test of a node's iterate whose nonzeros (and only those)
+// are listed in idx / val (ns entries, J1 and J0 entries flagged with
+// kJ1Flag / kJ0Flag), for the node with parameters P, by one workgroup of NTH
+// threads: theta = sum of the free |x_j|, the J1 sum of squares and the
+// largest |x_j| off and on J0 in one block reduction (the dom test of the
+// node step), then Algorithm 1 over the free magnitudes as the fixed point
+// s <- (sum of the values <= s) / (kbar - #{q > s}) from s = theta / kbar,
+// one block reduction per round (zeros of the free set change none of these
+// sums).  Each pass loads eight entries per thread before using them.
+// Writes S->gval and S->indom.  Runs as one extra workgroup of the X^T r
+// product, which follows the column-list product of the same iterate and
+// outlasts this evaluation.
+template <int NTH>
 __device__ void list_values(const NodeParams *__restrict__ P, const int32_t *__restrict__ idx,
                             const double *__restrict__ val, int ns, NodeState *S) {
-  constexpr int NWS = kGemvThreads / 64;
+  constexpr int NWS = NTH / 64;
+  constexpr int U = 8;
   __shared__ double red[NWS * 4];
   const int kbar = P->kbar;
   const double M = P->M;
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // theta, sum_{J1} x^2, max |x| off J0, max |x| on J0
-  for (int t = threadIdx.x; t < ns; t += kGemvThreads) {
-    const int32_t it = idx[t];
-    const double xj = val[t], ax = fabs(xj);
-    if (it & kJ0Flag) {
-      v[3] = fmax(v[3], ax);
-    } else {
-      if (it & kJ1Flag) v[1] += xj * xj;
-      else v[0] += ax;
-      v[2] = fmax(v[2], ax);
+  for (int t0 = threadIdx.x; t0 < ns; t0 += U * NTH) {
+    int32_t it[U];
+    double xv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int t = t0 + u * NTH;
+      it[u] = t < ns ? idx[t] : 0;
+      xv[u] = t < ns ? val[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const double ax = fabs(xv[u]);
+      if (it[u] & kJ0Flag) {
+        v[3] = fmax(v[3], ax);
+      } else {
+        if (it[u] & kJ1Flag) v[1] += xv[u] * xv[u];
+        else v[0] += ax;
+        v[2] = fmax(v[2], ax);
+      }
     }
   }
   v[0] = wave_sum(v[0]);
@@ -106,19 +120,30 @@ __device__ void list_values(const NodeParams *__restrict__ P, const int32_t *__r
     const double K = (double)kbar;
     double sv = theta / K, prevK = 0.0;
     a1 = NAN;
-    for (int it = 0; it <= kbar + 1; it++) {
+    for (int round = 0; round <= kbar + 1; round++) {
       double r[3] = {0.0, 0.0, 0.0};  // #{q > s}, sum of q <= s, sum of q^2 over q > s
-      for (int t = threadIdx.x; t < ns; t += kGemvThreads) {
-        if (idx[t] & (kJ1Flag | kJ0Flag)) continue;
-        const double q = fabs(val[t]);
-        if (q > sv) {
-          r[0] += 1.0;
-          r[2] += q * q;
-        } else {
-          r[1] += q;
+      for (int t0 = threadIdx.x; t0 < ns; t0 += U * NTH) {
+        int32_t it[U];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int t = t0 + u * NTH;
+          it[u] = t < ns ? idx[t] : kJ0Flag;  // past the list: skipped below
+          xv[u] = t < ns ? val[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          if (it[u] & (kJ1Flag | kJ0Flag)) continue;
+          const double q = fabs(xv[u]);
+          if (q > sv) {
+            r[0] += 1.0;
+            r[2] += q * q;
+          } else {
+            r[1] += q;
+          }
         }
       }
-      block_sum<kGemvThreads, 3>(r, red);
+      block_sum<NTH, 3>(r, red);
       if (r[0] == prevK || r[0] >= K) {
         a1 = 0.5 * (r[2] + (K - r[0]) * sv * sv);
         break;
@@ -132,6 +157,7 @@ __device__ void list_values(const NodeParams *__restrict__ P, const int32_t *__r
     S->indom = ok;
   }
 }
+
 
 template <typename T, int NRHS>
 __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X, int64_t n, int64_t p,
@@ -150,7 +176,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
   int bx = (int)blockIdx.x;
   if (node) {
     if (bx == 0) {
-      list_values(node, sidx, sval, *nlist, S);
+      list_values<kGemvThreads>(node, sidx, sval, *nlist, S);
       return;
     }
     bx--;
