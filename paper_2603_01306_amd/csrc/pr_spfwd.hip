@@ -5,8 +5,10 @@
 // k_spfwd_part  grid = row blocks x column chunks.  The list entries of a
 //               chunk are wave-uniform, so column bases live in scalar
 //               registers and every lane keeps 16 independent 16-byte
-//               non-temporal loads in flight (4 to 8 rows per lane), converted
-//               to FP64 at the FMA.  Writes its partial sums to part[chunk][n].
+//               non-temporal loads in flight (2 to 8 rows per lane),
+//               converted to FP64 at the FMA; the chunk's last columns form
+//               one masked round of 16.  Writes its partial sums to
+//               part[chunk][n].
 // k_spfwd_final grid over rows: sums the chunk partials in chunk order (so the
 //               result does not depend on scheduling) and runs the epilogue:
 //   least squares: r = y - u, F = ||r||^2, -F*(-zeta) = 2 r^T y - ||r||^2;
@@ -50,6 +52,32 @@ struct XRaw<uint16_t> {
   }
 };
 
+// One round of kSpInFlight column loads (16 bytes per lane each) for list
+// entries t .. t + kSpInFlight - 1.  A full round reads its indices as one
+// block; in the chunk's last, partial round the slots at or past t1 re-read
+// the chunk's last column, which sp_use_r then weights by zero.
+template <typename T, bool FULL>
+__device__ __forceinline__ void sp_issue_r(u4_t (&raw)[kSpInFlight], const T *__restrict__ X, int64_t n,
+                                           int64_t row0, const int32_t *__restrict__ idx, int t, int t1) {
+#pragma unroll
+  for (int c = 0; c < kSpInFlight; c++) {
+    const int tc = (FULL || t + c < t1) ? t + c : t1 - 1;
+    const T *col = X + (int64_t)(idx[tc] & kIdxMask) * n;   // wave-uniform column base
+    raw[c] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
+  }
+}
+
+template <typename T, bool FULL>
+__device__ __forceinline__ void sp_use_r(const u4_t (&raw)[kSpInFlight], double (&acc)[XRaw<T>::VEC],
+                                         const double *__restrict__ val, int t, int t1) {
+#pragma unroll
+  for (int c = 0; c < kSpInFlight; c++) {
+    const double w = FULL ? val[t + c] : ((t + c < t1) ? val[t + c < t1 ? t + c : t1 - 1] : 0.0);
+#pragma unroll
+    for (int e = 0; e < XRaw<T>::VEC; e++) acc[e] = fma(XRaw<T>::at(raw[c], e), w, acc[e]);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kSpThreads) void k_spfwd_part(const T *__restrict__ X, int64_t n, ProbBufs B,
                                                            const int32_t *__restrict__ idx,
@@ -68,27 +96,18 @@ __global__ __launch_bounds__(kSpThreads) void k_spfwd_part(const T *__restrict__
   double acc[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; e++) acc[e] = 0.0;
+  // full rounds of kSpInFlight columns, then the chunk's remaining columns as
+  // one masked round (all its loads in flight together)
   int t = t0;
   for (; t + kSpInFlight <= t1; t += kSpInFlight) {
     u4_t raw[kSpInFlight];
-#pragma unroll
-    for (int c = 0; c < kSpInFlight; c++) {
-      const T *col = X + (int64_t)(idx[t + c] & kIdxMask) * n;   // wave-uniform column base
-      raw[c] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
-    }
-#pragma unroll
-    for (int c = 0; c < kSpInFlight; c++) {
-      const double w = val[t + c];
-#pragma unroll
-      for (int e = 0; e < VEC; e++) acc[e] = fma(XRaw<T>::at(raw[c], e), w, acc[e]);
-    }
+    sp_issue_r<T, true>(raw, X, n, row0, idx, t, t1);
+    sp_use_r<T, true>(raw, acc, val, t, t1);
   }
-  for (; t < t1; t++) {
-    const T *col = X + (int64_t)(idx[t] & kIdxMask) * n;
-    const u4_t raw = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
-    const double w = val[t];
-#pragma unroll
-    for (int e = 0; e < VEC; e++) acc[e] = fma(XRaw<T>::at(raw, e), w, acc[e]);
+  if (t < t1) {
+    u4_t raw[kSpInFlight];
+    sp_issue_r<T, false>(raw, X, n, row0, idx, t, t1);
+    sp_use_r<T, false>(raw, acc, val, t, t1);
   }
   double *part = B.part + (int64_t)ch * n + row0;
 #pragma unroll
