@@ -312,19 +312,37 @@ double tridiag_max_eig(const double *a, const double *b, int m) {
   return hi;
 }
 
-// ||X||_2^2 = lambda_max(X^T X) by the Lanczos recurrence on X^T X from the
-// all-ones direction: each step is one product X v, one X^T u and one
+// ||X||_2^2 = lambda_max(X^T X) by the Lanczos recurrence on X^T X from a
+// fixed pseudo-random direction: each step is one product X v, one X^T u and one
 // single-workgroup update, with no host round trip; every kLanczosCheck steps
 // the host takes the top eigenvalue of the tridiagonal matrix of the
 // recurrence coefficients (a lower bound that rises to lambda_max) and stops
 // once it moved by at most 1e-13 relative over the last check interval, when
-// the recurrence breaks down (an invariant subspace: the value is exact), or
+// the recurrence breaks down (an invariant subspace that holds every
+// eigenvector the start direction touches, generically all: the value is
+// exact), or
 // after min(p, kLanczosMax) steps.  Without reorthogonalisation the extreme
 // value still converges; lost orthogonality only repeats converged values.
 int lanczos_norm2(pr_ctx *c) {
   const int64_t n = c->P.n, p = c->P.p;
-  std::vector<double> ones((size_t)p, 1.0 / sqrt((double)p));
-  PR_TRY(hipMemcpyAsync(c->d_v, ones.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->stream));
+  // start vector: fixed pseudo-random entries (splitmix64 of the index) with
+  // random signs, so that no structure of X^T X (an eigenvector orthogonal to
+  // the all-ones direction, say) can hide its top eigenvector from the
+  // recurrence; the same vector on every run
+  std::vector<double> v0((size_t)p);
+  double nv = 0.0;
+  for (int64_t j = 0; j < p; j++) {
+    uint64_t z = (uint64_t)j * 0x9E3779B97F4A7C15ull + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = 0.5 + (double)(z >> 11) * 0x1.0p-53;   // [0.5, 1.5)
+    v0[(size_t)j] = (z & 1u) ? -u : u;
+    nv += u * u;
+  }
+  nv = 1.0 / sqrt(nv);
+  for (double &x : v0) x *= nv;
+  PR_TRY(hipMemcpyAsync(c->d_v, v0.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->stream));
   double *alpha = c->d_lam, *beta = c->d_lam + kLanczosMax;
   std::vector<double> ha(kLanczosMax), hb(kLanczosMax);
   const int mmax = (int)std::min<int64_t>(kLanczosMax, p);

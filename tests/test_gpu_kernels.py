@@ -182,6 +182,22 @@ def test_norm2_matches_exact_eigenvalue(dev, n, p, corr, storage):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,q", [(300, 1), (400, 50), (2048, 700)])
+def test_norm2_of_mirrored_design(dev, n, q):
+    """X = [A, -A]: every eigenvector of X^T X with a nonzero eigenvalue is
+    (v, -v), orthogonal to the all-ones direction, so a recurrence started
+    there sees only the zero eigenvalue.  ||X||_2^2 = 2 ||A||_2^2 exactly."""
+    import torch
+    pr = _pr()
+    inst = make_instance(n=n, p=q, corr=0.5, k_true=1, snr=5.0, loss=0, seed=4, storage="f64")
+    Xcm = np.ascontiguousarray(np.concatenate([inst.Xcm, -inst.Xcm], axis=0))
+    ctx = pr.Context(torch.from_numpy(Xcm).to(dev), torch.from_numpy(inst.y).to(dev), 0)
+    A = inst.X64()
+    lam = 2.0 * np.linalg.eigvalsh(A @ A.T if q <= n else A.T @ A).max()
+    assert abs(ctx.norm2() - lam) <= 1e-10 * lam
+    ctx.close()
+
+
 @pytest.mark.parametrize("p", [100, 6400, 102400])
 def test_prox_and_g_at_microbenchmark_shapes(dev, p):
     """The paper's subroutine benchmark: gamma ~ N(0, I_p), root node, k = 10,

@@ -101,6 +101,28 @@ def test_small_nodes_lower_bound_parity(dev, loss, node_seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("loss", [0, 1])
+def test_default_step_on_mirrored_design(dev, loss):
+    """Default L (from the context's ||X||_2^2) on X = [A, -A], whose top
+    eigenvector is orthogonal to the all-ones direction: the solve converges
+    to the oracle's bound, the oracle run with the exact eigenvalue."""
+    import torch
+    pr = _pr()
+    inst = make_instance(n=600, p=60, corr=0.6, k_true=4, snr=5.0, loss=loss, seed=21, storage="f64")
+    Xcm = np.ascontiguousarray(np.concatenate([inst.Xcm, -inst.Xcm], axis=0))
+    ctx = pr.Context(torch.from_numpy(Xcm).to(dev), torch.from_numpy(inst.y).to(dev), loss)
+    A = inst.X64()
+    lam = 2.0 * float(np.linalg.eigvalsh(A @ A.T).max())
+    node = pr.Node(5, 0.5, 2.0)
+    res = ctx.solve(node, rel_gap_tol=1e-8, max_iter=20000)
+    assert abs(res["L"] - 1.01 * (2.0 if loss == 0 else 0.25) * lam) <= 1e-9 * res["L"]
+    ref = oracle.solve(Xcm, inst.y, loss, 0.5, 2.0, 5, L=1.01 * (2.0 if loss == 0 else 0.25) * lam, tol=1e-10)
+    print(res["iters"], ref["iters"], res["lower_bound"], ref["lb"])
+    assert res["status"] == pr.CONVERGED
+    assert abs(res["lower_bound"] - ref["lb"]) <= 1e-7 * abs(ref["lb"])
+    ctx.close()
+
+
 @pytest.mark.parametrize("p,n,lam2", [(1000, 256, 0.5), (1500, 256, 0.75), (3000, 256, 1.5), (17000, 128, 20.0)])
 @pytest.mark.parametrize("loss", [0, 1])
 def test_node_step_tiers_match_oracle(dev, p, n, lam2, loss):
