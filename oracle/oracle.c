@@ -334,7 +334,21 @@ void orc_rmatvec(const void *X, int xdt, int64_t n, int64_t p, const double *r, 
 double orc_power_norm2(const void *X, int xdt, int64_t n, int64_t p, int64_t max_iter, double tol) {
   double *v = (double *)malloc(sizeof(double) * (size_t)p);
   double *u = (double *)malloc(sizeof(double) * (size_t)n);
-  for (int64_t j = 0; j < p; j++) v[j] = 1.0 / sqrt((double)p);
+  /* start: entries of random sign and magnitude (xorshift64*, fixed seed), so
+     that no eigenvector of X^T X is orthogonal to it except by accident; a
+     constant start misses the top eigenvector of designs such as [A, -A] */
+  uint64_t sx = 0x2545F4914F6CDD1Dull;
+  double n0 = 0.0;
+  for (int64_t j = 0; j < p; j++) {
+    sx ^= sx >> 12;
+    sx ^= sx << 25;
+    sx ^= sx >> 27;
+    const uint64_t r = sx * 0x2545F4914F6CDD1Dull;
+    const double mag = 1.0 + (double)(r >> 11) / 9007199254740992.0; /* [1, 2) */
+    v[j] = (r & 1u) ? -mag : mag;
+    n0 += mag * mag;
+  }
+  for (int64_t j = 0; j < p; j++) v[j] /= sqrt(n0);
   double lam = 0.0;
   for (int64_t it = 0; it < max_iter; it++) {
     orc_matvec(X, xdt, n, p, v, u);

@@ -400,3 +400,15 @@ def test_restart_epochs_contract_by_eta():
     assert res["status"] == oracle.CONVERGED and res["restarts"] >= 1
     bound = math.ceil(math.log(tr[0] / tr[-1]) / math.log(eta))
     assert res["restarts"] <= bound
+
+
+def test_power_norm2_on_mirrored_integer_design():
+    """X = [B, -B] with integer entries: X 1 = 0 exactly, so a constant start
+    would see only the zero eigenvalue; ||X||_2^2 = 2 ||B||_2^2 by a dense
+    symmetric eigensolver."""
+    inst = make_instance(n=300, p=40, corr=0.5, k_true=1, snr=5.0, loss=0, seed=9, storage="f64")
+    B = np.round(inst.Xcm * 4.0)
+    Xcm = np.ascontiguousarray(np.concatenate([B, -B], axis=0))
+    assert np.all(oracle.matvec(Xcm, np.ones(80)) == 0.0)
+    lam = 2.0 * np.linalg.eigvalsh(B @ B.T).max()
+    assert oracle.power_norm2(Xcm) == pytest.approx(lam, rel=1e-9)
