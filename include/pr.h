@@ -168,6 +168,24 @@ int pr_solve(pr_ctx *ctx, const pr_node *node, const pr_opts *opts, const double
 int pr_prox(void *stream, const double *v, int64_t p, double rho, int32_t k, double M,
             const int8_t *status, double *out);
 
+/* prox_{rho g_N}(v) exactly as pr_prox (same kernel arithmetic, bit-identical
+ * output), for callers that cannot allocate: code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Nothing is allocated, on
+ * the device or the host: the workspace is a fixed device array of the
+ * library, one copy per GPU, held until the process ends (8 bytes per
+ * coordinate of PR_PROX_NOALLOC_MAX_P plus 256 bytes, 8 MiB).  |J1| and |J_f|
+ * are counted on the device from `status`, so the host never reads it.
+ *   Arguments as pr_prox; additionally p <= PR_PROX_NOALLOC_MAX_P.
+ *   Returns PR_EINVAL for a bad argument, p > PR_PROX_NOALLOC_MAX_P, a status
+ *   code outside {PR_FREE, PR_ZERO, PR_ONE} or |J1| > k (then `out` is not
+ *   written), PR_EDEVICE for a HIP error.  Synchronises `stream`.
+ * Every call on one GPU uses that GPU's single workspace: calls that overlap
+ * in time on the same GPU (other streams or host threads) race and must be
+ * serialised by the caller. */
+#define PR_PROX_NOALLOC_MAX_P 1048576
+int pr_prox_noalloc(void *stream, const double *v, int64_t p, double rho, int32_t k, double M,
+                    const int8_t *status, double *out);
+
 /* g_N(beta) by Algorithm 1 (+inf off dom g_N, tested with relative slack
  * 1e-9) and g_N*(alpha) by Lemma function_g_conjugate_in_BnB, each skipped
  * when its input pointer is NULL.  beta, alpha, status device p; outputs host. */

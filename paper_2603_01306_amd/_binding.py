@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpr.so")
 
 PR_OK, PR_EINVAL, PR_EOVERLAP, PR_EDEVICE, PR_ENOMEM = 0, -1, -2, -3, -4
+PROX_NOALLOC_MAX_P = 1048576
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
 FISTA_GAP, FISTA, FISTA_FV, PGD = 0, 1, 2, 3
@@ -23,7 +24,7 @@ F64, F32, BF16 = 0, 1, 2
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
            "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
-           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_strerror"]
+           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
 
@@ -94,6 +95,9 @@ def load():
         L.pr_prox.restype = ctypes.c_int
         L.pr_prox.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                               P, P]
+        L.pr_prox_noalloc.restype = ctypes.c_int
+        L.pr_prox_noalloc.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                      P, P]
         L.pr_regularizer.restype = ctypes.c_int
         L.pr_regularizer.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -414,6 +418,18 @@ def prox(v, rho, k, M, status):
     out = torch.empty_like(v)
     _check(load().pr_prox(_stream_ptr(), _dptr(v.contiguous()), v.numel(), float(rho), int(k), float(M),
                           _dptr(status.contiguous()), _dptr(out)), "pr_prox")
+    return out
+
+
+def prox_noalloc(v, rho, k, M, status, out=None):
+    """prox_{rho g_N}(v) through pr_prox_noalloc (no allocation inside the
+    library; `out`, a CUDA float64 tensor like v, is allocated here if not
+    given)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(v)
+    _check(load().pr_prox_noalloc(_stream_ptr(), _dptr(v.contiguous()), v.numel(), float(rho), int(k), float(M),
+                                  _dptr(status.contiguous()), _dptr(out)), "pr_prox_noalloc")
     return out
 
 

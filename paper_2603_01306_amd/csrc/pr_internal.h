@@ -217,6 +217,10 @@ hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t los
                               hipStream_t s);
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,
                        const int8_t *st, double *abuf, double *vtmp, hipStream_t s);
+// prox with kbar counted on the device from st; *flag: 0 ok, 1 bad status
+// code, 2 |J1| > k (out untouched unless 0).  abuf: p doubles of scratch.
+hipError_t launch_prox_counted(const double *v, double *out, int64_t p, double rho, int32_t k, double M,
+                               const int8_t *st, double *abuf, int32_t *flag, hipStream_t s);
 hipError_t launch_regularizer(const double *beta, const double *alpha, int64_t p, int32_t kbar,
                               double M, const int8_t *st, double *abuf, double *out2,
                               hipStream_t s);

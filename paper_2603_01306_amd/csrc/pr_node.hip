@@ -586,6 +586,50 @@ __global__ __launch_bounds__(NT) void k_prox(const double *v, double *out, int64
   }
 }
 
+// The same prox with the node dimensions counted on the device, for callers
+// that pass no host-side status: |J1| and |J_f| are reduced from st, kbar =
+// min(k - |J1|, |J_f|).  *flag receives 0, or 1 for a status code outside
+// {free, J0, J1}, or 2 for |J1| > k; out is not written when *flag != 0.
+// abuf and the flag are caller-provided scratch (nothing needs clearing:
+// every entry read is written first).  Its output equals k_prox's bit for bit.
+__global__ __launch_bounds__(NT) void k_prox_counted(const double *v, double *out, int64_t p, double rho,
+                                                     int k, double M, const int8_t *__restrict__ st,
+                                                     double *abuf, int32_t *flag) {
+  __shared__ double red[NW * 4];
+  double cnt[3] = {0.0, 0.0, 0.0};  // |J1|, |J_f|, invalid codes
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
+    const int s = st[j];
+    cnt[0] += (s == kOne) ? 1.0 : 0.0;
+    cnt[1] += (s == kFree) ? 1.0 : 0.0;
+    cnt[2] += (s != kFree && s != kZero && s != kOne) ? 1.0 : 0.0;
+    abuf[j] = (s == kFree) ? fabs(v[j]) : -1.0;
+  }
+  block_sum<NT, 3>(cnt, red);
+  const int32_t err = cnt[2] > 0.0 ? 1 : (cnt[0] > (double)k ? 2 : 0);
+  if (threadIdx.x == 0) *flag = err;
+  if (err) return;  // uniform across the workgroup
+  const double kb = fmin((double)k - cnt[0], cnt[1]);
+  const int kbar = (int)kb;
+  __syncthreads();
+  int evals;
+  const double tau = solve_tau(abuf, p, kbar, rho, M, -1.0, red, &evals);
+  const double inv1p = 1.0 / (1.0 + rho);
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
+    const double vj = v[j];
+    const int s = st[j];
+    double x = 0.0;
+    if (s != kZero) {
+      const double av = fabs(vj);
+      double r = fmin(av * inv1p, M);
+      if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
+      x = (r == 0.0) ? 0.0 : copysign(r, vj);
+    }
+    out[j] = x;
+  }
+}
+
 // g_N(beta) (Algorithm 1, +inf off dom) into out2[0]; g_N*(alpha) into out2[1].
 __global__ __launch_bounds__(NT) void k_regularizer(const double *beta, const double *alpha, int64_t p,
                                                     int kbar, double M, const int8_t *__restrict__ st,
@@ -1993,6 +2037,12 @@ hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t los
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,
                        const int8_t *st, double *abuf, double *, hipStream_t s) {
   k_prox<<<1, NT, 0, s>>>(v, out, p, rho, kbar, M, st, abuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_prox_counted(const double *v, double *out, int64_t p, double rho, int32_t k, double M,
+                               const int8_t *st, double *abuf, int32_t *flag, hipStream_t s) {
+  k_prox_counted<<<1, NT, 0, s>>>(v, out, p, rho, k, M, st, abuf, flag);
   return hipGetLastError();
 }
 
