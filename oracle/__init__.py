@@ -6,7 +6,7 @@ library never calls it, shares no code with it, and has no fallback to it.
 
 All arrays are numpy float64 (vectors) plus the stored design matrix in its
 storage dtype (column-major, i.e. a C-contiguous ``(p, n)`` array whose row j
-is column j of X).  Function names follow the paper: ``g`` is Algorithm 1,
+is column j of X).  Function names follow the paper: ``g`` is g_N by Theorem compute_g_value,
 ``prox_gstar`` Algorithm 2, ``prox_g`` the Moreau identity (prox:gN), ``gstar``
 the closed form of the conjugate, ``dual`` the Fenchel dual objective.
 """
@@ -69,7 +69,7 @@ def lib():
         L.orc_dual.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p, _p]
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p,
-                                _d, _d, _d, _i64, _d, _p, _p, _p, _p, _p, _i64, ctypes.c_int, _p]
+                                _d, _d, _d, _i64, _d, _p, _p, _p, _p, _p, _i64, ctypes.c_int, _p, _p, _i64]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         _lib = L
@@ -220,11 +220,12 @@ FISTA_GAP, FISTA, FISTA_FV, PGD = 0, 1, 2, 3
 
 
 def solve(Xcm, y, kind, lambda2, M, k, status=None, L=0.0, tol=1e-8, eta=math.exp(3.0),
-          max_iter=100000, cutoff=float("nan"), beta0=None, trace_cap=0, method=FISTA_GAP):
+          max_iter=100000, cutoff=float("nan"), beta0=None, trace_cap=0, method=FISTA_GAP, restart_cap=0):
     """FISTA + duality-gap restart (or, with `method`, FISTA without restart,
     FISTA with function-value restart, or PGD).  Returns a dict with lb, ub,
     rel_gap, L, iters, restarts, status, beta, zeta (dual vector attaining
-    lb), and with trace_cap > 0 the traces of Phi - Psi and Phi per iterate."""
+    lb), with trace_cap > 0 the traces of Phi - Psi and Phi per iterate, and
+    with restart_cap > 0 the iterate indices at which restarts were taken."""
     X, code, n, p = _xinfo(Xcm)
     y = _f64(y)
     s = _st(status, p)
@@ -234,15 +235,18 @@ def solve(Xcm, y, kind, lambda2, M, k, status=None, L=0.0, tol=1e-8, eta=math.ex
     res = np.zeros(8)
     trace = np.full(max(trace_cap, 1), np.nan)
     phi = np.full(max(trace_cap, 1), np.nan)
+    rst = np.full(max(restart_cap, 1), -1, dtype=np.int64)
     lib().orc_solve(_ptr(X), code, _ptr(y), n, p, int(kind), float(lambda2), float(M), int(k),
                     _ptr(s), float(L), float(tol), float(eta), int(max_iter), float(cutoff),
                     None if b0 is None else _ptr(b0), _ptr(beta), _ptr(zeta), _ptr(res),
                     _ptr(trace) if trace_cap > 0 else None, int(trace_cap), int(method),
-                    _ptr(phi) if trace_cap > 0 else None)
+                    _ptr(phi) if trace_cap > 0 else None, _ptr(rst) if restart_cap > 0 else None,
+                    int(restart_cap))
     m = int(res[4]) + 1
     return dict(lb=res[0], ub=res[1], rel_gap=res[2], L=res[3], iters=int(res[4]),
                 restarts=int(res[5]), status=int(res[6]), beta=beta, zeta=zeta,
-                trace=trace[:m] if trace_cap > 0 else None, phi_trace=phi[:m] if trace_cap > 0 else None)
+                trace=trace[:m] if trace_cap > 0 else None, phi_trace=phi[:m] if trace_cap > 0 else None,
+                restart_at=rst[:min(int(res[5]), restart_cap)] if restart_cap > 0 else None)
 
 
 def num_threads():

@@ -98,38 +98,56 @@ int orc_node_dims(const int8_t *st, int64_t p, int32_t k, int64_t *pbar, int64_t
 
 /* --------------------------------------------------- regulariser g_N, g_N* */
 
-/* Algorithm 1 (Section 4.2, Theorem compute_g_value): value of g_N(beta) for
- * beta in dom g_N.  The majorising vector omega is built over the top-kbar
- * magnitudes of beta restricted to J_f; a full sort satisfies the partial
- * ordering the algorithm asks for. */
+/* g_N(beta) for beta in dom g_N, from Theorem compute_g_value (Section 4.2):
+ * g_N(beta) = 1/2 sum_{J_1} beta_j^2 + 1/2 min sum_{j <= kbar} omega_j^2 over
+ * non-increasing omega >= 0 supported on the first kbar positions that
+ * majorise the sorted free magnitudes q_1 >= q_2 >= ... (q = |beta_{J_f}|).
+ * The minimiser fills the kbar slots to a common water level s where it can:
+ * omega_j = max(q_j, s), j <= kbar, with s the root of
+ *     phi(s) = sum_{j <= kbar} max(q_j, s) - theta = 0,   theta = sum_j q_j,
+ * (equal total, as majorisation requires; the partial-sum conditions hold
+ * because omega dominates q term by term on the first kbar positions and the
+ * tail of q is below s).  phi is non-decreasing and piecewise linear with
+ * breakpoints at the q_j; phi(q_j) = sum_{i < j} q_i + (kbar - j + 1) q_j -
+ * theta is non-increasing in j and phi(q_kbar) = phi(0) <= 0, so the number
+ * of entries above the level is m = #{j <= kbar : phi(q_j) > 0} and on that
+ * piece s = (theta - sum_{j <= m} q_j) / (kbar - m).  A full sort (a library
+ * primitive) orders q. */
 double orc_g(const double *beta, const int8_t *st, int64_t p, int32_t k) {
   int64_t pbar, kbar;
   if (orc_node_dims(st, p, k, &pbar, &kbar) < 0) return INFINITY;
   double s1 = 0.0, theta = 0.0;
-  double *a = (double *)malloc(sizeof(double) * (size_t)(pbar > 0 ? pbar : 1));
-  int64_t m = 0;
+  double *q = (double *)malloc(sizeof(double) * (size_t)(pbar > 0 ? pbar : 1));
+  int64_t nq = 0;
   for (int64_t j = 0; j < p; j++) {
     if (st[j] == ORC_ONE) s1 += beta[j] * beta[j];
-    else if (st[j] == ORC_FREE) {
-      a[m] = fabs(beta[j]);
-      theta += a[m];
-      m++;
-    }
+    else if (st[j] == ORC_FREE) q[nq++] = fabs(beta[j]);
   }
-  qsort(a, (size_t)m, sizeof(double), cmp_desc);
-  double sw = 0.0;
-  for (int64_t j = 0; j < kbar; j++) {
-    /* paper index j+1: thetabar = theta / (kbar - (j+1) + 1) */
-    double tb = theta / (double)(kbar - j);
-    if (tb >= a[j]) {
-      sw += (double)(kbar - j) * tb * tb; /* omega_[j:kbar] = thetabar */
-      break;
+  qsort(q, (size_t)nq, sizeof(double), cmp_desc);
+  /* theta summed in sorted order, the order of the partial sums below: adding
+     non-negative terms never decreases a rounded sum, so phi(q_kbar) <= 0
+     holds in floating point too and m < kbar */
+  for (int64_t j = 0; j < nq; j++) theta += q[j];
+  double free_part = 0.0;
+  if (kbar > 0 && theta > 0.0) {
+    /* m = number of leading entries kept above the water level */
+    int64_t m = 0;
+    double head = 0.0; /* sum of the first j - 1 sorted magnitudes */
+    for (int64_t j = 0; j < kbar; j++) {
+      const double phi_j = head + (double)(kbar - j) * q[j] - theta;
+      if (phi_j > 0.0) m = j + 1;
+      head += q[j];
     }
-    sw += a[j] * a[j]; /* omega_j = |beta_(j)| */
-    theta -= a[j];
+    double kept = 0.0, kept_sq = 0.0;
+    for (int64_t j = 0; j < m; j++) {
+      kept += q[j];
+      kept_sq += q[j] * q[j];
+    }
+    const double level = (theta - kept) / (double)(kbar - m);
+    free_part = kept_sq + (double)(kbar - m) * level * level;
   }
-  free(a);
-  return 0.5 * s1 + 0.5 * sw;
+  free(q);
+  return 0.5 * s1 + 0.5 * free_part;
 }
 
 /* Membership test for dom g_N (Section 2.3, domain D; Lemma
@@ -422,12 +440,15 @@ enum { ORC_FISTA_GAP = 0, ORC_FISTA = 1, ORC_FISTA_FV = 2, ORC_PGD = 3 };
  * res[0..7] = {LB, UB, rel_gap, L, iters, restarts, status, 0}.
  * trace (optional, length trace_cap) receives Phi - Psi at iterates 0, 1, ...
  * and phi_trace (optional, same length) Phi at those iterates.
+ * restart_at (optional, length restart_cap) receives the iterate indices t at
+ * which a restart was taken (the next step starts from x^t with t <- 1).
  * zeta_out receives the dual vector that attains LB.
  */
 int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int loss, double lambda2,
               double M, int32_t k, const int8_t *st, double L, double tol, double eta, int64_t max_iter,
               double cutoff, const double *beta0, double *beta_out, double *zeta_out, double *res,
-              double *trace, int64_t trace_cap, int method, double *phi_trace) {
+              double *trace, int64_t trace_cap, int method, double *phi_trace, int64_t *restart_at,
+              int64_t restart_cap) {
   int64_t pbar, kbar;
   for (int i = 0; i < 8; i++) res[i] = 0.0;
   if (orc_node_dims(st, p, k, &pbar, &kbar) < 0) {
@@ -525,6 +546,7 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
     if (restart) {
       memcpy(yv, x, sizeof(double) * (size_t)p);
       t = 1.0;
+      if (restart_at && restarts < restart_cap) restart_at[restarts] = it;
       restarts++;
     }
     Phi_prev = Phi;

@@ -35,7 +35,7 @@ double orc_dual(const void *, int, const double *, int64_t, int64_t, int, double
                 const int8_t *, const double *);
 int orc_solve(const void *, int, const double *, int64_t, int64_t, int, double, double, int32_t,
               const int8_t *, double, double, double, int64_t, double, const double *, double *,
-              double *, double *, double *, int64_t, int, double *);
+              double *, double *, double *, int64_t, int, double *, int64_t *, int64_t);
 
 static uint64_t state = 0x9E3779B97F4A7C15ull;
 static double urand(void) {  /* xorshift64*, uniform in [0, 1) */
@@ -73,11 +73,12 @@ static int run_case(int64_t n, int64_t p, int loss, int xdt, int32_t k, double M
   double L = (loss ? 0.25 : 2.0) * orc_power_norm2(X, xdt, n, p, 200, 1e-10) * 1.01 + 1e-12;
   double *beta = malloc(sizeof(double) * (p > 0 ? p : 1)), *zeta = malloc(sizeof(double) * (n > 0 ? n : 1));
   double res[8], tr[64], ptr[64];
+  int64_t rst[16];
   int rc = orc_solve(X, xdt, y, n, p, loss, 0.5, M, k, st, L, 1e-7, exp(3.0), 300, NAN, NULL, beta, zeta, res,
-                     tr, 64, method, ptr);
+                     tr, 64, method, ptr, rst, 16);
   /* warm start from the solution, with a cutoff */
   rc |= orc_solve(X, xdt, y, n, p, loss, 0.5, M, k, st, L, 1e-7, exp(3.0), 50, res[1], beta, out, zeta, res,
-                  NULL, 0, method, NULL);
+                  NULL, 0, method, NULL, NULL, 0);
   volatile double pd = orc_primal(X, xdt, y, n, p, loss, 0.5, M, k, st, out) +
                        orc_dual(X, xdt, y, n, p, loss, 0.5, M, k, st, zeta);
   (void)pd;
