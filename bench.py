@@ -5,7 +5,7 @@ every kernel of the path on the GPU): least squares, X n=16384 x p=8192
 stored FP32 (column-major), rows N(0, Sigma) with Sigma_ij = 0.9^|i-j|,
 standardised columns, k = 20 unit coefficients equally spaced, SNR 5,
 lambda2 = 0.1, k = 20, M = 2, relative gap 1e-6.  Inputs are resident in HBM
-before the timed region; the per-matrix setup (||X||^2 by power iteration,
+before the timed region; the per-matrix setup (||X||^2 by Lanczos,
 shared by every node of a tree) runs before it and is reported separately.
 
 Also reported: the dominant kernel (X^T r, FP64 accumulation) against the
@@ -24,7 +24,13 @@ formed once per design, timed apart; each iteration then reads only the Gram
 columns of the current support), with the number of solves that repay G.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
+"c1": the small root (n = 500, p = 200, FP64 X) to a 1e-8 gap, latency-bound.
+"logistic": the logistic root (n = 32768, p = 16384, FP32 X) to a 1e-6 gap,
+with its two-right-hand-side X^T pass against the HBM roofline.  Each of
+these carries its own cpu_baseline (the oracle on the same instance).
+
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
+  python bench.py --kernel-probe-logistic   # the same for the logistic X^T pass
   python bench.py --learned [--pairs N] [--epochs E]   # learned warm start experiment
   python bench.py --e1               # g_N and prox evaluation times at the paper's microbenchmark shapes
   python bench.py --e3               # convergence of the iteration variants (gap restart vs others)
@@ -62,13 +68,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def _traffic_from_summary():
-    """HBM bytes per gemv_t dispatch from the committed rocprofv3 --pmc summary,
+def _traffic_from_summary(path=PMC_SUMMARY):
+    """HBM bytes per gemv_t dispatch from a committed rocprofv3 --pmc summary,
     or None when the summary is missing or was taken on other kernel source."""
-    if not os.path.exists(PMC_SUMMARY):
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -119,6 +125,28 @@ def kernel_probe():
                       "solve_iters": res["iters"]}), flush=True)
 
 
+def kernel_probe_logistic():
+    """The two-right-hand-side X^T pass of the logistic workload, five timing
+    launches through pr_time_gemv_t, plus a plain 512 MiB device copy for
+    scaling rocprofv3 counters."""
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import config_instance
+    dev = torch.device("cuda:0")
+    inst = config_instance(C3_WORKLOAD)
+    ctx = pr.Context(torch.from_numpy(inst.Xcm).to(dev), torch.from_numpy(inst.y).to(dev), pr.LOGISTIC)
+    r = torch.randn(inst.n, dtype=torch.float64, device=dev)
+    ms = ctx.time_gemv_t(r, reps=5)
+    src = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev).fill_(1.0)   # 512 MiB
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)          # a plain streaming kernel: reads and writes 512 MiB
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                      "gemv_t2_ms": ms}), flush=True)
+    ctx.close()
+
+
 def cpu_baseline(inst, cfg, gpu_iters_per_solve, budget_s=20.0):
     """The FP64 oracle (FISTA + gap restart, dense textbook products) on the
     host: time a bounded number of its iterations on the same instance and
@@ -137,6 +165,117 @@ def cpu_baseline(inst, cfg, gpu_iters_per_solve, budget_s=20.0):
             "sample": (f"{iters} oracle FISTA iterations on the full {WORKLOAD} instance in {dt:.1f} s "
                        f"({it_s:.3f} it/s), divided by the {gpu_iters_per_solve:.0f} iterations a full "
                        f"solve to 1e-6 takes")}
+
+
+C1_WORKLOAD = "ls_root_n500_p200_f64"
+C3_WORKLOAD = "logistic_root_n32768_p16384_f32"
+PMC_SUMMARY_LOGISTIC = os.path.join(ROOT, "profiles", "gemv_t2_logistic_n32768_p16384_f32_pmc.txt")
+
+
+def c1_bench(dev, steps, with_cpu):
+    """The small root relaxation (n = 500, p = 200, FP64 X, least squares,
+    lambda2 = 1, k = 10, M = 2) to a 1e-8 relative gap: latency-bound (X is
+    800 kB and stays in cache), so no roofline claim; with the CPU leg, the
+    oracle solves the same node (same step constant) and its bound is set
+    beside the GPU's."""
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import config_instance, CONFIGS
+    cfg = CONFIGS[C1_WORKLOAD]
+    inst = config_instance(C1_WORKLOAD)
+    ctx = pr.Context(torch.from_numpy(inst.Xcm).to(dev), torch.from_numpy(inst.y).to(dev), pr.LSQ)
+    node = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
+    for _ in range(3):
+        ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"]) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(r["iters"] for r in res)
+    out = {"workload": C1_WORKLOAD, "n": inst.n, "p": inst.p, "x_storage": "f64", "loss": "least_squares",
+           "rel_gap_tol": cfg["tol"], "value": round(steps / dt, 2), "unit": "node relaxations/s", "steps": steps,
+           "ms_per_step": round(1e3 * dt / steps, 3), "iters_per_solve": iters / steps,
+           "iters_per_s": round(iters / dt, 1), "us_per_iter": round(1e6 * dt / iters, 2),
+           "all_converged": all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in res),
+           "lower_bound": res[-1]["lower_bound"], "roofline": None}
+    if with_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.solve(inst.Xcm, inst.y, 0, cfg["lambda2"], cfg["M"], cfg["k"], L=res[-1]["L"],
+                           tol=cfg["tol"])
+        dto = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / dto, 3), "unit": "node relaxations/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"one full oracle solve of the same node to {cfg['tol']:g} "
+                                         f"({ref['iters']} iterations, {dto:.3f} s)",
+                               "oracle_lower_bound": ref["lb"],
+                               "gpu_bound_rel_diff": abs(ref["lb"] - out["lower_bound"]) / abs(ref["ub"])}
+    ctx.close()
+    return out
+
+
+def logistic_bench(dev, steps, with_cpu, budget_s=15.0):
+    """The logistic root relaxation (n = 32768, p = 16384, FP32 X, rows with
+    Sigma_ij = 0.7^|i-j|, labels sign(X beta* + noise) at SNR 5, lambda2 = 0.1,
+    k = 15, M = 2) to a 1e-6 FP64 gap; its dominant kernel is the
+    two-right-hand-side X^T pass ([X^T zeta, X^T grad F] per iteration)."""
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import config_instance, CONFIGS
+    cfg = CONFIGS[C3_WORKLOAD]
+    t0 = time.perf_counter()
+    inst = config_instance(C3_WORKLOAD)
+    gen_s = time.perf_counter() - t0
+    print(json.dumps({"progress": "logistic instance", "generate_s": round(gen_s, 1)}), flush=True)
+    X = torch.from_numpy(inst.Xcm).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = pr.Context(X, y, pr.LOGISTIC)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    node = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
+    ctx.solve(node, want_beta=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [ctx.solve(node, want_beta=False) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(r["iters"] for r in res)
+    r = torch.randn(inst.n, dtype=torch.float64, device=dev)
+    ms = ctx.time_gemv_t(r, reps=20)
+    per_launch = inst.n * inst.p * 4 + 16 * inst.n + 16 * inst.p
+    ach = per_launch / (ms * 1e-3) / 1e9
+    out = {"workload": C3_WORKLOAD, "n": inst.n, "p": inst.p, "x_storage": "f32", "loss": "logistic",
+           "corr": cfg["corr"], "k": cfg["k"], "lambda2": cfg["lambda2"], "M": cfg["M"], "rel_gap_tol": cfg["tol"],
+           "value": round(steps / dt, 3), "unit": "node relaxations/s", "steps": steps,
+           "ms_per_step": round(1e3 * dt / steps, 2), "iters_per_solve": iters / steps,
+           "iters_per_s": round(iters / dt, 1), "us_per_iter": round(1e6 * dt / iters, 1),
+           "all_converged": all(q["status"] == 1 and q["rel_gap"] <= cfg["tol"] for q in res),
+           "lower_bound": res[-1]["lower_bound"], "setup_s_per_matrix": round(setup_s, 3),
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": _traffic_from_summary(PMC_SUMMARY_LOGISTIC),
+                        "kernel": "k_gemv_t<float,2>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}}
+    ctx.close()
+    del X, y
+    if with_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.solve(inst.Xcm, inst.y, 1, cfg["lambda2"], cfg["M"], cfg["k"], L=1.0, tol=0.0, max_iter=1)
+        t1 = time.perf_counter() - t0
+        its = max(2, min(20, int(budget_s / max(t1 / 2.0, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.solve(inst.Xcm, inst.y, 1, cfg["lambda2"], cfg["M"], cfg["k"], L=1.0, tol=0.0, max_iter=its)
+        dto = time.perf_counter() - t0
+        it_s = its / dto
+        out["cpu_baseline"] = {"value": it_s / (iters / steps), "unit": "node relaxations/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": (f"{its} oracle iterations on the full {C3_WORKLOAD} instance in "
+                                          f"{dto:.1f} s ({it_s:.3f} it/s), divided by the {iters / steps:.0f} "
+                                          f"iterations a full solve to 1e-6 takes")}
+    return out
 
 
 def batch_bench(dev, steps, n_single=16):
@@ -459,7 +598,7 @@ def paper_shapes_bench(sizes=(1000, 2000, 4000, 8000, 16000), seeds=(0, 1, 2, 3,
     tables (Section 5.2): n = p, rows N(0, Sigma) with Sigma_ij = 0.5^|i-j|,
     k = 10 unit coefficients, SNR 5, lambda2 = 1, M = 2, relative gap 1e-6,
     cold start, least squares and logistic, five seeds.  X is stored FP32.
-    Per seed: context setup (||X||^2 by power iteration, once per design),
+    Per seed: context setup (||X||^2 by Lanczos, once per design),
     the first solve (graph capture included) and a repeated solve."""
     import numpy as np
     import torch
@@ -511,9 +650,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel-probe", action="store_true")
+    ap.add_argument("--kernel-probe-logistic", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
     ap.add_argument("--gram-steps", type=int, default=10, help="timed root solves in Gram mode (0 skips them)")
+    ap.add_argument("--c1-steps", type=int, default=50, help="timed solves of the n=500, p=200 root (0 skips them)")
+    ap.add_argument("--logistic-steps", type=int, default=4,
+                    help="timed solves of the n=32768, p=16384 logistic root (0 skips them)")
     ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
@@ -528,6 +671,9 @@ def main():
         sys.exit(2)
     if args.kernel_probe:
         kernel_probe()
+        return
+    if args.kernel_probe_logistic:
+        kernel_probe_logistic()
         return
     if args.learned:
         learned_bench(args.pairs, args.epochs)
@@ -585,6 +731,11 @@ def main():
         line["batch"] = batch_bench(dev, args.batch_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst, cfg, iters / args.steps)
+    del inst
+    if args.c1_steps > 0:
+        line["c1"] = c1_bench(dev, args.c1_steps, not args.no_cpu_baseline)
+    if args.logistic_steps > 0:
+        line["logistic"] = logistic_bench(dev, args.logistic_steps, not args.no_cpu_baseline)
     print(json.dumps(line), flush=True)
 
 

@@ -128,6 +128,12 @@ void pr_opts_default(pr_opts *opts);
  * for n < 1, p < 1, p >= 2^29 or max_batch < 1. */
 int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void *stream);
 int pr_ctx_destroy(pr_ctx *ctx);
+/* Test switches of a context (a bit set; 0 = normal operation).
+ * PR_DEBUG_GRAM_RECHECK: in Gram mode, treat every pr_solve decision as not
+ * confirmed by the recomputation over X, so the matrix-vector re-solve runs
+ * (lets tests reach that path).  PR_EINVAL for unknown bits. */
+#define PR_DEBUG_GRAM_RECHECK 1
+int pr_ctx_set_debug(pr_ctx *ctx, int32_t flags);
 /* Cached estimate of ||X||_2^2 (largest eigenvalue of X^T X). */
 int pr_ctx_norm2(pr_ctx *ctx, double *norm2_out);
 
@@ -139,7 +145,9 @@ int pr_ctx_norm2(pr_ctx *ctx, double *norm2_out);
  * y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F for zeta =
  * 2 (y - X x), the same iteration in exact arithmetic.  At the end of each
  * solve the reported bounds are recomputed over the stored X (pr_dual_bound)
- * and a decision they do not confirm is redone on the matrix-vector path.
+ * and a decision they do not confirm is redone on the matrix-vector path
+ * from the best iterate (that run's bounds and zeta are then returned; iters
+ * and restarts count both runs).
  * On a context with the batched path, pr_solve_batch then runs one product
  * U = G X_it per iteration (FP64 MFMA over the m current iterates; its
  * reduction split is autotuned here) in place of its two products with X, and
@@ -232,7 +240,10 @@ int pr_time_prox(void *stream, const double *v, int64_t p, double rho, int32_t k
 
 /* Time `reps` back-to-back launches of the X^T r kernel (the solver's
  * dominant kernel, same launch configuration) with HIP events on the
- * context stream; *ms_avg = elapsed / reps.  r device n, h device p. */
+ * context stream; *ms_avg = elapsed / reps.  r device n, h device p.  On a
+ * logistic context the kernel is timed in the two-right-hand-side form the
+ * logistic solve runs ([X^T r, X^T r'] in one pass over X, r' a copy of r in
+ * the context's workspace); h receives X^T r. */
 int pr_time_gemv_t(pr_ctx *ctx, const double *r, double *h, int32_t reps, double *ms_avg);
 
 /* Splits chosen by the context's batched-GEMM autotuner (run at context
@@ -292,10 +303,11 @@ int pr_gemm(void *stream, const uint16_t *A, int64_t lda, const double *B, int64
  * incumbent (Section 5.3).  Branching on the free coordinate with the largest
  * |beta_j| of the node's relaxation solution (children: fixed to one, fixed to
  * zero), children warm-started from the parent's solution.  Incumbents on the
- * support S = J1 + the kbar largest free |beta_j| of each relaxation solution
- * (at most 32 coordinates): least squares, the ridge fit on S clipped to the
- * box; logistic, pr_solve on the leaf node J1 = S, J0 = the rest (there the
- * relaxation is problem (1) restricted to S), each support once. */
+ * support S = J1 + the kbar largest free |beta_j| of each relaxation solution:
+ * pr_solve on the leaf node J1 = S, J0 = the rest, to a 1e-9 relative gap
+ * (there the relaxation is problem (1) restricted to S, the box-constrained
+ * fit on S), each support once; a node with nothing left to branch on is
+ * such a leaf and is offered as an incumbent before it is fathomed. */
 #define PR_BNB_OPTIMAL 1     /* (UB - LB) / |UB| <= rel_gap_tol */
 #define PR_BNB_NODE_LIMIT 2
 #define PR_BNB_TIME_LIMIT 3

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libpr.so")
 
 PR_OK, PR_EINVAL, PR_EOVERLAP, PR_EDEVICE, PR_ENOMEM = 0, -1, -2, -3, -4
 PROX_NOALLOC_MAX_P = 1048576
+DEBUG_GRAM_RECHECK = 1
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
 FISTA_GAP, FISTA, FISTA_FV, PGD = 0, 1, 2, 3
@@ -24,7 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
            "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
-           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_strerror"]
+           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_ctx_set_debug", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
 
@@ -87,6 +88,8 @@ def load():
         L.pr_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(PrProblem), ctypes.c_int32, P]
         L.pr_ctx_destroy.restype = ctypes.c_int
         L.pr_ctx_destroy.argtypes = [P]
+        L.pr_ctx_set_debug.restype = ctypes.c_int
+        L.pr_ctx_set_debug.argtypes = [P, ctypes.c_int32]
         L.pr_ctx_norm2.restype = ctypes.c_int
         L.pr_ctx_norm2.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
         L.pr_solve.restype = ctypes.c_int
@@ -266,6 +269,11 @@ class Context:
     def enable_gram(self):
         """Switch the context's least-squares solves to the Gram form h = b - G x."""
         _check(load().pr_ctx_enable_gram(self.h), "pr_ctx_enable_gram")
+
+    def set_debug(self, flags):
+        """Test switches (pr_ctx_set_debug); DEBUG_GRAM_RECHECK forces Gram-mode
+        solves onto the matrix-vector re-solve."""
+        _check(load().pr_ctx_set_debug(self.h, int(flags)), "pr_ctx_set_debug")
 
     def norm2(self):
         v = ctypes.c_double()

@@ -60,6 +60,8 @@ struct pr_ctx {
   double *d_regscratch = nullptr;  // 3p
   hipGraphExec_t gexec = nullptr;
   int32_t graph_units = 0;
+  bool graph_gram = false;  // the iteration graph was captured in Gram mode
+  int32_t debug = 0;        // pr_ctx_set_debug flags
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
   // batched path (least squares, BF16 X, n and p multiples of 128, p <= 16384)
@@ -257,7 +259,7 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
 // is done exit at once).
 int ensure_graph(pr_ctx *c, int32_t units) {
   units += units & 1;
-  if (c->gexec && c->graph_units == units) return PR_OK;
+  if (c->gexec && c->graph_units == units && c->graph_gram == c->gram) return PR_OK;
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -278,6 +280,7 @@ int ensure_graph(pr_ctx *c, int32_t units) {
     return PR_EDEVICE;
   }
   c->graph_units = units;
+  c->graph_gram = c->gram;
   return PR_OK;
 }
 
@@ -865,6 +868,12 @@ int pr_ctx_destroy(pr_ctx *c) {
   return PR_OK;
 }
 
+int pr_ctx_set_debug(pr_ctx *c, int32_t flags) {
+  if (!c || (flags & ~PR_DEBUG_GRAM_RECHECK)) return PR_EINVAL;
+  c->debug = flags;
+  return PR_OK;
+}
+
 int pr_ctx_norm2(pr_ctx *c, double *out) {
   if (!c || !out) return PR_EINVAL;
   *out = c->norm2;
@@ -897,15 +906,17 @@ static int gram_certify(pr_ctx *c, const pr_node *node, const pr_opts *opts, con
   if (st == kConverged) confirmed = rel <= opts->rel_gap_tol;
   else if (st == kCutoffPrune) confirmed = lb >= opts->cutoff;
   else if (st == kCutoffBranch) confirmed = ub <= opts->cutoff;
+  if (c->debug & PR_DEBUG_GRAM_RECHECK) confirmed = false;
   if (!confirmed) {
-    // rare: redo on the matrix-vector path, warm-started from the best iterate
+    // rare: redo on the matrix-vector path (its own iteration graph, see
+    // ensure_graph), warm-started from the best iterate.  Its bounds are the
+    // FP64 values over the stored X of that run, returned with its own zeta.
     PR_TRY(hipMemcpyAsync(c->nb.vbuf, c->nb.xbest, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     c->gram = false;
     pr_opts o2 = *opts;
     rc = pr_solve(c, node, &o2, c->nb.vbuf, beta_out, zeta_out, out);
     c->gram = true;
     if (rc == PR_OK) {
-      if (out->lower_bound < lb) out->lower_bound = lb;
       out->iters += hs.iter;
       out->restarts += hs.restarts;
     }
@@ -1213,9 +1224,15 @@ int pr_gemv_t(pr_ctx *c, const double *r, double *h) {
 
 int pr_time_gemv_t(pr_ctx *c, const double *r, double *h, int32_t reps, double *ms_avg) {
   if (!c || !r || !h || reps < 1 || !ms_avg) return PR_EINVAL;
-  PR_TRY(launch_gemv_t(c->P, r, nullptr, h, nullptr, nullptr, c->stream));
+  // logistic solves run the two-right-hand-side form: [X^T r, X^T r2] with r2
+  // the context's gradient buffer (here a copy of r) and its output buffer
+  const bool two = c->P.loss == kLogistic;
+  const double *r2 = two ? c->B.gm : nullptr;
+  double *h2 = two ? c->B.h2 : nullptr;
+  if (two) PR_TRY(hipMemcpyAsync(c->B.gm, r, sizeof(double) * c->P.n, hipMemcpyDeviceToDevice, c->stream));
+  PR_TRY(launch_gemv_t(c->P, r, r2, h, h2, nullptr, c->stream));
   PR_TRY(hipEventRecord(c->tev[0], c->stream));
-  for (int i = 0; i < reps; i++) PR_TRY(launch_gemv_t(c->P, r, nullptr, h, nullptr, nullptr, c->stream));
+  for (int i = 0; i < reps; i++) PR_TRY(launch_gemv_t(c->P, r, r2, h, h2, nullptr, c->stream));
   PR_TRY(hipEventRecord(c->tev[1], c->stream));
   PR_TRY(hipEventSynchronize(c->tev[1]));
   float ms = 0.0f;

@@ -12,16 +12,15 @@
 // j fixed to one, j fixed to zero).
 //
 // Incumbent: the support S = J1 + the kbar largest |beta_j| over the free
-// coordinates of each node's relaxation solution.  Least squares: the ridge
-// problem min ||y - X_S b||^2 + lambda2 ||b||^2 is solved on S (Cholesky of
-// X_S^T X_S + lambda2 I) and b is clipped to the box [-M, M], which keeps it
-// feasible; its objective, computed exactly from X_S^T X_S, X_S^T y and y^T y,
-// is an upper bound on the optimum of (1).  Logistic: the leaf node J1 = S,
-// J0 = the rest has kbar = 0, where g_N is half the squared norm and the
-// relaxation is problem (1) restricted to S (Section 3); pr_solve on it
-// (warm-started from the node's solution) returns a feasible point whose
-// primal value, evaluated in FP64 over the stored X, is the objective of (1)
-// there.  Each support is tried once.
+// coordinates of each node's relaxation solution, and the leaf node J1 = S,
+// J0 = the rest.  At that leaf kbar = 0, so g_N is half the squared norm on S
+// and the relaxation is problem (1) restricted to S (the box-constrained
+// ridge fit for least squares): pr_solve on it (warm-started from the node's
+// solution, solved to a 1e-9 relative gap) returns a feasible k-sparse point
+// whose primal value, evaluated in FP64 over the stored X, is the objective
+// of (1) there.  Each support is tried once.  A node with nothing left to
+// branch on is such a leaf itself, so its own problem is always offered as an
+// incumbent before it is fathomed.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -30,7 +29,6 @@
 #include <set>
 #include <vector>
 
-#include "pr_device.h"
 #include "pr_internal.h"
 
 #define PR_TRY(expr)                          \
@@ -41,107 +39,6 @@
 
 namespace pr {
 namespace {
-
-constexpr int kSubMax = 32;  // largest support the incumbent kernel handles
-
-// out[a * (m + 1) + b] = X[:, S[a]] . X[:, S[b]] (b < m), out[a * (m + 1) + m]
-// = X[:, S[a]] . y; block a computes row a, FP64 accumulation over the stored X.
-template <typename T>
-__global__ __launch_bounds__(256) void k_subgram(const T *__restrict__ X, int64_t n, const int32_t *__restrict__ S,
-                                                 int m, const double *__restrict__ y, double *__restrict__ out) {
-  __shared__ double red[4][kSubMax + 1];
-  const int a = blockIdx.x;
-  const T *__restrict__ xa = X + (int64_t)S[a] * n;
-  double acc[kSubMax + 1];
-#pragma unroll
-  for (int b = 0; b <= kSubMax; b++) acc[b] = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const double va = (double)xa[i];
-#pragma unroll
-    for (int b = 0; b < kSubMax; b++)
-      if (b < m) acc[b] += va * (double)X[(int64_t)S[b] * n + i];
-    acc[kSubMax] += va * y[i];
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int b = 0; b <= kSubMax; b++) {
-    const double v = dev::wave_sum(acc[b]);
-    if (lane == 0) red[w][b] = v;
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b <= m; b += blockDim.x) {
-    const int src = b < m ? b : kSubMax;
-    out[(int64_t)a * (m + 1) + b] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-  }
-}
-
-__global__ __launch_bounds__(256) void k_subgram_bf16(const uint16_t *__restrict__ X, int64_t n,
-                                                      const int32_t *__restrict__ S, int m,
-                                                      const double *__restrict__ y, double *__restrict__ out) {
-  __shared__ double red[4][kSubMax + 1];
-  const int a = blockIdx.x;
-  const uint16_t *__restrict__ xa = X + (int64_t)S[a] * n;
-  double acc[kSubMax + 1];
-#pragma unroll
-  for (int b = 0; b <= kSubMax; b++) acc[b] = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const double va = (double)__uint_as_float(((unsigned int)xa[i]) << 16);
-#pragma unroll
-    for (int b = 0; b < kSubMax; b++)
-      if (b < m) acc[b] += va * (double)__uint_as_float(((unsigned int)X[(int64_t)S[b] * n + i]) << 16);
-    acc[kSubMax] += va * y[i];
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int b = 0; b <= kSubMax; b++) {
-    const double v = dev::wave_sum(acc[b]);
-    if (lane == 0) red[w][b] = v;
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b <= m; b += blockDim.x) {
-    const int src = b < m ? b : kSubMax;
-    out[(int64_t)a * (m + 1) + b] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-  }
-}
-
-hipError_t launch_subgram(const Problem &P, const int32_t *S, int m, double *out, hipStream_t s) {
-  switch (P.xdt) {
-    case kF64: k_subgram<double><<<m, 256, 0, s>>>((const double *)P.X, P.n, S, m, P.y, out); break;
-    case kF32: k_subgram<float><<<m, 256, 0, s>>>((const float *)P.X, P.n, S, m, P.y, out); break;
-    default: k_subgram_bf16<<<m, 256, 0, s>>>((const uint16_t *)P.X, P.n, S, m, P.y, out); break;
-  }
-  return hipGetLastError();
-}
-
-// Cholesky solve of (G + lam I) b = c, G m x m row-major; false if not SPD.
-bool ridge_solve(const std::vector<double> &G, const std::vector<double> &c, int m, double lam, std::vector<double> &b) {
-  std::vector<double> Lw((size_t)m * m, 0.0);
-  for (int i = 0; i < m; i++) {
-    for (int j = 0; j <= i; j++) {
-      double sum = G[(size_t)i * m + j] + (i == j ? lam : 0.0);
-      for (int q = 0; q < j; q++) sum -= Lw[(size_t)i * m + q] * Lw[(size_t)j * m + q];
-      if (i == j) {
-        if (!(sum > 0.0)) return false;
-        Lw[(size_t)i * m + i] = std::sqrt(sum);
-      } else {
-        Lw[(size_t)i * m + j] = sum / Lw[(size_t)j * m + j];
-      }
-    }
-  }
-  std::vector<double> z((size_t)m);
-  for (int i = 0; i < m; i++) {
-    double sum = c[(size_t)i];
-    for (int q = 0; q < i; q++) sum -= Lw[(size_t)i * m + q] * z[(size_t)q];
-    z[(size_t)i] = sum / Lw[(size_t)i * m + i];
-  }
-  b.assign((size_t)m, 0.0);
-  for (int i = m - 1; i >= 0; i--) {
-    double sum = z[(size_t)i];
-    for (int q = i + 1; q < m; q++) sum -= Lw[(size_t)q * m + i] * b[(size_t)q];
-    b[(size_t)i] = sum / Lw[(size_t)i * m + i];
-  }
-  return true;
-}
 
 struct Open {
   double bound;
@@ -160,23 +57,21 @@ struct BnbState {
   Problem P;
   hipStream_t s;
   int64_t n, p;
-  double yy = 0.0;
-  int32_t *d_S = nullptr;
-  double *d_sub = nullptr;
   double *arena = nullptr;  // [slots][p] parent solutions
   int32_t slots = 0;
   std::vector<int32_t> free_slots, refs;
   double *d_B0 = nullptr, *d_Bout = nullptr;
-  double *d_cand = nullptr;  // p: logistic incumbent candidate
+  double *d_cand = nullptr;  // p: incumbent candidate
   double ub = INFINITY;
   std::vector<double> best;  // dense incumbent (host)
-  std::set<std::vector<int32_t>> tried;  // logistic supports already solved
+  std::set<std::vector<int32_t>> tried;  // supports already solved
 };
 
-// Incumbent candidate from a relaxation solution (host copy beta); updates
-// st.ub / st.best when it improves.
+// Incumbent candidate from a relaxation solution (host copy beta, device copy
+// d_beta): the leaf node of its support S solved by pr_solve; updates
+// st.ub / st.best when its objective improves.
 static int try_incumbent(BnbState &st, const pr_node &node, const std::vector<int8_t> &status,
-                         const std::vector<double> &beta, const double *d_beta, double lam2, double M) {
+                         const std::vector<double> &beta, const double *d_beta) {
   const int64_t p = st.p;
   std::vector<int32_t> S;
   int32_t kbar = node.k;
@@ -191,59 +86,32 @@ static int try_incumbent(BnbState &st, const pr_node &node, const std::vector<in
   const size_t take = std::min<size_t>(fr.size(), (size_t)std::max(kbar, 0));
   std::partial_sort(fr.begin(), fr.begin() + take, fr.end());
   for (size_t q = 0; q < take; q++) S.push_back(fr[q].second);
-  const int m = (int)S.size();
-  if (m == 0 || m > kSubMax) return PR_OK;
+  const int64_t m = (int64_t)S.size();
   std::sort(S.begin(), S.end());
-  if (st.P.loss == kLogistic) {
-    if (!st.tried.insert(S).second) return PR_OK;
-    std::vector<int32_t> J0;
-    J0.reserve((size_t)(p - m));
-    size_t q = 0;
-    for (int64_t j = 0; j < p; j++) {
-      if (q < S.size() && S[q] == (int32_t)j) q++;
-      else J0.push_back((int32_t)j);
-    }
-    pr_node leaf = node;
-    leaf.J1 = S.data();
-    leaf.n1 = m;
-    leaf.J0 = J0.empty() ? nullptr : J0.data();
-    leaf.n0 = (int64_t)J0.size();
-    pr_opts lo;
-    pr_opts_default(&lo);
-    lo.rel_gap_tol = 1e-9;
-    pr_result r;
-    int rc = pr_solve(st.c, &leaf, &lo, d_beta, st.d_cand, nullptr, &r);
-    if (rc != PR_OK) return rc;
-    if (r.primal < st.ub) {
-      st.ub = r.primal;
-      st.best.assign((size_t)p, 0.0);
-      PR_TRY(hipMemcpyAsync(st.best.data(), st.d_cand, sizeof(double) * p, hipMemcpyDeviceToHost, st.s));
-      PR_TRY(hipStreamSynchronize(st.s));
-    }
-    return PR_OK;
+  if (!st.tried.insert(S).second) return PR_OK;
+  std::vector<int32_t> J0;
+  J0.reserve((size_t)(p - m));
+  size_t q = 0;
+  for (int64_t j = 0; j < p; j++) {
+    if (q < S.size() && S[q] == (int32_t)j) q++;
+    else J0.push_back((int32_t)j);
   }
-  PR_TRY(hipMemcpyAsync(st.d_S, S.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st.s));
-  PR_TRY(launch_subgram(st.P, st.d_S, m, st.d_sub, st.s));
-  std::vector<double> sub((size_t)m * (m + 1));
-  PR_TRY(hipMemcpyAsync(sub.data(), st.d_sub, sizeof(double) * sub.size(), hipMemcpyDeviceToHost, st.s));
-  PR_TRY(hipStreamSynchronize(st.s));
-  std::vector<double> G((size_t)m * m), cv((size_t)m), b;
-  for (int a = 0; a < m; a++) {
-    for (int q = 0; q < m; q++) G[(size_t)a * m + q] = sub[(size_t)a * (m + 1) + q];
-    cv[(size_t)a] = sub[(size_t)a * (m + 1) + m];
-  }
-  if (!ridge_solve(G, cv, m, lam2, b)) return PR_OK;
-  for (double &v : b) v = std::min(M, std::max(-M, v));
-  double f = st.yy;
-  for (int a = 0; a < m; a++) {
-    double gb = 0.0;
-    for (int q = 0; q < m; q++) gb += G[(size_t)a * m + q] * b[(size_t)q];
-    f += b[(size_t)a] * (gb - 2.0 * cv[(size_t)a]) + lam2 * b[(size_t)a] * b[(size_t)a];
-  }
-  if (f < st.ub) {
-    st.ub = f;
+  pr_node leaf = node;
+  leaf.J1 = S.empty() ? nullptr : S.data();
+  leaf.n1 = m;
+  leaf.J0 = J0.empty() ? nullptr : J0.data();
+  leaf.n0 = (int64_t)J0.size();
+  pr_opts lo;
+  pr_opts_default(&lo);
+  lo.rel_gap_tol = 1e-9;
+  pr_result r;
+  int rc = pr_solve(st.c, &leaf, &lo, d_beta, st.d_cand, nullptr, &r);
+  if (rc != PR_OK) return rc;
+  if (r.primal < st.ub) {
+    st.ub = r.primal;
     st.best.assign((size_t)p, 0.0);
-    for (int a = 0; a < m; a++) st.best[(size_t)S[(size_t)a]] = b[(size_t)a];
+    PR_TRY(hipMemcpyAsync(st.best.data(), st.d_cand, sizeof(double) * p, hipMemcpyDeviceToHost, st.s));
+    PR_TRY(hipStreamSynchronize(st.s));
   }
   return PR_OK;
 }
@@ -290,28 +158,18 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
   st.slots = std::min<int32_t>(o.max_nodes + 1, 4 * 4096);
   memset(out, 0, sizeof(*out));
   int rc = PR_OK;
-  bool ok = hipMalloc((void **)&st.d_S, sizeof(int32_t) * kSubMax) == hipSuccess;
-  ok = ok && hipMalloc((void **)&st.d_sub, sizeof(double) * kSubMax * (kSubMax + 1)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&st.arena, sizeof(double) * st.slots * P.p) == hipSuccess;
+  bool ok = hipMalloc((void **)&st.arena, sizeof(double) * st.slots * P.p) == hipSuccess;
   ok = ok && hipMalloc((void **)&st.d_B0, sizeof(double) * B * P.p) == hipSuccess;
   ok = ok && hipMalloc((void **)&st.d_Bout, sizeof(double) * B * P.p) == hipSuccess;
   ok = ok && hipMalloc((void **)&st.d_cand, sizeof(double) * P.p) == hipSuccess;
   auto cleanup = [&]() {
-    void *bufs[] = {st.d_S, st.d_sub, st.arena, st.d_B0, st.d_Bout, st.d_cand};
+    void *bufs[] = {st.arena, st.d_B0, st.d_Bout, st.d_cand};
     for (void *q : bufs)
       if (q) (void)hipFree(q);
   };
   if (!ok) {
     cleanup();
     return PR_ENOMEM;
-  }
-  {
-    std::vector<double> yh((size_t)P.n);
-    if (hipMemcpy(yh.data(), P.y, sizeof(double) * P.n, hipMemcpyDeviceToHost) != hipSuccess) {
-      cleanup();
-      return PR_EDEVICE;
-    }
-    for (double v : yh) st.yy += v * v;
   }
   st.refs.assign((size_t)st.slots, 0);
   for (int32_t q = st.slots - 1; q >= 0; q--) st.free_slots.push_back(q);
@@ -329,7 +187,6 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
   int64_t solved = 0, pruned = 0;
   int32_t maxdepth = 0;
   double relax_s = 0.0;
-  const double lam2 = root->lambda2, M = root->M;
   std::vector<double> bh((size_t)P.p);
   int status = PR_BNB_OPTIMAL;
   auto gap_closed = [&](double lb) { return std::isfinite(st.ub) && st.ub - lb <= o.rel_gap_tol * std::fabs(st.ub); };
@@ -409,7 +266,7 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
         rc = PR_EDEVICE;
         break;
       }
-      rc = try_incumbent(st, nodes[(size_t)i], sv, bh, st.d_Bout + (int64_t)i * P.p, lam2, M);
+      rc = try_incumbent(st, nodes[(size_t)i], sv, bh, st.d_Bout + (int64_t)i * P.p);
       if (rc != PR_OK) break;
       if (gap_closed(bound)) {
         pruned++;
@@ -423,7 +280,7 @@ int pr_bnb(pr_ctx *c, const pr_node *root, const pr_bnb_opts *opts_in, double *b
           amax = std::fabs(bh[(size_t)j]);
           jb = (int32_t)j;
         }
-      if (jb < 0 || kbar <= 0) {  // nothing left to decide: the relaxation is the restricted problem
+      if (jb < 0 || kbar <= 0) {  // a leaf: its own problem was offered as an incumbent above
         pruned++;
         continue;
       }

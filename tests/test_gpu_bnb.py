@@ -74,6 +74,37 @@ def test_bnb_logistic_matches_enumeration(dev, seed, k, lam2, J0, J1):
     ctx.close()
 
 
+@pytest.mark.parametrize("loss,seed,k,lam2", [(0, 13, 3, 0.2), (0, 14, 4, 0.05), (1, 15, 3, 0.1)])
+def test_bnb_with_a_binding_box_matches_enumeration(dev, loss, seed, k, lam2):
+    """Box M = 0.3 binds at the optimum: the incumbent must be the box-constrained
+    fit of its support (not a ridge fit clipped to the box), and leaves must
+    offer their own problem as an incumbent, or the tree would close above the
+    enumerated optimum."""
+    import paper_2603_01306_amd as pr
+    M = 0.3
+    inst = make_instance(n=120, p=12, corr=0.5, k_true=3, snr=8.0, loss=loss, seed=seed, storage="f64")
+    X, y = inst.X64().T, inst.y
+    ctx = _ctx(inst, dev, 8)
+    res, beta = ctx.bnb(pr.Node(k, lam2, M), rel_gap_tol=1e-7, node_opts=dict(rel_gap_tol=1e-9, max_iter=200000))
+    if loss == 0:
+        opt, S, bopt = ksparse_bruteforce(X, y, k, lam2, M)
+    else:
+        opt, S, bopt = ksparse_bruteforce_logistic(X, y, k, lam2, M)
+    print(loss, seed, res, opt, S, bopt, flush=True)
+    assert np.max(np.abs(bopt)) >= M * (1 - 1e-6)             # the box is active at the optimum
+    assert res["status"] == pr.BNB_OPTIMAL
+    assert res["lower_bound"] <= opt * (1 + 1e-9)
+    assert abs(res["upper_bound"] - opt) <= 2e-7 * opt
+    b = beta.cpu().numpy()
+    assert np.count_nonzero(b) <= k and np.all(np.abs(b) <= M * (1 + 1e-12))
+    if loss == 0:
+        obj = _objective(X, y, b, lam2)
+    else:
+        obj = float(np.sum(np.logaddexp(0.0, -y * (X @ b))) + lam2 * b @ b)
+    assert abs(obj - res["upper_bound"]) <= 1e-10 * res["upper_bound"]
+    ctx.close()
+
+
 def test_bnb_on_the_batched_path(dev):
     """BF16 design on the batched path: bounds ordered, incumbent objective
     exact, node accounting consistent."""
@@ -93,22 +124,37 @@ def test_bnb_on_the_batched_path(dev):
     ctx.close()
 
 
-def test_batched_cutoff_decisions_match_single_path(dev):
+def test_batched_cutoff_decisions_match_oracle(dev):
+    """Batched dynamic termination against the oracle's decisions: each node's
+    relaxation value is at least 1% away from the cutoff, so prune (value above
+    the cutoff) or branch (below) is the only correct outcome, and the oracle
+    run with the same step reaches it at (nearly) the same iterate."""
     import paper_2603_01306_amd as pr
     inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=0, seed=10, storage="bf16")
     ctx = _ctx(inst, dev, 16)
     rng = np.random.default_rng(0)
-    nodes = [pr.Node(6, 0.5, 2.0, J0=rng.choice(512, 20, replace=False)) for _ in range(8)]
+    # fixed-zero sets of growing size spread the nodes' relaxation values
+    nodes = [pr.Node(6, 0.5, 2.0, J0=rng.choice(512, 40 * q, replace=False)) for q in range(8)]
     free, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-9)
-    vals = sorted(r["lower_bound"] for r in free)
-    cutoff = 0.5 * (vals[3] + vals[4])                        # half the nodes prune, half branch
-    res, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-9, cutoff=cutoff)
-    for nd, r, f in zip(nodes, res, free):
-        assert r["status"] in (pr.CUTOFF_PRUNE, pr.CUTOFF_BRANCH, pr.CONVERGED)
+    vals = np.sort([r["lower_bound"] for r in free])
+    gaps = np.diff(vals) / vals[1:]
+    i = int(np.argmax(gaps[1:6])) + 1                          # the widest gap between inner values
+    cutoff = 0.5 * (vals[i] + vals[i + 1])
+    assert min(abs(v - cutoff) for v in vals) >= 1e-3 * cutoff
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-9, cutoff=cutoff)
+    Bh = B.cpu().numpy()
+    kinds = set()
+    for q, (nd, r, f) in enumerate(zip(nodes, res, free)):
+        st = nd.status(inst.p)
+        ref = oracle.solve(inst.Xcm, inst.y, 0, 0.5, 2.0, 6, status=st, L=r["L"], tol=1e-9, cutoff=cutoff)
+        assert r["status"] == ref["status"], (q, r, ref["status"])
+        assert abs(r["iters"] - ref["iters"]) <= 2
+        kinds.add(r["status"])
         if r["status"] == pr.CUTOFF_PRUNE:
-            assert r["lower_bound"] >= cutoff and f["lower_bound"] >= cutoff * (1 - 1e-9)
-        if r["status"] == pr.CUTOFF_BRANCH:
-            assert r["primal"] <= cutoff and f["lower_bound"] <= cutoff * (1 + 1e-9)
-        s = ctx.solve(nd, rel_gap_tol=1e-9, cutoff=cutoff)
-        assert (s["status"] == pr.CUTOFF_PRUNE) == (r["status"] == pr.CUTOFF_PRUNE)
+            assert r["lower_bound"] >= cutoff and ref["lb"] >= cutoff
+        else:
+            assert r["status"] == pr.CUTOFF_BRANCH and r["primal"] <= cutoff
+            phi = oracle.primal(inst.Xcm, inst.y, Bh[q], 0, 0.5, 2.0, 6, status=st)
+            assert abs(phi - r["primal"]) <= 1e-11 * abs(phi)
+    assert kinds == {pr.CUTOFF_PRUNE, pr.CUTOFF_BRANCH}
     ctx.close()

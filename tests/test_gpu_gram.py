@@ -211,3 +211,43 @@ def test_gram_cutoff_warm_start_and_iteration_limit(dev):
     assert abs(psi - short["lower_bound"]) <= 1e-11 * abs(psi) and psi <= lb * (1 + 1e-12)
     cg.close()
     cm.close()
+
+
+def test_gram_unconfirmed_decision_reruns_on_matvec_path(dev):
+    """A Gram-mode decision the recomputation over X does not confirm is redone
+    on the matrix-vector path (forced here by the context's test switch).  The
+    re-solve must use that path's own iteration graph: its bound is then the
+    FP64 value over the stored X of the zeta it returns (the oracle
+    recomputes it), and a Gram solve after the switch is cleared is again the
+    plain Gram run."""
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=512, corr=0.7, k_true=8, snr=5.0, loss=0, seed=33, storage="f32")
+    c = _ctx(inst, dev, True)
+    node = pr.Node(8, 0.3, 2.0, J0=[3, 77], J1=[5])
+    st = node.status(inst.p)
+    plain = c.solve(node, rel_gap_tol=1e-9, want_zeta=True)
+    ref = oracle.solve(inst.Xcm, inst.y, 0, 0.3, 2.0, 8, status=st, L=plain["L"], tol=1e-11)
+    c.set_debug(pr.DEBUG_GRAM_RECHECK)
+    cases = [dict(rel_gap_tol=1e-9, want=pr.CONVERGED),
+             dict(rel_gap_tol=1e-9, cutoff=ref["lb"] * 0.995, want=pr.CUTOFF_PRUNE),
+             dict(rel_gap_tol=1e-9, cutoff=ref["lb"] * 1.005, want=pr.CUTOFF_BRANCH)]
+    for cs in cases:
+        want = cs.pop("want")
+        r = c.solve(node, want_zeta=True, **cs)
+        print(want, {k: v for k, v in r.items() if k not in ("beta", "zeta")}, flush=True)
+        assert r["status"] == want
+        psi = oracle.dual(inst.Xcm, inst.y, r["zeta"].cpu().numpy(), 0, 0.3, 2.0, 8, status=st)
+        phi = oracle.primal(inst.Xcm, inst.y, r["beta"].cpu().numpy(), 0, 0.3, 2.0, 8, status=st)
+        assert abs(psi - r["lower_bound"]) <= 1e-11 * abs(psi)
+        assert abs(phi - r["primal"]) <= 1e-11 * abs(phi)
+        assert r["lower_bound"] <= ref["ub"] * (1 + 1e-12)
+        if want == pr.CONVERGED:
+            assert abs(r["lower_bound"] - ref["lb"]) <= 1e-8 * abs(ref["ub"])
+        elif want == pr.CUTOFF_PRUNE:
+            assert r["lower_bound"] >= cs["cutoff"]
+        else:
+            assert r["primal"] <= cs["cutoff"]
+    c.set_debug(0)
+    again = c.solve(node, rel_gap_tol=1e-9, want_zeta=True)
+    assert again["iters"] == plain["iters"] and again["lower_bound"] == plain["lower_bound"]
+    c.close()

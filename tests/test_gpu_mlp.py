@@ -106,6 +106,77 @@ def test_gradient_matches_oracle(dev, rows):
         assert err <= 0.025 * np.linalg.norm(ref[a:b]) + 1e-7, (a, b, err, np.linalg.norm(ref[a:b]))
 
 
+def _grad_error_bound(P, F, T):
+    """Per-parameter bound on |g_gpu - g_oracle(P_bf16)| where P_bf16 rounds
+    W1, W2 to BF16 as the kernels do.  Errors are propagated through absolute
+    values of the oracle's own layers: FP32 accumulation (1e-6 of the absolute
+    sum), BF16 rounding (U) of a1 and of dz2, dz1 where they enter an MFMA
+    product, and every ReLU mask whose pre-activation is within its own error
+    bound of zero counted as fully uncertain.  A factor 2 covers second-order
+    terms."""
+    W1, b1, W2, b2, w3, b3 = omlp.unpack(P)
+    N = F.shape[0]
+    aF, aW1, aW2, aw3 = np.abs(F), np.abs(W1), np.abs(W2), np.abs(w3)
+    eps32 = 1e-6
+    z1 = F @ W1.T + b1
+    a1 = np.maximum(z1, 0.0)
+    Ez1 = eps32 * (aF @ aW1.T + np.abs(b1))
+    Ea1 = Ez1 + U * a1
+    z2 = a1 @ W2.T + b2
+    a2 = np.maximum(z2, 0.0)
+    Ez2 = Ea1 @ aW2.T + eps32 * (a1 @ aW2.T + np.abs(b2))
+    Ea2 = Ez2 + U * a2
+    out = a2 @ w3 + b3
+    Eout = Ea2 @ aw3 + eps32 * (a2 @ aw3 + abs(b3))
+    dout = 2.0 * (out - T) / N
+    Edout = 2.0 * Eout / N
+    u1, u2 = np.abs(z1) <= Ez1, np.abs(z2) <= Ez2          # masks that may flip
+    dz2 = np.outer(dout, w3) * (z2 > 0)
+    Edz2 = np.outer(Edout, aw3) + U * np.abs(dz2) + u2 * np.abs(np.outer(dout, w3))
+    dz1 = (dz2 @ W2) * (z1 > 0)
+    Edz1 = (Edz2 @ aW2 + U * (np.abs(dz2) @ aW2)) * ((z1 > 0) | u1) + u1 * (np.abs(dz2) @ aW2)
+    gW3 = Edout @ a2 + np.abs(dout) @ Ea2 + eps32 * (np.abs(dout) @ a2)
+    gB3 = np.sum(Edout) + eps32 * np.sum(np.abs(dout))
+    gW2 = Edz2.T @ a1 + np.abs(dz2).T @ Ea1 + eps32 * (np.abs(dz2).T @ a1)
+    gB2 = Edz2.sum(axis=0) + eps32 * np.abs(dz2).sum(axis=0)
+    gW1 = Edz1.T @ aF + eps32 * (np.abs(dz1).T @ aF)
+    gB1 = Edz1.sum(axis=0) + eps32 * np.abs(dz1).sum(axis=0)
+    return 2.0 * omlp.pack(gW1, gB1, gW2, gB2, gW3, gB3) + 1e-9
+
+
+@pytest.mark.parametrize("rows", [37, 5000, 131109])
+def test_gradient_with_fp32_master_weights(dev, rows):
+    """General FP32 master weights (training's case, not BF16-exact): each
+    gradient entry against the oracle evaluated at the BF16-rounded weights
+    the kernels use, within a bound derived per entry from the arithmetic."""
+    import torch
+    pr = _pr()
+    P = _rand_params(11 + rows, bf16_weights=False)
+    F, T = _rand_rows(13 + rows, rows)
+    Pb = P.copy()
+    Pb[omlp.OFF_W1:omlp.OFF_B1] = _bf16(P[omlp.OFF_W1:omlp.OFF_B1])
+    Pb[omlp.OFF_W2:omlp.OFF_B2] = _bf16(P[omlp.OFF_W2:omlp.OFF_B2])
+    assert np.any(Pb != P)
+    g = pr.mlp_grad(_dev(P, torch.float32), _dev(F, torch.float32).to(torch.bfloat16),
+                    _dev(T, torch.float32)).cpu().numpy().astype(np.float64)
+    loss, ref = omlp.loss_grad(Pb, F, T)
+    bound = _grad_error_bound(Pb, F, T)
+    err = np.abs(g[:-1] - ref)
+    worst = int(np.argmax(err / bound))
+    print(f"rows={rows} max err/bound={err[worst] / bound[worst]:.3f} at {worst}, "
+          f"median bound/|g|={np.median(bound / (np.abs(ref) + 1e-30)):.3g}", flush=True)
+    assert np.all(err <= bound), (worst, err[worst], bound[worst], ref[worst])
+    assert abs(g[-1] - loss) <= 0.02 * loss
+    # the entry bounds grow where a gradient sums terms of both signs; each
+    # parameter block as a whole stays within a few BF16 roundings
+    blocks = [(omlp.OFF_W1, omlp.OFF_B1), (omlp.OFF_B1, omlp.OFF_W2), (omlp.OFF_W2, omlp.OFF_B2),
+              (omlp.OFF_B2, omlp.OFF_W3), (omlp.OFF_W3, omlp.OFF_B3), (omlp.OFF_B3, omlp.NPARAM)]
+    for a, b in blocks:
+        rel = np.linalg.norm(g[a:b] - ref[a:b]) / (np.linalg.norm(ref[a:b]) + 1e-30)
+        print(f"  block {a}:{b} relative error {rel:.2e}", flush=True)
+        assert rel <= 0.025
+
+
 def test_gradient_is_deterministic(dev):
     import torch
     pr = _pr()

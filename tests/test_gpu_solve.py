@@ -123,13 +123,16 @@ def test_default_step_on_mirrored_design(dev, loss):
     ctx.close()
 
 
-@pytest.mark.parametrize("p,n,lam2", [(1000, 256, 0.5), (1500, 256, 0.75), (3000, 256, 1.5), (17000, 128, 20.0)])
+@pytest.mark.parametrize("p,n,lam2", [(1000, 256, 0.5), (1500, 256, 0.75), (3000, 256, 1.5), (6000, 256, 3.0),
+                                      (8192, 256, 4.0), (16000, 256, 8.0), (16384, 128, 8.0), (17000, 128, 20.0)])
 @pytest.mark.parametrize("loss", [0, 1])
 def test_node_step_tiers_match_oracle(dev, p, n, lam2, loss):
-    """The per-node step keeps 2, 4 or 8 entries per thread in registers for
-    p <= 1024, 2048, 4096 and switches to the strided kernel over HBM vectors
-    beyond 16384 entries: first iterates and the converged bound agree with
-    the oracle on each tier, p ragged against the workgroup."""
+    """The per-node step keeps 2, 4, 8, 16 or 32 entries per thread in
+    registers for p <= 1024, 2048, 4096, 8192, 16384 (the 16- and 32-entry
+    tiers are the ones the full-size roots run) and switches to the strided
+    kernel over HBM vectors beyond 16384 entries: first iterates and the
+    converged bound agree with the oracle on each tier, p ragged against the
+    workgroup and exactly at the tier limits."""
     inst = make_instance(n=n, p=p, corr=0.5, k_true=6, snr=5.0, loss=loss, seed=40 + loss, storage="f32")
     ctx = _ctx(dev, inst)
     pr = _pr()
@@ -179,16 +182,31 @@ def test_node_edge_cases(c1):
 
 
 def test_cutoff_and_maxiter(c1):
+    """Cutoff decisions and the iterate that takes them equal the oracle's
+    (same step L); an iteration limit still reports a valid bound."""
     inst, ctx, lam = c1
     pr = _pr()
-    ref = ctx.solve(pr.Node(10, 1.0, 2.0), rel_gap_tol=1e-8)
-    r1 = ctx.solve(pr.Node(10, 1.0, 2.0), cutoff=ref["lower_bound"] * 0.9)
-    assert r1["status"] == pr.CUTOFF_PRUNE and r1["lower_bound"] >= ref["lower_bound"] * 0.9
-    r2 = ctx.solve(pr.Node(10, 1.0, 2.0), cutoff=ref["primal"] * 1.5)
-    assert r2["status"] == pr.CUTOFF_BRANCH and r2["primal"] <= ref["primal"] * 1.5
-    r3 = ctx.solve(pr.Node(10, 1.0, 2.0), max_iter=3, rel_gap_tol=0.0)
-    assert r3["status"] == pr.MAXITER and r3["iters"] == 3
-    assert r3["lower_bound"] <= ref["lower_bound"] * (1 + 1e-12)   # still a valid bound
+    lam = 2.0 * lam * 1.01                       # the step constant L of both runs
+    ref = oracle.solve(inst.Xcm, inst.y, 0, 1.0, 2.0, 10, L=lam, tol=1e-10)
+    for cutoff, want in ((ref["lb"] * 0.99, pr.CUTOFF_PRUNE), (ref["lb"] * 1.01, pr.CUTOFF_BRANCH),
+                         (ref["lb"] * 0.5, pr.CUTOFF_PRUNE), (ref["ub"] * 1.5, pr.CUTOFF_BRANCH)):
+        r = ctx.solve(pr.Node(10, 1.0, 2.0), cutoff=cutoff, L=lam, want_zeta=True, rel_gap_tol=1e-10)
+        o = oracle.solve(inst.Xcm, inst.y, 0, 1.0, 2.0, 10, L=lam, tol=1e-10, cutoff=cutoff)
+        assert r["status"] == o["status"] == want, (cutoff, r["status"], o["status"])
+        assert r["iters"] == o["iters"]
+        if want == pr.CUTOFF_PRUNE:
+            assert r["lower_bound"] >= cutoff
+            assert abs(r["lower_bound"] - o["lb"]) <= 1e-10 * abs(o["lb"])
+            psi = oracle.dual(inst.Xcm, inst.y, r["zeta"].cpu().numpy(), 0, 1.0, 2.0, 10)
+            assert abs(psi - r["lower_bound"]) <= 1e-12 * abs(psi)
+        else:
+            assert r["primal"] <= cutoff
+            assert abs(r["primal"] - o["ub"]) <= 1e-10 * abs(o["ub"])
+    r3 = ctx.solve(pr.Node(10, 1.0, 2.0), max_iter=3, rel_gap_tol=0.0, L=lam)
+    o3 = oracle.solve(inst.Xcm, inst.y, 0, 1.0, 2.0, 10, L=lam, tol=0.0, max_iter=3)
+    assert r3["status"] == pr.MAXITER and r3["iters"] == 3 and o3["iters"] == 3
+    assert abs(r3["lower_bound"] - o3["lb"]) <= 1e-10 * abs(ref["ub"])
+    assert r3["lower_bound"] <= ref["lb"] * (1 + 1e-12)   # still a valid bound
 
 
 def test_warm_start_and_determinism(c1):
