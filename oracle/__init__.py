@@ -70,6 +70,21 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p,
                                 _d, _d, _d, _i64, _d, _p, _p, _p, _p, _p, _i64, ctypes.c_int, _p, _p, _i64]
+        L.orc_solve_acfgm.restype = ctypes.c_int
+        L.orc_solve_acfgm.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p,
+                                      _d, _d, _d, ctypes.c_int, _d, _d, _i64, _p, _p, _p, _p, _p, _p, _p, _p,
+                                      _i64]
+        L.orc_lasso_G.restype = _d
+        L.orc_lasso_G.argtypes = [ctypes.c_int, _p, _i64, _d]
+        L.orc_lasso_Gstar.restype = _d
+        L.orc_lasso_Gstar.argtypes = [ctypes.c_int, _p, _i64, _d]
+        L.orc_lasso_prox.restype = None
+        L.orc_lasso_prox.argtypes = [ctypes.c_int, _p, _i64, _d, _d, _p]
+        L.orc_lasso_dual.restype = _d
+        L.orc_lasso_dual.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _p, _p]
+        L.orc_lasso_solve.restype = ctypes.c_int
+        L.orc_lasso_solve.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _d, _d, _i64,
+                                      ctypes.c_int, _p, _p, _p, _p, _p, _p, _i64]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         _lib = L
@@ -251,3 +266,86 @@ def solve(Xcm, y, kind, lambda2, M, k, status=None, L=0.0, tol=1e-8, eta=math.ex
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def solve_acfgm(Xcm, y, kind, lambda2, M, k, status=None, L0=1.0, c=2.0, b=0.1, restart=True, tol=1e-8,
+                eta=math.exp(3.0), max_iter=100000, beta0=None, trace_cap=0):
+    """AC-FGM (Li and Lan) with, if `restart`, the duality-gap restart.
+    Returns lb, ub, rel_gap, L1 (accepted first-step constant), iters
+    (evaluations), restarts, status, rejected (line-search trials), beta (the
+    iterate attaining ub), zeta (dual vector attaining lb), and with
+    trace_cap > 0 per-evaluation traces: gap, phi, lhat, step (epoch step
+    index t, negative for a rejected trial)."""
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    s = _st(status, p)
+    b0 = None if beta0 is None else _f64(beta0)
+    beta = np.empty(p)
+    zeta = np.empty(n)
+    res = np.zeros(8)
+    tr = [np.full(max(trace_cap, 1), np.nan) for _ in range(4)]
+    lib().orc_solve_acfgm(_ptr(X), code, _ptr(y), n, p, int(kind), float(lambda2), float(M), int(k), _ptr(s),
+                          float(L0), float(c), float(b), int(bool(restart)), float(tol), float(eta), int(max_iter),
+                          None if b0 is None else _ptr(b0), _ptr(beta), _ptr(zeta), _ptr(res),
+                          *[(_ptr(a) if trace_cap > 0 else None) for a in tr], int(trace_cap))
+    m = int(res[4]) + 1
+    out = dict(lb=res[0], ub=res[1], rel_gap=res[2], L1=res[3], iters=int(res[4]), restarts=int(res[5]),
+               status=int(res[6]), rejected=int(res[7]), beta=beta, zeta=zeta)
+    if trace_cap > 0:
+        out.update(trace=tr[0][:m], phi_trace=tr[1][:m], lhat=tr[2][:m], step=tr[3][:m])
+    return out
+
+
+L1_REG, L1_BALL = 0, 1
+
+
+def lasso_G(kind, beta, lam):
+    b = _f64(beta)
+    return lib().orc_lasso_G(int(kind), _ptr(b), b.size, float(lam))
+
+
+def lasso_Gstar(kind, w, lam):
+    a = _f64(w)
+    return lib().orc_lasso_Gstar(int(kind), _ptr(a), a.size, float(lam))
+
+
+def lasso_prox(kind, v, t, lam):
+    v = _f64(v)
+    out = np.empty_like(v)
+    lib().orc_lasso_prox(int(kind), _ptr(v), v.size, float(t), float(lam), _ptr(out))
+    return out
+
+
+def lasso_dual(Xcm, y, kind, lam, zeta):
+    """(Psi, scale) at the dual-feasible point built from zeta (see oracle.c)."""
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    z = _f64(zeta)
+    sc = np.zeros(1)
+    v = lib().orc_lasso_dual(_ptr(X), code, _ptr(y), n, p, int(kind), float(lam), _ptr(z), _ptr(sc))
+    return v, float(sc[0])
+
+
+def lasso_solve(Xcm, y, kind, lam, L=0.0, tol=1e-8, eta=math.exp(3.0), max_iter=100000, method=FISTA_GAP,
+                beta0=None, trace_cap=0):
+    """FISTA (with the duality-gap restart unless method == FISTA) on the LASSO
+    problem of `kind` (L1_REG: ||y - X b||^2 + lam ||b||_1; L1_BALL: the same
+    loss over ||b||_1 <= lam).  Returns lb, ub, rel_gap, L, iters, restarts,
+    status, beta (iterate attaining ub), zeta (dual point attaining lb),
+    traces of gap and Phi with trace_cap > 0."""
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    b0 = None if beta0 is None else _f64(beta0)
+    beta = np.empty(p)
+    zeta = np.empty(n)
+    res = np.zeros(8)
+    trace = np.full(max(trace_cap, 1), np.nan)
+    phi = np.full(max(trace_cap, 1), np.nan)
+    lib().orc_lasso_solve(_ptr(X), code, _ptr(y), n, p, int(kind), float(lam), float(L), float(tol), float(eta),
+                          int(max_iter), int(method), None if b0 is None else _ptr(b0), _ptr(beta), _ptr(zeta),
+                          _ptr(res), _ptr(trace) if trace_cap > 0 else None,
+                          _ptr(phi) if trace_cap > 0 else None, int(trace_cap))
+    m = int(res[4]) + 1
+    return dict(lb=res[0], ub=res[1], rel_gap=res[2], L=res[3], iters=int(res[4]), restarts=int(res[5]),
+                status=int(res[6]), beta=beta, zeta=zeta,
+                trace=trace[:m] if trace_cap > 0 else None, phi_trace=phi[:m] if trace_cap > 0 else None)

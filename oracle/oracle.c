@@ -570,6 +570,344 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
   return status;
 }
 
+/* ------------------------------------------------------------ AC-FGM */
+
+/* Gradient of f(beta) = F(X beta) at x (p-vector g), the induced dual vector
+ * zeta = -grad F(X x) (n-vector), F(X x) and Psi(zeta).  u: n scratch. */
+static void orc_eval_point(const void *X, int xdt, const double *y, int64_t n, int64_t p, int loss,
+                           double lambda2, double M, int32_t k, const int8_t *st, const double *x, double *u,
+                           double *zeta, double *g, double *Fx, double *Psi) {
+  orc_matvec(X, xdt, n, p, x, u);
+  orc_loss_grad(loss, u, y, n, zeta); /* zeta <- grad F(u) */
+  orc_rmatvec(X, xdt, n, p, zeta, g); /* g = X^T grad F(X x) */
+  for (int64_t i = 0; i < n; i++) zeta[i] = -zeta[i];
+  *Fx = orc_loss(loss, u, y, n);
+  *Psi = orc_dual(X, xdt, y, n, p, loss, lambda2, M, k, st, zeta);
+}
+
+static double orc_dist(const double *a, const double *b, int64_t m) {
+  double s = 0.0;
+  for (int64_t j = 0; j < m; j++) s += (a[j] - b[j]) * (a[j] - b[j]);
+  return sqrt(s);
+}
+
+/* AC-FGM (accelerated composite fast gradient method of Li and Lan, "A simple
+ * uniformly optimal method without line search for convex optimization",
+ * 2023), the parameter-free method of Section 3.3's rate table and the
+ * Section 5.2 convergence study, applied to Phi = f + G with f(beta) =
+ * F(X beta), G = 2 lambda2 g_N.  Three sequences: the prox step
+ *     z_t = prox_{eta_t G}(y_{t-1} - eta_t grad f(x_{t-1})),
+ * the averaged prox centre y_t = (1 - b) y_{t-1} + b z_t (b = the averaging
+ * weight, in (0, 1 - sqrt(6)/3]) and the iterate x_t = (z_t + tau_t x_{t-1}) /
+ * (1 + tau_t) with tau_1 = 0, tau_t = t / 2.  Step sizes from the local
+ * curvature estimates Lhat_t = ||grad f(x_t) - grad f(x_{t-1})|| /
+ * ||x_t - x_{t-1}||: eta_2 = min((1 - b) eta_1, 1 / (4 Lhat_1)), eta_t =
+ * min((tau_{t-1} + 1) / tau_t eta_{t-1}, tau_{t-1} / (4 Lhat_{t-1})) for
+ * t >= 3.  The first step is a backtracking line search from an initial
+ * underestimate L0 of the curvature: eta_1 = 1 / L1, and while Lhat_1 > L1
+ * the trial is rejected and L1 <- c L1 (c > 1).  The iterate x_t is the
+ * primal point of the certificate: zeta_t = -grad F(X x_t) (Section 3.2).
+ * The readings (step rules, first-step test, what a restart keeps) are listed
+ * in the design notes.
+ *
+ * With restart_gap the duality-gap restart of Section 3.3 applies: when the
+ * gap at an accepted iterate falls to 1/eta of the gap at the epoch start,
+ * the method restarts from that iterate (x_0 = y_0 = x_t, t = 1) keeping the
+ * accepted first-step constant L1.  Every evaluated point (rejected trials
+ * included) enters the best-so-far bounds and the stopping test.
+ *
+ * res[0..7] = {LB, UB, rel_gap, final L1, evaluations, restarts, status,
+ * rejected trials}.  Traces (length trace_cap, optional) per evaluation:
+ * gap, Phi, Lhat (against the point the step left from) and the epoch step
+ * index t (negative for a rejected trial). */
+int orc_solve_acfgm(const void *X, int xdt, const double *y, int64_t n, int64_t p, int loss, double lambda2,
+                    double M, int32_t k, const int8_t *st, double L0, double c, double b, int restart_gap,
+                    double tol, double eta, int64_t max_iter, const double *beta0, double *beta_out,
+                    double *zeta_out, double *res, double *trace, double *phi_trace, double *lhat_trace,
+                    double *step_trace, int64_t trace_cap) {
+  int64_t pbar, kbar;
+  for (int i = 0; i < 8; i++) res[i] = 0.0;
+  if (orc_node_dims(st, p, k, &pbar, &kbar) < 0) {
+    res[0] = INFINITY;
+    res[1] = INFINITY;
+    res[6] = ORC_INFEASIBLE;
+    for (int64_t j = 0; j < p; j++) beta_out[j] = 0.0;
+    return ORC_INFEASIBLE;
+  }
+  const size_t P8 = sizeof(double) * (size_t)p, N8 = sizeof(double) * (size_t)n;
+  double *x = (double *)calloc((size_t)p, sizeof(double)); /* x_{t-1} before a step, x_t after */
+  double *g = (double *)malloc(P8);                         /* grad f at x */
+  double *xo = (double *)malloc(P8), *go = (double *)malloc(P8); /* the point the step left from */
+  double *yv = (double *)malloc(P8), *z = (double *)malloc(P8), *v = (double *)malloc(P8);
+  double *xn = (double *)malloc(P8), *gn = (double *)malloc(P8), *yn = (double *)malloc(P8);
+  double *xbest = (double *)malloc(P8);
+  double *u = (double *)malloc(N8), *zeta = (double *)malloc(N8);
+  if (beta0)
+    for (int64_t j = 0; j < p; j++) x[j] = beta0[j];
+  double Fx, Psi;
+  orc_eval_point(X, xdt, y, n, p, loss, lambda2, M, k, st, x, u, zeta, g, &Fx, &Psi);
+  double Phi = orc_in_dom(x, st, p, k, M, 1e-9) ? Fx + 2.0 * lambda2 * orc_g(x, st, p, k) : INFINITY;
+  double LB = Psi, UB = Phi, gap_ref = Phi - Psi;
+  memcpy(zeta_out, zeta, N8);
+  memcpy(xbest, x, P8);
+  if (trace && trace_cap > 0) trace[0] = Phi - Psi;
+  if (phi_trace && trace_cap > 0) phi_trace[0] = Phi;
+  if (lhat_trace && trace_cap > 0) lhat_trace[0] = NAN;
+  if (step_trace && trace_cap > 0) step_trace[0] = 0.0;
+  memcpy(yv, x, P8);
+  double L1 = L0, eta_prev = 0.0, tau_prev = 0.0, lhat_prev = 0.0;
+  int64_t t = 1, it = 0, restarts = 0, rejected = 0;
+  int status = ORC_MAXITER;
+  double rel = (UB - LB) / fmax(fabs(UB), 1e-300);
+  if (rel <= tol) status = ORC_CONVERGED;
+  while (status == ORC_MAXITER && it < max_iter) {
+    it++;
+    double eta_t, tau_t;
+    if (t == 1) {
+      eta_t = 1.0 / L1;
+      tau_t = 0.0;
+    } else {
+      tau_t = 0.5 * (double)t;
+      const double cap = (lhat_prev > 0.0) ? tau_prev / (4.0 * lhat_prev) : INFINITY;
+      if (t == 2) eta_t = fmin((1.0 - b) * eta_prev, (lhat_prev > 0.0) ? 1.0 / (4.0 * lhat_prev) : INFINITY);
+      else eta_t = fmin((tau_prev + 1.0) / tau_t * eta_prev, cap);
+    }
+    /* z_t = prox_{eta_t G}(y_{t-1} - eta_t grad f(x_{t-1})), G = 2 lambda2 g_N */
+    for (int64_t j = 0; j < p; j++) v[j] = yv[j] - eta_t * g[j];
+    orc_prox_g(v, st, p, 2.0 * lambda2 * eta_t, k, M, z);
+    for (int64_t j = 0; j < p; j++) {
+      yn[j] = (1.0 - b) * yv[j] + b * z[j];
+      xn[j] = (z[j] + tau_t * x[j]) / (1.0 + tau_t);
+    }
+    double Fn, Psin;
+    orc_eval_point(X, xdt, y, n, p, loss, lambda2, M, k, st, xn, u, zeta, gn, &Fn, &Psin);
+    const double Phin = orc_in_dom(xn, st, p, k, M, 1e-9) ? Fn + 2.0 * lambda2 * orc_g(xn, st, p, k) : INFINITY;
+    const double dx = orc_dist(xn, x, p);
+    const double lhat = dx > 0.0 ? orc_dist(gn, g, p) / dx : 0.0;
+    if (Psin > LB) {
+      LB = Psin;
+      memcpy(zeta_out, zeta, N8);
+    }
+    if (Phin < UB) {
+      UB = Phin;
+      memcpy(xbest, xn, P8);
+    }
+    const int reject = (t == 1 && lhat > L1);
+    if (it < trace_cap) {
+      if (trace) trace[it] = Phin - Psin;
+      if (phi_trace) phi_trace[it] = Phin;
+      if (lhat_trace) lhat_trace[it] = lhat;
+      if (step_trace) step_trace[it] = reject ? -(double)t : (double)t;
+    }
+    rel = (UB - LB) / fmax(fabs(UB), 1e-300);
+    if (rel <= tol) {
+      status = ORC_CONVERGED;
+      break;
+    }
+    if (reject) { /* line search of the first step: a larger curvature estimate */
+      L1 *= c;
+      rejected++;
+      continue;
+    }
+    memcpy(xo, x, P8);
+    memcpy(go, g, P8);
+    memcpy(x, xn, P8);
+    memcpy(g, gn, P8);
+    memcpy(yv, yn, P8);
+    eta_prev = eta_t;
+    tau_prev = tau_t;
+    lhat_prev = lhat;
+    t++;
+    if (restart_gap && Phin - Psin <= gap_ref / eta) {
+      gap_ref = Phin - Psin;
+      memcpy(yv, x, P8);
+      t = 1;
+      restarts++;
+    }
+  }
+  memcpy(beta_out, xbest, P8);
+  res[0] = LB;
+  res[1] = UB;
+  res[2] = (UB - LB) / fmax(fabs(UB), 1e-300);
+  res[3] = L1;
+  res[4] = (double)it;
+  res[5] = (double)restarts;
+  res[6] = (double)status;
+  res[7] = (double)rejected;
+  free(x); free(g); free(xo); free(go); free(yv); free(z); free(v); free(xn); free(gn); free(yn); free(xbest);
+  free(u); free(zeta);
+  return status;
+}
+
+/* ------------------------------------------------------------ LASSO */
+
+/* The duality-gap restart applied beyond the perspective relaxation
+ * (Section 5.2): least squares F(u) = ||u - y||^2 with
+ *   kind 0 (l1-regularised): G(beta) = lam ||beta||_1,
+ *   kind 1 (l1-ball):        G(beta) = indicator of ||beta||_1 <= lam.
+ * Conjugates: kind 0, G*(w) = indicator of ||w||_inf <= lam; kind 1,
+ * G*(w) = lam ||w||_inf.  Prox of t G: kind 0, soft thresholding at t lam;
+ * kind 1, Euclidean projection onto the l1-ball (sort-based: the threshold
+ * theta solves sum_j max(|v_j| - theta, 0) = lam). */
+double orc_lasso_G(int kind, const double *beta, int64_t p, double lam) {
+  double l1 = 0.0;
+  for (int64_t j = 0; j < p; j++) l1 += fabs(beta[j]);
+  if (kind == 0) return lam * l1;
+  return (l1 <= lam * (1.0 + 1e-9)) ? 0.0 : INFINITY;
+}
+
+double orc_lasso_Gstar(int kind, const double *w, int64_t p, double lam) {
+  double mx = 0.0;
+  for (int64_t j = 0; j < p; j++) mx = fmax(mx, fabs(w[j]));
+  if (kind == 0) return (mx <= lam) ? 0.0 : INFINITY;
+  return lam * mx;
+}
+
+void orc_lasso_prox(int kind, const double *v, int64_t p, double t, double lam, double *out) {
+  if (kind == 0) {
+    const double th = t * lam;
+    for (int64_t j = 0; j < p; j++) {
+      const double a = fabs(v[j]) - th;
+      out[j] = a > 0.0 ? copysign(a, v[j]) : 0.0;
+    }
+    return;
+  }
+  double l1 = 0.0;
+  for (int64_t j = 0; j < p; j++) l1 += fabs(v[j]);
+  if (l1 <= lam) {
+    memcpy(out, v, sizeof(double) * (size_t)p);
+    return;
+  }
+  double *a = (double *)malloc(sizeof(double) * (size_t)p);
+  for (int64_t j = 0; j < p; j++) a[j] = fabs(v[j]);
+  qsort(a, (size_t)p, sizeof(double), cmp_desc);
+  /* theta = (sum of the m largest - lam) / m for the largest m with
+     a_(m) > (sum of the m largest - lam) / m */
+  double cum = 0.0, theta = 0.0;
+  for (int64_t m = 1; m <= p; m++) {
+    cum += a[m - 1];
+    const double th = (cum - lam) / (double)m;
+    if (a[m - 1] > th) theta = th;
+  }
+  free(a);
+  for (int64_t j = 0; j < p; j++) {
+    const double r = fabs(v[j]) - theta;
+    out[j] = r > 0.0 ? copysign(r, v[j]) : 0.0;
+  }
+}
+
+/* Psi at a dual-feasible point built from zeta = -grad F(X beta) = 2 (y - X beta):
+ * kind 0 scales it into dom G*, s = min(1, lam / ||X^T zeta||_inf), Psi =
+ * -F*(-s zeta); kind 1 uses zeta itself, Psi = -F*(-zeta) - lam ||X^T zeta||_inf.
+ * *scale_out (optional) receives s (1 for kind 1). */
+double orc_lasso_dual(const void *X, int xdt, const double *y, int64_t n, int64_t p, int kind, double lam,
+                      const double *zeta, double *scale_out) {
+  double *w = (double *)malloc(sizeof(double) * (size_t)p);
+  orc_rmatvec(X, xdt, n, p, zeta, w);
+  double mx = 0.0;
+  for (int64_t j = 0; j < p; j++) mx = fmax(mx, fabs(w[j]));
+  free(w);
+  double zy = 0.0, zz = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    zy += zeta[i] * y[i];
+    zz += zeta[i] * zeta[i];
+  }
+  if (kind == 0) {
+    const double s = (mx > lam) ? lam / mx : 1.0;
+    if (scale_out) *scale_out = s;
+    return s * zy - 0.25 * s * s * zz;
+  }
+  if (scale_out) *scale_out = 1.0;
+  return zy - 0.25 * zz - lam * mx;
+}
+
+/* FISTA (fixed step 1/L) with the duality-gap restart on the LASSO problem of
+ * `kind`; the same loop as orc_solve with G and its prox replaced.
+ * res[0..7] = {LB, UB, rel_gap, L, iters, restarts, status, 0}; trace and
+ * phi_trace as orc_solve (method: ORC_FISTA_GAP or ORC_FISTA). */
+int orc_lasso_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int kind, double lam, double L,
+                    double tol, double eta, int64_t max_iter, int method, const double *beta0, double *beta_out,
+                    double *zeta_out, double *res, double *trace, double *phi_trace, int64_t trace_cap) {
+  for (int i = 0; i < 8; i++) res[i] = 0.0;
+  if (L <= 0.0) L = 2.0 * orc_power_norm2(X, xdt, n, p, 2000, 1e-12);
+  const size_t P8 = sizeof(double) * (size_t)p, N8 = sizeof(double) * (size_t)n;
+  double *x = (double *)calloc((size_t)p, sizeof(double));
+  double *xn = (double *)malloc(P8), *yv = (double *)malloc(P8), *gp = (double *)malloc(P8);
+  double *u = (double *)malloc(N8), *gn = (double *)malloc(N8), *zeta = (double *)malloc(N8);
+  double *xbest = (double *)malloc(P8);
+  if (beta0)
+    for (int64_t j = 0; j < p; j++) x[j] = beta0[j];
+  memcpy(yv, x, P8);
+  memcpy(xbest, x, P8);
+  double t = 1.0, s = 1.0;
+#define ORC_LEVAL(PHI, PSI)                                                      \
+  do {                                                                           \
+    orc_matvec(X, xdt, n, p, x, u);                                              \
+    for (int64_t i_ = 0; i_ < n; i_++) zeta[i_] = 2.0 * (y[i_] - u[i_]);         \
+    PSI = orc_lasso_dual(X, xdt, y, n, p, kind, lam, zeta, &s);                  \
+    PHI = orc_loss(ORC_LSQ, u, y, n) + orc_lasso_G(kind, x, p, lam);             \
+  } while (0)
+  double Phi, Psi;
+  ORC_LEVAL(Phi, Psi);
+  double LB = Psi, UB = Phi, gap_ref = Phi - Psi;
+  for (int64_t i = 0; i < n; i++) zeta_out[i] = s * zeta[i];
+  if (trace && trace_cap > 0) trace[0] = Phi - Psi;
+  if (phi_trace && trace_cap > 0) phi_trace[0] = Phi;
+  int64_t it = 0, restarts = 0;
+  int status = ORC_MAXITER;
+  double rel = (UB - LB) / fmax(fabs(UB), 1e-300);
+  if (rel <= tol) status = ORC_CONVERGED;
+  while (status == ORC_MAXITER && it < max_iter) {
+    it++;
+    orc_matvec(X, xdt, n, p, yv, u);
+    orc_loss_grad(ORC_LSQ, u, y, n, gn);
+    orc_rmatvec(X, xdt, n, p, gn, gp);
+    for (int64_t j = 0; j < p; j++) gp[j] = yv[j] - gp[j] / L;
+    orc_lasso_prox(kind, gp, p, 1.0 / L, lam, xn);
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    const double mom = (t - 1.0) / tn;
+    for (int64_t j = 0; j < p; j++) {
+      yv[j] = xn[j] + mom * (xn[j] - x[j]);
+      x[j] = xn[j];
+    }
+    t = tn;
+    ORC_LEVAL(Phi, Psi);
+    if (Psi > LB) {
+      LB = Psi;
+      for (int64_t i = 0; i < n; i++) zeta_out[i] = s * zeta[i];
+    }
+    if (Phi < UB) {
+      UB = Phi;
+      memcpy(xbest, x, P8);
+    }
+    const double gap = Phi - Psi;
+    if (trace && it < trace_cap) trace[it] = gap;
+    if (phi_trace && it < trace_cap) phi_trace[it] = Phi;
+    rel = (UB - LB) / fmax(fabs(UB), 1e-300);
+    if (rel <= tol) {
+      status = ORC_CONVERGED;
+      break;
+    }
+    if (method == ORC_FISTA_GAP && gap <= gap_ref / eta) {
+      gap_ref = gap;
+      memcpy(yv, x, P8);
+      t = 1.0;
+      restarts++;
+    }
+  }
+#undef ORC_LEVAL
+  memcpy(beta_out, xbest, P8);
+  res[0] = LB;
+  res[1] = UB;
+  res[2] = (UB - LB) / fmax(fabs(UB), 1e-300);
+  res[3] = L;
+  res[4] = (double)it;
+  res[5] = (double)restarts;
+  res[6] = (double)status;
+  free(x); free(xn); free(yv); free(gp); free(u); free(gn); free(zeta); free(xbest);
+  return status;
+}
+
 /* Number of OpenMP threads the matrix products use. */
 int orc_num_threads(void) {
   int nt = 1;
