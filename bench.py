@@ -33,7 +33,8 @@ these carries its own cpu_baseline (the oracle on the same instance).
   python bench.py --kernel-probe-logistic   # the same for the logistic X^T pass
   python bench.py --learned [--pairs N] [--epochs E]   # learned warm start experiment
   python bench.py --e1               # g_N and prox evaluation times at the paper's microbenchmark shapes
-  python bench.py --e3               # convergence of the iteration variants (gap restart vs others)
+  python bench.py --e3               # convergence of the iteration variants (gap restart vs others, AC-FGM)
+  python bench.py --lasso            # the gap restart on l1-regularised and l1-ball LASSO
   python bench.py --bnb              # branch and bound on the paper's synthetic setting
   python bench.py --paper-shapes     # root solve times at the paper's n = p = 1000 ... 16000 shapes
 """
@@ -520,7 +521,10 @@ def e3_bench(max_iter=20000):
                                 ("fista_gap_restart_e", pr.FISTA_GAP, math.e),
                                 ("fista_no_restart", pr.FISTA, math.exp(3.0)),
                                 ("fista_function_value_restart", pr.FISTA_FV, math.exp(3.0)),
-                                ("proximal_gradient", pr.PGD, math.exp(3.0))):
+                                ("proximal_gradient", pr.PGD, math.exp(3.0)),
+                                ("acfgm_gap_restart_e3", pr.ACFGM_GAP, math.exp(3.0)),
+                                ("acfgm_gap_restart_e", pr.ACFGM_GAP, math.e),
+                                ("acfgm_no_restart", pr.ACFGM, math.exp(3.0))):
             tr = torch.full((2 * (cap + 1),), float("nan"), dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -541,11 +545,65 @@ def e3_bench(max_iter=20000):
             k = k[k >= k.size // 5] if k.size > 10 else k
             slope = float(np.polyfit(k, np.log10(rel[k]), 1)[0]) if k.size > 2 else None
             res[name] = {"status": r["status"], "iters": r["iters"], "restarts": r["restarts"], "seconds": round(dt, 3),
+                         "us_per_iter": round(1e6 * dt / max(r["iters"], 1), 1), "linesearch_rejections": r["trials"],
                          "final_rel_gap": r["rel_gap"], "iterations_to_rel_gap": reach,
                          "log10_gap_per_iteration": None if slope is None else round(slope, 5)}
             print(json.dumps({"progress": "e3", "workload": wl, "variant": name, **res[name]}), flush=True)
         out["workloads"][wl] = {"cap": cap, "variants": res}
         ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def lasso_bench(max_iter=20000):
+    """The duality-gap restart on LASSO (least squares on the n = 16384,
+    p = 8192 FP32 design of the root workload): l1-regularised with lam = 0.05
+    of the smallest penalty that zeroes beta (2 ||X^T y||_inf), and l1-ball
+    with radius ||beta*||_1 = 20; FISTA with the gap restart at eta = e^3 and
+    eta = e, and FISTA without restart, each to a 1e-6 relative gap
+    (iterations, time, iterations to each gap level from the (Phi, Psi)
+    trace)."""
+    import math
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import config_instance
+    dev = torch.device("cuda:0")
+    inst = config_instance(WORKLOAD)
+    X = torch.from_numpy(inst.Xcm).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    ctx = pr.Context(X, y, pr.LSQ)
+    hmax = float(ctx.gemv_t(y).abs().max())
+    forms = (("l1_regularised", pr.L1_REG, 0.05 * 2.0 * hmax),
+             ("l1_ball", pr.L1_BALL, float(np.abs(inst.beta_true).sum())))
+    out = {"metric": "LASSO iterations and time to 1e-6 relative duality gap, gap restart vs none",
+           "workload": WORKLOAD, "n": inst.n, "p": inst.p, "x_storage": "f32", "forms": {}}
+    for fname, kind, lam in forms:
+        rows = {}
+        for name, meth, eta in (("fista_gap_restart_e3", pr.FISTA_GAP, math.exp(3.0)),
+                                ("fista_gap_restart_e", pr.FISTA_GAP, math.e),
+                                ("fista_no_restart", pr.FISTA, math.exp(3.0))):
+            ctx.lasso_solve(kind, lam, want_beta=False, max_iter=64, method=meth, eta=eta)   # graph capture
+            tr = torch.full((2 * (max_iter + 1),), float("nan"), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.lasso_solve(kind, lam, want_beta=False, max_iter=max_iter, method=meth, eta=eta, trace=tr)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t = tr.cpu().numpy().reshape(-1, 2)[: r["iters"] + 1]
+            ub = np.minimum.accumulate(t[:, 0])
+            lb = np.maximum.accumulate(t[:, 1])
+            rel = (ub - lb) / np.abs(ub)
+            reach = {}
+            for lvl in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+                hit = np.flatnonzero(rel <= lvl)
+                reach[f"{lvl:.0e}"] = int(hit[0]) if hit.size else None
+            rows[name] = {"status": r["status"], "iters": r["iters"], "restarts": r["restarts"],
+                          "seconds": round(dt, 4), "us_per_iter": round(1e6 * dt / max(r["iters"], 1), 1),
+                          "final_rel_gap": r["rel_gap"], "lower_bound": r["lower_bound"],
+                          "iterations_to_rel_gap": reach}
+            print(json.dumps({"progress": "lasso", "form": fname, "variant": name, **rows[name]}), flush=True)
+        out["forms"][fname] = {"lam": lam, "variants": rows}
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 
@@ -661,6 +719,7 @@ def main():
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
     ap.add_argument("--bnb", action="store_true", help="branch and bound on the paper's synthetic setting instead")
+    ap.add_argument("--lasso", action="store_true", help="the gap restart on LASSO instead")
     ap.add_argument("--paper-shapes", action="store_true", help="root solve times at the paper's table shapes instead")
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=4)
@@ -683,6 +742,9 @@ def main():
         return
     if args.e3:
         e3_bench()
+        return
+    if args.lasso:
+        lasso_bench()
         return
     if args.bnb:
         bnb_bench(loss=0)

@@ -84,12 +84,29 @@ typedef struct {
 /* Iteration variants (pr_opts.method), as compared in the paper's
  * convergence study (Section 5.2): FISTA with the duality-gap restart of
  * Section 3.3 (the method; default), FISTA without restarts, FISTA restarted
- * whenever Phi increases (function-value restart), proximal gradient.  All
- * evaluate the same bounds and stopping test. */
+ * whenever Phi increases (function-value restart), proximal gradient, and
+ * AC-FGM (the accelerated composite method of Li and Lan with its first-step
+ * line search, Section 3.3's rate table) with and without the duality-gap
+ * restart.  All evaluate the same bounds and stopping test.
+ *
+ * AC-FGM as implemented (this library's reading; the paper cites the method
+ * without restating it): z_t = prox_{eta_t G}(y_{t-1} - eta_t grad f(x_{t-1})),
+ * y_t = (1 - b) y_{t-1} + b z_t, x_t = (z_t + tau_t x_{t-1}) / (1 + tau_t),
+ * tau_1 = 0, tau_t = t / 2; with Lhat_t = ||grad f(x_t) - grad f(x_{t-1})|| /
+ * ||x_t - x_{t-1}||: eta_1 = 1 / L1, eta_2 = min((1 - b) eta_1, 1 / (4 Lhat_1)),
+ * eta_t = min((tau_{t-1} + 1) / tau_t eta_{t-1}, tau_{t-1} / (4 Lhat_{t-1}));
+ * the first step is retried with L1 <- c L1 while Lhat_1 > L1 (L1 starts at
+ * L0).  x_t is the primal iterate of the certificate.  A gap restart starts a
+ * new epoch at x_t (y = x_t, t = 1) keeping L1.  One X^T pass per
+ * evaluation (the gradient point is the certificate's point) for both
+ * losses, and a product over the support of z_t.  Every evaluated point,
+ * rejected trials included, counts in pr_result.iters. */
 #define PR_FISTA_GAP 0
 #define PR_FISTA 1
 #define PR_FISTA_FV 2
 #define PR_PGD 3
+#define PR_ACFGM_GAP 4
+#define PR_ACFGM 5
 
 typedef struct {
   double rel_gap_tol; /* stop when (UB - LB) / |UB| <= tol; default 1e-6 */
@@ -100,8 +117,11 @@ typedef struct {
   int32_t check_every; /* iterations per captured graph launch; default 32 */
   int32_t method;      /* iteration variant, PR_FISTA_GAP (default) .. PR_PGD */
   int32_t pad0;
-  double *trace;       /* pr_solve only, optional device array of 2 * (max_iter + 1)
-                          doubles: (Phi, Psi) of iterates 0, 1, ..., iters */
+  double *trace;       /* pr_solve / pr_lasso_solve only, optional device array of
+                          2 * (max_iter + 1) doubles: (Phi, Psi) of iterates 0, 1, ..., iters */
+  double acfgm_b;      /* AC-FGM averaging weight b in (0, 1 - sqrt(6)/3]; default 0.1 */
+  double acfgm_c;      /* AC-FGM line-search factor c > 1; default 2 */
+  double L0;           /* AC-FGM initial curvature estimate; 0 = the default L / 64 */
 } pr_opts;
 
 typedef struct {
@@ -112,7 +132,7 @@ typedef struct {
   int32_t iters;      /* proximal-gradient steps taken */
   int32_t restarts;   /* duality-gap restarts */
   int32_t status;     /* PR_CONVERGED ... PR_CUTOFF_BRANCH */
-  int32_t pad0;
+  int32_t trials;     /* AC-FGM: first-step trials rejected by the line search; else 0 */
 } pr_result;
 
 typedef struct pr_ctx pr_ctx;
@@ -167,6 +187,32 @@ int pr_ctx_enable_gram(pr_ctx *ctx);
  *   out      host. */
 int pr_solve(pr_ctx *ctx, const pr_node *node, const pr_opts *opts, const double *beta0,
              double *beta_out, double *zeta_out, pr_result *out);
+
+/* ---- The duality-gap restart beyond perspective relaxations: LASSO ------
+ * (Section 5.2.)  Least squares F(u) = ||u - y||^2 on the context's X and y
+ * with G = lam ||beta||_1 (PR_L1_REG) or G = the indicator of the l1-ball
+ * ||beta||_1 <= lam (PR_L1_BALL), solved by FISTA with step 1/L and the
+ * duality-gap restart of Section 3.3 (opts->method PR_FISTA_GAP, default) or
+ * without it (PR_FISTA).  Dual points from zeta = -grad F(X beta) =
+ * 2 (y - X beta): for PR_L1_REG zeta is scaled by s = min(1, lam /
+ * ||X^T zeta||_inf) into dom G* (G* = indicator of ||w||_inf <= lam) and
+ * Psi = s zeta^T y - s^2 ||zeta||^2 / 4; for PR_L1_BALL G*(w) = lam ||w||_inf
+ * and Psi = zeta^T y - ||zeta||^2 / 4 - lam ||X^T zeta||_inf.  Prox: soft
+ * thresholding at lam / L; Euclidean projection onto the l1-ball.
+ *   beta0 device p or NULL; beta_out device p or NULL (iterate attaining
+ *   primal); zeta_out device n or NULL (the scaled dual point attaining
+ *   lower_bound); out host.  PR_EINVAL for a logistic context, kind outside
+ *   the two forms, lam <= 0, or another method. */
+#define PR_L1_REG 0
+#define PR_L1_BALL 1
+typedef struct {
+  int32_t kind;  /* PR_L1_REG or PR_L1_BALL */
+  int32_t pad0;
+  double lam;    /* penalty weight, or the ball's radius */
+} pr_lasso;
+
+int pr_lasso_solve(pr_ctx *ctx, const pr_lasso *lasso, const pr_opts *opts, const double *beta0, double *beta_out,
+                   double *zeta_out, pr_result *out);
 
 /* prox_{rho g_N}(v) by the extended Moreau decomposition (eq. prox:gN) and
  * Algorithm 2, for the node given by `status` (device int8 p, PR_FREE /

@@ -17,7 +17,8 @@ PROX_NOALLOC_MAX_P = 1048576
 DEBUG_GRAM_RECHECK = 1
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
-FISTA_GAP, FISTA, FISTA_FV, PGD = 0, 1, 2, 3
+FISTA_GAP, FISTA, FISTA_FV, PGD, ACFGM_GAP, ACFGM = 0, 1, 2, 3, 4, 5
+L1_REG, L1_BALL = 0, 1
 BNB_OPTIMAL, BNB_NODE_LIMIT, BNB_TIME_LIMIT = 1, 2, 3
 LSQ, LOGISTIC = 0, 1
 F64, F32, BF16 = 0, 1, 2
@@ -25,7 +26,7 @@ F64, F32, BF16 = 0, 1, 2
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_solve_batch",
            "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
-           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_ctx_set_debug", "pr_strerror"]
+           "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_ctx_set_debug", "pr_lasso_solve", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
 
@@ -45,7 +46,12 @@ class PrOpts(ctypes.Structure):
     _fields_ = [("rel_gap_tol", ctypes.c_double), ("eta", ctypes.c_double),
                 ("cutoff", ctypes.c_double), ("L", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("pad0", ctypes.c_int32), ("trace", ctypes.c_void_p)]
+                ("method", ctypes.c_int32), ("pad0", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("acfgm_b", ctypes.c_double), ("acfgm_c", ctypes.c_double), ("L0", ctypes.c_double)]
+
+
+class PrLasso(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad0", ctypes.c_int32), ("lam", ctypes.c_double)]
 
 
 class PrBnbOpts(ctypes.Structure):
@@ -63,11 +69,11 @@ class PrBnbResult(ctypes.Structure):
 class PrResult(ctypes.Structure):
     _fields_ = [("lower_bound", ctypes.c_double), ("primal", ctypes.c_double),
                 ("rel_gap", ctypes.c_double), ("L", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("restarts", ctypes.c_int32), ("status", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+                ("restarts", ctypes.c_int32), ("status", ctypes.c_int32), ("trials", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(lower_bound=self.lower_bound, primal=self.primal, rel_gap=self.rel_gap, L=self.L,
-                    iters=self.iters, restarts=self.restarts, status=self.status)
+                    iters=self.iters, restarts=self.restarts, status=self.status, trials=self.trials)
 
 
 _lib = None
@@ -113,6 +119,9 @@ def load():
         L.pr_gemv_t.argtypes = [P, P, P]
         L.pr_time_gemv_t.restype = ctypes.c_int
         L.pr_time_gemv_t.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.pr_lasso_solve.restype = ctypes.c_int
+        L.pr_lasso_solve.argtypes = [P, ctypes.POINTER(PrLasso), ctypes.POINTER(PrOpts), P, P, P,
+                                     ctypes.POINTER(PrResult)]
         L.pr_solve_batch.restype = ctypes.c_int
         L.pr_solve_batch.argtypes = [P, ctypes.POINTER(PrNode), ctypes.c_int32, ctypes.POINTER(PrOpts),
                                      P, P, ctypes.POINTER(PrResult)]
@@ -292,6 +301,27 @@ class Context:
         nd = node.c()
         _check(load().pr_solve(self.h, ctypes.byref(nd), ctypes.byref(o), _dptr(beta0), _dptr(beta),
                                _dptr(zeta), ctypes.byref(res)), "pr_solve")
+        out = res.as_dict()
+        out["beta"] = beta
+        out["zeta"] = zeta
+        return out
+
+    def lasso_solve(self, kind, lam, beta0=None, want_beta=True, want_zeta=False, **opts):
+        """LASSO with the duality-gap restart (kind L1_REG: penalty lam; L1_BALL:
+        radius lam) on the context's least-squares problem."""
+        import torch
+        o = default_opts(**opts)
+        dev = self.X.device
+        beta = torch.empty(self.p, dtype=torch.float64, device=dev) if want_beta else None
+        zeta = torch.empty(self.n, dtype=torch.float64, device=dev) if want_zeta else None
+        if beta0 is not None:
+            beta0 = beta0.to(device=dev, dtype=torch.float64).contiguous()
+        lp = PrLasso()
+        lp.kind = int(kind)
+        lp.lam = float(lam)
+        res = PrResult()
+        _check(load().pr_lasso_solve(self.h, ctypes.byref(lp), ctypes.byref(o), _dptr(beta0), _dptr(beta),
+                                     _dptr(zeta), ctypes.byref(res)), "pr_lasso_solve")
         out = res.as_dict()
         out["beta"] = beta
         out["zeta"] = zeta

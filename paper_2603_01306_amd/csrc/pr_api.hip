@@ -117,6 +117,14 @@ struct pr_ctx {
   double gyy = 0.0;      // y^T y
   Problem PG{};          // G viewed as the "design" of the column-list GEMV (n = p, y = b)
   ProbBufs BG{};         // its partial sums; h goes to B.h1
+  // iteration variants (AC-FGM, LASSO; allocated on first use) and their graph
+  AcState *d_ac = nullptr;
+  AcBufs ab{};
+  LassoState *d_lx = nullptr;
+  hipGraphExec_t vgexec = nullptr;
+  int32_t vgraph_units = 0;
+  int32_t vgraph_kind = -1;   // 0 AC-FGM, 1 + LASSO kind
+  double vgraph_key[3] = {0.0, 0.0, 0.0};
   // learned warm start (allocated on first use)
   uint16_t *mF = nullptr;  // [p][8] features of one node
   float *mout = nullptr;   // [p] network outputs
@@ -147,6 +155,13 @@ void free_ctx(pr_ctx *c) {
   if (!c) return;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
+  if (c->vgexec) (void)hipGraphExecDestroy(c->vgexec);
+  {
+    void *vb[] = {c->d_ac, c->d_lx, c->ab.xb, c->ab.gb, c->ab.yb, c->ab.xc, c->ab.yc, c->ab.z, c->ab.sidx2,
+                  c->ab.sval2, c->ab.uz, c->ab.ucur};
+    for (void *b : vb)
+      if (b) (void)hipFree(b);
+  }
   if (c->cg_own && c->CG) (void)hipFree(c->CG);
   {
     void *ub[] = {c->d_umask, c->d_ulist, c->d_olist, c->d_ocnt, c->d_oidx, c->d_oval, c->BxU, c->GU, c->XrU,
@@ -221,7 +236,11 @@ namespace {
 int check_opts(const pr_opts *o) {
   if (!o) return PR_OK;
   if (!(o->rel_gap_tol >= 0.0) || !(o->eta > 1.0) || o->max_iter < 0 || o->check_every < 1 ||
-      !(o->L >= 0.0) || !isfinite(o->L) || o->method < kFistaGap || o->method > kPgd)
+      !(o->L >= 0.0) || !isfinite(o->L) || o->method < kFistaGap || o->method > kAcfgm)
+    return PR_EINVAL;
+  if (o->method >= kAcfgmGap &&
+      (!(o->acfgm_b > 0.0) || !(o->acfgm_b < 1.0) || !(o->acfgm_c > 1.0) || !isfinite(o->acfgm_c) ||
+       !(o->L0 >= 0.0) || !isfinite(o->L0)))
     return PR_EINVAL;
   return PR_OK;
 }
@@ -281,6 +300,102 @@ int ensure_graph(pr_ctx *c, int32_t units) {
   }
   c->graph_units = units;
   c->graph_gram = c->gram;
+  return PR_OK;
+}
+
+// Launch a captured iteration graph until the node state reports done (or
+// max_launches): two launches in flight, each followed by a copy of the node
+// state into its own pinned slot and an event.
+hipError_t run_graph(pr_ctx *c, hipGraphExec_t g, int64_t max_launches) {
+  auto issue = [&](int slot) -> hipError_t {
+    hipError_t e = hipGraphLaunch(g, c->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&c->h_state[slot], c->d_state, sizeof(NodeState), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(c->ev[slot], c->stream);
+  };
+  int64_t launched = 0;
+  hipError_t e = issue(0);
+  if (e != hipSuccess) return e;
+  launched++;
+  e = issue(1);
+  if (e != hipSuccess) return e;
+  launched++;
+  for (int64_t i = 0;; i++) {
+    const int slot = (int)(i & 1);
+    e = hipEventSynchronize(c->ev[slot]);
+    if (e != hipSuccess) return e;
+    if (c->h_state[slot].done) break;
+    if (launched >= max_launches) break;
+    e = issue(slot);
+    if (e != hipSuccess) return e;
+    launched++;
+  }
+  return hipStreamSynchronize(c->stream);
+}
+
+// Buffers of the iteration variants, allocated on first use.
+int ensure_variant_bufs(pr_ctx *c) {
+  if (c->d_ac) return PR_OK;
+  const int64_t n = c->P.n, p = c->P.p;
+  AcBufs &a = c->ab;
+  bool ok = dalloc(&c->d_lx, 1) == hipSuccess;
+  ok = ok && dalloc(&a.xb, p) == hipSuccess && dalloc(&a.gb, p) == hipSuccess && dalloc(&a.yb, p) == hipSuccess;
+  ok = ok && dalloc(&a.xc, p) == hipSuccess && dalloc(&a.yc, p) == hipSuccess && dalloc(&a.z, p) == hipSuccess;
+  ok = ok && dalloc(&a.sidx2, p) == hipSuccess && dalloc(&a.sval2, p) == hipSuccess;
+  ok = ok && dalloc(&a.uz, n) == hipSuccess && dalloc(&a.ucur, n) == hipSuccess;
+  ok = ok && dalloc(&c->d_ac, 1) == hipSuccess;  // last: marks the set complete
+  if (!ok) return PR_ENOMEM;
+  PR_TRY(hipMemsetAsync(a.ucur, 0, sizeof(double) * n, c->stream));
+  return PR_OK;
+}
+
+// One unit of an iteration variant: AC-FGM (kind 0) or LASSO (kind 1 + form).
+hipError_t enqueue_variant_unit(pr_ctx *c, hipStream_t s, int kind, const double *key) {
+  if (kind == 0) {
+    hipError_t e = launch_spfwd(c->P, c->B, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, kSpPlain, c->d_state,
+                                c->ab.uz, s);
+    if (e == hipSuccess) e = launch_ac_resid(c->P, c->B, c->ab.uz, c->ab.ucur, c->d_state, c->d_ac, s);
+    if (e == hipSuccess) e = launch_gemv_t(c->P, c->B.r, nullptr, c->B.h1, nullptr, &c->d_state->done, s);
+    if (e == hipSuccess)
+      e = launch_ac_step(c->d_prm, c->d_state, c->d_ac, c->ab, c->nb, c->B, key[0], key[1], (int32_t)key[2], s);
+    return e;
+  }
+  hipError_t e = launch_spfwd(c->P, c->B, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, kSpLsq, c->d_state, nullptr,
+                              s);
+  if (e == hipSuccess) e = launch_gemv_t(c->P, c->B.r, nullptr, c->B.h1, nullptr, &c->d_state->done, s);
+  if (e == hipSuccess) e = launch_lasso_step(c->d_prm, c->d_state, c->d_lx, c->nb, c->B, kind - 1, key[0], s);
+  return e;
+}
+
+// The captured graph of `units` variant iterations; the step parameters that
+// the kernels take as arguments are part of the cache key.
+int ensure_variant_graph(pr_ctx *c, int kind, const double *key, int32_t units) {
+  if (c->vgexec && c->vgraph_units == units && c->vgraph_kind == kind && c->vgraph_key[0] == key[0] &&
+      c->vgraph_key[1] == key[1] && c->vgraph_key[2] == key[2])
+    return PR_OK;
+  if (c->vgexec) {
+    (void)hipGraphExecDestroy(c->vgexec);
+    c->vgexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  PR_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < units && e == hipSuccess; i++) e = enqueue_variant_unit(c, c->cap, kind, key);
+  hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return PR_EDEVICE;
+  }
+  e = hipGraphInstantiate(&c->vgexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->vgexec = nullptr;
+    return PR_EDEVICE;
+  }
+  c->vgraph_units = units;
+  c->vgraph_kind = kind;
+  for (int i = 0; i < 3; i++) c->vgraph_key[i] = key[i];
   return PR_OK;
 }
 
@@ -761,6 +876,9 @@ void pr_opts_default(pr_opts *o) {
   o->method = PR_FISTA_GAP;
   o->pad0 = 0;
   o->trace = nullptr;
+  o->acfgm_b = 0.1;
+  o->acfgm_c = 2.0;
+  o->L0 = 0.0;
 }
 
 const char *pr_strerror(int code) {
@@ -934,6 +1052,90 @@ static int gram_certify(pr_ctx *c, const pr_node *node, const pr_opts *opts, con
   return PR_OK;
 }
 
+// AC-FGM on the node whose parameters are already on the device (pr_solve).
+static int solve_acfgm(pr_ctx *c, const pr_opts *opts, double L, const double *beta0, double *beta_out,
+                       double *zeta_out, pr_result *out) {
+  const int64_t n = c->P.n, p = c->P.p;
+  int rc = ensure_variant_bufs(c);
+  if (rc != PR_OK) return rc;
+  const double L0 = opts->L0 > 0.0 ? opts->L0 : L / 64.0;
+  PR_TRY(launch_ac_init(c->d_prm, c->d_state, c->d_ac, c->ab, c->nb, beta0, L0, c->stream));
+  const double key[3] = {opts->acfgm_b, opts->acfgm_c, opts->method == kAcfgmGap ? 1.0 : 0.0};
+  rc = ensure_variant_graph(c, 0, key, opts->check_every);
+  if (rc != PR_OK) return rc;
+  PR_TRY(run_graph(c, c->vgexec, (int64_t)opts->max_iter / opts->check_every + 3));
+  PR_TRY(launch_zbest_final(c->d_state, c->B, c->P.loss, n, c->stream));
+  NodeState hs;
+  AcState ha;
+  PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
+  PR_TRY(hipMemcpyAsync(&ha, c->d_ac, sizeof(ha), hipMemcpyDeviceToHost, c->stream));
+  if (beta_out)
+    PR_TRY(hipMemcpyAsync(beta_out, c->nb.xbest, sizeof(double) * p, hipMemcpyDeviceToDevice, c->stream));
+  if (zeta_out)
+    PR_TRY(hipMemcpyAsync(zeta_out, c->B.zbest, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  out->lower_bound = hs.lb;
+  out->primal = hs.ub;
+  out->rel_gap = hs.rel_gap;
+  out->L = ha.L1;
+  out->iters = hs.iter;
+  out->restarts = hs.restarts;
+  out->status = hs.done ? hs.status : PR_MAXITER;
+  out->trials = ha.rejected;
+  return PR_OK;
+}
+
+int pr_lasso_solve(pr_ctx *c, const pr_lasso *lp, const pr_opts *opts_in, const double *beta0, double *beta_out,
+                   double *zeta_out, pr_result *out) {
+  if (!c || !lp || !out) return PR_EINVAL;
+  pr_opts opts;
+  pr_opts_default(&opts);
+  if (opts_in) opts = *opts_in;
+  if (check_opts(&opts) != PR_OK) return PR_EINVAL;
+  if (c->P.loss != kLsq || (lp->kind != PR_L1_REG && lp->kind != PR_L1_BALL) || !(lp->lam > 0.0) ||
+      !isfinite(lp->lam) || (opts.method != kFistaGap && opts.method != kFista))
+    return PR_EINVAL;
+  const int64_t n = c->P.n, p = c->P.p;
+  int rc = ensure_variant_bufs(c);
+  if (rc != PR_OK) return rc;
+  memset(out, 0, sizeof(*out));
+  const double L = opts.L > 0.0 ? opts.L : 1.01 * curvature(kLsq) * c->norm2;
+  NodeParams prm{};
+  prm.st = c->d_status;
+  prm.p = p;
+  prm.loss = kLsq;
+  prm.eta = opts.eta;
+  prm.tol = opts.rel_gap_tol;
+  prm.cutoff = NAN;
+  prm.max_iter = opts.max_iter;
+  prm.method = opts.method;
+  prm.trace = opts.trace;
+  PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
+  PR_TRY(launch_lasso_init(c->d_state, c->d_lx, c->nb, beta0, p, lp->kind, lp->lam, L, c->stream));
+  const double key[3] = {lp->lam, 0.0, 0.0};
+  rc = ensure_variant_graph(c, 1 + lp->kind, key, opts.check_every);
+  if (rc != PR_OK) return rc;
+  PR_TRY(run_graph(c, c->vgexec, (int64_t)opts.max_iter / opts.check_every + 3));
+  PR_TRY(launch_zbest_final(c->d_state, c->B, kLsq, n, c->stream));
+  NodeState hs;
+  LassoState hl;
+  PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
+  PR_TRY(hipMemcpyAsync(&hl, c->d_lx, sizeof(hl), hipMemcpyDeviceToHost, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  if (beta_out)
+    PR_TRY(hipMemcpyAsync(beta_out, c->nb.xbest, sizeof(double) * p, hipMemcpyDeviceToDevice, c->stream));
+  if (zeta_out) PR_TRY(launch_scale_copy(c->B.zbest, zeta_out, hl.zscale_best, n, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  out->lower_bound = hs.lb;
+  out->primal = hs.ub;
+  out->rel_gap = hs.rel_gap;
+  out->L = L;
+  out->iters = hs.iter;
+  out->restarts = hs.restarts;
+  out->status = hs.done ? hs.status : PR_MAXITER;
+  return PR_OK;
+}
+
 int pr_ctx_enable_gram(pr_ctx *c) {
   if (!c) return PR_EINVAL;
   const int64_t n = c->P.n, p = c->P.p;
@@ -1033,33 +1235,11 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   PR_TRY(hipMemcpyAsync(c->d_stp, c->h_stp.data(), sizeof(uint32_t) * c->h_stp.size(), hipMemcpyHostToDevice,
                         c->stream));
   PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
+  if (opts.method >= kAcfgmGap) return solve_acfgm(c, &opts, L, beta0, beta_out, zeta_out, out);
   PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, p, c->stream));
   rc = ensure_graph(c, opts.check_every);
   if (rc != PR_OK) return rc;
-  // keep two graph launches in flight; each is followed by a copy of the
-  // node state into its own pinned slot and an event
-  auto issue = [&](int slot) -> hipError_t {
-    hipError_t e = hipGraphLaunch(c->gexec, c->stream);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(&c->h_state[slot], c->d_state, sizeof(NodeState), hipMemcpyDeviceToHost, c->stream);
-    if (e != hipSuccess) return e;
-    return hipEventRecord(c->ev[slot], c->stream);
-  };
-  const int64_t max_launches = (int64_t)opts.max_iter / opts.check_every + 3;
-  int64_t launched = 0;
-  PR_TRY(issue(0));
-  launched++;
-  PR_TRY(issue(1));
-  launched++;
-  for (int64_t i = 0;; i++) {
-    const int slot = (int)(i & 1);
-    PR_TRY(hipEventSynchronize(c->ev[slot]));
-    if (c->h_state[slot].done) break;
-    if (launched >= max_launches) break;
-    PR_TRY(issue(slot));
-    launched++;
-  }
-  PR_TRY(hipStreamSynchronize(c->stream));
+  PR_TRY(run_graph(c, c->gexec, (int64_t)opts.max_iter / opts.check_every + 3));
   NodeState hs;
   if (c->gram) {
     PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));

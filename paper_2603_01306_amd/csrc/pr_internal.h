@@ -27,7 +27,7 @@ enum : int32_t { kConverged = 1, kMaxIter = 2, kInfeasible = 3, kCutoffPrune = 4
 
 // Per-node constants, device resident (written by the host before a solve).
 // iteration variants (pr_opts.method)
-enum { kFistaGap = 0, kFista = 1, kFistaFv = 2, kPgd = 3 };
+enum { kFistaGap = 0, kFista = 1, kFistaFv = 2, kPgd = 3, kAcfgmGap = 4, kAcfgm = 5 };
 
 struct NodeParams {
   const int8_t *st;   // status, p entries
@@ -109,6 +109,29 @@ struct BatchBufs {
   int64_t stpw;
   const double *gb;     // Gram mode: b = X^T y (NULL: products over X); gyy = y^T y
   double gyy;
+};
+
+// AC-FGM state of a single-node solve (pr_variants.hip), device resident.
+struct AcState {
+  double L1;         // first-step curvature estimate (line search)
+  double gap_ref;    // gap at the start of the current epoch
+  double eta_cur, tau_cur;  // step size and tau that produced the point being evaluated
+  double eta_prev, tau_prev, lhat_prev;  // of the last accepted step
+  int32_t step;      // epoch step index t of the point being evaluated (0: the start point)
+  int32_t rejected;  // first-step trials rejected by the line search
+};
+// AC-FGM vectors: base (accepted) point x_b, its gradient g_b and prox centre
+// y_b; the evaluated point x_c with its y_c and z; the support list of x_c
+// (scratch of the Algorithm 1 evaluation); X z and X x_c (n).
+struct AcBufs {
+  double *xb, *gb, *yb, *xc, *yc, *z;
+  int32_t *sidx2;
+  double *sval2;
+  double *uz, *ucur;
+};
+// LASSO state beside NodeState: the scale s of the last dual point, of the best one.
+struct LassoState {
+  double zscale, zscale_best;
 };
 
 struct Problem {
@@ -236,5 +259,16 @@ hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const dou
 hipError_t launch_lanczos(double *w, double *v, double *vprev, const double *alpha, const double *beta_prev,
                           double *beta_out, int64_t p, hipStream_t s);
 hipError_t launch_iota(int32_t *idx, int64_t n, hipStream_t s);
+// iteration variants (pr_variants.hip)
+hipError_t launch_ac_init(const NodeParams *prm, NodeState *S, AcState *A, const AcBufs &ab, const NodeBufs &nb,
+                          const double *beta0, double L0, hipStream_t s);
+hipError_t launch_ac_resid(const Problem &P, const ProbBufs &B, const double *uz, double *ucur, const NodeState *S,
+                           const AcState *A, hipStream_t s);
+hipError_t launch_ac_step(const NodeParams *prm, NodeState *S, AcState *A, const AcBufs &ab, const NodeBufs &nb,
+                          const ProbBufs &B, double b, double c, int32_t restart_gap, hipStream_t s);
+hipError_t launch_lasso_init(NodeState *S, LassoState *LX, const NodeBufs &nb, const double *beta0, int64_t p,
+                             int32_t kind, double lam, double L, hipStream_t s);
+hipError_t launch_lasso_step(const NodeParams *prm, NodeState *S, LassoState *LX, const NodeBufs &nb,
+                             const ProbBufs &B, int32_t kind, double lam, hipStream_t s);
 
 }  // namespace pr

@@ -43,7 +43,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     import paper_2603_01306_amd._binding as b
     structs = {"pr_problem": b.PrProblem, "pr_node": b.PrNode, "pr_opts": b.PrOpts, "pr_result": b.PrResult,
-               "pr_bnb_opts": b.PrBnbOpts, "pr_bnb_result": b.PrBnbResult}
+               "pr_bnb_opts": b.PrBnbOpts, "pr_bnb_result": b.PrBnbResult, "pr_lasso": b.PrLasso}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pr.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
