@@ -148,6 +148,33 @@ def kernel_probe_logistic():
     ctx.close()
 
 
+def mlp_probe(rows=1 << 20, reps=10):
+    """The network's training kernel (forward + backward, pr_mlp_grad) on
+    `rows` random BF16 feature rows, reps HIP-event-timed launches, for
+    rocprofv3 counter runs."""
+    import torch
+    import paper_2603_01306_amd as pr
+    from paper_2603_01306_amd import learned
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(0)
+    F = torch.randn((rows, pr.MLP_NFEAT), generator=g, device=dev).to(torch.bfloat16)
+    T = torch.randn(rows, generator=g, device=dev, dtype=torch.float32)
+    params = learned.init_params(1, dev)
+    work = torch.empty(pr.mlp_workspace(rows), dtype=torch.float32, device=dev)
+    grad = torch.empty(pr.MLP_NPARAM + 1, dtype=torch.float32, device=dev)
+    pr.mlp_grad(params, F, T, work, grad)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pr.mlp_grad(params, F, T, work, grad)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flop = 6 * (8 * 64 + 64 * 64 + 64) * rows
+    print(json.dumps({"probe": "mlp_grad", "rows": rows, "ms": round(ms, 4), "rows_per_s": round(rows / ms * 1e3),
+                      "tflops_mfma_shaped": round(flop / (ms * 1e-3) / 1e12, 2)}), flush=True)
+
+
 def cpu_baseline(inst, cfg, gpu_iters_per_solve, budget_s=20.0):
     """The FP64 oracle (FISTA + gap restart, dense textbook products) on the
     host: time a bounded number of its iterations on the same instance and
@@ -447,8 +474,8 @@ def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
         bp.append(Bp)
     Bp = torch.cat(bp)
     ev = learned.evaluate(ctx, params, ch, Bp, rel_gap_tol=cfg["tol"])
-    arrays = {k: ev.pop(k) for k in ("iters_parent", "iters_learned", "choice", "gaps")}
-    ip, im = arrays["iters_parent"], arrays["iters_learned"]
+    arrays = {k: ev.pop(k) for k in ("iters_parent", "iters_prox_parent", "iters_learned", "choice", "gaps")}
+    ip, ia, im = arrays["iters_parent"], arrays["iters_prox_parent"], arrays["iters_learned"]
     out = {"metric": "learned warm start: iterations and time to 1e-6 FP64 gap vs parent warm start",
            "workload": BATCH_WORKLOAD, "n": inst.n, "p": inst.p, "k": cfg["k"], "lambda2": cfg["lambda2"],
            "pairs": n_pairs, "rows": n_pairs * inst.p, "generation_s": round(gen_s, 1),
@@ -459,7 +486,10 @@ def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
            "grad_tflops_mfma_shaped": round(flop_row * batch_rows / (grad_ms * 1e-3) / 1e12, 2),
            "eval": ev,
            "eval_iters_saved_fraction": round(float(1.0 - im.sum() / max(ip.sum(), 1)), 4),
-           "eval_children_fewer_iters": int((im < ip).sum()), "eval_children_more_iters": int((im > ip).sum())}
+           "eval_iters_saved_vs_prox_parent": round(float(1.0 - im.sum() / max(ia.sum(), 1)), 4),
+           "eval_children_fewer_iters": int((im < ip).sum()), "eval_children_more_iters": int((im > ip).sum()),
+           "eval_children_fewer_iters_than_prox_parent": int((im < ia).sum()),
+           "eval_children_more_iters_than_prox_parent": int((im > ia).sum())}
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -709,6 +739,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kernel-probe", action="store_true")
     ap.add_argument("--kernel-probe-logistic", action="store_true")
+    ap.add_argument("--mlp-probe", action="store_true", help="time the network's training kernel, for counter runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
     ap.add_argument("--gram-steps", type=int, default=10, help="timed root solves in Gram mode (0 skips them)")
@@ -733,6 +764,9 @@ def main():
         return
     if args.kernel_probe_logistic:
         kernel_probe_logistic()
+        return
+    if args.mlp_probe:
+        mlp_probe()
         return
     if args.learned:
         learned_bench(args.pairs, args.epochs)
