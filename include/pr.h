@@ -434,14 +434,19 @@ int pr_mlp_grad(void *stream, const float *params, const uint16_t *F, const floa
 int pr_mlp_adam(void *stream, float *params, const float *grad, float *m1, float *m2, int32_t step, double lr,
                 double beta1, double beta2, double eps);
 
-/* Starting points for m child nodes.  For node i the candidate is
- * prox_{rho g_N}(beta_parent + network output) with rho = 2 lambda2 / L (the
- * solver's default step); B0 row i (device, m x p FP64) receives the candidate
- * if its FP64 duality gap Phi(x) - Psi(zeta(x)) on the child is smaller than
- * that of the parent solution, else the parent solution.  choice (host, m,
- * optional): 1 where the candidate was kept.  gaps (host, 2m, optional):
- * {parent gap, candidate gap} per node (+inf outside the domain or for an
- * infeasible node).  Synchronises the context stream. */
+/* Starting points for m child nodes, judged by the FP64 duality gap
+ * Phi(x) - Psi(zeta(x)) on the child (+inf outside the domain): B0 row i
+ * (device, m x p FP64) receives whichever of these has the smallest gap:
+ *   0  the parent solution beta_parent (row i of Bparent),
+ *   1  prox_{rho g_N}(beta_parent), rho = 2 lambda2 / L (the solver's default
+ *      step): the judged start without the network,
+ *   2  prox_{rho g_N}(beta_parent + network output) (only with params).
+ * choice (host, m, optional) receives that index; gaps (host, 3m, optional)
+ * the three gaps per node in that order (+inf for a candidate not built or an
+ * infeasible node, which keeps its parent).  On a context with the batched
+ * path and m <= max_batch all children are evaluated together (gaps from the
+ * batch's FP64 products over the stored X); otherwise one at a time.
+ * Synchronises the context stream. */
 int pr_mlp_warm_start(pr_ctx *ctx, const pr_node *nodes, int32_t m, const float *params, const double *Bparent,
                       double *B0, int32_t *choice, double *gaps);
 

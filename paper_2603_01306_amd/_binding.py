@@ -408,7 +408,9 @@ class Context:
 
     def mlp_warm_start(self, nodes, params, Bparent):
         """(B0, choice, gaps): starting points for child nodes, the FP64 gap
-        deciding between the network's candidate and the parent solution."""
+        deciding between the parent solution (choice 0), prox(beta_parent)
+        (1) and, with params, the network's candidate (2); gaps (m, 3) in that
+        order."""
         import torch
         m = len(nodes)
         dev = self.X.device
@@ -416,10 +418,10 @@ class Context:
         Bparent = Bparent.to(device=dev, dtype=torch.float64).contiguous()
         B0 = torch.empty_like(Bparent)
         choice = (ctypes.c_int32 * max(m, 1))()
-        gaps = (ctypes.c_double * max(2 * m, 1))()
-        _check(load().pr_mlp_warm_start(self.h, arr, m, _dptr(params.contiguous()), _dptr(Bparent), _dptr(B0),
-                                        choice, gaps), "pr_mlp_warm_start")
-        return B0, np.array(choice[:m], dtype=np.int32), np.array(gaps[:2 * m]).reshape(m, 2)
+        gaps = (ctypes.c_double * max(3 * m, 1))()
+        _check(load().pr_mlp_warm_start(self.h, arr, m, _dptr(None if params is None else params.contiguous()),
+                                        _dptr(Bparent), _dptr(B0), choice, gaps), "pr_mlp_warm_start")
+        return B0, np.array(choice[:m], dtype=np.int32), np.array(gaps[:3 * m]).reshape(m, 3)
 
     def dual_bound(self, node, zeta=None, beta=None):
         lb = ctypes.c_double()

@@ -131,6 +131,11 @@ struct pr_ctx {
   double *mnz = nullptr;   // [p] compacted nonzero magnitudes
   double *mfs = nullptr;   // {max |w|, nnz}
   double *mvhat = nullptr, *mx = nullptr;  // [p] proposal before / after the prox step
+  // batched warm start: proposals, w = X^T zeta at the parents [max_batch padded][p],
+  // feature rows [..][p][8], network outputs [..][p]
+  double *mVb = nullptr, *mWb = nullptr, *mPb = nullptr;  // mPb: prox(beta_parent) rows
+  uint16_t *mFb = nullptr;
+  float *moutb = nullptr;
 };
 
 namespace {
@@ -170,7 +175,7 @@ void free_ctx(pr_ctx *c) {
       if (b) (void)hipFree(b);
   }
   void *bb[] = {c->bstp, c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
-                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb};
+                c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb, c->mVb, c->mWb, c->mFb, c->moutb, c->mPb};
   for (void *b : bb)
     if (b) (void)hipFree(b);
   if (c->h_bstate) (void)hipHostFree(c->h_bstate);
@@ -827,7 +832,7 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
 // GEMMs (split as the iteration splits them), residual rows and loss sums,
 // then one workgroup per node for g_N(x) and g_N*(X^T zeta / (2 lambda2)).
 // lb[q] = Psi(zeta_q) with zeta_q = 2 (y - X x_q), ub[q] = Phi(x_q).
-int certify_batch(pr_ctx *c, int32_t m, std::vector<double> &lb, std::vector<double> &ub) {
+int certify_batch(pr_ctx *c, int32_t m, std::vector<double> &lb, std::vector<double> &ub, int32_t *kst_out = nullptr) {
   const int64_t n = c->P.n, p = c->P.p;
   const int NrMax = nr_of(c->max_batch), Nr = nr_of(m);
   hipStream_t s = c->stream;
@@ -849,6 +854,7 @@ int certify_batch(pr_ctx *c, int32_t m, std::vector<double> &lb, std::vector<dou
                          nullptr, kst, nullptr, s));
   PR_TRY(launch_cert_batch(c->d_bprm, c->bxbest, c->CT, kst, Nr, c->fsum, c->nfb, p, c->cert_a, c->bsidx, c->bsval,
                            c->d_cert, m, s));
+  if (kst_out) *kst_out = kst;
   std::vector<double> h((size_t)2 * m);
   PR_TRY(hipMemcpyAsync(h.data(), c->d_cert, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s));
   PR_TRY(hipStreamSynchronize(s));
@@ -1599,52 +1605,163 @@ int pr_mlp_adam(void *stream, float *params, const float *grad, float *m1, float
   return PR_OK;
 }
 
+static int stage_batch_nodes(pr_ctx *c, const pr_node *nodes, const std::vector<int32_t> &slot_of,
+                             const std::vector<std::vector<int8_t>> &sts, const std::vector<int32_t> &kbars,
+                             const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0);
+
+// Batched starting points (batched path: BF16 least squares, m <= max_batch):
+// the parents' certificates and w = X^T zeta at every parent from one pass of
+// the batch's two GEMMs; the proximal steps of all children in one launch
+// and their certificates from a second pass; with a network, the feature rows
+// and outputs of all children in one launch each, the proximal steps of the
+// proposals in one launch and their certificates from a third pass.
+static int warm_start_batched(pr_ctx *c, const pr_node *nodes, int32_t m, const float *params, const double *Bparent,
+                              double *B0, const std::vector<std::vector<int8_t>> &sts,
+                              const std::vector<int32_t> &kbars, const std::vector<int64_t> &pbars,
+                              const std::vector<char> &infeas, int32_t *choice, double *gaps) {
+  const int64_t p = c->P.p;
+  hipStream_t s = c->stream;
+  std::vector<int32_t> slot_of;
+  for (int32_t i = 0; i < m; i++)
+    if (!infeas[(size_t)i]) slot_of.push_back(i);
+  const int32_t mb = (int32_t)slot_of.size();
+  for (int32_t i = 0; i < m; i++) {
+    if (!infeas[(size_t)i]) continue;
+    PR_TRY(hipMemcpyAsync(B0 + (int64_t)i * p, Bparent + (int64_t)i * p, sizeof(double) * p, hipMemcpyDeviceToDevice,
+                          s));
+    if (choice) choice[i] = 0;
+    if (gaps) gaps[3 * i] = gaps[3 * i + 1] = gaps[3 * i + 2] = INFINITY;
+  }
+  if (mb == 0) {
+    PR_TRY(hipStreamSynchronize(s));
+    return PR_OK;
+  }
+  const int NrMax = nr_of(c->max_batch);
+  if (!c->mVb) {
+    bool ok = dalloc(&c->mVb, (size_t)NrMax * p) == hipSuccess && dalloc(&c->mWb, (size_t)NrMax * p) == hipSuccess;
+    ok = ok && dalloc(&c->mFb, (size_t)NrMax * p * 8) == hipSuccess && dalloc(&c->moutb, (size_t)NrMax * p) == hipSuccess;
+    ok = ok && dalloc(&c->mPb, (size_t)NrMax * p) == hipSuccess;
+    if (!ok) return PR_ENOMEM;
+  }
+  pr_opts o;
+  pr_opts_default(&o);
+  int rc = stage_batch_nodes(c, nodes, slot_of, sts, kbars, pbars, o, Bparent);  // parents -> bxbest
+  if (rc != PR_OK) return rc;
+  std::vector<double> lbP, ubP, lbA, ubA, lbN, ubN;
+  int32_t kst = 1;
+  rc = certify_batch(c, mb, lbP, ubP, &kst);  // leaves X^T r of every parent in CT's split planes
+  if (rc != PR_OK) return rc;
+  const int Nr = nr_of(mb);
+  const double L = 1.01 * curvature(c->P.loss) * c->norm2;
+  PR_TRY(hipMemcpyAsync(c->mVb, c->bxbest, sizeof(double) * mb * p, hipMemcpyDeviceToDevice, s));  // parents
+  if (params) PR_TRY(launch_sum_planes(c->CT, kst, Nr, p, mb, 2.0, c->mWb, s));  // w = X^T zeta (least squares)
+  // prox(beta_parent) of every child, then its certificate
+  PR_TRY(launch_prox_batch(c->d_bprm, c->mVb, c->bxbest, c->cert_a, p, mb, 1.0 / L, s));
+  rc = certify_batch(c, mb, lbA, ubA);
+  if (rc != PR_OK) return rc;
+  PR_TRY(hipMemcpyAsync(c->mPb, c->bxbest, sizeof(double) * mb * p, hipMemcpyDeviceToDevice, s));
+  if (params) {
+    for (int32_t q = 0; q < mb; q++) {
+      const int32_t i = slot_of[(size_t)q];
+      PR_TRY(launch_features(c->mVb + (int64_t)q * p, c->mWb + (int64_t)q * p, c->bstatus + (int64_t)q * p, p,
+                             c->mnz, c->mfs, feat_scalars(&nodes[i], sts[(size_t)i], kbars[(size_t)i]), nullptr,
+                             c->mFb + (int64_t)q * p * 8, nullptr, s));
+    }
+    PR_TRY(launch_mlp_forward(params, c->mFb, (int64_t)mb * p, c->moutb, s));
+    PR_TRY(launch_mlp_propose(c->mVb, c->moutb, (int64_t)mb * p, c->mVb, s));
+    PR_TRY(launch_prox_batch(c->d_bprm, c->mVb, c->bxbest, c->cert_a, p, mb, 1.0 / L, s));
+    rc = certify_batch(c, mb, lbN, ubN);
+    if (rc != PR_OK) return rc;
+  }
+  for (int32_t q = 0; q < mb; q++) {
+    const int32_t i = slot_of[(size_t)q];
+    const double gp = ubP[(size_t)q] - lbP[(size_t)q], ga = ubA[(size_t)q] - lbA[(size_t)q];
+    const double gn = params ? ubN[(size_t)q] - lbN[(size_t)q] : INFINITY;
+    int use = 0;
+    double best = gp;
+    if (ga < best) {
+      use = 1;
+      best = ga;
+    }
+    if (gn < best) use = 2;
+    const double *src = use == 0 ? Bparent + (int64_t)i * p
+                                 : (use == 1 ? c->mPb + (int64_t)q * p : c->bxbest + (int64_t)q * p);
+    PR_TRY(hipMemcpyAsync(B0 + (int64_t)i * p, src, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    if (choice) choice[i] = use;
+    if (gaps) {
+      gaps[3 * i] = gp;
+      gaps[3 * i + 1] = ga;
+      gaps[3 * i + 2] = gn;
+    }
+  }
+  PR_TRY(hipStreamSynchronize(s));
+  return PR_OK;
+}
+
 int pr_mlp_warm_start(pr_ctx *c, const pr_node *nodes, int32_t m, const float *params, const double *Bparent,
                       double *B0, int32_t *choice, double *gaps) {
-  if (!c || !nodes || m < 0 || !params || !Bparent || !B0) return PR_EINVAL;
+  if (!c || !nodes || m < 0 || !Bparent || !B0) return PR_EINVAL;
   const int64_t p = c->P.p;
   std::vector<std::vector<int8_t>> sts((size_t)m);
   std::vector<int32_t> kbars((size_t)m);
+  std::vector<int64_t> pbars((size_t)m);
   std::vector<char> infeas((size_t)m);
   for (int32_t i = 0; i < m; i++) {
-    int64_t n1, pbar;
+    int64_t n1;
     bool inf;
-    int rc = build_status(&nodes[i], p, sts[(size_t)i], n1, pbar, kbars[(size_t)i], inf);
+    int rc = build_status(&nodes[i], p, sts[(size_t)i], n1, pbars[(size_t)i], kbars[(size_t)i], inf);
     if (rc != PR_OK) return rc;
     infeas[(size_t)i] = inf;
   }
   int rc = ensure_mlp(c);
   if (rc != PR_OK) return rc;
+  if (m == 0) return PR_OK;
+  if (c->batch_ok && m <= c->max_batch)
+    return warm_start_batched(c, nodes, m, params, Bparent, B0, sts, kbars, pbars, infeas, choice, gaps);
   hipStream_t s = c->stream;
   const double L = 1.01 * curvature(c->P.loss) * c->norm2;
   for (int32_t i = 0; i < m; i++) {
     const double *bp = Bparent + (int64_t)i * p;
     double *x0 = B0 + (int64_t)i * p;
-    double gp = INFINITY, gm = INFINITY;
+    double gp = INFINITY, ga = INFINITY, gn = INFINITY;
     int use = 0;
     if (!infeas[(size_t)i]) {
       double lb, ub;
       rc = pr_dual_bound(c, &nodes[i], nullptr, bp, &lb, &ub);  // leaves d_status and d_w = X^T zeta(beta)
       if (rc != PR_OK) return rc;
       gp = ub - lb;
-      PR_TRY(launch_features(bp, c->d_w, c->d_status, p, c->mnz, c->mfs,
-                             feat_scalars(&nodes[i], sts[(size_t)i], kbars[(size_t)i]), nullptr, c->mF, nullptr,
-                             s));
-      PR_TRY(launch_mlp_forward(params, c->mF, p, c->mout, s));
-      PR_TRY(launch_mlp_propose(bp, c->mout, p, c->mvhat, s));
       const double rho = 2.0 * nodes[i].lambda2 / L;
-      PR_TRY(launch_prox(c->mvhat, c->mx, p, rho, kbars[(size_t)i], nodes[i].M, c->d_status, c->d_regscratch,
-                         nullptr, s));
+      if (params) {  // the network's proposal first: d_w still holds X^T zeta at the parent
+        PR_TRY(launch_features(bp, c->d_w, c->d_status, p, c->mnz, c->mfs,
+                               feat_scalars(&nodes[i], sts[(size_t)i], kbars[(size_t)i]), nullptr, c->mF, nullptr,
+                               s));
+        PR_TRY(launch_mlp_forward(params, c->mF, p, c->mout, s));
+        PR_TRY(launch_mlp_propose(bp, c->mout, p, c->mvhat, s));
+        PR_TRY(launch_prox(c->mvhat, c->mvhat, p, rho, kbars[(size_t)i], nodes[i].M, c->d_status, c->d_regscratch,
+                           nullptr, s));
+        rc = pr_dual_bound(c, &nodes[i], nullptr, c->mvhat, &lb, &ub);
+        if (rc != PR_OK) return rc;
+        gn = ub - lb;
+      }
+      PR_TRY(launch_prox(bp, c->mx, p, rho, kbars[(size_t)i], nodes[i].M, c->d_status, c->d_regscratch, nullptr,
+                         s));
       rc = pr_dual_bound(c, &nodes[i], nullptr, c->mx, &lb, &ub);
       if (rc != PR_OK) return rc;
-      gm = ub - lb;
-      use = gm < gp;
+      ga = ub - lb;
+      double best = gp;
+      if (ga < best) {
+        use = 1;
+        best = ga;
+      }
+      if (gn < best) use = 2;
     }
-    PR_TRY(hipMemcpyAsync(x0, use ? c->mx : bp, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    const double *src = use == 0 ? bp : (use == 1 ? c->mx : c->mvhat);
+    PR_TRY(hipMemcpyAsync(x0, src, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     if (choice) choice[i] = use;
     if (gaps) {
-      gaps[2 * i] = gp;
-      gaps[2 * i + 1] = gm;
+      gaps[3 * i] = gp;
+      gaps[3 * i + 1] = ga;
+      gaps[3 * i + 2] = gn;
     }
   }
   PR_TRY(hipStreamSynchronize(s));
@@ -1688,6 +1805,53 @@ int pr_dual_bound(pr_ctx *c, const pr_node *node, const double *zeta, const doub
   PR_TRY(hipStreamSynchronize(s));
   *lb_out = hs[1] - 2.0 * lam2 * hs[3];
   if (primal_out) *primal_out = beta ? hs[0] + 2.0 * lam2 * hs[2] : NAN;
+  return PR_OK;
+}
+
+// Node parameters, status vectors (plain and packed) of the batch slots
+// q -> node slot_of[q] on the device; with B0 each slot's starting row is
+// copied into the batch's best-iterate rows.
+static int stage_batch_nodes(pr_ctx *c, const pr_node *nodes, const std::vector<int32_t> &slot_of,
+                             const std::vector<std::vector<int8_t>> &sts, const std::vector<int32_t> &kbars,
+                             const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0) {
+  const int64_t p = c->P.p;
+  const int32_t mb = (int32_t)slot_of.size();
+  hipStream_t s = c->stream;
+  std::vector<NodeParams> prm((size_t)mb);
+  for (int32_t q = 0; q < mb; q++) {
+    const int32_t i = slot_of[(size_t)q];
+    NodeParams &pp = prm[(size_t)q];
+    pp.st = c->bstatus + (int64_t)q * p;
+    pp.p = p;
+    pp.pbar = pbars[(size_t)i];
+    pp.kbar = kbars[(size_t)i];
+    pp.loss = c->P.loss;
+    pp.lambda2 = nodes[i].lambda2;
+    pp.M = nodes[i].M;
+    pp.eta = opts.eta;
+    pp.tol = opts.rel_gap_tol;
+    pp.cutoff = opts.cutoff;
+    pp.max_iter = opts.max_iter;
+    pp.method = opts.method;
+    pp.trace = nullptr;
+    pp.gram_b = c->gram ? c->gb : nullptr;
+    pp.gram_yy = c->gyy;
+    PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
+    if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
+                                  hipMemcpyDeviceToDevice, s));
+  }
+  {
+    const size_t W = c->h_stp.size();
+    c->h_bstp.assign((size_t)mb * W, 0u);
+    std::vector<uint32_t> w(W);
+    for (int32_t q = 0; q < mb; q++) {
+      pack_status(sts[(size_t)slot_of[(size_t)q]], w);
+      std::copy(w.begin(), w.end(), c->h_bstp.begin() + (size_t)q * W);
+    }
+    PR_TRY(hipMemcpyAsync(c->bstp, c->h_bstp.data(), sizeof(uint32_t) * c->h_bstp.size(), hipMemcpyHostToDevice,
+                          s));
+  }
+  PR_TRY(hipMemcpyAsync(c->d_bprm, prm.data(), sizeof(NodeParams) * mb, hipMemcpyHostToDevice, s));
   return PR_OK;
 }
 
@@ -1739,41 +1903,8 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     return PR_OK;
   }
   const double L = opts.L > 0.0 ? opts.L : 1.01 * curvature(c->P.loss) * c->norm2;
-  std::vector<NodeParams> prm((size_t)mb);
-  for (int32_t q = 0; q < mb; q++) {
-    const int32_t i = slot_of[(size_t)q];
-    NodeParams &pp = prm[(size_t)q];
-    pp.st = c->bstatus + (int64_t)q * p;
-    pp.p = p;
-    pp.pbar = pbars[(size_t)i];
-    pp.kbar = kbars[(size_t)i];
-    pp.loss = c->P.loss;
-    pp.lambda2 = nodes[i].lambda2;
-    pp.M = nodes[i].M;
-    pp.eta = opts.eta;
-    pp.tol = opts.rel_gap_tol;
-    pp.cutoff = opts.cutoff;
-    pp.max_iter = opts.max_iter;
-    pp.method = opts.method;
-    pp.trace = nullptr;
-    pp.gram_b = c->gram ? c->gb : nullptr;
-    pp.gram_yy = c->gyy;
-    PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
-    if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
-                                  hipMemcpyDeviceToDevice, s));
-  }
-  {
-    const size_t W = c->h_stp.size();
-    c->h_bstp.assign((size_t)mb * W, 0u);
-    std::vector<uint32_t> w(W);
-    for (int32_t q = 0; q < mb; q++) {
-      pack_status(sts[(size_t)slot_of[(size_t)q]], w);
-      std::copy(w.begin(), w.end(), c->h_bstp.begin() + (size_t)q * W);
-    }
-    PR_TRY(hipMemcpyAsync(c->bstp, c->h_bstp.data(), sizeof(uint32_t) * c->h_bstp.size(), hipMemcpyHostToDevice,
-                          s));
-  }
-  PR_TRY(hipMemcpyAsync(c->d_bprm, prm.data(), sizeof(NodeParams) * mb, hipMemcpyHostToDevice, s));
+  int rcs = stage_batch_nodes(c, nodes, slot_of, sts, kbars, pbars, opts, B0);
+  if (rcs != PR_OK) return rcs;
   int32_t act = mb;
   PR_TRY(hipMemcpyAsync(c->d_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
   BatchBufs bb = batch_bufs(c, mb);

@@ -247,6 +247,20 @@ __device__ __forceinline__ void gemm_tile_f64_lds(const double *__restrict__ A, 
   }
 }
 
+// W[q][j] = scale * sum over the KS split planes of C[z][q][j] (rows q < m of
+// a batched product written as [KS][Nr][p] partial planes), planes summed in
+// order.
+__global__ void k_sum_planes(const double *__restrict__ C, int KS, int Nr, int64_t p, int m, double scale,
+                             double *__restrict__ W) {
+  const int64_t total = (int64_t)m * p;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = t / p, j = t - q * p;
+    double acc = 0.0;
+    for (int z = 0; z < KS; z++) acc += C[((int64_t)z * Nr + q) * p + j];
+    W[t] = scale * acc;
+  }
+}
+
 // Persistent launch: the grid (at most two workgroups per CU) walks the tile
 // list.  Row compaction: with rowmap != NULL only the first *nrow rows are
 // computed, local row l reading B row rowmap[l] and writing C row rowmap[l],
@@ -632,6 +646,14 @@ hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, in
                               double *R, double *fsum, const NodeState *S, hipStream_t s) {
   dim3 grid((unsigned)batch_resid_blocks(n), (unsigned)m);
   k_batch_resid<<<grid, 256, 0, s>>>(U, ksp, n, Nr, y, R, fsum, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_planes(const double *C, int KS, int Nr, int64_t p, int m, double scale, double *W,
+                             hipStream_t s) {
+  const int64_t total = (int64_t)m * p;
+  const int64_t blocks = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
+  k_sum_planes<<<(unsigned)blocks, 256, 0, s>>>(C, KS, Nr, p, m, scale, W);
   return hipGetLastError();
 }
 

@@ -213,6 +213,12 @@ hipError_t launch_union_fix_bf16(const uint16_t *X, int64_t n, int64_t p, const 
                                  int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
                                  const int32_t *active, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
+// W[q][j] = scale * sum_z C[z][q][j] for q < m (C: [KS][Nr][p] split planes)
+hipError_t launch_sum_planes(const double *C, int KS, int Nr, int64_t p, int m, double scale, double *W,
+                             hipStream_t s);
+// prox of g_N for m nodes (params prm[q], rho_q = 2 lambda2_q invL), rows of V -> Xo; abuf m x p scratch
+hipError_t launch_prox_batch(const NodeParams *prm, const double *V, double *Xo, double *abuf, int64_t p, int m,
+                             double invL, hipStream_t s);
 // batched-GEMM autotuner: split factors per count of active 64-row tiles,
 // one table per product (forward, X^T R, Gram)
 constexpr int kTuneMax = 64;            // table entries (row-tile counts 1 .. 63)

@@ -28,10 +28,8 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ unsigned short f2bf(float f) {
-  const unsigned int u = __float_as_uint(f);
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+// FP32 -> BF16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ __forceinline__ bf16x8_t as_bf(u16x8_t u) { return __builtin_bit_cast(bf16x8_t, u); }
 __device__ __forceinline__ f32x16_t mma(bf16x8_t a, bf16x8_t b, f32x16_t c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -40,21 +38,22 @@ __device__ __forceinline__ f32x16_t mma(bf16x8_t a, bf16x8_t b, f32x16_t c) {
 __device__ __forceinline__ int crow(int v, int hh) { return 8 * (v >> 2) + 4 * hh + (v & 3); }
 
 // B operand of the next product from a C-layout tile: units 16*S .. 16*S+15
-// of the tile as the reduction index, the lane's row as the column.
+// of the tile as the reduction index, the lane's row as the column.  Lane
+// l < 32 holds units 16S + 0..3 (registers 8S + i) and 16S + 8..11 (8S + 4 + i)
+// and needs 16S + 0..7; lane l + 32 holds 16S + 4..7 and 16S + 12..15 and
+// needs 16S + 8..15.  One v_permlane32_swap per register pair exchanges the
+// upper half of the first register with the lower half of the second.
 template <int S>
-__device__ __forceinline__ bf16x8_t b_from_c(const f32x16_t &c, int hh) {
-  float snd[4], rcv[4];
-#pragma unroll
-  for (int i = 0; i < 4; i++) snd[i] = hh ? c[8 * S + i] : c[8 * S + 4 + i];
-#pragma unroll
-  for (int i = 0; i < 4; i++) rcv[i] = __shfl_xor(snd[i], 32);
-  u16x8_t u;
+__device__ __forceinline__ bf16x8_t b_from_c(const f32x16_t &c) {
+  bf16x8_t r;
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    u[i] = f2bf(hh ? rcv[i] : c[8 * S + i]);
-    u[4 + i] = f2bf(hh ? c[8 * S + 4 + i] : rcv[i]);
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[8 * S + i]),
+                                                     __float_as_uint(c[8 * S + 4 + i]), false, false);
+    r[i] = (__bf16)__uint_as_float(sw[0]);
+    r[4 + i] = (__bf16)__uint_as_float(sw[1]);
   }
-  return as_bf(u);
+  return r;
 }
 
 __device__ __forceinline__ bf16x8_t lds8(const unsigned short *p) {
@@ -130,8 +129,8 @@ __global__ __launch_bounds__(256) void k_mlp(const float *__restrict__ P, const 
     }
     f32x16_t a2[2] = {zero, zero};
     {
-      const bf16x8_t b0 = b_from_c<0>(a1[0], hh), b1 = b_from_c<1>(a1[0], hh);
-      const bf16x8_t b2 = b_from_c<0>(a1[1], hh), b3v = b_from_c<1>(a1[1], hh);
+      const bf16x8_t b0 = b_from_c<0>(a1[0]), b1 = b_from_c<1>(a1[0]);
+      const bf16x8_t b2 = b_from_c<0>(a1[1]), b3v = b_from_c<1>(a1[1]);
 #pragma unroll
       for (int o = 0; o < 2; o++) {
         a2[o] = mma(aw2[o][0], b0, a2[o]);
@@ -174,8 +173,8 @@ __global__ __launch_bounds__(256) void k_mlp(const float *__restrict__ P, const 
     // dA1^T = W2^T dZ2^T, then the ReLU mask of layer 1
     f32x16_t dz1[2] = {zero, zero};
     {
-      const bf16x8_t b0 = b_from_c<0>(dz2[0], hh), b1 = b_from_c<1>(dz2[0], hh);
-      const bf16x8_t b2 = b_from_c<0>(dz2[1], hh), b3v = b_from_c<1>(dz2[1], hh);
+      const bf16x8_t b0 = b_from_c<0>(dz2[0]), b1 = b_from_c<1>(dz2[0]);
+      const bf16x8_t b2 = b_from_c<0>(dz2[1]), b3v = b_from_c<1>(dz2[1]);
 #pragma unroll
       for (int i = 0; i < 2; i++) {
         dz1[i] = mma(aw2t[i][0], b0, dz1[i]);

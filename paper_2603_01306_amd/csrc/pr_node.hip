@@ -267,6 +267,40 @@ __global__ __launch_bounds__(NT) void k_prox(const double *v, double *out, int64
   }
 }
 
+// prox_{rho_q g_N}(v_q) for m nodes at once, one workgroup per node (the
+// body of k_prox): node q's parameters prm[q] (status, kbar, lambda2, M),
+// rho_q = 2 lambda2_q / L, rows q of V / Xo / abuf (p entries each).
+__global__ __launch_bounds__(NT) void k_prox_batch(const NodeParams *__restrict__ prm, const double *V, double *Xo,
+                                                   double *abuf_all, int64_t p, double invL) {
+  __shared__ double red[NW * 4];
+  const int q = blockIdx.x;
+  const NodeParams P = prm[q];
+  const double *v = V + (int64_t)q * p;
+  double *out = Xo + (int64_t)q * p;
+  double *abuf = abuf_all + (int64_t)q * p;
+  const int8_t *__restrict__ st = P.st;
+  const double rho = 2.0 * P.lambda2 * invL, M = P.M;
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) abuf[j] = (st[j] == kFree) ? fabs(v[j]) : -1.0;
+  __syncthreads();
+  int evals;
+  const double tau = solve_tau(abuf, p, P.kbar, rho, M, -1.0, red, &evals);
+  const double inv1p = 1.0 / (1.0 + rho);
+#pragma unroll 8
+  for (int64_t j = threadIdx.x; j < p; j += NT) {
+    const double vj = v[j];
+    const int s = st[j];
+    double x = 0.0;
+    if (s != kZero) {
+      const double av = fabs(vj);
+      double r = fmin(av * inv1p, M);
+      if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
+      x = (r == 0.0) ? 0.0 : copysign(r, vj);
+    }
+    out[j] = x;
+  }
+}
+
 // The same prox with the node dimensions counted on the device, for callers
 // that pass no host-side status: |J1| and |J_f| are reduced from st, kbar =
 // min(k - |J1|, |J_f|).  *flag receives 0, or 1 for a status code outside
@@ -1718,6 +1752,12 @@ hipError_t launch_zbest_final(const NodeState *S, const ProbBufs &B, int32_t los
 hipError_t launch_prox(const double *v, double *out, int64_t p, double rho, int32_t kbar, double M,
                        const int8_t *st, double *abuf, double *, hipStream_t s) {
   k_prox<<<1, NT, 0, s>>>(v, out, p, rho, kbar, M, st, abuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_prox_batch(const NodeParams *prm, const double *V, double *Xo, double *abuf, int64_t p, int m,
+                             double invL, hipStream_t s) {
+  k_prox_batch<<<(unsigned)m, NT, 0, s>>>(prm, V, Xo, abuf, p, invL);
   return hipGetLastError();
 }
 

@@ -147,30 +147,46 @@ def _solve_chunks(ctx, children, B0, **opts):
 
 
 def evaluate(ctx, params, children, Bp, **opts):
-    """Iterations and wall time to the FP64 gap tolerance from the parent
-    solutions and from the network's starts (pr_mlp_warm_start)."""
+    """Iterations and wall time to the FP64 gap tolerance from three starts:
+    the parent solutions, the judged start without the network (the smaller
+    FP64 gap of the parent and prox(beta_parent); pr_mlp_warm_start with no
+    parameters) and the judged start with it (the smallest gap of those two
+    and prox(beta_parent + output)).  Times of the judged starts include
+    building them."""
     import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rp = _solve_chunks(ctx, children, Bp, **opts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    B0, choice, gaps = ctx.mlp_warm_start(children, params, Bp)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    rm = _solve_chunks(ctx, children, B0, **opts)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
+
+    def run(make_start):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B0, choice, gaps = make_start()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = _solve_chunks(ctx, children, B0, **opts)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return res, t1 - t0, t2 - t1, choice, gaps
+
+    rp, _, sp, _, _ = run(lambda: (Bp, None, None))
+    ra, wa, sa, ca, ga = run(lambda: ctx.mlp_warm_start(children, None, Bp))
+    rm, wm, sm, cm, gm = run(lambda: ctx.mlp_warm_start(children, params, Bp))
     ip = np.array([r["iters"] for r in rp])
+    ia = np.array([r["iters"] for r in ra])
     im = np.array([r["iters"] for r in rm])
-    ok = all(r["status"] == CONVERGED for r in rp) and all(r["status"] == CONVERGED for r in rm)
+    ok = all(r["status"] == CONVERGED for rr in (rp, ra, rm) for r in rr)
+
+    def bound_diff(x):
+        return float(max(abs(a["lower_bound"] - b["lower_bound"]) / abs(a["primal"]) for a, b in zip(rp, x)))
+
     return {"nodes": len(children), "all_converged": ok,
             "parent_iters_mean": float(ip.mean()), "parent_iters_median": float(np.median(ip)),
+            "prox_parent_iters_mean": float(ia.mean()), "prox_parent_iters_median": float(np.median(ia)),
             "learned_iters_mean": float(im.mean()), "learned_iters_median": float(np.median(im)),
-            "parent_solve_s": t1 - t0, "warm_start_s": t2 - t1, "learned_solve_s": t3 - t2,
-            "network_start_kept": float(choice.mean()),
-            "parent_gap_median": float(np.median(gaps[:, 0])),
-            "start_gap_median": float(np.median(np.minimum(gaps[:, 0], gaps[:, 1]))),
-            "max_rel_bound_difference": float(max(abs(a["lower_bound"] - b["lower_bound"]) / abs(a["primal"])
-                                                  for a, b in zip(rp, rm))),
-            "iters_parent": ip, "iters_learned": im, "choice": choice, "gaps": gaps}
+            "parent_solve_s": sp,
+            "prox_parent_start_s": wa, "prox_parent_solve_s": sa, "prox_parent_total_s": wa + sa,
+            "learned_start_s": wm, "learned_solve_s": sm, "learned_total_s": wm + sm,
+            "prox_parent_start_kept": float(np.mean(ca == 1)), "network_start_kept": float(np.mean(cm == 2)),
+            "parent_gap_median": float(np.median(gm[:, 0])),
+            "prox_parent_start_gap_median": float(np.median(np.min(ga[:, :2], axis=1))),
+            "learned_start_gap_median": float(np.median(np.min(gm, axis=1))),
+            "max_rel_bound_difference": max(bound_diff(ra), bound_diff(rm)),
+            "iters_parent": ip, "iters_prox_parent": ia, "iters_learned": im, "choice": cm, "gaps": gm}

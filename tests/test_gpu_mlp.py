@@ -238,37 +238,66 @@ def test_features_match_oracle(inst_ctx):
         assert np.array_equal(T[i], (Bc[i] - Bp[i]).astype(np.float32))
 
 
-def test_warm_start_judge(inst_ctx):
-    """The start kept for each node is the candidate or the parent solution,
-    whichever the oracle also finds to have the smaller FP64 gap."""
+@pytest.mark.parametrize("batched", [True, False])
+@pytest.mark.parametrize("with_net", [True, False])
+def test_warm_start_judge(inst_ctx, dev, batched, with_net):
+    """Every reported gap is the oracle's FP64 gap of its candidate (the parent,
+    prox(beta_parent) -- exactly the oracle's prox_{rho g_N} with rho =
+    2 lambda2 / L -- and, with a network, its proposal), and the start kept is
+    the candidate with the smallest gap; the batched evaluation (all children
+    at once) and the one-at-a-time path alike."""
     import torch
     pr = _pr()
-    inst, ctx = inst_ctx
+    inst, bctx = inst_ctx
     from paper_2603_01306_amd import learned
+    if batched:
+        ctx = bctx
+    else:
+        X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+        ctx = pr.Context(X, torch.from_numpy(inst.y).to(dev), 0, max_batch=1)
     rng = np.random.default_rng(2)
     root = pr.Node(8, 0.2, 2.0)
     res, Br = ctx.solve_batch([root], rel_gap_tol=1e-8)
     children = learned.random_children([root] * 6, inst.p, rng)
-    Bp = Br.repeat(6, 1)
-    params = learned.init_params(0, "cuda")
+    children.append(pr.Node(2, 0.2, 2.0, J1=[1, 2, 3]))       # infeasible: keeps the parent
+    Bp = Br.repeat(len(children), 1)
+    params = learned.init_params(0, "cuda") if with_net else None
     B0, choice, gaps = ctx.mlp_warm_start(children, params, Bp)
     B0 = B0.cpu().numpy()
+    L = 1.01 * 2.0 * ctx.norm2()
+    X = inst.X64().T
+
+    def gap(st, b):
+        ph = oracle.primal(inst.Xcm, inst.y, b, 0, 0.2, 2.0, 8, status=st)
+        if not math.isfinite(ph):
+            return math.inf, ph
+        zeta = 2.0 * (inst.y - X @ b)
+        return ph - oracle.dual(inst.Xcm, inst.y, zeta, 0, 0.2, 2.0, 8, status=st), ph
+
     for i, nd in enumerate(children):
         st = nd.status(inst.p)
         par = Bp[i].cpu().numpy()
-        ph_p = oracle.primal(inst.Xcm, inst.y, par, 0, 0.2, 2.0, 8, status=st)
-        if choice[i]:
-            assert not np.array_equal(B0[i], par)
-            assert gaps[i, 1] < gaps[i, 0]
-            ph = oracle.primal(inst.Xcm, inst.y, B0[i], 0, 0.2, 2.0, 8, status=st)
-            assert math.isfinite(ph)
-        else:
+        if i == len(children) - 1:
+            assert choice[i] == 0 and np.array_equal(B0[i], par) and np.all(np.isinf(gaps[i]))
+            continue
+        assert choice[i] == int(np.argmin(gaps[i]))
+        if not with_net:
+            assert math.isinf(gaps[i, 2])
+        gp, php = gap(st, par)
+        assert (math.isinf(gp) and math.isinf(gaps[i, 0])) or abs(gp - gaps[i, 0]) <= 1e-9 * abs(php)
+        pp = oracle.prox_g(par, 2.0 * 0.2 / L, 8, 2.0, st)
+        ga, pha = gap(st, pp)
+        assert abs(ga - gaps[i, 1]) <= 1e-9 * abs(pha)
+        if choice[i] == 0:
             assert np.array_equal(B0[i], par)
-            assert not gaps[i, 1] < gaps[i, 0]
-        if math.isfinite(ph_p):
-            zeta = 2.0 * (inst.y - inst.X64().T @ par)
-            gp = ph_p - oracle.dual(inst.Xcm, inst.y, zeta, 0, 0.2, 2.0, 8, status=st)
-            assert abs(gp - gaps[i, 0]) <= 1e-9 * abs(ph_p)
+        elif choice[i] == 1:
+            assert np.max(np.abs(B0[i] - pp)) <= 1e-12 * max(1.0, np.max(np.abs(pp)))
+        else:
+            gn, phn = gap(st, B0[i])
+            assert abs(gn - gaps[i, 2]) <= 1e-9 * abs(phn)
+    assert np.sum(choice[:-1] > 0) >= 1
+    if not batched:
+        ctx.close()
 
 
 def test_training_gains_over_parent_start(inst_ctx):
@@ -297,3 +326,11 @@ def test_training_gains_over_parent_start(inst_ctx):
     ev = learned.evaluate(ctx, params, children, Bp, rel_gap_tol=1e-7)
     print({k: v for k, v in ev.items() if not isinstance(v, np.ndarray)}, flush=True)
     assert ev["all_converged"] and ev["max_rel_bound_difference"] <= 2e-7
+    # what the network adds over the same judged start without it: its
+    # candidate joins the judged ones, so the start gap can only fall; the
+    # held-out iterations of the three starts are reported (the gain is small,
+    # and on this branching process the network's candidate is rarely kept)
+    print("iterations: parent", ev["parent_iters_mean"], "prox(parent)", ev["prox_parent_iters_mean"],
+          "network", ev["learned_iters_mean"], "network kept", ev["network_start_kept"], flush=True)
+    assert ev["learned_start_gap_median"] <= ev["prox_parent_start_gap_median"]
+    assert ev["prox_parent_start_gap_median"] <= ev["parent_gap_median"]
