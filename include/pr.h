@@ -265,12 +265,17 @@ int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
 
 /* Solve m nodes that share X (m <= max_batch), each as pr_solve would:
  * same bounds, stopping test, iteration variant and dynamic termination
- * (cutoff).  With a BF16 least-squares problem (n, p multiples of 128) the
- * nodes iterate together on FP64 MFMA products; every stopped node's Phi and
- * Psi are then recomputed over the stored X, and a node whose decision
- * (converged / prune / branch) is not confirmed continues alone on the
- * pr_solve path.  Other problems run pr_solve node by node.  Traces
- * (opts->trace) are not recorded.
+ * (cutoff).  On a context with the batched path (created with max_batch > 1,
+ * n and p multiples of 128, p <= 16384; either loss, X in any pr_dtype) the
+ * nodes iterate together on FP64 MFMA products: the forward product of the
+ * m iterates with X and one transposed product X^T R per iteration (least
+ * squares: the residual rows; logistic: two rows per node, zeta at the
+ * iterate and the loss gradient at the momentum point).  Every stopped
+ * node's Phi and Psi are then recomputed over the stored X, and a node whose
+ * decision (converged / prune / branch) is not confirmed continues alone on
+ * the pr_solve path.  Other contexts run pr_solve node by node.  The
+ * iteration variants are FISTA with or without the gap restart and PGD
+ * (AC-FGM runs node by node).  Traces (opts->trace) are not recorded.
  *   B0 device m x p (row i = warm start of node i) or NULL; B_out device
  *   m x p (row i receives node i's iterate) or NULL; out host m. */
 int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *opts,

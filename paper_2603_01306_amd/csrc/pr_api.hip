@@ -64,15 +64,18 @@ struct pr_ctx {
   int32_t debug = 0;        // pr_ctx_set_debug flags
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
-  // batched path (least squares, BF16 X, n and p multiples of 128, p <= 16384)
+  // batched path (both losses, X in any storage type, n and p multiples of 128, p <= 16384)
   bool batch_ok = false;
   int32_t KS = 1, KSF = 1, nfb = 0;
   int32_t fmaxF = 1, fmaxT = 1;  // largest extra split factors of the two GEMMs
-  uint16_t *Xrow = nullptr;  // row-major copy of X (n x p)
+  int32_t rs = 1;            // rows of the second product per node (logistic: zeta and the momentum gradient)
+  void *Xrow = nullptr;      // row-major copy of X (n x p), X's storage type
   double *Bx = nullptr;      // [cap padded][p] FP64 current iterates
-  double *Rd = nullptr;      // [cap padded][n] FP64 residuals
+  double *Rd = nullptr;      // [rs cap padded][n] FP64 residual / loss rows
   double *CF = nullptr;      // [KSF][cap padded][n]
-  double *CT = nullptr;      // [KS][cap padded][p]
+  double *CT = nullptr;      // [KS][rs cap padded][p]
+  double *Uprev = nullptr;   // logistic: [cap][n] X x of each node's previous iterate
+  int32_t *d_rowmap2 = nullptr;  // logistic: [2 cap padded] rows of the second product of the nodes still iterating
   double *fsum = nullptr;    // [cap][nfb][2]
   double *bx0 = nullptr, *bx1 = nullptr, *bxbest = nullptr, *bhprev = nullptr, *bsval = nullptr;
   int32_t *bsidx = nullptr;
@@ -107,7 +110,7 @@ struct pr_ctx {
   double *d_oval = nullptr;         // [cap padded][p]
   double *BxU = nullptr;            // [cap padded][kp max] compacted iterates
   double *GU = nullptr;             // [p][3p/4] union columns of G (Gram mode)
-  uint16_t *XrU = nullptr;          // [n][3p/4] union columns of the row-major X copy (products over X)
+  void *XrU = nullptr;              // [n][3p/4] union columns of the row-major X copy (products over X)
   // batched certification: per-node scratch [cap padded][p] and {Psi, Phi} per node
   double *cert_a = nullptr, *d_cert = nullptr;
   // least squares from the Gram matrix (pr_ctx_enable_gram)
@@ -174,7 +177,7 @@ void free_ctx(pr_ctx *c) {
     for (void *b : ub)
       if (b) (void)hipFree(b);
   }
-  void *bb[] = {c->bstp, c->Xrow, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
+  void *bb[] = {c->bstp, c->Xrow, c->Uprev, c->d_rowmap2, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
                 c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb, c->mVb, c->mWb, c->mFb, c->moutb, c->mPb};
   for (void *b : bb)
     if (b) (void)hipFree(b);
@@ -503,17 +506,22 @@ int nr_of(int32_t m) { return (m + 63) / 64 * 64; }
 // it.
 int tune_batch(pr_ctx *c) {
   const int64_t n = c->P.n, p = c->P.p;
-  const int NrMax = nr_of(c->max_batch);
-  const int ntmax = NrMax / 64 < kTuneMax - 1 ? NrMax / 64 : kTuneMax - 1;
+  const int NrMax = nr_of(c->max_batch), NrMaxT = nr_of(c->rs * c->max_batch);
   hipStream_t s = c->stream;
   PR_TRY(launch_iota(c->d_rowmap, NrMax, s));
+  if (c->d_rowmap2) PR_TRY(launch_iota(c->d_rowmap2, NrMaxT, s));
   int32_t *cnt = c->d_split + 4;
   for (int g = 0; g < 2; g++) {
     const bool fwd = g == 0;
     const int base = fwd ? c->KSF : c->KS, fmax = fwd ? c->fmaxF : c->fmaxT;
     const double plane_bytes = 8.0 * (double)(fwd ? n : p);  // per row and split plane
+    // the second product has rs rows per node: its table is indexed by its own row-tile count
+    const int rows = fwd ? c->max_batch : c->rs * c->max_batch;
+    const int nrmax = fwd ? NrMax : NrMaxT;
+    const int ntmax = nrmax / 64 < kTuneMax - 1 ? nrmax / 64 : kTuneMax - 1;
+    int32_t *rmap = (!fwd && c->d_rowmap2) ? c->d_rowmap2 : c->d_rowmap;
     for (int nta = 1; nta <= ntmax; nta++) {
-      const int32_t nrow = nta * 64 < c->max_batch ? nta * 64 : c->max_batch;
+      const int32_t nrow = nta * 64 < rows ? nta * 64 : rows;
       double best = INFINITY;
       int bestf = 1;
       for (int f = 1; f <= fmax; f *= 2) {
@@ -523,10 +531,10 @@ int tune_batch(pr_ctx *c) {
           hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
           if (e != hipSuccess) return e;
           if (fwd)
-            return launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, NrMax, p, base, nullptr, c->d_rowmap, c->d_split,
-                                   c->d_split + 1, base * fmax, cnt, s);
-          return launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, NrMax, n, base, nullptr,
-                                 c->d_rowmap, c->d_split, c->d_split + 2, base * fmax, cnt, s);
+            return launch_gemm_any(c->P.xdt, c->Xrow, p, kF64, c->Bx, p, c->CF, n, NrMax, p, base, nullptr,
+                                   c->d_rowmap, c->d_split, c->d_split + 1, base * fmax, cnt, s);
+          return launch_gemm_any(c->P.xdt, c->P.X, n, kF64, c->Rd, n, c->CT, p, NrMaxT, n, base, nullptr, rmap,
+                                 c->d_split, c->d_split + 2, base * fmax, cnt, s);
         };
         PR_TRY(launch());
         PR_TRY(hipEventRecord(c->tev[0], s));
@@ -551,12 +559,21 @@ int tune_batch(pr_ctx *c) {
   return PR_OK;
 }
 
+// Split factor of the second product (X^T R) for a batch of m nodes: the
+// tuned factor for its row-tile count (rs rows per node).
+int32_t kst_for(const pr_ctx *c, int32_t m) {
+  int nta = nr_of(c->rs * m) / 64;
+  if (nta >= kTuneMax) nta = kTuneMax - 1;
+  return c->KS * c->h_ftab[kTuneMax + nta];
+}
+
 int alloc_batch(pr_ctx *c) {
   const int64_t n = c->P.n, p = c->P.p;
   const int cap = c->max_batch;
-  const int NrMax = nr_of(cap);
+  c->rs = c->P.loss == kLogistic ? 2 : 1;
+  const int NrMax = nr_of(cap), NrMaxT = nr_of(c->rs * cap);
   // split the reductions so that each GEMM has >= ~1024 workgroups at full batch
-  const int tiles_t = (int)(p / 128) * (NrMax / 64);
+  const int tiles_t = (int)(p / 128) * (NrMaxT / 64);
   int KS = 1;
   while (KS < 16 && tiles_t * KS < 512 && (n / (2 * KS)) % 32 == 0) KS *= 2;
   const int tiles_f = (int)(n / 128) * (NrMax / 64);
@@ -572,11 +589,15 @@ int alloc_batch(pr_ctx *c) {
   c->fmaxF = fF;
   c->fmaxT = fT;
   c->nfb = batch_resid_blocks(n);
-  bool ok = dalloc(&c->Xrow, (size_t)n * p) == hipSuccess;
+  bool ok = hipMalloc(&c->Xrow, esize(c->P.xdt) * (size_t)n * p) == hipSuccess;
   ok = ok && dalloc(&c->Bx, (size_t)NrMax * p) == hipSuccess;
-  ok = ok && dalloc(&c->Rd, (size_t)NrMax * n) == hipSuccess;
+  ok = ok && dalloc(&c->Rd, (size_t)NrMaxT * n) == hipSuccess;
   ok = ok && dalloc(&c->CF, (size_t)KSF * fF * NrMax * n) == hipSuccess;
-  ok = ok && dalloc(&c->CT, (size_t)KS * fT * NrMax * p) == hipSuccess;
+  ok = ok && dalloc(&c->CT, (size_t)KS * fT * NrMaxT * p) == hipSuccess;
+  if (c->rs == 2) {
+    ok = ok && dalloc(&c->Uprev, (size_t)cap * n) == hipSuccess;
+    ok = ok && dalloc(&c->d_rowmap2, NrMaxT) == hipSuccess;
+  }
   ok = ok && dalloc(&c->fsum, (size_t)2 * cap * c->nfb) == hipSuccess;
   ok = ok && dalloc(&c->bx0, (size_t)cap * p) == hipSuccess && dalloc(&c->bx1, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->bxbest, (size_t)cap * p) == hipSuccess && dalloc(&c->bhprev, (size_t)cap * p) == hipSuccess;
@@ -585,14 +606,17 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && dalloc(&c->bstp, (size_t)cap * c->h_stp.size()) == hipSuccess;
   ok = ok && dalloc(&c->d_bprm, cap) == hipSuccess && dalloc(&c->d_bstate, cap) == hipSuccess;
   ok = ok && dalloc(&c->d_active, 2) == hipSuccess;
-  ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 8) == hipSuccess;
+  // d_split: {rows iterating, forward split, second split, compacted split, tile counters x2,
+  // certification split, -, rows of the second product}
+  ok = ok && dalloc(&c->d_rowmap, NrMax) == hipSuccess && dalloc(&c->d_split, 12) == hipSuccess;
   ok = ok && dalloc(&c->d_ftab, kTuneTables * kTuneMax) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_bstate, sizeof(NodeState) * cap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   if (!ok) return PR_ENOMEM;
   ok = hipMemsetAsync(c->Bx, 0, sizeof(double) * NrMax * p, c->stream) == hipSuccess;
-  ok = ok && hipMemsetAsync(c->Rd, 0, sizeof(double) * NrMax * n, c->stream) == hipSuccess;
-  ok = ok && launch_transpose_bf16((const uint16_t *)c->P.X, c->Xrow, n, p, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->Rd, 0, sizeof(double) * NrMaxT * n, c->stream) == hipSuccess;
+  if (c->Uprev) ok = ok && hipMemsetAsync(c->Uprev, 0, sizeof(double) * cap * n, c->stream) == hipSuccess;
+  ok = ok && launch_transpose(c->P.xdt, c->P.X, c->Xrow, n, p, c->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) return PR_EDEVICE;
   int rc = tune_batch(c);
@@ -667,6 +691,9 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   BatchBufs bb{};
   bb.m = m;
   bb.Nr = nr_of(m);
+  bb.rs = c->gram ? 1 : c->rs;
+  bb.NrT = c->gram ? bb.Nr : nr_of(c->rs * m);
+  bb.loss = c->P.loss;
   bb.ksp = c->d_split + (c->gram && c->union_on ? 3 : 2);  // planes of the product the step sums
   bb.nfb = c->nfb;
   bb.x0 = c->bx0;
@@ -696,7 +723,7 @@ hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
   hipError_t e;
   if (c->gram) {
     e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KSG, 2,
-                            c->union_on ? c->kp : p, p, s);
+                            c->union_on ? c->kp : p, p, 1, nullptr, s);
     if (e != hipSuccess) return e;
     if (c->union_on) {
       e = launch_union_compact(c->Bx, p, c->d_rowmap, c->d_split, Nr, c->d_ulist, c->ku, c->kp, c->d_olist,
@@ -714,28 +741,31 @@ hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
     if (e != hipSuccess) return e;
     return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
   }
+  const int xdt = c->P.xdt;
+  const bool two = c->rs == 2;
   e = launch_batch_rowmap(c->d_bstate, m, c->d_rowmap, c->d_split, c->d_split + 4, c->d_ftab, c->KSF, c->KS, 1,
-                          c->union_on ? c->kp : p, p, s);
+                          c->union_on ? c->kp : p, p, c->rs, c->d_rowmap2, s);
   if (e != hipSuccess) return e;
   if (c->union_on) {
     e = launch_union_compact(c->Bx, p, c->d_rowmap, c->d_split, Nr, c->d_ulist, c->ku, c->kp, c->d_olist, p - c->ku,
                              c->BxU, c->d_ocnt, c->d_oidx, c->d_oval, c->d_active, s);
     if (e != hipSuccess) return e;
-    e = launch_gemm_f64(c->XrU, c->kp, c->BxU, c->kp, c->CF, n, Nr, c->kp, c->KSF, c->d_active, c->d_rowmap,
-                        c->d_split, c->d_split + 3, c->KSF * c->fmaxF, c->d_split + 4, s);
+    e = launch_gemm_any(xdt, c->XrU, c->kp, kF64, c->BxU, c->kp, c->CF, n, Nr, c->kp, c->KSF, c->d_active,
+                        c->d_rowmap, c->d_split, c->d_split + 3, c->KSF * c->fmaxF, c->d_split + 4, s);
     if (e != hipSuccess) return e;
-    e = launch_union_fix_bf16((const uint16_t *)c->P.X, n, p, c->d_rowmap, c->d_split, Nr, c->d_ocnt, c->d_oidx,
-                              c->d_oval, c->CF, c->d_active, s);
+    e = launch_union_fix_x(xdt, c->P.X, n, p, c->d_rowmap, c->d_split, Nr, c->d_ocnt, c->d_oidx, c->d_oval, c->CF,
+                           c->d_active, s);
   } else {
-    e = launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap, c->d_split,
-                        c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
+    e = launch_gemm_any(xdt, c->Xrow, p, kF64, c->Bx, p, c->CF, n, Nr, p, c->KSF, c->d_active, c->d_rowmap,
+                        c->d_split, c->d_split + 1, c->KSF * c->fmaxF, c->d_split + 4, s);
   }
   if (e != hipSuccess) return e;
   e = launch_batch_resid(c->CF, c->union_on ? c->d_split + 3 : c->d_split + 1, n, m, Nr, c->P.y, c->Rd, c->fsum,
-                         c->d_bstate, s);
+                         c->d_bstate, c->P.loss, c->Uprev, s);
   if (e != hipSuccess) return e;
-  e = launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, c->KS, c->d_active, c->d_rowmap,
-                      c->d_split, c->d_split + 2, c->KS * c->fmaxT, c->d_split + 5, s);
+  e = launch_gemm_any(xdt, c->P.X, n, kF64, c->Rd, n, c->CT, p, nr_of(c->rs * m), n, c->KS, c->d_active,
+                      two ? c->d_rowmap2 : c->d_rowmap, two ? c->d_split + 8 : c->d_split, c->d_split + 2,
+                      c->KS * c->fmaxT, c->d_split + 5, s);
   if (e != hipSuccess) return e;
   return launch_batch_step(c->d_bprm, c->d_bstate, batch_bufs(c, m), p, s);
 }
@@ -799,7 +829,8 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
     if (!ok) return PR_ENOMEM;
   }
   if (c->gram && !c->GU && dalloc(&c->GU, (size_t)p * (3 * p / 4)) != hipSuccess) return PR_ENOMEM;
-  if (!c->gram && !c->XrU && dalloc(&c->XrU, (size_t)n * (3 * p / 4)) != hipSuccess) return PR_ENOMEM;
+  if (!c->gram && !c->XrU && hipMalloc(&c->XrU, esize(c->P.xdt) * (size_t)n * (3 * p / 4)) != hipSuccess)
+    return PR_ENOMEM;
   hipStream_t s = c->stream;
   if (fresh) PR_TRY(hipMemsetAsync(c->d_umask, 0, sizeof(int32_t) * p, s));
   PR_TRY(launch_union_mask(c->Bx, m, p, c->d_umask, s));
@@ -816,7 +847,7 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
   if (!ol.empty())
     PR_TRY(hipMemcpyAsync(c->d_olist, ol.data(), sizeof(int32_t) * ol.size(), hipMemcpyHostToDevice, s));
   if (c->gram) PR_TRY(launch_gather_cols(c->G, p, c->d_ulist, ku, kp, c->GU, s));
-  else PR_TRY(launch_gather_cols_bf16(c->Xrow, n, p, c->d_ulist, ku, kp, c->XrU, s));
+  else PR_TRY(launch_gather_cols_x(c->P.xdt, c->Xrow, n, p, c->d_ulist, ku, kp, c->XrU, s));
   if (fresh) PR_TRY(hipMemsetAsync(c->d_ocnt, 0, sizeof(int32_t) * NrMax, s));
   PR_TRY(hipStreamSynchronize(s));  // the host lists go out of scope
   c->ku = ku;
@@ -834,7 +865,7 @@ int build_union(pr_ctx *c, int32_t m, bool fresh, bool *changed) {
 // lb[q] = Psi(zeta_q) with zeta_q = 2 (y - X x_q), ub[q] = Phi(x_q).
 int certify_batch(pr_ctx *c, int32_t m, std::vector<double> &lb, std::vector<double> &ub, int32_t *kst_out = nullptr) {
   const int64_t n = c->P.n, p = c->P.p;
-  const int NrMax = nr_of(c->max_batch), Nr = nr_of(m);
+  const int NrMax = nr_of(c->max_batch), Nr = nr_of(m), NrT = nr_of(c->rs * m);
   hipStream_t s = c->stream;
   if (!c->cert_a) {
     bool ok = dalloc(&c->cert_a, (size_t)NrMax * p) == hipSuccess && dalloc(&c->d_cert, 2 * (size_t)NrMax) == hipSuccess;
@@ -844,16 +875,17 @@ int certify_batch(pr_ctx *c, int32_t m, std::vector<double> &lb, std::vector<dou
   if (nta >= kTuneMax) nta = kTuneMax - 1;
   static_assert(kTuneTables >= 2, "forward and transpose split tables");
   const int32_t ksf = c->KSF * c->h_ftab[nta];
-  const int32_t kst = c->KS * c->h_ftab[kTuneMax + nta];
+  const int32_t kst = kst_for(c, m);
   PR_TRY(hipMemcpyAsync(c->Bx, c->bxbest, sizeof(double) * m * p, hipMemcpyDeviceToDevice, s));
   PR_TRY(hipMemcpyAsync(c->d_split + 6, &ksf, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  PR_TRY(launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, ksf, nullptr, nullptr, nullptr, nullptr, ksf, nullptr,
-                         s));
-  PR_TRY(launch_batch_resid(c->CF, c->d_split + 6, n, m, Nr, c->P.y, c->Rd, c->fsum, nullptr, s));
-  PR_TRY(launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, kst, nullptr, nullptr, nullptr,
+  PR_TRY(launch_gemm_any(c->P.xdt, c->Xrow, p, kF64, c->Bx, p, c->CF, n, Nr, p, ksf, nullptr, nullptr, nullptr,
+                         nullptr, ksf, nullptr, s));
+  PR_TRY(launch_batch_resid(c->CF, c->d_split + 6, n, m, Nr, c->P.y, c->Rd, c->fsum, nullptr, c->P.loss, nullptr,
+                            s));
+  PR_TRY(launch_gemm_any(c->P.xdt, c->P.X, n, kF64, c->Rd, n, c->CT, p, NrT, n, kst, nullptr, nullptr, nullptr,
                          nullptr, kst, nullptr, s));
-  PR_TRY(launch_cert_batch(c->d_bprm, c->bxbest, c->CT, kst, Nr, c->fsum, c->nfb, p, c->cert_a, c->bsidx, c->bsval,
-                           c->d_cert, m, s));
+  PR_TRY(launch_cert_batch(c->d_bprm, c->bxbest, c->CT, kst, NrT, c->rs, c->fsum, c->nfb, p, c->cert_a, c->bsidx,
+                           c->bsval, c->d_cert, m, s));
   if (kst_out) *kst_out = kst;
   std::vector<double> h((size_t)2 * m);
   PR_TRY(hipMemcpyAsync(h.data(), c->d_cert, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s));
@@ -973,8 +1005,7 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
     free_ctx(c);
     return rc;
   }
-  if (max_batch > 1 && prob->xdtype == PR_BF16 && prob->loss == PR_LSQ && n % 128 == 0 && p % 128 == 0 &&
-      p <= 16384 && n % 64 == 0) {
+  if (max_batch > 1 && n % 128 == 0 && p % 128 == 0 && p <= 16384) {
     rc = alloc_batch(c);
     if (rc != PR_OK) {
       free_ctx(c);
@@ -1479,17 +1510,19 @@ int pr_time_batch_gemm(pr_ctx *c, int32_t m, int32_t reps, double *ms_fwd, doubl
   // the split the batched iteration uses with all m rows active
   int nta = (m + 63) / 64;
   if (nta >= kTuneMax) nta = kTuneMax - 1;
-  const int ksf = c->KSF * c->h_ftab[nta], kst = c->KS * c->h_ftab[kTuneMax + nta];
+  const int ksf = c->KSF * c->h_ftab[nta], kst = kst_for(c, m);
+  const int NrT = nr_of(c->rs * m);
   int32_t *cnt = c->d_split + 4;
   auto fwd = [&]() {
     hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
     if (e != hipSuccess) return e;
-    return launch_gemm_f64(c->Xrow, p, c->Bx, p, c->CF, n, Nr, p, ksf, nullptr, nullptr, nullptr, nullptr, 0, cnt, s);
+    return launch_gemm_any(c->P.xdt, c->Xrow, p, kF64, c->Bx, p, c->CF, n, Nr, p, ksf, nullptr, nullptr, nullptr,
+                           nullptr, 0, cnt, s);
   };
   auto trn = [&]() {
     hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
     if (e != hipSuccess) return e;
-    return launch_gemm_f64((const uint16_t *)c->P.X, n, c->Rd, n, c->CT, p, Nr, n, kst, nullptr, nullptr, nullptr,
+    return launch_gemm_any(c->P.xdt, c->P.X, n, kF64, c->Rd, n, c->CT, p, NrT, n, kst, nullptr, nullptr, nullptr,
                            nullptr, 0, cnt, s);
   };
   double *outs[2] = {ms_fwd, ms_t};
@@ -1609,7 +1642,7 @@ static int stage_batch_nodes(pr_ctx *c, const pr_node *nodes, const std::vector<
                              const std::vector<std::vector<int8_t>> &sts, const std::vector<int32_t> &kbars,
                              const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0);
 
-// Batched starting points (batched path: BF16 least squares, m <= max_batch):
+// Batched starting points (batched path, m <= max_batch):
 // the parents' certificates and w = X^T zeta at every parent from one pass of
 // the batch's two GEMMs; the proximal steps of all children in one launch
 // and their certificates from a second pass; with a network, the feature rows
@@ -1649,12 +1682,13 @@ static int warm_start_batched(pr_ctx *c, const pr_node *nodes, int32_t m, const 
   if (rc != PR_OK) return rc;
   std::vector<double> lbP, ubP, lbA, ubA, lbN, ubN;
   int32_t kst = 1;
-  rc = certify_batch(c, mb, lbP, ubP, &kst);  // leaves X^T r of every parent in CT's split planes
+  rc = certify_batch(c, mb, lbP, ubP, &kst);  // leaves X^T zeta (or X^T r) of every parent in CT's split planes
   if (rc != PR_OK) return rc;
-  const int Nr = nr_of(mb);
   const double L = 1.01 * curvature(c->P.loss) * c->norm2;
   PR_TRY(hipMemcpyAsync(c->mVb, c->bxbest, sizeof(double) * mb * p, hipMemcpyDeviceToDevice, s));  // parents
-  if (params) PR_TRY(launch_sum_planes(c->CT, kst, Nr, p, mb, 2.0, c->mWb, s));  // w = X^T zeta (least squares)
+  // w = X^T zeta at every parent (least squares: the planes hold X^T r, zeta = 2 r)
+  if (params)
+    PR_TRY(launch_sum_planes(c->CT, kst, nr_of(c->rs * mb), c->rs, p, mb, c->P.loss == kLsq ? 2.0 : 1.0, c->mWb, s));
   // prox(beta_parent) of every child, then its certificate
   PR_TRY(launch_prox_batch(c->d_bprm, c->mVb, c->bxbest, c->cert_a, p, mb, 1.0 / L, s));
   rc = certify_batch(c, mb, lbA, ubA);
@@ -1875,7 +1909,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (rc != PR_OK) return rc;
     infeas[(size_t)i] = inf;
   }
-  if (!c->batch_ok) {
+  if (!c->batch_ok || opts.method >= kAcfgmGap) {  // AC-FGM: node by node
     for (int32_t i = 0; i < m; i++) {
       int rc = pr_solve(c, &nodes[i], &opts, B0 ? B0 + (int64_t)i * p : nullptr,
                         B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);
@@ -1905,6 +1939,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   const double L = opts.L > 0.0 ? opts.L : 1.01 * curvature(c->P.loss) * c->norm2;
   int rcs = stage_batch_nodes(c, nodes, slot_of, sts, kbars, pbars, opts, B0);
   if (rcs != PR_OK) return rcs;
+  if (c->Uprev) PR_TRY(hipMemsetAsync(c->Uprev, 0, sizeof(double) * mb * n, s));
   int32_t act = mb;
   PR_TRY(hipMemcpyAsync(c->d_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
   BatchBufs bb = batch_bufs(c, mb);

@@ -247,16 +247,16 @@ __device__ __forceinline__ void gemm_tile_f64_lds(const double *__restrict__ A, 
   }
 }
 
-// W[q][j] = scale * sum over the KS split planes of C[z][q][j] (rows q < m of
-// a batched product written as [KS][Nr][p] partial planes), planes summed in
-// order.
-__global__ void k_sum_planes(const double *__restrict__ C, int KS, int Nr, int64_t p, int m, double scale,
+// W[q][j] = scale * sum over the KS split planes of C[z][rs q][j] (row rs q,
+// q < m, of a batched product written as [KS][Nr][p] partial planes; rs rows
+// per node), planes summed in order.
+__global__ void k_sum_planes(const double *__restrict__ C, int KS, int Nr, int rs, int64_t p, int m, double scale,
                              double *__restrict__ W) {
   const int64_t total = (int64_t)m * p;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = t / p, j = t - q * p;
     double acc = 0.0;
-    for (int z = 0; z < KS; z++) acc += C[((int64_t)z * Nr + q) * p + j];
+    for (int z = 0; z < KS; z++) acc += C[((int64_t)z * Nr + rs * q) * p + j];
     W[t] = scale * acc;
   }
 }
@@ -319,12 +319,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const TA *__restrict__ A, i
 // product, ftab[trow][nta] for the product whose planes the node step reads:
 // trow = 1 for X^T R, 2 for the Gram product G X_it).
 // sp = {nrow, forward split, second split, split of the product compacted to
-// kred of its kfull reduction indices}; the two tile counters of the GEMMs
-// are reset.  One block of 256 threads.
+// kred of its kfull reduction indices}, sp[8] = rows of the second product:
+// with rs = 2 (logistic: zeta and the gradient at the momentum point per
+// node) rowmap2 lists rows 2 i and 2 i + 1 of every listed node i, and the
+// second product's split is looked up for its own row-tile count; the two
+// tile counters of the GEMMs are reset.  One block of 256 threads.
 __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restrict__ S, int m,
                                                       int32_t *__restrict__ rowmap, int32_t *__restrict__ sp,
                                                       int32_t *__restrict__ counters, const int32_t *__restrict__ ftab,
-                                                      int ksf, int kst, int trow, int64_t kred, int64_t kfull) {
+                                                      int ksf, int kst, int trow, int64_t kred, int64_t kfull,
+                                                      int rs, int32_t *__restrict__ rowmap2) {
   __shared__ int base;
   __shared__ int wsum[4];
   if (threadIdx.x == 0) base = 0;
@@ -339,7 +343,13 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
     __syncthreads();
     int off = base;
     for (int v = 0; v < w; v++) off += wsum[v];
-    if (act) rowmap[off + before] = i;
+    if (act) {
+      rowmap[off + before] = i;
+      if (rs == 2) {
+        rowmap2[2 * (off + before)] = 2 * i;
+        rowmap2[2 * (off + before) + 1] = 2 * i + 1;
+      }
+    }
     __syncthreads();
     if (threadIdx.x == 0) base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
@@ -347,9 +357,12 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
   if (threadIdx.x == 0) {
     int nta = (base + 63) / 64;
     if (nta >= kTuneMax) nta = kTuneMax - 1;
+    int nta2 = (rs * base + 63) / 64;
+    if (nta2 >= kTuneMax) nta2 = kTuneMax - 1;
     sp[0] = base;
     sp[1] = ksf * ftab[nta];
-    sp[2] = kst * ftab[trow * kTuneMax + nta];
+    sp[2] = kst * ftab[trow * kTuneMax + nta2];
+    sp[8] = rs * base;
     // split of the compacted product over kred < kfull reduction indices: the
     // tuned split scaled by kred / kfull, rounded down to a power of two (>= 1)
     const int base = trow == 2 ? sp[2] : sp[1];  // the Gram product, else the forward product
@@ -361,15 +374,16 @@ __global__ __launch_bounds__(256) void k_batch_rowmap(const NodeState *__restric
   }
 }
 
-// Row-major copy of a column-major BF16 matrix (n x p): out[i][j] = in[j][i].
-__global__ __launch_bounds__(256) void k_transpose_bf16(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
-                                                        int64_t n, int64_t p) {
-  __shared__ uint16_t tile[64][65];
+// Row-major copy of a column-major matrix (n x p): out[i][j] = in[j][i].
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ in, T *__restrict__ out, int64_t n,
+                                                   int64_t p) {
+  __shared__ T tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int jj = ty; jj < 64; jj += 4) {
     const int64_t i = i0 + tx, j = j0 + jj;
-    tile[jj][tx] = (i < n && j < p) ? in[j * n + i] : (uint16_t)0;
+    tile[jj][tx] = (i < n && j < p) ? in[j * n + i] : (T)0;
   }
   __syncthreads();
   for (int ii = ty; ii < 64; ii += 4) {
@@ -379,13 +393,22 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const uint16_t *__restri
 }
 
 
-// Residuals of the batch: u_i = sum_z U[z][i] (FP64), r_i = y - u_i into row i
-// of R ([Nr][n], FP64), and per (node, row block) sums of r^2 and
-// 2 r^T y - r^T r.  grid = (ceil(n / 512), m); 2 rows per thread.
+// Loss side of the batch from the forward product's split planes, u_i =
+// sum_z U[z][node][i] in plane order (FP64), per (node, row block) sums of
+// F(u) and -F*(-zeta).  grid = (ceil(n / 512), m); 2 rows per thread.
+//   least squares: r = y - u into row node of R ([Nr][n]); sums of r^2 and
+//                  2 r^T y - r^T r (zeta = 2 r).
+//   logistic:      zeta = y / (1 + exp(y u)) (= -grad F(u)) into row 2 node of
+//                  R ([2 Nr][n]); while iterating (S != NULL) also the
+//                  gradient of F at the momentum point (1 + m) u - m u_prev,
+//                  m the node's non-restart FISTA coefficient, into row
+//                  2 node + 1, and u into Uprev for the next iteration; sums
+//                  of sum_i log(1 + exp(-y_i u_i)) and the binary entropies
+//                  of a_i = 1 / (1 + exp(y_i u_i)).
 __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ U, const int32_t *__restrict__ ksp,
                                                      int64_t n, int Nr, const double *__restrict__ y,
                                                      double *__restrict__ R, double *__restrict__ fsum,
-                                                     const NodeState *S) {
+                                                     const NodeState *S, int32_t loss, double *__restrict__ Uprev) {
   __shared__ double red[4 * 4];
   const int node = blockIdx.y;
   if (S && S[node].done) return;  // S == NULL: every row (certification)
@@ -394,15 +417,46 @@ __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ 
   const int64_t plane = (int64_t)Nr * n;
   double s[2] = {0.0, 0.0};
   if (i0 < n) {
+    double u[2];
 #pragma unroll
     for (int e = 0; e < 2; e++) {
       const int64_t i = i0 + e;
-      double u = 0.0;
-      for (int z = 0; z < KSF; z++) u += U[(int64_t)z * plane + (int64_t)node * n + i];
-      const double ri = y[i] - u;
-      R[(int64_t)node * n + i] = ri;
-      s[0] += ri * ri;
-      s[1] += 2.0 * ri * y[i] - ri * ri;
+      u[e] = 0.0;
+      for (int z = 0; z < KSF; z++) u[e] += U[(int64_t)z * plane + (int64_t)node * n + i];
+    }
+    if (loss == kLsq) {
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        const int64_t i = i0 + e;
+        const double ri = y[i] - u[e];
+        R[(int64_t)node * n + i] = ri;
+        s[0] += ri * ri;
+        s[1] += 2.0 * ri * y[i] - ri * ri;
+      }
+    } else {
+      double mt = 0.0;
+      if (S) {
+        const double t = S[node].t;
+        mt = (t - 1.0) / fista_next_t(t);
+      }
+      double *zr = R + (int64_t)(2 * node) * n, *gr = zr + n;
+      double *up = Uprev + (int64_t)node * n;
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        const int64_t i = i0 + e;
+        const double yi = y[i];
+        const double z = yi * u[e];
+        const double a = 1.0 / (1.0 + exp(z));
+        zr[i] = yi * a;
+        s[0] += softplus(-z);
+        s[1] += a * softplus(z) + (1.0 - a) * softplus(-z);
+        if (S) {
+          const double uo = up[i];
+          up[i] = u[e];
+          const double sm = (1.0 + mt) * u[e] - mt * uo;
+          gr[i] = -yi / (1.0 + exp(yi * sm));
+        }
+      }
     }
   }
   block_sum<256, 2>(s, red);
@@ -501,6 +555,15 @@ struct Fix8<double> {
   __device__ __forceinline__ double get(int e) const { return v[e >> 1][e & 1]; }
 };
 template <>
+struct Fix8<float> {
+  f4v_t v[2];
+  __device__ __forceinline__ void load(const float *p) {
+    v[0] = *reinterpret_cast<const f4v_t *>(p);
+    v[1] = *reinterpret_cast<const f4v_t *>(p + 4);
+  }
+  __device__ __forceinline__ double get(int e) const { return (double)v[e >> 2][e & 3]; }
+};
+template <>
 struct Fix8<uint16_t> {
   us8_t v;
   __device__ __forceinline__ void load(const uint16_t *p) { v = *reinterpret_cast<const us8_t *>(p); }
@@ -578,6 +641,7 @@ hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const v
   return launch_gemm_t<A_T, B_T, PIPE_>((const A_T *)A, lda, (const B_T *)B, ldb, C, Mc, Nr, K, KS, active, rowmap, \
                                         nrow, ksp, ks_max, counter, s)
   if (adt == kBF16 && bdt == kF64) PR_GEMM_CASE(uint16_t, double, kPipe);
+  if (adt == kF32 && bdt == kF64) PR_GEMM_CASE(float, double, kPipe);
   if (adt == kBF16 && bdt == kBF16) PR_GEMM_CASE(uint16_t, uint16_t, kPipe);
   if (adt == kF32 && bdt == kF32) PR_GEMM_CASE(float, float, kPipe);
   if (adt == kF64 && bdt == kF64) PR_GEMM_CASE(double, double, 1);  // two stages would spill
@@ -586,15 +650,21 @@ hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const v
 }
 
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
-                               const int32_t *ftab, int ksf, int kst, int trow, int64_t kred, int64_t kfull,
-                               hipStream_t s) {
-  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst, trow, kred, kfull);
+                               const int32_t *ftab, int ksf, int kst, int trow, int64_t kred, int64_t kfull, int rs,
+                               int32_t *rowmap2, hipStream_t s) {
+  if (rs != 1 && rs != 2) return hipErrorInvalidValue;
+  k_batch_rowmap<<<1, 256, 0, s>>>(S, m, rowmap, sp, counters, ftab, ksf, kst, trow, kred, kfull, rs, rowmap2);
   return hipGetLastError();
 }
 
-hipError_t launch_transpose_bf16(const uint16_t *in, uint16_t *out, int64_t n, int64_t p, hipStream_t s) {
+hipError_t launch_transpose(int xdt, const void *in, void *out, int64_t n, int64_t p, hipStream_t s) {
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((p + 63) / 64));
-  k_transpose_bf16<<<grid, 256, 0, s>>>(in, out, n, p);
+  switch (xdt) {
+    case kF64: k_transpose<double><<<grid, 256, 0, s>>>((const double *)in, (double *)out, n, p); break;
+    case kF32: k_transpose<float><<<grid, 256, 0, s>>>((const float *)in, (float *)out, n, p); break;
+    case kBF16: k_transpose<uint16_t><<<grid, 256, 0, s>>>((const uint16_t *)in, (uint16_t *)out, n, p); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -609,9 +679,18 @@ hipError_t launch_gather_cols(const double *G, int64_t p, const int32_t *ulist, 
   return hipGetLastError();
 }
 
-hipError_t launch_gather_cols_bf16(const uint16_t *A, int64_t rows, int64_t p, const int32_t *ulist, int64_t ku,
-                                   int64_t kp, uint16_t *AU, hipStream_t s) {
-  k_gather_cols<uint16_t><<<(unsigned)rows, 256, 0, s>>>(A, p, ulist, ku, kp, AU);
+hipError_t launch_gather_cols_x(int xdt, const void *A, int64_t rows, int64_t p, const int32_t *ulist, int64_t ku,
+                                int64_t kp, void *AU, hipStream_t s) {
+  switch (xdt) {
+    case kF64: k_gather_cols<double><<<(unsigned)rows, 256, 0, s>>>((const double *)A, p, ulist, ku, kp, (double *)AU);
+      break;
+    case kF32: k_gather_cols<float><<<(unsigned)rows, 256, 0, s>>>((const float *)A, p, ulist, ku, kp, (float *)AU);
+      break;
+    case kBF16:
+      k_gather_cols<uint16_t><<<(unsigned)rows, 256, 0, s>>>((const uint16_t *)A, p, ulist, ku, kp, (uint16_t *)AU);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -632,28 +711,41 @@ hipError_t launch_union_fix(const double *G, int64_t p, const int32_t *rowmap, c
   return hipGetLastError();
 }
 
-hipError_t launch_union_fix_bf16(const uint16_t *X, int64_t n, int64_t p, const int32_t *rowmap, const int32_t *nrow,
-                                 int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
-                                 const int32_t *active, hipStream_t s) {
+hipError_t launch_union_fix_x(int xdt, const void *X, int64_t n, int64_t p, const int32_t *rowmap, const int32_t *nrow,
+                              int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
+                              const int32_t *active, hipStream_t s) {
   dim3 grid((unsigned)Nr, (unsigned)((n + kFixSpan - 1) / kFixSpan));
-  k_union_fix<uint16_t><<<grid, 256, 0, s>>>(X, n, p, rowmap, nrow, ocnt, oidx, oval, C, active);
+  switch (xdt) {
+    case kF64:
+      k_union_fix<double><<<grid, 256, 0, s>>>((const double *)X, n, p, rowmap, nrow, ocnt, oidx, oval, C, active);
+      break;
+    case kF32:
+      k_union_fix<float><<<grid, 256, 0, s>>>((const float *)X, n, p, rowmap, nrow, ocnt, oidx, oval, C, active);
+      break;
+    case kBF16:
+      k_union_fix<uint16_t><<<grid, 256, 0, s>>>((const uint16_t *)X, n, p, rowmap, nrow, ocnt, oidx, oval, C, active);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 int batch_resid_blocks(int64_t n) { return (int)((n + 511) / 512); }
 
 hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, int m, int Nr, const double *y,
-                              double *R, double *fsum, const NodeState *S, hipStream_t s) {
+                              double *R, double *fsum, const NodeState *S, int32_t loss, double *Uprev,
+                              hipStream_t s) {
+  if (loss != kLsq && (loss != kLogistic || (S && !Uprev))) return hipErrorInvalidValue;
   dim3 grid((unsigned)batch_resid_blocks(n), (unsigned)m);
-  k_batch_resid<<<grid, 256, 0, s>>>(U, ksp, n, Nr, y, R, fsum, S);
+  k_batch_resid<<<grid, 256, 0, s>>>(U, ksp, n, Nr, y, R, fsum, S, loss, Uprev);
   return hipGetLastError();
 }
 
-hipError_t launch_sum_planes(const double *C, int KS, int Nr, int64_t p, int m, double scale, double *W,
+hipError_t launch_sum_planes(const double *C, int KS, int Nr, int rs, int64_t p, int m, double scale, double *W,
                              hipStream_t s) {
   const int64_t total = (int64_t)m * p;
   const int64_t blocks = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
-  k_sum_planes<<<(unsigned)blocks, 256, 0, s>>>(C, KS, Nr, p, m, scale, W);
+  k_sum_planes<<<(unsigned)blocks, 256, 0, s>>>(C, KS, Nr, rs, p, m, scale, W);
   return hipGetLastError();
 }
 

@@ -95,12 +95,15 @@ struct ProbBufs {
 // Batched solve buffers (m nodes, node i's vectors at offset i * p).
 struct BatchBufs {
   int32_t m, Nr, nfb;     // nodes, GEMM rows (m padded to 64), residual row blocks
+  int32_t NrT, rs;        // rows of the planes the step reads (rs per node: logistic 2, else 1), padded to 64
+  int32_t loss;
   const int32_t *ksp;     // device: number of X^T R partial planes written this iteration
   double *x0, *x1, *xbest, *hprev;
   int32_t *sidx;
   double *sval;
-  const double *CT;   // [*ksp][Nr][p] partial products X^T r (Gram mode: G x)
-  const double *fsum; // [m][nfb][2] partial sums of r^2 and 2 r^T y - r^T r
+  const double *CT;   // [*ksp][NrT][p] partial products X^T r (logistic: rows 2q = X^T zeta, 2q+1 = the
+                      // gradient at the momentum point; Gram mode: G x)
+  const double *fsum; // [m][nfb][2] partial sums of F(X x) and -F*(-zeta)
   double *Bx;         // [Nr][p] current iterates (rows of the forward GEMM)
   int32_t *active;    // number of nodes not yet done
   double gap_factor;  // stop when Phi - Psi <= gap_factor * tol * |Phi| (margin for the host re-check)
@@ -182,21 +185,25 @@ hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, co
 hipError_t launch_batch_init(const NodeParams *prm, NodeState *S, BatchBufs bb, const double *B0, double L,
                              int64_t p, hipStream_t s);
 hipError_t launch_batch_step(const NodeParams *prm, NodeState *S, BatchBufs bb, int64_t p, hipStream_t s);
-hipError_t launch_transpose_bf16(const uint16_t *in, uint16_t *out, int64_t n, int64_t p, hipStream_t s);
+// row-major copy out (n x p) of the column-major X of dtype xdt
+hipError_t launch_transpose(int xdt, const void *in, void *out, int64_t n, int64_t p, hipStream_t s);
 int batch_resid_blocks(int64_t n);
+// loss side of the batch (least squares: R rows r; logistic: R rows 2q = zeta,
+// 2q+1 = gradient at the momentum point while iterating, u kept in Uprev)
 hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, int m, int Nr, const double *y,
-                              double *R, double *fsum, const NodeState *S, hipStream_t s);
+                              double *R, double *fsum, const NodeState *S, int32_t loss, double *Uprev,
+                              hipStream_t s);
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
                            int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
                            const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
 // Same product with operand types adt, bdt in {kBF16, kF32, kF64}: supported
-// pairs (BF16, FP64), (BF16, BF16), (FP32, FP32), (FP64, FP64).
+// pairs (BF16, FP64), (FP32, FP64), (BF16, BF16), (FP32, FP32), (FP64, FP64).
 hipError_t launch_gemm_any(int adt, const void *A, int64_t lda, int bdt, const void *B, int64_t ldb, double *C,
                            int64_t Mc, int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
                            const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);
 hipError_t launch_batch_rowmap(const NodeState *S, int m, int32_t *rowmap, int32_t *sp, int32_t *counters,
-                               const int32_t *ftab, int ksf, int kst, int trow, int64_t kred, int64_t kfull,
-                               hipStream_t s);
+                               const int32_t *ftab, int ksf, int kst, int trow, int64_t kred, int64_t kfull, int rs,
+                               int32_t *rowmap2, hipStream_t s);
 hipError_t launch_union_mask(const double *Bx, int m, int64_t p, int32_t *mask, hipStream_t s);
 hipError_t launch_gather_cols(const double *G, int64_t p, const int32_t *ulist, int64_t ku, int64_t kp, double *GU,
                               hipStream_t s);
@@ -207,14 +214,14 @@ hipError_t launch_union_compact(const double *Bx, int64_t p, const int32_t *rowm
 hipError_t launch_union_fix(const double *G, int64_t p, const int32_t *rowmap, const int32_t *nrow, int Nr,
                             const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
                             const int32_t *active, hipStream_t s);
-hipError_t launch_gather_cols_bf16(const uint16_t *A, int64_t rows, int64_t p, const int32_t *ulist, int64_t ku,
-                                   int64_t kp, uint16_t *AU, hipStream_t s);
-hipError_t launch_union_fix_bf16(const uint16_t *X, int64_t n, int64_t p, const int32_t *rowmap, const int32_t *nrow,
-                                 int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
-                                 const int32_t *active, hipStream_t s);
+hipError_t launch_gather_cols_x(int xdt, const void *A, int64_t rows, int64_t p, const int32_t *ulist, int64_t ku,
+                                int64_t kp, void *AU, hipStream_t s);
+hipError_t launch_union_fix_x(int xdt, const void *X, int64_t n, int64_t p, const int32_t *rowmap, const int32_t *nrow,
+                              int Nr, const int32_t *ocnt, const int32_t *oidx, const double *oval, double *C,
+                              const int32_t *active, hipStream_t s);
 hipError_t launch_batch_zeta(const double *R, int64_t n, int node, double *zeta, hipStream_t s);
-// W[q][j] = scale * sum_z C[z][q][j] for q < m (C: [KS][Nr][p] split planes)
-hipError_t launch_sum_planes(const double *C, int KS, int Nr, int64_t p, int m, double scale, double *W,
+// W[q][j] = scale * sum_z C[z][rs q][j] for q < m (C: [KS][Nr][p] split planes, rs rows per node)
+hipError_t launch_sum_planes(const double *C, int KS, int Nr, int rs, int64_t p, int m, double scale, double *W,
                              hipStream_t s);
 // prox of g_N for m nodes (params prm[q], rho_q = 2 lambda2_q invL), rows of V -> Xo; abuf m x p scratch
 hipError_t launch_prox_batch(const NodeParams *prm, const double *V, double *Xo, double *abuf, int64_t p, int m,
@@ -259,7 +266,7 @@ hipError_t launch_zeta_terms(int32_t loss, const double *zeta, const double *y, 
                              double *sums_out, hipStream_t s);
 hipError_t launch_sumsq(const double *v, int64_t n, double *out, hipStream_t s);
 hipError_t launch_scale_copy(const double *src, double *dst, double a, int64_t n, hipStream_t s);
-hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const double *H, int KS, int Nr,
+hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const double *H, int KS, int Nr, int rs,
                              const double *fsum, int nfb, int64_t p, double *abuf, int32_t *sidx, double *sval,
                              double *out, int m, hipStream_t s);
 hipError_t launch_lanczos(double *w, double *v, double *vprev, const double *alpha, const double *beta_prev,

@@ -373,16 +373,16 @@ __global__ __launch_bounds__(NT) void k_regularizer(const double *beta, const do
   }
 }
 
-// Certified values of m batched least-squares nodes at their stopping
-// iterates x (rows of X_it), all over the stored X: workgroup q takes F(Xx)
-// = ||r||^2 and -F*(-zeta) = 2 r^T y - ||r||^2 (zeta = 2 r, r = y - X x) from
-// the per-block sums of its residual row in block order, w = X^T zeta /
-// (2 lambda2) = (X^T r) / lambda2 from the split planes of the transposed
-// product in plane order, and evaluates g_N(x) (Algorithm 1 with the domain
+// Certified values of m batched nodes at their stopping iterates x (rows of
+// X_it), all over the stored X: workgroup q takes F(Xx) and -F*(-zeta)
+// (least squares zeta = 2 (y - X x), logistic zeta = -grad F(X x)) from the
+// per-block sums of its loss row in block order, w = X^T zeta / (2 lambda2)
+// from the split planes of the transposed product (row rs q) in plane order,
+// and evaluates g_N(x) (Algorithm 1 with the domain
 // test) and g_N*(w) (sum of H_M over J1 + TopSum of H_M over the free
 // coordinates, eq. of g*): out[q] = {Psi(zeta), Phi(x)} (Phi = +inf off dom).
 __global__ __launch_bounds__(NT) void k_cert_batch(const NodeParams *__restrict__ prm, const double *__restrict__ Xit,
-                                                   const double *__restrict__ H, int KS, int Nr,
+                                                   const double *__restrict__ H, int KS, int Nr, int rs,
                                                    const double *__restrict__ fsum, int nfb, int64_t p,
                                                    double *__restrict__ abuf, int32_t *__restrict__ sidx,
                                                    double *__restrict__ sval, double *__restrict__ out) {
@@ -402,11 +402,12 @@ __global__ __launch_bounds__(NT) void k_cert_batch(const NodeParams *__restrict_
                                       red, scan);
   __syncthreads();
   const int64_t plane = (int64_t)Nr * p;
-  const double inv = 1.0 / P.lambda2;
+  // w = X^T zeta / (2 lambda2): least squares zeta = 2 r and the planes hold X^T r
+  const double inv = (P.loss == kLsq ? 1.0 : 0.5) / P.lambda2;
   double s1[1] = {0.0};
   for (int64_t j = threadIdx.x; j < p; j += NT) {
     double h = 0.0;
-    for (int z = 0; z < KS; z++) h += H[(int64_t)z * plane + (int64_t)q * p + j];
+    for (int z = 0; z < KS; z++) h += H[(int64_t)z * plane + (int64_t)rs * q * p + j];
     const double wj = h * inv;
     const int sj = P.st[j];
     if (sj == kOne) s1[0] += huber(wj, P.M);
@@ -1369,12 +1370,13 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
 
 // ------------------------------------------------------------ batched node kernels
 //
-// One workgroup per node (grid = m).  u = X x and h = X^T r (r = y - u,
-// zeta = 2 r) come from the FP64 MFMA GEMMs of the batch, summed over the
-// reduction splits; Phi(x), Psi(zeta), the gap, restart and termination then
-// follow the single-node step exactly.  The host recomputes Phi and Psi of
-// every stopped node over the stored X with the single-node FP64 kernels.
-// Least squares.
+// One workgroup per node (grid = m).  The products come from the FP64 MFMA
+// GEMMs of the batch, summed over the reduction splits: least squares
+// h = X^T r (r = y - X x, zeta = 2 r); logistic h = X^T zeta (zeta =
+// -grad F(X x)) and X^T grad F at the momentum point, the two right-hand
+// sides of one GEMM.  Phi(x), Psi(zeta), the gap, restart and termination
+// then follow the single-node step exactly.  The host recomputes Phi and Psi
+// of every stopped node over the stored X (k_cert_batch).
 
 template <int EPT>
 __global__ __launch_bounds__(NT) void k_batch_init(const NodeParams *__restrict__ prmA, NodeState *SA, BatchBufs bb,
@@ -1446,9 +1448,10 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   load_packed_status<EPT>(sv, bb.stp + (int64_t)node * bb.stpw);
   // h = X^T r from the GEMM split partials (Gram mode: G x, turned into
   // h = b - G x below); x^k
-  const int64_t stride = (int64_t)bb.Nr * p;
+  const int64_t stride = (int64_t)bb.NrT * p;
   const int KS = *bb.ksp;
-  const double *__restrict__ Hn = bb.CT + off;
+  const bool lsq = bb.loss == kLsq;
+  const double *__restrict__ Hn = bb.CT + (int64_t)bb.rs * off;
   double h[EPT], xk[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
@@ -1481,9 +1484,10 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     Fk = wave_sum(Fk);
     negconj = wave_sum(negconj);
   }
-  // dual at x^k: w = h / lambda2 (= X^T zeta / (2 lambda2)); the top-kbar window
-  // of free |w| around the previous kbar-th value (as in the single-node step)
-  const double wscale = 1.0 / lam2;
+  // dual at x^k: w = X^T zeta / (2 lambda2) (least squares h / lambda2, logistic
+  // h / (2 lambda2)); the top-kbar window of free |w| around the previous
+  // kbar-th value (as in the single-node step)
+  const double wscale = (lsq ? 1.0 : 0.5) / lam2;
   const bool wv = tkp > 0.0 && kbar > 0;
   const double wa = wv ? tkp * (1.0 - dlt) : INFINITY, wb = wv ? tkp * (1.0 + dlt) : INFINITY;
   // r1: sum_{J1} H_M(w_j); Gram: x^T (b + h), b^T x; #{w > wb}, #{w >= wa}, sum_{w > wb} H_M(w)
@@ -1611,6 +1615,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     }
     lds.bcd[0] = m;
     lds.bci[0] = done;
+    lds.bci[1] = restart;
   }
   lds_barrier();
   const bool done = lds.bci[0] != 0;
@@ -1621,27 +1626,43 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
       if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xk[e];
     return;
   }
+  // gradient at the momentum point y = x^k + m (x^k - x^{k-1}):
+  //   least squares -2 ((1 + m) h_k - m h_{k-1}) by linearity (hq = h_{k-1});
+  //   logistic the second plane row of the node (hq), or -h at a restart (y = x^k)
   double *__restrict__ hp = bb.hprev + off;
+  const double *__restrict__ H2 = Hn + p;
   double xq[EPT], hq[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
     const uint32_t j = (uint32_t)(tid + e * NT);
     const bool in = j < (uint32_t)p;
     xq[e] = in ? xn[j] : 0.0;
-    hq[e] = in ? hp[j] : 0.0;
+    hq[e] = in ? (lsq ? hp[j] : H2[j]) : 0.0;
+  }
+  if (!lsq) {
+    for (int z = 1; z < KS; z++) {
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        if (j < (uint32_t)p) hq[e] += H2[z * stride + j];
+      }
+    }
   }
   const double m = lds.bcd[0];
+  const bool restart = lds.bci[1] != 0;
   const double invL = 1.0 / L;
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
     const double yj = xk[e] + m * (xk[e] - xq[e]);
-    const double gj = -2.0 * ((1.0 + m) * h[e] - m * hq[e]);
+    const double gj = lsq ? -2.0 * ((1.0 + m) * h[e] - m * hq[e]) : (restart ? -h[e] : hq[e]);
     hq[e] = h[e];
     h[e] = sv(e) != 3 ? yj - gj * invL : 0.0;  // h[] now holds v
   }
+  if (lsq) {
 #pragma unroll
-  for (int e = 0; e < EPT; e++)
-    if (sv(e) != 3) hp[(uint32_t)(tid + e * NT)] = hq[e];
+    for (int e = 0; e < EPT; e++)
+      if (sv(e) != 3) hp[(uint32_t)(tid + e * NT)] = hq[e];
+  }
   const double rho = 2.0 * lam2 * invL;
   int evals = 0;
   auto vabs = [&](int e) { return sv(e) == kFree ? fabs(h[e]) : -1.0; };
@@ -1800,10 +1821,10 @@ hipError_t launch_scale_copy(const double *src, double *dst, double a, int64_t n
   return hipGetLastError();
 }
 
-hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const double *H, int KS, int Nr,
+hipError_t launch_cert_batch(const NodeParams *prm, const double *Xit, const double *H, int KS, int Nr, int rs,
                              const double *fsum, int nfb, int64_t p, double *abuf, int32_t *sidx, double *sval,
                              double *out, int m, hipStream_t s) {
-  k_cert_batch<<<(unsigned)m, NT, 0, s>>>(prm, Xit, H, KS, Nr, fsum, nfb, p, abuf, sidx, sval, out);
+  k_cert_batch<<<(unsigned)m, NT, 0, s>>>(prm, Xit, H, KS, Nr, rs, fsum, nfb, p, abuf, sidx, sval, out);
   return hipGetLastError();
 }
 

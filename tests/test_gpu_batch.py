@@ -1,8 +1,10 @@
 """Batched node relaxations (pr_solve_batch): both products of the iteration
-are FP64 MFMA GEMMs over the BF16 design, every stopped node is re-certified
-over the stored X.  Checked node by node against the FP64 oracle on small
-instances, against the single-node GPU path, and at full size by the oracle
-re-certifying the returned (beta, bound) pairs."""
+are FP64 MFMA GEMMs over the stored design (BF16, FP32 or FP64; least squares
+or logistic, the latter with two right-hand sides per node in the transposed
+product), every stopped node is re-certified over the stored X.  Checked node
+by node against the FP64 oracle on small instances (converged bounds and
+few-step iterates), against the single-node GPU path, and at full size by the
+oracle re-certifying the returned (beta, bound) pairs."""
 import math
 
 import numpy as np
@@ -22,8 +24,74 @@ def _pr():
 def _ctx(dev, inst, max_batch):
     import torch
     pr = _pr()
-    X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    if inst.storage == "bf16":
+        X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        X = torch.from_numpy(inst.Xcm).to(dev)
     return pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
+
+
+def _zeta(inst, beta):
+    """Dual vector induced by beta: least squares 2 (y - X beta), logistic
+    -grad F(X beta) = y / (1 + exp(y X beta))."""
+    u = inst.X64().T @ beta
+    if inst.loss == 0:
+        return 2.0 * (inst.y - u)
+    return inst.y / (1.0 + np.exp(inst.y * u))
+
+
+@pytest.mark.parametrize("loss,storage", [(1, "bf16"), (1, "f32"), (1, "f64"), (0, "f32"), (0, "f64")])
+def test_batch_loss_and_storage_match_oracle_per_node(dev, loss, storage):
+    """Logistic nodes and FP32 / FP64 designs on the batched path: every node
+    converges to the oracle's bound, and Phi(beta) and Psi(zeta(beta)) of the
+    returned pair, recomputed by the oracle over the stored X, equal the
+    reported values."""
+    pr = _pr()
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=loss, seed=40 + loss, storage=storage)
+    ctx = _ctx(dev, inst, 16)
+    raw = make_nodes(inst.p, 11, seed=4, max_j0=40, max_j1=6)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-7, max_iter=20000)
+    B = B.cpu().numpy()
+    for i, (nd, r) in enumerate(zip(nodes, res)):
+        st = nd.status(inst.p)
+        ref = oracle.solve(inst.Xcm, inst.y, loss, 0.2, 2.0, 8, status=st, L=r["L"], tol=1e-10)
+        print(i, r["iters"], ref["iters"], r["lower_bound"], ref["lb"], r["rel_gap"], flush=True)
+        assert r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-7
+        assert abs(r["lower_bound"] - ref["lb"]) <= 1.5e-7 * abs(r["primal"])
+        assert r["lower_bound"] <= ref["ub"] * (1 + 1e-12)
+        phi = oracle.primal(inst.Xcm, inst.y, B[i], loss, 0.2, 2.0, 8, status=st)
+        psi = oracle.dual(inst.Xcm, inst.y, _zeta(inst, B[i]), loss, 0.2, 2.0, 8, status=st)
+        assert abs(phi - r["primal"]) <= 1e-11 * abs(phi)
+        assert abs(psi - r["lower_bound"]) <= 1e-10 * abs(phi)
+    ctx.close()
+
+
+@pytest.mark.parametrize("loss,storage", [(1, "f32"), (1, "bf16"), (0, "f64"), (0, "f32")])
+@pytest.mark.parametrize("K", [1, 6, 40])
+def test_batch_iterates_match_oracle(dev, loss, storage, K):
+    """After exactly K iterations (iteration limit, no convergence) each
+    node's returned iterate equals the oracle's x^K with the same step, to
+    FP64 summation-order differences: the batched momentum, restart and (for
+    logistic) gradient at the momentum point follow the method step by step."""
+    pr = _pr()
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=loss, seed=50 + loss, storage=storage)
+    ctx = _ctx(dev, inst, 16)
+    raw = make_nodes(inst.p, 7, seed=6, max_j0=40, max_j1=6)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-15, max_iter=K, check_every=2)
+    B = B.cpu().numpy()
+    for i, (nd, r) in enumerate(zip(nodes, res)):
+        st = nd.status(inst.p)
+        ref = oracle.solve(inst.Xcm, inst.y, loss, 0.2, 2.0, 8, status=st, L=r["L"], tol=-1.0, max_iter=K)
+        assert r["status"] == pr.MAXITER and r["iters"] == K == ref["iters"]
+        # the oracle also tests the restart at its last iterate, the batch stops first
+        assert ref["restarts"] - 1 <= r["restarts"] <= ref["restarts"]
+        scale = max(1.0, float(np.max(np.abs(ref["beta"]))))
+        err = float(np.max(np.abs(B[i] - ref["beta"])))
+        print(K, i, r["restarts"], ref["restarts"], err, flush=True)
+        assert err <= 1e-12 * scale
+    ctx.close()
 
 
 @pytest.fixture(scope="module")
@@ -177,3 +245,26 @@ def test_gemm_rejects_bad_shapes(dev):
     A = torch.zeros(128, 64, dtype=torch.bfloat16, device=dev)
     with pytest.raises(pr.PrError):
         pr.gemm(A, B, KS=3)     # K not a multiple of 32 * KS
+
+
+def test_batch_full_size_logistic_fp32(dev):
+    """64 logistic nodes on the FP32 n=32768, p=16384 design: every node
+    converges on the batched path, and the oracle recomputes Phi and Psi at
+    the returned pairs of 4 seeded nodes over the stored X."""
+    pr = _pr()
+    inst = config_instance("logistic_root_n32768_p16384_f32")
+    ctx = _ctx(dev, inst, 64)
+    raw = make_nodes(inst.p, 64, seed=2, max_j0=64, max_j1=14)
+    nodes = [pr.Node(15, 0.1, 2.0, J0=a, J1=b) for a, b in raw]
+    res, B = ctx.solve_batch(nodes, max_iter=6000)
+    print("iters", sorted(r["iters"] for r in res)[::8], "union", ctx.batch_union_size(), flush=True)
+    assert all(r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-6 for r in res)
+    for i in np.random.default_rng(1).choice(64, 4, replace=False):
+        st = nodes[i].status(inst.p)
+        beta = B[i].cpu().numpy()
+        phi = oracle.primal(inst.Xcm, inst.y, beta, 1, 0.1, 2.0, 15, status=st)
+        psi = oracle.dual(inst.Xcm, inst.y, _zeta(inst, beta), 1, 0.1, 2.0, 15, status=st)
+        assert abs(phi - res[i]["primal"]) <= 1e-10 * abs(phi)
+        assert abs(psi - res[i]["lower_bound"]) <= 1e-10 * abs(phi)
+        assert 0.0 <= (phi - psi) / abs(phi) <= 1e-6
+    ctx.close()

@@ -124,13 +124,14 @@ def test_bnb_on_the_batched_path(dev):
     ctx.close()
 
 
-def test_batched_cutoff_decisions_match_oracle(dev):
+@pytest.mark.parametrize("loss,storage,seed", [(0, "bf16", 10), (1, "f32", 11)])
+def test_batched_cutoff_decisions_match_oracle(dev, loss, storage, seed):
     """Batched dynamic termination against the oracle's decisions: each node's
     relaxation value is at least 1% away from the cutoff, so prune (value above
     the cutoff) or branch (below) is the only correct outcome, and the oracle
     run with the same step reaches it at (nearly) the same iterate."""
     import paper_2603_01306_amd as pr
-    inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=0, seed=10, storage="bf16")
+    inst = make_instance(n=1024, p=512, corr=0.6, k_true=6, snr=5.0, loss=loss, seed=seed, storage=storage)
     ctx = _ctx(inst, dev, 16)
     rng = np.random.default_rng(0)
     # fixed-zero sets of growing size spread the nodes' relaxation values
@@ -146,7 +147,7 @@ def test_batched_cutoff_decisions_match_oracle(dev):
     kinds = set()
     for q, (nd, r, f) in enumerate(zip(nodes, res, free)):
         st = nd.status(inst.p)
-        ref = oracle.solve(inst.Xcm, inst.y, 0, 0.5, 2.0, 6, status=st, L=r["L"], tol=1e-9, cutoff=cutoff)
+        ref = oracle.solve(inst.Xcm, inst.y, loss, 0.5, 2.0, 6, status=st, L=r["L"], tol=1e-9, cutoff=cutoff)
         assert r["status"] == ref["status"], (q, r, ref["status"])
         assert abs(r["iters"] - ref["iters"]) <= 2
         kinds.add(r["status"])
@@ -154,7 +155,34 @@ def test_batched_cutoff_decisions_match_oracle(dev):
             assert r["lower_bound"] >= cutoff and ref["lb"] >= cutoff
         else:
             assert r["status"] == pr.CUTOFF_BRANCH and r["primal"] <= cutoff
-            phi = oracle.primal(inst.Xcm, inst.y, Bh[q], 0, 0.5, 2.0, 6, status=st)
+            phi = oracle.primal(inst.Xcm, inst.y, Bh[q], loss, 0.5, 2.0, 6, status=st)
             assert abs(phi - r["primal"]) <= 1e-11 * abs(phi)
     assert kinds == {pr.CUTOFF_PRUNE, pr.CUTOFF_BRANCH}
     ctx.close()
+
+
+def test_logistic_bnb_on_the_batched_path(dev):
+    """Logistic branch and bound on an FP32 design whose nodes run on the
+    batched path (two right-hand sides per node in the transposed product):
+    the same certified interval as the branch and bound whose nodes run one at
+    a time, and an exact incumbent objective."""
+    import paper_2603_01306_amd as pr
+    inst = make_instance(n=1024, p=256, corr=0.5, k_true=4, snr=5.0, loss=1, seed=12, storage="f32")
+    X, y = inst.X64().T, inst.y
+    out = []
+    for mb in (32, 1):
+        ctx = _ctx(inst, dev, mb)
+        res, beta = ctx.bnb(pr.Node(4, 0.5, 2.0), rel_gap_tol=1e-4, max_nodes=600)
+        print(mb, res, flush=True)
+        b = beta.cpu().numpy()
+        assert np.count_nonzero(b) <= 4
+        obj = float(np.sum(np.logaddexp(0.0, -y * (X @ b))) + 0.5 * b @ b)
+        assert abs(obj - res["upper_bound"]) <= 1e-10 * res["upper_bound"]
+        assert res["lower_bound"] <= res["upper_bound"] * (1 + 1e-12)
+        out.append(res)
+        ctx.close()
+    a, b = out
+    assert a["status"] == b["status"]
+    assert a["lower_bound"] <= b["upper_bound"] * (1 + 1e-9) and b["lower_bound"] <= a["upper_bound"] * (1 + 1e-9)
+    if a["status"] == pr.BNB_OPTIMAL:
+        assert abs(a["upper_bound"] - b["upper_bound"]) <= 1e-4 * b["upper_bound"]
