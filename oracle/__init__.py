@@ -74,6 +74,9 @@ def lib():
         L.orc_solve_acfgm.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p,
                                       _d, _d, _d, ctypes.c_int, _d, _d, _i64, _p, _p, _p, _p, _p, _p, _p, _p,
                                       _i64]
+        L.orc_solve_bt.restype = ctypes.c_int
+        L.orc_solve_bt.argtypes = [_p, ctypes.c_int, _p, _i64, _i64, ctypes.c_int, _d, _d, _i32, _p,
+                                   _d, _d, _d, ctypes.c_int, _d, _d, _i64, _d, _p, _p, _p, _p, _p, _p, _p, _i64]
         L.orc_lasso_G.restype = _d
         L.orc_lasso_G.argtypes = [ctypes.c_int, _p, _i64, _d]
         L.orc_lasso_Gstar.restype = _d
@@ -293,6 +296,39 @@ def solve_acfgm(Xcm, y, kind, lambda2, M, k, status=None, L0=1.0, c=2.0, b=0.1, 
                status=int(res[6]), rejected=int(res[7]), beta=beta, zeta=zeta)
     if trace_cap > 0:
         out.update(trace=tr[0][:m], phi_trace=tr[1][:m], lhat=tr[2][:m], step=tr[3][:m])
+    return out
+
+
+def solve_bt(Xcm, y, kind, lambda2, M, k, status=None, L0=1.0, c=2.0, Lmax=None, restart=True, tol=1e-8,
+             eta=math.exp(3.0), max_iter=100000, cutoff=float("nan"), beta0=None, trace_cap=0):
+    """FISTA with backtracking (Beck's monotone rule from L0, factor c, capped
+    at Lmax: default the loss curvature times ||X||_2^2 by power iteration)
+    and, if `restart`, the duality-gap restart.  Returns lb, ub, rel_gap, L
+    (final), iters (accepted), restarts, status, rejected, beta (last
+    iterate), zeta (dual vector attaining lb), and with trace_cap > 0 per
+    accepted iterate: trace (gap), phi_trace, L_trace."""
+    X, code, n, p = _xinfo(Xcm)
+    y = _f64(y)
+    s = _st(status, p)
+    if Lmax is None:
+        nrm = lib().orc_power_norm2(_ptr(X), code, n, p, 2000, 1e-12)
+        Lmax = (2.0 if kind == LSQ else 0.25) * nrm
+    b0 = None if beta0 is None else _f64(beta0)
+    beta = np.empty(p)
+    zeta = np.empty(n)
+    res = np.zeros(8)
+    tr = [np.full(max(trace_cap, 1), np.nan) for _ in range(3)]
+    rc = lib().orc_solve_bt(_ptr(X), code, _ptr(y), n, p, int(kind), float(lambda2), float(M), int(k), _ptr(s),
+                            float(L0), float(c), float(Lmax), int(bool(restart)), float(tol), float(eta),
+                            int(max_iter), float(cutoff), None if b0 is None else _ptr(b0), _ptr(beta), _ptr(zeta),
+                            _ptr(res), *[(_ptr(a) if trace_cap > 0 else None) for a in tr], int(trace_cap))
+    if rc < 0:
+        raise ValueError("solve_bt: needs L0 > 0, c > 1 and Lmax >= L0")
+    m = int(res[4]) + 1
+    out = dict(lb=res[0], ub=res[1], rel_gap=res[2], L=res[3], iters=int(res[4]), restarts=int(res[5]),
+               status=int(res[6]), rejected=int(res[7]), beta=beta, zeta=zeta, Lmax=float(Lmax))
+    if trace_cap > 0:
+        out.update(trace=tr[0][:m], phi_trace=tr[1][:m], L_trace=tr[2][:m])
     return out
 
 

@@ -570,6 +570,192 @@ int orc_solve(const void *X, int xdt, const double *y, int64_t n, int64_t p, int
   return status;
 }
 
+/* Euclidean distance of two m-vectors. */
+static double orc_dist(const double *a, const double *b, int64_t m) {
+  double s = 0.0;
+  for (int64_t j = 0; j < m; j++) s += (a[j] - b[j]) * (a[j] - b[j]);
+  return sqrt(s);
+}
+
+/* ------------------------------------------- FISTA with backtracking */
+
+/* Bregman remainder of F between two points u (at x) and w (at y) in the
+ * image of X: F(u) - F(w) - <grad F(w), u - w>, summed row by row.  For the
+ * smooth part f(beta) = F(X beta) this is f(x) - f(y) - <grad f(y), x - y>,
+ * the quantity bounded by the quadratic model of a step 1/L.  Least squares:
+ * (u_i - w_i)^2 exactly.  Logistic: with a = -y_i w_i and d = -y_i (u_i -
+ * w_i), log(1 + exp(a + d)) - log(1 + exp(a)) - sigma(a) d, the first
+ * difference taken as log1p(sigma(a) expm1(d)) so that it carries no
+ * cancellation of the two softplus values. */
+static double orc_bregman(int loss, const double *u, const double *w, const double *y, int64_t n) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    if (loss == ORC_LSQ) {
+      s += (u[i] - w[i]) * (u[i] - w[i]);
+    } else {
+      const double a = -y[i] * w[i], d = -y[i] * (u[i] - w[i]);
+      const double sg = 1.0 / (1.0 + exp(-a));
+      s += log1p(sg * expm1(d)) - sg * d;
+    }
+  }
+  return s;
+}
+
+/* FISTA with backtracking (Beck, "First-Order Methods in Optimization",
+ * 2017, Section 10.7, the monotone backtracking rule), the "FISTA with line
+ * search" of Section 5 that the paper runs with its duality-gap restart.
+ * From the momentum point y with gradient grad f(y), the step constant L
+ * starts from the previous one and is multiplied by c until the trial
+ * x = prox_{(2 lambda2 / L) g_N}(y - grad f(y) / L) satisfies the
+ * quadratic-model condition
+ *     f(x) <= f(y) + <grad f(y), x - y> + (L / 2) ||x - y||^2,
+ * tested in the Bregman form above; L never exceeds Lmax (a Lipschitz
+ * constant of grad f, where the condition holds by itself: a trial at Lmax is
+ * accepted).  The accepted trial is the next iterate; momentum, the bounds,
+ * the stopping test and the dynamic termination are those of orc_solve at
+ * the accepted iterates; rejected trials are not evaluated.  With restart_gap
+ * the duality-gap restart runs the method afresh from the restart iterate:
+ * t <- 1, y <- x and the line search starts again from L0.  restart_gap = 0
+ * runs plain FISTA with backtracking.
+ *
+ * res[0..7] = {LB, UB, rel_gap, final L, iterations (accepted), restarts,
+ * status, rejected trials}.  Traces (length trace_cap, optional) per accepted
+ * iterate: Phi - Psi, Phi, and the L of the step that produced it (L0 at the
+ * start point). */
+int orc_solve_bt(const void *X, int xdt, const double *y, int64_t n, int64_t p, int loss, double lambda2,
+                 double M, int32_t k, const int8_t *st, double L0, double c, double Lmax, int restart_gap,
+                 double tol, double eta, int64_t max_iter, double cutoff, const double *beta0, double *beta_out,
+                 double *zeta_out, double *res, double *trace, double *phi_trace, double *L_trace,
+                 int64_t trace_cap) {
+  int64_t pbar, kbar;
+  for (int i = 0; i < 8; i++) res[i] = 0.0;
+  if (orc_node_dims(st, p, k, &pbar, &kbar) < 0) {
+    res[0] = INFINITY;
+    res[1] = INFINITY;
+    res[6] = ORC_INFEASIBLE;
+    for (int64_t j = 0; j < p; j++) beta_out[j] = 0.0;
+    return ORC_INFEASIBLE;
+  }
+  if (!(L0 > 0.0) || !(c > 1.0) || !(Lmax >= L0)) return -1;
+  double *x = (double *)calloc((size_t)p, sizeof(double));
+  double *xn = (double *)malloc(sizeof(double) * (size_t)p);
+  double *yv = (double *)malloc(sizeof(double) * (size_t)p);
+  double *gp = (double *)malloc(sizeof(double) * (size_t)p);
+  double *vv = (double *)malloc(sizeof(double) * (size_t)p);
+  double *uy = (double *)malloc(sizeof(double) * (size_t)n);
+  double *ux = (double *)malloc(sizeof(double) * (size_t)n);
+  double *gn = (double *)malloc(sizeof(double) * (size_t)n);
+  double *zeta = (double *)malloc(sizeof(double) * (size_t)n);
+  if (beta0)
+    for (int64_t j = 0; j < p; j++) x[j] = beta0[j];
+  memcpy(yv, x, sizeof(double) * (size_t)p);
+  double t = 1.0, L = L0;
+
+  /* (Phi, Psi) at the iterate x from u = X x */
+#define ORC_EVAL_BT(PHI, PSI)                                                  \
+  do {                                                                         \
+    orc_loss_grad(loss, ux, y, n, gn);                                         \
+    for (int64_t i_ = 0; i_ < n; i_++) zeta[i_] = -gn[i_];                     \
+    PSI = orc_dual(X, xdt, y, n, p, loss, lambda2, M, k, st, zeta);            \
+    PHI = orc_in_dom(x, st, p, k, M, 1e-9)                                     \
+              ? orc_loss(loss, ux, y, n) + 2.0 * lambda2 * orc_g(x, st, p, k)  \
+              : INFINITY;                                                      \
+  } while (0)
+
+  double Phi, Psi;
+  orc_matvec(X, xdt, n, p, x, ux);
+  ORC_EVAL_BT(Phi, Psi);
+  double LB = Psi, UB = Phi, gap_ref = Phi - Psi;
+  memcpy(zeta_out, zeta, sizeof(double) * (size_t)n);
+  if (trace_cap > 0) {
+    if (trace) trace[0] = Phi - Psi;
+    if (phi_trace) phi_trace[0] = Phi;
+    if (L_trace) L_trace[0] = L;
+  }
+  int64_t it = 0, restarts = 0, rejected = 0;
+  int status = ORC_MAXITER;
+  double rel = (UB - LB) / fmax(fabs(UB), 1e-300);
+  if (rel <= tol) status = ORC_CONVERGED;
+  else if (!isnan(cutoff) && LB >= cutoff) status = ORC_CUTOFF_PRUNE;
+  else if (!isnan(cutoff) && UB <= cutoff) status = ORC_CUTOFF_BRANCH;
+  while (status == ORC_MAXITER && it < max_iter) {
+    it++;
+    /* gradient of f at the momentum point */
+    orc_matvec(X, xdt, n, p, yv, uy);
+    orc_loss_grad(loss, uy, y, n, gn);
+    orc_rmatvec(X, xdt, n, p, gn, gp);
+    for (;;) {
+      for (int64_t j = 0; j < p; j++) vv[j] = yv[j] - gp[j] / L;
+      orc_prox_g(vv, st, p, 2.0 * lambda2 / L, k, M, xn);
+      orc_matvec(X, xdt, n, p, xn, ux);
+      if (L >= Lmax) break;
+      const double dxy = orc_dist(xn, yv, p);
+      if (orc_bregman(loss, ux, uy, y, n) <= 0.5 * L * dxy * dxy) break;
+      L = fmin(c * L, Lmax);
+      rejected++;
+    }
+    double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    double mom = (t - 1.0) / tn;
+    for (int64_t j = 0; j < p; j++) {
+      yv[j] = xn[j] + mom * (xn[j] - x[j]);
+      x[j] = xn[j];
+    }
+    t = tn;
+    ORC_EVAL_BT(Phi, Psi);
+    if (Psi > LB) {
+      LB = Psi;
+      memcpy(zeta_out, zeta, sizeof(double) * (size_t)n);
+    }
+    if (Phi < UB) UB = Phi;
+    double gap = Phi - Psi;
+    if (it < trace_cap) {
+      if (trace) trace[it] = gap;
+      if (phi_trace) phi_trace[it] = Phi;
+      if (L_trace) L_trace[it] = L;
+    }
+    rel = (UB - LB) / fmax(fabs(UB), 1e-300);
+    if (rel <= tol) {
+      status = ORC_CONVERGED;
+      break;
+    }
+    if (!isnan(cutoff) && LB >= cutoff) {
+      status = ORC_CUTOFF_PRUNE;
+      break;
+    }
+    if (!isnan(cutoff) && UB <= cutoff) {
+      status = ORC_CUTOFF_BRANCH;
+      break;
+    }
+    if (restart_gap && gap <= gap_ref / eta) {
+      gap_ref = gap;
+      memcpy(yv, x, sizeof(double) * (size_t)p);
+      t = 1.0;
+      L = L0;
+      restarts++;
+    }
+  }
+#undef ORC_EVAL_BT
+  memcpy(beta_out, x, sizeof(double) * (size_t)p);
+  res[0] = LB;
+  res[1] = UB;
+  res[2] = (UB - LB) / fmax(fabs(UB), 1e-300);
+  res[3] = L;
+  res[4] = (double)it;
+  res[5] = (double)restarts;
+  res[6] = (double)status;
+  res[7] = (double)rejected;
+  free(x);
+  free(xn);
+  free(yv);
+  free(gp);
+  free(vv);
+  free(uy);
+  free(ux);
+  free(gn);
+  free(zeta);
+  return status;
+}
+
 /* ------------------------------------------------------------ AC-FGM */
 
 /* Gradient of f(beta) = F(X beta) at x (p-vector g), the induced dual vector
@@ -583,12 +769,6 @@ static void orc_eval_point(const void *X, int xdt, const double *y, int64_t n, i
   for (int64_t i = 0; i < n; i++) zeta[i] = -zeta[i];
   *Fx = orc_loss(loss, u, y, n);
   *Psi = orc_dual(X, xdt, y, n, p, loss, lambda2, M, k, st, zeta);
-}
-
-static double orc_dist(const double *a, const double *b, int64_t m) {
-  double s = 0.0;
-  for (int64_t j = 0; j < m; j++) s += (a[j] - b[j]) * (a[j] - b[j]);
-  return sqrt(s);
 }
 
 /* AC-FGM (accelerated composite fast gradient method of Li and Lan, "A simple
