@@ -7,6 +7,10 @@ standardised columns, k = 20 unit coefficients equally spaced, SNR 5,
 lambda2 = 0.1, k = 20, M = 2, relative gap 1e-6.  Inputs are resident in HBM
 before the timed region; the per-matrix setup (||X||^2 by Lanczos,
 shared by every node of a tree) runs before it and is reported separately.
+The root solves run the paper's method, FISTA with line search (backtracking
+from L/16, capped at L) and the duality-gap restart; "fixed_step" reports
+FISTA with the fixed step 1/L on the same root (--method fixed makes it the
+headline).  The batched solves use the fixed step.
 
 Also reported: the dominant kernel (X^T r, FP64 accumulation) against the
 HBM roofline, timed with HIP events on the stream it runs on, and the FP64
@@ -50,6 +54,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "ls_root_n16384_p8192_f32"
+# iteration of the root solves: the paper's FISTA with line search (backtracking)
+# and the duality-gap restart; --method fixed runs FISTA with the fixed step 1/L
+SOLVE_KW = {"method": 6}
+METHOD_NAME = {6: "fista_backtracking_gap_restart", 0: "fista_fixed_step_gap_restart"}
 BATCH_WORKLOAD = "ls_batch256_n16384_p8192_bf16"
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
@@ -175,22 +183,33 @@ def mlp_probe(rows=1 << 20, reps=10):
                       "tflops_mfma_shaped": round(flop / (ms * 1e-3) / 1e12, 2)}), flush=True)
 
 
-def cpu_baseline(inst, cfg, gpu_iters_per_solve, budget_s=20.0):
-    """The FP64 oracle (FISTA + gap restart, dense textbook products) on the
-    host: time a bounded number of its iterations on the same instance and
-    convert to solves/s with the iteration count of a full solve."""
+def _oracle_iters(inst, cfg, loss, iters, Lmax):
+    """iters oracle iterations of the bench's method on the instance (no stopping)."""
+    import oracle
+    if SOLVE_KW["method"] == 6:
+        return oracle.solve_bt(inst.Xcm, inst.y, loss, cfg["lambda2"], cfg["M"], cfg["k"], L0=Lmax / 16.0, c=2.0,
+                               Lmax=Lmax, tol=-1.0, max_iter=iters)
+    return oracle.solve(inst.Xcm, inst.y, loss, cfg["lambda2"], cfg["M"], cfg["k"], L=Lmax, tol=0.0, max_iter=iters)
+
+
+def cpu_baseline(inst, cfg, gpu_iters_per_solve, Lmax, budget_s=20.0):
+    """The FP64 oracle (the bench's method with dense textbook products) on
+    the host: time a bounded number of its iterations on the same instance
+    (same step cap; with backtracking the sample's rejected trials included)
+    and convert to solves/s with the iteration count of a full GPU solve."""
     import oracle
     t0 = time.perf_counter()
-    oracle.solve(inst.Xcm, inst.y, 0, cfg["lambda2"], cfg["M"], cfg["k"], L=1.0, tol=0.0, max_iter=1)
+    _oracle_iters(inst, cfg, 0, 1, Lmax)
     t1 = time.perf_counter() - t0
     iters = max(2, min(40, int(budget_s / max(t1 / 2.0, 1e-3))))
     t0 = time.perf_counter()
-    oracle.solve(inst.Xcm, inst.y, 0, cfg["lambda2"], cfg["M"], cfg["k"], L=1.0, tol=0.0, max_iter=iters)
+    r = _oracle_iters(inst, cfg, 0, iters, Lmax)
     dt = time.perf_counter() - t0
     it_s = iters / dt
     return {"value": it_s / gpu_iters_per_solve, "unit": "node relaxations/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": (f"{iters} oracle FISTA iterations on the full {WORKLOAD} instance in {dt:.1f} s "
+            "sample": (f"{iters} oracle iterations ({METHOD_NAME[SOLVE_KW['method']]}, "
+                       f"{r.get('rejected', 0)} rejected trials) on the full {WORKLOAD} instance in {dt:.1f} s "
                        f"({it_s:.3f} it/s), divided by the {gpu_iters_per_solve:.0f} iterations a full "
                        f"solve to 1e-6 takes")}
 
@@ -214,14 +233,15 @@ def c1_bench(dev, steps, with_cpu):
     ctx = pr.Context(torch.from_numpy(inst.Xcm).to(dev), torch.from_numpy(inst.y).to(dev), pr.LSQ)
     node = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
     for _ in range(3):
-        ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"])
+        ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"]) for _ in range(steps)]
+    res = [ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     iters = sum(r["iters"] for r in res)
     out = {"workload": C1_WORKLOAD, "n": inst.n, "p": inst.p, "x_storage": "f64", "loss": "least_squares",
+           "method": METHOD_NAME[SOLVE_KW["method"]], "trials_per_solve": sum(r["trials"] for r in res) / steps,
            "rel_gap_tol": cfg["tol"], "value": round(steps / dt, 2), "unit": "node relaxations/s", "steps": steps,
            "ms_per_step": round(1e3 * dt / steps, 3), "iters_per_solve": iters / steps,
            "iters_per_s": round(iters / dt, 1), "us_per_iter": round(1e6 * dt / iters, 2),
@@ -230,8 +250,12 @@ def c1_bench(dev, steps, with_cpu):
     if with_cpu:
         import oracle
         t0 = time.perf_counter()
-        ref = oracle.solve(inst.Xcm, inst.y, 0, cfg["lambda2"], cfg["M"], cfg["k"], L=res[-1]["L"],
-                           tol=cfg["tol"])
+        Lmax = 1.01 * 2.0 * ctx.norm2()
+        if SOLVE_KW["method"] == 6:
+            ref = oracle.solve_bt(inst.Xcm, inst.y, 0, cfg["lambda2"], cfg["M"], cfg["k"], L0=Lmax / 16.0, c=2.0,
+                                  Lmax=Lmax, tol=cfg["tol"])
+        else:
+            ref = oracle.solve(inst.Xcm, inst.y, 0, cfg["lambda2"], cfg["M"], cfg["k"], L=Lmax, tol=cfg["tol"])
         dto = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(1.0 / dto, 3), "unit": "node relaxations/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
@@ -243,7 +267,59 @@ def c1_bench(dev, steps, with_cpu):
     return out
 
 
-def logistic_bench(dev, steps, with_cpu, budget_s=15.0):
+def logistic_batch_bench(dev, inst, cfg, ctx1, X, y, m, steps, n_single=4):
+    """m logistic nodes of the branch-and-bound shape (fixed-zero sets of 0-64
+    and fixed-one sets of 0-14 coordinates, seeded) on the same design, solved
+    together by pr_solve_batch (two right-hand sides per node in the X^T R
+    GEMM) and, for the first n_single nodes, one at a time on the single-node
+    path of ctx1, all to the same FP64 gap."""
+    import numpy as np
+    import torch
+    import paper_2603_01306_amd as pr
+    from workloads import make_nodes
+    raw = make_nodes(inst.p, m, seed=2, max_j0=64, max_j1=cfg["k"] - 1)
+    nodes = [pr.Node(cfg["k"], cfg["lambda2"], cfg["M"], J0=a, J1=b) for a, b in raw]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [ctx1.solve(nd, want_beta=False, rel_gap_tol=cfg["tol"]) for nd in nodes[:n_single]]
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx = pr.Context(X, y, pr.LOGISTIC, max_batch=m)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])       # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    res = runs[-1]
+    it = np.array([r["iters"] for r in res])
+    ms_f, ms_t = ctx.time_batch_gemm(m, reps=5)
+    nr2 = (2 * m + 63) // 64 * 64
+    flop = 2.0 * inst.n * inst.p * nr2
+    ach = flop / (ms_t * 1e-3) / 1e12
+    lbd = max(abs(a["lower_bound"] - b["lower_bound"]) / abs(b["primal"]) for a, b in zip(res, single))
+    out = {"nodes": m, "value": round(m * steps / dt_b, 3), "unit": "node relaxations/s", "steps": steps,
+           "ms_per_step": round(1e3 * dt_b / steps, 2), "context_setup_s": round(setup_s, 3),
+           "all_converged": all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for run in runs for r in run),
+           "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 1),
+           "union": list(ctx.batch_union_size()),
+           "single_path": {"value": round(n_single / dt_s, 3), "unit": "node relaxations/s", "nodes": n_single,
+                           "all_converged": all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in single),
+                           "iters_mean": round(sum(r["iters"] for r in single) / n_single, 1),
+                           "max_rel_bound_diff_vs_batch": lbd},
+           "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(ach / FP64_MFMA_PEAK_TFS, 4), "traffic": None,
+                        "kernel": "k_gemm_f64<float,double> (X^T R, 2 rows per node)", "flop_per_launch": flop,
+                        "avg_launch_ms": round(ms_t, 4), "forward_avg_launch_ms": round(ms_f, 4)}}
+    out["speedup_vs_single"] = round(out["value"] / out["single_path"]["value"], 2)
+    ctx.close()
+    return out
+
+
+def logistic_bench(dev, steps, with_cpu, budget_s=15.0, batch_nodes=64):
     """The logistic root relaxation (n = 32768, p = 16384, FP32 X, rows with
     Sigma_ij = 0.7^|i-j|, labels sign(X beta* + noise) at SNR 5, lambda2 = 0.1,
     k = 15, M = 2) to a 1e-6 FP64 gap; its dominant kernel is the
@@ -264,38 +340,52 @@ def logistic_bench(dev, steps, with_cpu, budget_s=15.0):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     node = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
-    ctx.solve(node, want_beta=False)
+    ctx.solve(node, want_beta=False, **SOLVE_KW)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [ctx.solve(node, want_beta=False) for _ in range(steps)]
+    res = [ctx.solve(node, want_beta=False, **SOLVE_KW) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     iters = sum(r["iters"] for r in res)
+    trials = sum(r["trials"] for r in res)
+    # the fixed-step method on the same root, for reference
+    t0 = time.perf_counter()
+    fx = ctx.solve(node, want_beta=False)
+    torch.cuda.synchronize()
+    dt_fx = time.perf_counter() - t0
     r = torch.randn(inst.n, dtype=torch.float64, device=dev)
     ms = ctx.time_gemv_t(r, reps=20)
     per_launch = inst.n * inst.p * 4 + 16 * inst.n + 16 * inst.p
     ach = per_launch / (ms * 1e-3) / 1e9
     out = {"workload": C3_WORKLOAD, "n": inst.n, "p": inst.p, "x_storage": "f32", "loss": "logistic",
            "corr": cfg["corr"], "k": cfg["k"], "lambda2": cfg["lambda2"], "M": cfg["M"], "rel_gap_tol": cfg["tol"],
+           "method": METHOD_NAME[SOLVE_KW["method"]],
            "value": round(steps / dt, 3), "unit": "node relaxations/s", "steps": steps,
            "ms_per_step": round(1e3 * dt / steps, 2), "iters_per_solve": iters / steps,
-           "iters_per_s": round(iters / dt, 1), "us_per_iter": round(1e6 * dt / iters, 1),
+           "trials_per_solve": trials / steps,
+           "iters_per_s": round(iters / dt, 1), "us_per_evaluation": round(1e6 * dt / (iters + trials), 1),
            "all_converged": all(q["status"] == 1 and q["rel_gap"] <= cfg["tol"] for q in res),
            "lower_bound": res[-1]["lower_bound"], "setup_s_per_matrix": round(setup_s, 3),
+           "fixed_step": {"value": round(1.0 / dt_fx, 3), "unit": "node relaxations/s", "iters": fx["iters"],
+                          "lower_bound": fx["lower_bound"], "converged": fx["status"] == 1},
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4),
                         "traffic": _traffic_from_summary(PMC_SUMMARY_LOGISTIC),
                         "kernel": "k_gemv_t<float,2>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}}
+    if batch_nodes > 0:
+        out["batch"] = logistic_batch_bench(dev, inst, cfg, ctx, X, y, batch_nodes, max(1, min(2, steps)))
+    nrm2 = ctx.norm2()
     ctx.close()
     del X, y
     if with_cpu:
         import oracle
         t0 = time.perf_counter()
-        oracle.solve(inst.Xcm, inst.y, 1, cfg["lambda2"], cfg["M"], cfg["k"], L=1.0, tol=0.0, max_iter=1)
+        Lmax = 1.01 * 0.25 * nrm2
+        _oracle_iters(inst, cfg, 1, 1, Lmax)
         t1 = time.perf_counter() - t0
         its = max(2, min(20, int(budget_s / max(t1 / 2.0, 1e-3))))
         t0 = time.perf_counter()
-        oracle.solve(inst.Xcm, inst.y, 1, cfg["lambda2"], cfg["M"], cfg["k"], L=1.0, tol=0.0, max_iter=its)
+        _oracle_iters(inst, cfg, 1, its, Lmax)
         dto = time.perf_counter() - t0
         it_s = its / dto
         out["cpu_baseline"] = {"value": it_s / (iters / steps), "unit": "node relaxations/s",
@@ -306,9 +396,10 @@ def logistic_bench(dev, steps, with_cpu, budget_s=15.0):
     return out
 
 
-def batch_bench(dev, steps, n_single=16):
+def batch_bench(dev, steps, n_single=16, inst_f32=None):
     """Nodes/s of pr_solve_batch on the 256-node workload and of the single-node
-    path on its first n_single nodes, both to the same FP64 gap."""
+    path on its first n_single nodes, both to the same FP64 gap; with inst_f32
+    (the same design stored in FP32) the 256 nodes again on FP32 X."""
     import numpy as np
     import torch
     import paper_2603_01306_amd as pr
@@ -381,6 +472,30 @@ def batch_bench(dev, steps, n_single=16):
                                 "kernel": "k_gemm_f64<double,double> (G X_it)", "flop_per_launch": flop_g,
                                 "avg_launch_ms": round(ms_g, 4)}}
     ctx.close()
+    if inst_f32 is not None:
+        Xf = torch.from_numpy(inst_f32.Xcm).to(dev)
+        ctx = pr.Context(Xf, torch.from_numpy(inst_f32.y).to(dev), pr.LSQ, max_batch=m)
+        ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])      # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fruns = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt_f = time.perf_counter() - t0
+        fit = np.array([r["iters"] for r in fruns[-1]])
+        ms_ff, ms_ft = ctx.time_batch_gemm(m, reps=10)
+        ach_f = flop / (ms_ft * 1e-3) / 1e12
+        out["fp32"] = {"x_storage": "f32", "value": round(m * steps / dt_f, 3), "unit": "node relaxations/s",
+                       "steps": steps, "ms_per_step": round(1e3 * dt_f / steps, 2),
+                       "all_converged": all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"]
+                                            for run in fruns for r in run),
+                       "iters_mean": round(float(fit.mean()), 1), "union": list(ctx.batch_union_size()),
+                       "roofline": {"bound": "mfma", "achieved": round(ach_f, 2), "peak": FP64_MFMA_PEAK_TFS,
+                                    "unit": "TFLOP/s", "frac": round(ach_f / FP64_MFMA_PEAK_TFS, 4),
+                                    "traffic": None, "kernel": "k_gemm_f64<float,double> (X^T R)",
+                                    "flop_per_launch": flop, "avg_launch_ms": round(ms_ft, 4),
+                                    "forward_avg_launch_ms": round(ms_ff, 4)}}
+        ctx.close()
+        del Xf
     return out
 
 
@@ -395,10 +510,10 @@ def gram_bench(ctx, node, cfg, steps, ref):
     ctx.enable_gram()
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
-    ctx.solve(node, want_beta=False)
+    ctx.solve(node, want_beta=False, **SOLVE_KW)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [ctx.solve(node, want_beta=False) for _ in range(steps)]
+    res = [ctx.solve(node, want_beta=False, **SOLVE_KW) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     iters = sum(r["iters"] for r in res)
@@ -741,11 +856,15 @@ def main():
     ap.add_argument("--kernel-probe-logistic", action="store_true")
     ap.add_argument("--mlp-probe", action="store_true", help="time the network's training kernel, for counter runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--method", choices=("bt", "fixed"), default="bt",
+                    help="root solves: FISTA with backtracking (the paper's line search; default) or fixed step")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed pr_solve_batch calls (0 skips the batch)")
     ap.add_argument("--gram-steps", type=int, default=10, help="timed root solves in Gram mode (0 skips them)")
     ap.add_argument("--c1-steps", type=int, default=50, help="timed solves of the n=500, p=200 root (0 skips them)")
     ap.add_argument("--logistic-steps", type=int, default=4,
                     help="timed solves of the n=32768, p=16384 logistic root (0 skips them)")
+    ap.add_argument("--logistic-batch-nodes", type=int, default=64,
+                    help="logistic nodes solved together on the same design (0 skips them)")
     ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
@@ -755,6 +874,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args()
+    SOLVE_KW["method"] = 6 if args.method == "bt" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
               "of this path is a design note, not a built feature", file=sys.stderr)
@@ -791,13 +911,14 @@ def main():
     dev = torch.device("cuda:0")
     inst, cfg, ctx, node, setup_s = _setup(dev)
     for _ in range(args.warmup):
-        ctx.solve(node, want_beta=False)
+        ctx.solve(node, want_beta=False, **SOLVE_KW)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [ctx.solve(node, want_beta=False) for _ in range(args.steps)]
+    results = [ctx.solve(node, want_beta=False, **SOLVE_KW) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     iters = sum(r["iters"] for r in results)
+    trials = sum(r["trials"] for r in results)
     ok = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in results)
     value = args.steps / elapsed
     # dominant kernel: X^T r, timed with HIP events on the context stream
@@ -815,23 +936,39 @@ def main():
             "data": "synthetic",
             "config": {"workload": WORKLOAD, "n": inst.n, "p": inst.p, "x_storage": "f32", "loss": "least_squares",
                        "corr": cfg["corr"], "k": cfg["k"], "lambda2": cfg["lambda2"], "M": cfg["M"],
-                       "rel_gap_tol": cfg["tol"], "start": "cold (beta0 = 0)"},
-            "iters_per_solve": iters / args.steps, "iters_per_s": round(iters / elapsed, 1),
+                       "rel_gap_tol": cfg["tol"], "start": "cold (beta0 = 0)",
+                       "method": METHOD_NAME[SOLVE_KW["method"]]},
+            "iters_per_solve": iters / args.steps, "trials_per_solve": trials / args.steps,
+            "iters_per_s": round(iters / elapsed, 1),
+            "us_per_evaluation": round(1e6 * elapsed / (iters + trials), 2),
             "all_converged": ok, "lower_bound": results[-1]["lower_bound"],
             "setup_s_per_matrix": round(setup_s, 3),
             "roofline": roof}
+    if SOLVE_KW["method"] != 0:
+        # the fixed-step method (step 1/L) on the same root, for reference
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fxs = [ctx.solve(node, want_beta=False) for _ in range(3)]
+        torch.cuda.synchronize()
+        dfx = time.perf_counter() - t0
+        line["fixed_step"] = {"value": round(3 / dfx, 4), "unit": "node relaxations/s", "steps": 3,
+                              "iters_per_solve": fxs[-1]["iters"], "lower_bound": fxs[-1]["lower_bound"],
+                              "all_converged": all(q["status"] == 1 for q in fxs),
+                              "us_per_iter": round(1e6 * dfx / sum(q["iters"] for q in fxs), 2)}
+    Lmax_c2 = 1.01 * 2.0 * ctx.norm2()
     if args.gram_steps > 0:
         line["gram"] = gram_bench(ctx, node, cfg, args.gram_steps, line)
     ctx.close()
     if args.batch_steps > 0:
-        line["batch"] = batch_bench(dev, args.batch_steps)
+        line["batch"] = batch_bench(dev, args.batch_steps, inst_f32=inst)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(inst, cfg, iters / args.steps)
+        line["cpu_baseline"] = cpu_baseline(inst, cfg, iters / args.steps, Lmax_c2)
     del inst
     if args.c1_steps > 0:
         line["c1"] = c1_bench(dev, args.c1_steps, not args.no_cpu_baseline)
     if args.logistic_steps > 0:
-        line["logistic"] = logistic_bench(dev, args.logistic_steps, not args.no_cpu_baseline)
+        line["logistic"] = logistic_bench(dev, args.logistic_steps, not args.no_cpu_baseline,
+                                          batch_nodes=args.logistic_batch_nodes)
     print(json.dumps(line), flush=True)
 
 

@@ -107,6 +107,22 @@ typedef struct {
 #define PR_PGD 3
 #define PR_ACFGM_GAP 4
 #define PR_ACFGM 5
+/* FISTA with backtracking (the "FISTA with line search" the paper runs with
+ * its restart, Section 5; the monotone rule of Beck, First-Order Methods in
+ * Optimization, Section 10.7), with (PR_FISTA_BT_GAP) or without the
+ * duality-gap restart.  The step constant starts at L0 (opts->L0; 0 = L / 16)
+ * and is multiplied by c (opts->acfgm_c) while the trial x = prox(y -
+ * grad f(y) / L) breaks the quadratic model f(x) <= f(y) + <grad f(y), x - y>
+ * + (L / 2) ||x - y||^2; it never exceeds the fixed-step constant L
+ * (opts->L, default as above), at which a trial is accepted.  Momentum, the
+ * bounds, the stopping test and the restart act at accepted iterates; a
+ * restart runs the method afresh from its iterate, the line search from L0.
+ * A rejected trial costs one product over its support and one X^T pass and
+ * is not evaluated; pr_result.iters counts accepted iterates, .trials the
+ * rejected ones, .L is the last step constant.  pr_solve only (p <= 16384);
+ * pr_solve_batch runs these nodes one at a time. */
+#define PR_FISTA_BT_GAP 6
+#define PR_FISTA_BT 7
 
 typedef struct {
   double rel_gap_tol; /* stop when (UB - LB) / |UB| <= tol; default 1e-6 */
@@ -115,13 +131,14 @@ typedef struct {
   double L;           /* step 1/L; 0 = 1.01 * loss curvature * ||X||^2 estimate */
   int32_t max_iter;   /* default 100000 */
   int32_t check_every; /* iterations per captured graph launch; default 32 */
-  int32_t method;      /* iteration variant, PR_FISTA_GAP (default) .. PR_PGD */
+  int32_t method;      /* iteration variant, PR_FISTA_GAP (default) .. PR_FISTA_BT */
   int32_t pad0;
   double *trace;       /* pr_solve / pr_lasso_solve only, optional device array of
                           2 * (max_iter + 1) doubles: (Phi, Psi) of iterates 0, 1, ..., iters */
   double acfgm_b;      /* AC-FGM averaging weight b in (0, 1 - sqrt(6)/3]; default 0.1 */
-  double acfgm_c;      /* AC-FGM line-search factor c > 1; default 2 */
-  double L0;           /* AC-FGM initial curvature estimate; 0 = the default L / 64 */
+  double acfgm_c;      /* line-search factor c > 1 (AC-FGM's first step, FISTA with backtracking); default 2 */
+  double L0;           /* initial curvature estimate of the line search; 0 = the default
+                          (AC-FGM L / 64, FISTA with backtracking L / 16) */
 } pr_opts;
 
 typedef struct {

@@ -17,7 +17,7 @@ PROX_NOALLOC_MAX_P = 1048576
 DEBUG_GRAM_RECHECK = 1
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
-FISTA_GAP, FISTA, FISTA_FV, PGD, ACFGM_GAP, ACFGM = 0, 1, 2, 3, 4, 5
+FISTA_GAP, FISTA, FISTA_FV, PGD, ACFGM_GAP, ACFGM, FISTA_BT_GAP, FISTA_BT = 0, 1, 2, 3, 4, 5, 6, 7
 L1_REG, L1_BALL = 0, 1
 BNB_OPTIMAL, BNB_NODE_LIMIT, BNB_TIME_LIMIT = 1, 2, 3
 LSQ, LOGISTIC = 0, 1

@@ -189,7 +189,8 @@ void free_ctx(pr_ctx *c) {
   }
   if (c->cap) (void)hipStreamDestroy(c->cap);
   void *bufs[] = {c->d_prm, c->d_state, c->d_status, c->d_stp, c->nb.x0, c->nb.x1, c->nb.xbest, c->nb.hprev, c->nb.vbuf,
-                  c->nb.abuf, c->nb.sidx, c->nb.sval, c->B.r, c->B.gm, c->B.ucur, c->B.uprev,
+                  c->nb.abuf, c->nb.sidx, c->nb.sval, c->nb.ybt, c->nb.gbt, c->B.uy, c->B.dsum, c->B.r, c->B.gm,
+                  c->B.ucur, c->B.uprev,
                   c->B.zbest, c->B.h1, c->B.h2, c->B.part, c->B.rbsum, c->iota,
                   c->d_np, c->d_u, c->d_v, c->d_w, c->d_scal, c->d_lam, c->d_vprev, c->d_regscratch};
   for (void *b : bufs)
@@ -244,11 +245,13 @@ namespace {
 int check_opts(const pr_opts *o) {
   if (!o) return PR_OK;
   if (!(o->rel_gap_tol >= 0.0) || !(o->eta > 1.0) || o->max_iter < 0 || o->check_every < 1 ||
-      !(o->L >= 0.0) || !isfinite(o->L) || o->method < kFistaGap || o->method > kAcfgm)
+      !(o->L >= 0.0) || !isfinite(o->L) || o->method < kFistaGap || o->method > kFistaBt)
     return PR_EINVAL;
-  if (o->method >= kAcfgmGap &&
+  if ((o->method == kAcfgmGap || o->method == kAcfgm) &&
       (!(o->acfgm_b > 0.0) || !(o->acfgm_b < 1.0) || !(o->acfgm_c > 1.0) || !isfinite(o->acfgm_c) ||
        !(o->L0 >= 0.0) || !isfinite(o->L0)))
+    return PR_EINVAL;
+  if (is_bt(o->method) && (!(o->acfgm_c > 1.0) || !isfinite(o->acfgm_c) || !(o->L0 >= 0.0) || !isfinite(o->L0)))
     return PR_EINVAL;
   return PR_OK;
 }
@@ -970,12 +973,14 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   ok = ok && dalloc(&c->nb.hprev, p) == hipSuccess && dalloc(&c->nb.vbuf, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.abuf, p) == hipSuccess && dalloc(&c->nb.sidx, p) == hipSuccess;
   ok = ok && dalloc(&c->nb.sval, p) == hipSuccess;
+  ok = ok && dalloc(&c->nb.ybt, p) == hipSuccess && dalloc(&c->nb.gbt, p) == hipSuccess;
   ok = ok && dalloc(&c->B.r, n) == hipSuccess && dalloc(&c->B.gm, n) == hipSuccess;
   ok = ok && dalloc(&c->B.ucur, n) == hipSuccess && dalloc(&c->B.uprev, n) == hipSuccess;
   ok = ok && dalloc(&c->B.zbest, n) == hipSuccess;
   ok = ok && dalloc(&c->B.h1, p) == hipSuccess && dalloc(&c->B.h2, p) == hipSuccess;
   ok = ok && dalloc(&c->B.part, (size_t)nch * n) == hipSuccess;
   ok = ok && dalloc(&c->B.rbsum, 2 * (size_t)c->B.nfin) == hipSuccess;
+  ok = ok && dalloc(&c->B.dsum, (size_t)c->B.nfin) == hipSuccess && dalloc(&c->B.uy, n) == hipSuccess;
   ok = ok && dalloc(&c->iota, p) == hipSuccess && dalloc(&c->d_np, 1) == hipSuccess;
   ok = ok && dalloc(&c->d_u, n) == hipSuccess && dalloc(&c->d_v, p) == hipSuccess;
   ok = ok && dalloc(&c->d_w, p) == hipSuccess && dalloc(&c->d_scal, 8) == hipSuccess;
@@ -993,6 +998,7 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   ok = ok && hipMemsetAsync(c->B.uprev, 0, sizeof(double) * n, c->stream) == hipSuccess;
   ok = ok && hipMemsetAsync(c->B.r, 0, sizeof(double) * n, c->stream) == hipSuccess;
   ok = ok && hipMemsetAsync(c->B.gm, 0, sizeof(double) * n, c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->B.uy, 0, sizeof(double) * n, c->stream) == hipSuccess;
   ok = ok && hipMemcpyAsync(c->d_np, &pp, sizeof(int32_t), hipMemcpyHostToDevice, c->stream) == hipSuccess;
   ok = ok && launch_iota(c->iota, p, c->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
@@ -1074,6 +1080,7 @@ static int gram_certify(pr_ctx *c, const pr_node *node, const pr_opts *opts, con
     if (rc == PR_OK) {
       out->iters += hs.iter;
       out->restarts += hs.restarts;
+      out->trials += hs.trials;
     }
     return rc;
   }
@@ -1085,6 +1092,7 @@ static int gram_certify(pr_ctx *c, const pr_node *node, const pr_opts *opts, con
   out->L = hs.L;
   out->iters = hs.iter;
   out->restarts = hs.restarts;
+  out->trials = hs.trials;
   out->status = st;
   return PR_OK;
 }
@@ -1267,16 +1275,28 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   prm.gram_b = c->gram ? c->gb : nullptr;
   prm.gram_yy = c->gyy;
   prm.stp = c->d_stp;
+  double L_init = L;
+  if (is_bt(opts.method)) {
+    // backtracking from L0 (default L / 16), capped at L; register-resident steps only
+    if (node_ept(p) == 0) return PR_EINVAL;
+    prm.Lmax = L;
+    prm.L0 = opts.L0 > 0.0 ? fmin(opts.L0, L) : L / 16.0;
+    prm.ls_c = opts.acfgm_c;
+    L_init = prm.L0;
+  }
   pack_status(st, c->h_stp);
   PR_TRY(hipMemcpyAsync(c->d_status, st.data(), (size_t)p, hipMemcpyHostToDevice, c->stream));
   PR_TRY(hipMemcpyAsync(c->d_stp, c->h_stp.data(), sizeof(uint32_t) * c->h_stp.size(), hipMemcpyHostToDevice,
                         c->stream));
   PR_TRY(hipMemcpyAsync(c->d_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, c->stream));
-  if (opts.method >= kAcfgmGap) return solve_acfgm(c, &opts, L, beta0, beta_out, zeta_out, out);
-  PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L, p, c->stream));
+  if (opts.method == kAcfgmGap || opts.method == kAcfgm)
+    return solve_acfgm(c, &opts, L, beta0, beta_out, zeta_out, out);
+  PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L_init, p, c->stream));
   rc = ensure_graph(c, opts.check_every);
   if (rc != PR_OK) return rc;
-  PR_TRY(run_graph(c, c->gexec, (int64_t)opts.max_iter / opts.check_every + 3));
+  // backtracking: rejected trials take evaluations beyond the iteration budget
+  const int64_t launches = (int64_t)opts.max_iter / opts.check_every + 3;
+  PR_TRY(run_graph(c, c->gexec, is_bt(opts.method) ? 2 * launches : launches));
   NodeState hs;
   if (c->gram) {
     PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
@@ -1297,6 +1317,7 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   out->L = hs.L;
   out->iters = hs.iter;
   out->restarts = hs.restarts;
+  out->trials = hs.trials;
   out->status = hs.done ? hs.status : PR_MAXITER;
   return PR_OK;
 }
@@ -1909,7 +1930,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (rc != PR_OK) return rc;
     infeas[(size_t)i] = inf;
   }
-  if (!c->batch_ok || opts.method >= kAcfgmGap) {  // AC-FGM: node by node
+  if (!c->batch_ok || opts.method >= kAcfgmGap) {  // AC-FGM and backtracking FISTA: node by node
     for (int32_t i = 0; i < m; i++) {
       int rc = pr_solve(c, &nodes[i], &opts, B0 ? B0 + (int64_t)i * p : nullptr,
                         B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);

@@ -163,6 +163,7 @@ __device__ __forceinline__ int decide_restart(const NodeParams *prm, int it, dou
   }
   switch (prm->method) {
     case kFistaGap:
+    case kFistaBtGap:
       if (gap <= gap_ref / prm->eta) {
         gap_ref = gap;
         restarts++;

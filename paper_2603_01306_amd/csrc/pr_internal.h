@@ -27,7 +27,9 @@ enum : int32_t { kConverged = 1, kMaxIter = 2, kInfeasible = 3, kCutoffPrune = 4
 
 // Per-node constants, device resident (written by the host before a solve).
 // iteration variants (pr_opts.method)
-enum { kFistaGap = 0, kFista = 1, kFistaFv = 2, kPgd = 3, kAcfgmGap = 4, kAcfgm = 5 };
+enum { kFistaGap = 0, kFista = 1, kFistaFv = 2, kPgd = 3, kAcfgmGap = 4, kAcfgm = 5, kFistaBtGap = 6, kFistaBt = 7 };
+// FISTA with backtracking (with or without the gap restart)
+__host__ __device__ inline bool is_bt(int method) { return method == kFistaBtGap || method == kFistaBt; }
 
 struct NodeParams {
   const int8_t *st;   // status, p entries
@@ -38,8 +40,11 @@ struct NodeParams {
   int64_t p, pbar;
   int32_t kbar, loss;
   double lambda2, M, eta, tol, cutoff;  // cutoff NaN = off
-  int32_t max_iter, method;             // method: kFistaGap .. kPgd
+  int32_t max_iter, method;             // method: kFistaGap .. kFistaBt
   double *trace;                        // optional: (Phi, Psi) of iterates 0 .. max_iter
+  // backtracking (kFistaBt*): initial step constant (and after each restart),
+  // cap (a Lipschitz constant of grad f: a trial at Lmax is accepted), growth
+  double L0, Lmax, ls_c;
   // least squares from the Gram matrix (NULL: from the matrix-vector products):
   // b = X^T y, yy = y^T y; h = b - G x arrives in place of X^T r
   const double *gram_b;
@@ -63,9 +68,12 @@ struct NodeState {
   int32_t improved; // lb improved at the current iterate
   int32_t indom;   // current iterate lies in dom g_N
   int32_t tau_iters; // evaluations used by the last threshold search
-  int32_t pad[3];
+  int32_t bt;      // backtracking method (the loss epilogue keeps the momentum point's X y)
+  int32_t bt_acc;  // backtracking: the last evaluated point was accepted (or is the start point)
+  int32_t trials;  // backtracking: rejected trials
   double tk;       // kbar-th largest free |w| of the dual at the last iterate (<= 0: none)
   double tkw;      // relative half-width of the selection window around tk
+  double dxy;      // backtracking: ||x_trial - y||^2 of the pending trial
 };
 
 // Node-local vectors.
@@ -78,6 +86,7 @@ struct NodeBufs {
   int32_t *sidx;       // support list of the current iterate
   double *sval;
   double *xlb;         // Gram mode: iterate whose dual vector attains the best Psi
+  double *ybt, *gbt;   // backtracking: momentum point y of the pending trial and grad f(y)
 };
 
 // Shared per-problem vectors of a single-node solve.
@@ -89,6 +98,8 @@ struct ProbBufs {
   double *h1, *h2;      // X^T (first / second right-hand side)
   double *part;   // column-list GEMV partial sums [nch][n]
   double *rbsum;  // per finalize-block loss sums [nfin][2]
+  double *uy;     // logistic backtracking: X y of the pending trial's momentum point
+  double *dsum;   // logistic backtracking: per finalize-block Bregman remainder [nfin]
   int32_t rb, nch, rows, nfin;
 };
 

@@ -285,13 +285,25 @@ __global__ __launch_bounds__(256) void k_mlp(const float *__restrict__ P, const 
   if (threadIdx.x == 0) dst[kNP] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
 }
 
-// grad[i] = sum over blocks of part[b][i] in block order; grad[kNP] = loss
+// grad[i] = sum over blocks of part[b][i] in block order; grad[kNP] = loss.
+// The loads of 16 consecutive blocks are issued together and then added in
+// block order, so the sum is the plain sequential one without a memory round
+// trip per block.
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ part, int nblk, float inv_n,
                                                     float *__restrict__ grad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > kNP) return;
+  constexpr int kBatch = 16;
   float s = 0.f;
-  for (int b = 0; b < nblk; b++) s += part[(int64_t)b * kMlpPartStride + i];
+  int b = 0;
+  for (; b + kBatch <= nblk; b += kBatch) {
+    float v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; u++) v[u] = part[(int64_t)(b + u) * kMlpPartStride + i];
+#pragma unroll
+    for (int u = 0; u < kBatch; u++) s += v[u];
+  }
+  for (; b < nblk; b++) s += part[(int64_t)b * kMlpPartStride + i];
   grad[i] = i == kNP ? s * inv_n : s;
 }
 

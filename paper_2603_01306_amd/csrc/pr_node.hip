@@ -742,6 +742,7 @@ __global__ __launch_bounds__(NT) void k_node_init_r(const NodeParams *__restrict
     s.status = kMaxIter;
     s.nsupp = is.nsupp;
     s.indom = is.indom;
+    s.bt = is_bt(prm->method) ? 1 : 0;
     *S = s;
   }
 }
@@ -1037,11 +1038,15 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const int parity = A.parity;
   // scalar state and parameters: independent loads, issued together with the
   // vector loads below; the done test waits for them only after those
-  const int done0 = S->done, indom0 = S->indom;
-  const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw;
+  const int done0 = S->done, indom0 = S->indom, it0 = S->iter;
+  const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw, dxy0 = S->dxy;
   const int kbar = prm->kbar, loss = prm->loss;
   const double lam2 = prm->lambda2, M = prm->M;
-  const double *__restrict__ xc = parity ? nb.x1 : nb.x0;
+  const bool bt = is_bt(prm->method);
+  // x^k (backtracking: a rejected trial is overwritten by the last accepted
+  // iterate through xcw, so xc carries no restrict qualifier)
+  const double *xc = parity ? nb.x1 : nb.x0;
+  double *xcw = parity ? nb.x1 : nb.x0;
   double *__restrict__ xn = parity ? nb.x0 : nb.x1;  // holds x^{k-1}, receives x^{k+1}
   // the loads of the step: X^T r (Gram mode: b - G x), x^k and b first; the
   // operands of the gradient step (x^{k-1}, previous gradient) are issued
@@ -1115,6 +1120,110 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   if (!gb) {
     Fk = wave_sum(Fk);
     negconj = wave_sum(negconj);
+  }
+  // The proximal step from v (in x[]) with step constant Ls, shared by the
+  // accepted and the rejected branch: x[] <- prox_{(2 lambda2 / Ls) g_N}(v)
+  // by the pooled threshold, written to xn (after a rejected trial the last
+  // accepted iterate moves from xn to the current buffer first, so that the
+  // parity of the next evaluation finds the new trial current and x^k
+  // previous); backtracking keeps ||x - y||^2 for the test of the new trial.
+  auto prox_finish = [&](double Ls, bool rejected) {
+    const double rho = 2.0 * lam2 / Ls;
+    int evals = 0;
+    auto vabs = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
+    const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
+    const double inv1p = 1.0 / (1.0 + rho);
+    double dxy[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int s = sv(e);
+      double xv = 0.0;
+      if (s != 3) {
+        if (s != kZero) {
+          const double av = fabs(x[e]);
+          double r = fmin(av * inv1p, M);
+          if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
+          xv = (r == 0.0) ? 0.0 : copysign(r, x[e]);
+        }
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        if (rejected) xcw[j] = xn[j];
+        xn[j] = xv;
+        if (bt) {
+          const double dy = xv - nb.ybt[j];
+          dxy[0] += dy * dy;
+        }
+      }
+      x[e] = xv;
+    }
+    if (bt) R.sum(dxy);
+    if (A.gb) {
+      // Gram mode: no X^T r product follows, so the step evaluates g_N of the
+      // new iterate and its dom test itself
+      IterStats is = finish_2<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds, R);
+      if (tid == 0) {
+        S->gval = is.gval;
+        S->indom = is.indom;
+        S->nsupp = is.nsupp;
+      }
+    } else {
+      // the extra workgroup of the next X^T r product evaluates them from this
+      // support list (S->gval / S->indom before the next step reads them)
+      const int nsupp = support_list_2<EPT>(x, sv, nb.sidx, nb.sval, lds);
+      if (tid == 0) S->nsupp = nsupp;
+    }
+    if (tid == 0) {
+      S->tau = tau;
+      S->tau_iters = evals;
+      S->parity = parity ^ 1;
+      if (!rejected) S->iter = S->iter + 1;
+      if (bt) {
+        S->L = Ls;
+        S->dxy = dxy[0];
+        S->bt_acc = rejected ? 0 : 1;
+        if (rejected) {
+          S->trials = S->trials + 1;
+          S->improved = 0;
+        }
+      }
+    }
+  };
+  // Backtracking: every point after the start is a trial of the step from the
+  // momentum point y; it is accepted when f(x) - f(y) - <grad f(y), x - y> <=
+  // (L / 2) ||x - y||^2 (or L has reached Lmax), else the step is redone
+  // from the saved y and grad f(y) with c L, and the trial is not evaluated.
+  if (bt && it0 > 0) {
+    double dv = 0.0;
+    if (loss == kLsq) {
+      // f(x) - f(y) - <grad f(y), x - y> = ||X (x - y)||^2 = (x - y)^T (h(y) - h(x)),
+      // h = X^T (y_obs - X .) (Gram mode b - G .) and h(y) = -grad f(y) / 2
+      double d1[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        if (sv(e) == 3) continue;
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        double xe;
+        if constexpr (kHoldXk) xe = xk[e];
+        else xe = xc[j];
+        d1[0] += (xe - nb.ybt[j]) * (-0.5 * nb.gbt[j] - x[e]);
+      }
+      R.sum(d1);
+      dv = d1[0];
+    } else {
+      // logistic: the loss epilogue summed the remainder row by row
+      for (int i = lane_id(); i < B.nfin; i += 64) dv += B.dsum[i];
+      dv = wave_sum(dv);
+    }
+    if (!(L >= prm->Lmax || dv <= 0.5 * L * dxy0)) {
+      const double Ls = fmin(prm->ls_c * L, prm->Lmax);
+      const double invLs = 1.0 / Ls;
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        x[e] = sv(e) != 3 ? nb.ybt[j] - nb.gbt[j] * invLs : 0.0;
+      }
+      prox_finish(Ls, true);
+      return;
+    }
   }
   // dual value at x^k: w = X^T zeta / (2 lambda2); the top-kbar window of
   // free |w| around the previous kbar-th value
@@ -1260,7 +1369,9 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const bool done = lds.bci[0] != 0;
   const double m = lds.bcd[0];
   const int restart = lds.bci[1];
-  const double invL = 1.0 / L;
+  // backtracking: a restart runs the method afresh, the line search from L0
+  const double Lnew = (bt && restart) ? prm->L0 : L;
+  const double invL = 1.0 / Lnew;
   // gradient step at the momentum point on entries [e0, e1); x[] then holds v
   auto grad = [&](int e, double xke, double xqe, double g2e) {
     const double h = x[e];
@@ -1270,6 +1381,11 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     else gj = restart ? -h : g2e;
     x[e] = sv(e) != 3 ? yj - gj * invL : 0.0;
     if (loss == kLsq && sv(e) != 3) nb.hprev[(uint32_t)(tid + e * NT)] = h;
+    if (bt && sv(e) != 3) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      nb.ybt[j] = yj;
+      nb.gbt[j] = gj;
+    }
   };
   if constexpr (kHoldXk) {
     if (lds.bci[2]) {
@@ -1324,47 +1440,7 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     }
     if (done) return;
   }
-  const double rho = 2.0 * lam2 * invL;
-  int evals = 0;
-  auto vabs = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
-  const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
-  const double inv1p = 1.0 / (1.0 + rho);
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const int s = sv(e);
-    double xv = 0.0;
-    if (s != 3) {
-      if (s != kZero) {
-        const double av = fabs(x[e]);
-        double r = fmin(av * inv1p, M);
-        if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
-        xv = (r == 0.0) ? 0.0 : copysign(r, x[e]);
-      }
-      xn[(uint32_t)(tid + e * NT)] = xv;
-    }
-    x[e] = xv;
-  }
-  if (A.gb) {
-    // Gram mode: no X^T r product follows, so the step evaluates g_N of the
-    // new iterate and its dom test itself
-    IterStats is = finish_2<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds, R);
-    if (tid == 0) {
-      S->gval = is.gval;
-      S->indom = is.indom;
-      S->nsupp = is.nsupp;
-    }
-  } else {
-    // the extra workgroup of the next X^T r product evaluates them from this
-    // support list (S->gval / S->indom before the next step reads them)
-    const int nsupp = support_list_2<EPT>(x, sv, nb.sidx, nb.sval, lds);
-    if (tid == 0) S->nsupp = nsupp;
-  }
-  if (tid == 0) {
-    S->tau = tau;
-    S->tau_iters = evals;
-    S->parity = parity ^ 1;
-    S->iter = S->iter + 1;
-  }
+  prox_finish(Lnew, false);
 }
 
 

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
       u[1] += pv.y;
     }
   }
-  double sums[2] = {0.0, 0.0};
+  double sums[3] = {0.0, 0.0, 0.0};
   if (mode == kSpPlain) {
     if (active)
 #pragma unroll
@@ -175,12 +175,29 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
   } else {
     const double t = S->t;
     const double mt = (t - 1.0) / fista_next_t(t);
+    // backtracking: uprev holds X x of the last accepted iterate; when the
+    // previous evaluation was accepted it moves there and the momentum point
+    // y of the pending trial, X y = (1 + m) X x_k - m X x_{k-1} (m the step's
+    // momentum, 0 after a restart), is kept in uy until the trial is decided
+    const int bt = S->bt, acc = S->bt_acc;
+    const double mp = S->mom;
     if (active) {
 #pragma unroll
       for (int e = 0; e < VEC; e++) {
         const int64_t i = row0 + e;
         const double uo = B.ucur[i];
-        B.uprev[i] = uo;
+        double up = uo;
+        if (bt) {
+          up = B.uprev[i];
+          if (acc) {
+            const double uyv = (1.0 + mp) * uo - mp * up;
+            B.uy[i] = uyv;
+            up = uo;
+            B.uprev[i] = up;
+          }
+        } else {
+          B.uprev[i] = uo;
+        }
         B.ucur[i] = u[e];
         if (improved) B.zbest[i] = B.r[i];
         const double yi = y[i];
@@ -189,15 +206,25 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
         B.r[i] = yi * a;
         sums[0] += softplus(-z);
         sums[1] += a * softplus(z) + (1.0 - a) * softplus(-z);
-        const double sm = (1.0 + mt) * u[e] - mt * uo;
+        if (bt) {
+          // F(X x) - F(X y) - <grad F(X y), X x - X y> of this row, with
+          // a = -y_i (X y)_i and d = -y_i (X x - X y)_i: log1p(s expm1(d)) - s d,
+          // s = 1 / (1 + exp(-a))
+          const double uyv = B.uy[i];
+          const double aa = -yi * uyv, dd = -yi * (u[e] - uyv);
+          const double sg = 1.0 / (1.0 + exp(-aa));
+          sums[2] += log1p(sg * expm1(dd)) - sg * dd;
+        }
+        const double sm = (1.0 + mt) * u[e] - mt * up;
         B.gm[i] = -yi / (1.0 + exp(yi * sm));
       }
     }
   }
-  block_sum<kSpThreads, 2>(sums, red);
+  block_sum<kSpThreads, 3>(sums, red);
   if (threadIdx.x == 0) {
     B.rbsum[2 * fb] = sums[0];
     B.rbsum[2 * fb + 1] = sums[1];
+    if (B.dsum) B.dsum[fb] = sums[2];
   }
 }
 

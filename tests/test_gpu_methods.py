@@ -85,4 +85,4 @@ def test_rejects_unknown_method(c1):
     import paper_2603_01306_amd as pr
     inst, ctx, L = c1
     with pytest.raises(pr.PrError):
-        ctx.solve(pr.Node(10, 1.0, 2.0), method=7)
+        ctx.solve(pr.Node(10, 1.0, 2.0), method=8)
