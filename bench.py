@@ -10,7 +10,8 @@ shared by every node of a tree) runs before it and is reported separately.
 The root solves run the paper's method, FISTA with line search (backtracking
 from L/16, capped at L) and the duality-gap restart; "fixed_step" reports
 FISTA with the fixed step 1/L on the same root (--method fixed makes it the
-headline).  The batched solves use the fixed step.
+headline); the batched solves and their single-node comparisons run the same
+method.
 
 Also reported: the dominant kernel (X^T r, FP64 accumulation) against the
 HBM roofline, timed with HIP events on the stream it runs on, and the FP64
@@ -281,17 +282,17 @@ def logistic_batch_bench(dev, inst, cfg, ctx1, X, y, m, steps, n_single=4):
     nodes = [pr.Node(cfg["k"], cfg["lambda2"], cfg["M"], J0=a, J1=b) for a, b in raw]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single = [ctx1.solve(nd, want_beta=False, rel_gap_tol=cfg["tol"]) for nd in nodes[:n_single]]
+    single = [ctx1.solve(nd, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW) for nd in nodes[:n_single]]
     torch.cuda.synchronize()
     dt_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     ctx = pr.Context(X, y, pr.LOGISTIC, max_batch=m)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])       # warm-up (graph capture)
+    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)       # warm-up (graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+    runs = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)[0] for _ in range(steps)]
     torch.cuda.synchronize()
     dt_b = time.perf_counter() - t0
     res = runs[-1]
@@ -301,7 +302,9 @@ def logistic_batch_bench(dev, inst, cfg, ctx1, X, y, m, steps, n_single=4):
     flop = 2.0 * inst.n * inst.p * nr2
     ach = flop / (ms_t * 1e-3) / 1e12
     lbd = max(abs(a["lower_bound"] - b["lower_bound"]) / abs(b["primal"]) for a, b in zip(res, single))
-    out = {"nodes": m, "value": round(m * steps / dt_b, 3), "unit": "node relaxations/s", "steps": steps,
+    out = {"nodes": m, "method": METHOD_NAME[SOLVE_KW["method"]],
+           "trials_mean": round(float(np.mean([r["trials"] for r in res])), 1),
+           "value": round(m * steps / dt_b, 3), "unit": "node relaxations/s", "steps": steps,
            "ms_per_step": round(1e3 * dt_b / steps, 2), "context_setup_s": round(setup_s, 3),
            "all_converged": all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for run in runs for r in run),
            "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 1),
@@ -411,18 +414,19 @@ def batch_bench(dev, steps, n_single=16, inst_f32=None):
     ctx = pr.Context(X, torch.from_numpy(inst.y).to(dev), pr.LSQ, max_batch=m)
     raw = make_nodes(inst.p, m, seed=cfg["node_seed"], max_j0=64, max_j1=19)
     nodes = [pr.Node(cfg["k"], cfg["lambda2"], cfg["M"], J0=a, J1=b) for a, b in raw]
-    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])      # warm-up (graph capture)
+    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)      # warm-up (graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+    runs = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)[0] for _ in range(steps)]
     torch.cuda.synchronize()
     dt_b = time.perf_counter() - t0
     res = runs[-1]
     ok_b = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for run in runs for r in run)
     it = np.array([r["iters"] for r in res])
+    trials_b = float(np.mean([r["trials"] for r in res]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single = [ctx.solve(nd, want_beta=False, rel_gap_tol=cfg["tol"]) for nd in nodes[:n_single]]
+    single = [ctx.solve(nd, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW) for nd in nodes[:n_single]]
     torch.cuda.synchronize()
     dt_s = time.perf_counter() - t0
     ok_s = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for r in single)
@@ -433,6 +437,7 @@ def batch_bench(dev, steps, n_single=16, inst_f32=None):
     flop = 2.0 * inst.n * inst.p * nr
     ach = flop / (ms_t * 1e-3) / 1e12
     out = {"workload": BATCH_WORKLOAD, "nodes": m, "x_storage": "bf16", "rel_gap_tol": cfg["tol"],
+           "method": METHOD_NAME[SOLVE_KW["method"]], "trials_mean": round(trials_b, 1),
            "value": round(m * steps / dt_b, 3), "unit": "node relaxations/s", "steps": steps,
            "ms_per_step": round(1e3 * dt_b / steps, 2), "all_converged": ok_b,
            "autotuned_splits": {"active_row_tiles": list(range(1, tiles + 1)), "forward": tf, "transpose": tt},
@@ -445,16 +450,26 @@ def batch_bench(dev, steps, n_single=16, inst_f32=None):
                         "flop_per_launch": flop, "avg_launch_ms": round(ms_t, 4),
                         "forward_avg_launch_ms": round(ms_f, 4)}}
     out["speedup_vs_single"] = round(out["value"] / out["single_path"]["value"], 2)
+    if SOLVE_KW["method"] != 0:
+        # one batched solve of the same nodes with the fixed step, for reference
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fres = ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0]
+        torch.cuda.synchronize()
+        dfx = time.perf_counter() - t0
+        out["fixed_step"] = {"value": round(m / dfx, 3), "unit": "node relaxations/s",
+                             "iters_mean": round(float(np.mean([r["iters"] for r in fres])), 1),
+                             "all_converged": all(r["status"] == 1 for r in fres)}
     # the same nodes in batched Gram mode: one product G X_it per iteration
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.enable_gram()
     torch.cuda.synchronize()
     setup_g = time.perf_counter() - t0
-    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])      # warm-up (graph capture)
+    ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)      # warm-up (graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gruns = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+    gruns = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)[0] for _ in range(steps)]
     torch.cuda.synchronize()
     dt_g = time.perf_counter() - t0
     ok_g = all(r["status"] == 1 and r["rel_gap"] <= cfg["tol"] for run in gruns for r in run)
@@ -475,10 +490,10 @@ def batch_bench(dev, steps, n_single=16, inst_f32=None):
     if inst_f32 is not None:
         Xf = torch.from_numpy(inst_f32.Xcm).to(dev)
         ctx = pr.Context(Xf, torch.from_numpy(inst_f32.y).to(dev), pr.LSQ, max_batch=m)
-        ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])      # warm-up (graph capture)
+        ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)      # warm-up (graph capture)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fruns = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"])[0] for _ in range(steps)]
+        fruns = [ctx.solve_batch(nodes, want_beta=False, rel_gap_tol=cfg["tol"], **SOLVE_KW)[0] for _ in range(steps)]
         torch.cuda.synchronize()
         dt_f = time.perf_counter() - t0
         fit = np.array([r["iters"] for r in fruns[-1]])

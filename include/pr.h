@@ -119,8 +119,8 @@ typedef struct {
  * restart runs the method afresh from its iterate, the line search from L0.
  * A rejected trial costs one product over its support and one X^T pass and
  * is not evaluated; pr_result.iters counts accepted iterates, .trials the
- * rejected ones, .L is the last step constant.  pr_solve only (p <= 16384);
- * pr_solve_batch runs these nodes one at a time. */
+ * rejected ones, .L is the last step constant.  p <= 16384 (pr_solve returns
+ * PR_EINVAL beyond); pr_solve_batch runs it per node on the batched path. */
 #define PR_FISTA_BT_GAP 6
 #define PR_FISTA_BT 7
 
@@ -290,9 +290,9 @@ int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
  * iterate and the loss gradient at the momentum point).  Every stopped
  * node's Phi and Psi are then recomputed over the stored X, and a node whose
  * decision (converged / prune / branch) is not confirmed continues alone on
- * the pr_solve path.  Other contexts run pr_solve node by node.  The
- * iteration variants are FISTA with or without the gap restart and PGD
- * (AC-FGM runs node by node).  Traces (opts->trace) are not recorded.
+ * the pr_solve path.  Other contexts run pr_solve node by node.  Every
+ * iteration variant but AC-FGM (which runs node by node) runs batched, the
+ * backtracking line search per node.  Traces (opts->trace) are not recorded.
  *   B0 device m x p (row i = warm start of node i) or NULL; B_out device
  *   m x p (row i receives node i's iterate) or NULL; out host m. */
 int pr_solve_batch(pr_ctx *ctx, const pr_node *nodes, int32_t m, const pr_opts *opts,

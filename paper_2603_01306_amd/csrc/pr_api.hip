@@ -74,7 +74,10 @@ struct pr_ctx {
   double *Rd = nullptr;      // [rs cap padded][n] FP64 residual / loss rows
   double *CF = nullptr;      // [KSF][cap padded][n]
   double *CT = nullptr;      // [KS][rs cap padded][p]
-  double *Uprev = nullptr;   // logistic: [cap][n] X x of each node's previous iterate
+  double *Uprev = nullptr;   // logistic: [cap][n] X x of each node's previous (backtracking: last accepted) iterate
+  double *Ucur = nullptr, *Uy = nullptr;  // logistic backtracking: X x of the last evaluation, X y of the pending trial
+  double *bdsum = nullptr;   // logistic backtracking: [cap][nfb] Bregman remainder sums
+  double *bybt = nullptr, *bgbt = nullptr;  // backtracking: [cap][p] momentum point and grad f there
   int32_t *d_rowmap2 = nullptr;  // logistic: [2 cap padded] rows of the second product of the nodes still iterating
   double *fsum = nullptr;    // [cap][nfb][2]
   double *bx0 = nullptr, *bx1 = nullptr, *bxbest = nullptr, *bhprev = nullptr, *bsval = nullptr;
@@ -177,7 +180,7 @@ void free_ctx(pr_ctx *c) {
     for (void *b : ub)
       if (b) (void)hipFree(b);
   }
-  void *bb[] = {c->bstp, c->Xrow, c->Uprev, c->d_rowmap2, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
+  void *bb[] = {c->bstp, c->Xrow, c->Uprev, c->Ucur, c->Uy, c->bdsum, c->bybt, c->bgbt, c->d_rowmap2, c->Bx, c->Rd, c->CF, c->CT, c->fsum, c->bx0, c->bx1, c->bxbest, c->bhprev,
                 c->bsval, c->bsidx, c->bstatus, c->d_bprm, c->d_bstate, c->d_active, c->d_rowmap, c->d_split, c->d_ftab, c->mF, c->mout, c->mnz, c->mfs, c->mvhat, c->mx, c->G, c->gb, c->BG.part, c->nb.xlb, c->mVb, c->mWb, c->mFb, c->moutb, c->mPb};
   for (void *b : bb)
     if (b) (void)hipFree(b);
@@ -599,8 +602,11 @@ int alloc_batch(pr_ctx *c) {
   ok = ok && dalloc(&c->CT, (size_t)KS * fT * NrMaxT * p) == hipSuccess;
   if (c->rs == 2) {
     ok = ok && dalloc(&c->Uprev, (size_t)cap * n) == hipSuccess;
+    ok = ok && dalloc(&c->Ucur, (size_t)cap * n) == hipSuccess && dalloc(&c->Uy, (size_t)cap * n) == hipSuccess;
+    ok = ok && dalloc(&c->bdsum, (size_t)cap * batch_resid_blocks(n)) == hipSuccess;
     ok = ok && dalloc(&c->d_rowmap2, NrMaxT) == hipSuccess;
   }
+  ok = ok && dalloc(&c->bybt, (size_t)cap * p) == hipSuccess && dalloc(&c->bgbt, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->fsum, (size_t)2 * cap * c->nfb) == hipSuccess;
   ok = ok && dalloc(&c->bx0, (size_t)cap * p) == hipSuccess && dalloc(&c->bx1, (size_t)cap * p) == hipSuccess;
   ok = ok && dalloc(&c->bxbest, (size_t)cap * p) == hipSuccess && dalloc(&c->bhprev, (size_t)cap * p) == hipSuccess;
@@ -618,7 +624,8 @@ int alloc_batch(pr_ctx *c) {
   if (!ok) return PR_ENOMEM;
   ok = hipMemsetAsync(c->Bx, 0, sizeof(double) * NrMax * p, c->stream) == hipSuccess;
   ok = ok && hipMemsetAsync(c->Rd, 0, sizeof(double) * NrMaxT * n, c->stream) == hipSuccess;
-  if (c->Uprev) ok = ok && hipMemsetAsync(c->Uprev, 0, sizeof(double) * cap * n, c->stream) == hipSuccess;
+  for (double *u : {c->Uprev, c->Ucur, c->Uy})
+    if (u) ok = ok && hipMemsetAsync(u, 0, sizeof(double) * cap * n, c->stream) == hipSuccess;
   ok = ok && launch_transpose(c->P.xdt, c->P.X, c->Xrow, n, p, c->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) return PR_EDEVICE;
@@ -715,6 +722,9 @@ BatchBufs batch_bufs(pr_ctx *c, int32_t m) {
   bb.stpw = (int64_t)c->h_stp.size();
   bb.gb = c->gram ? c->gb : nullptr;
   bb.gyy = c->gyy;
+  bb.ybt = c->bybt;
+  bb.gbt = c->bgbt;
+  bb.dsum = c->bdsum;
   return bb;
 }
 
@@ -764,7 +774,7 @@ hipError_t enqueue_batch_unit(pr_ctx *c, int32_t m, hipStream_t s) {
   }
   if (e != hipSuccess) return e;
   e = launch_batch_resid(c->CF, c->union_on ? c->d_split + 3 : c->d_split + 1, n, m, Nr, c->P.y, c->Rd, c->fsum,
-                         c->d_bstate, c->P.loss, c->Uprev, s);
+                         c->d_bstate, c->P.loss, c->Uprev, s, c->Ucur, c->Uy, c->bdsum);
   if (e != hipSuccess) return e;
   e = launch_gemm_any(xdt, c->P.X, n, kF64, c->Rd, n, c->CT, p, nr_of(c->rs * m), n, c->KS, c->d_active,
                       two ? c->d_rowmap2 : c->d_rowmap, two ? c->d_split + 8 : c->d_split, c->d_split + 2,
@@ -1661,7 +1671,8 @@ int pr_mlp_adam(void *stream, float *params, const float *grad, float *m1, float
 
 static int stage_batch_nodes(pr_ctx *c, const pr_node *nodes, const std::vector<int32_t> &slot_of,
                              const std::vector<std::vector<int8_t>> &sts, const std::vector<int32_t> &kbars,
-                             const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0);
+                             const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0,
+                             double Lcap = 0.0);
 
 // Batched starting points (batched path, m <= max_batch):
 // the parents' certificates and w = X^T zeta at every parent from one pass of
@@ -1865,10 +1876,12 @@ int pr_dual_bound(pr_ctx *c, const pr_node *node, const double *zeta, const doub
 
 // Node parameters, status vectors (plain and packed) of the batch slots
 // q -> node slot_of[q] on the device; with B0 each slot's starting row is
-// copied into the batch's best-iterate rows.
+// copied into the batch's best-iterate rows.  Lcap: the fixed-step constant,
+// the cap of the backtracking line search.
 static int stage_batch_nodes(pr_ctx *c, const pr_node *nodes, const std::vector<int32_t> &slot_of,
                              const std::vector<std::vector<int8_t>> &sts, const std::vector<int32_t> &kbars,
-                             const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0) {
+                             const std::vector<int64_t> &pbars, const pr_opts &opts, const double *B0,
+                             double Lcap) {
   const int64_t p = c->P.p;
   const int32_t mb = (int32_t)slot_of.size();
   hipStream_t s = c->stream;
@@ -1891,6 +1904,11 @@ static int stage_batch_nodes(pr_ctx *c, const pr_node *nodes, const std::vector<
     pp.trace = nullptr;
     pp.gram_b = c->gram ? c->gb : nullptr;
     pp.gram_yy = c->gyy;
+    if (is_bt(opts.method)) {
+      pp.Lmax = Lcap;
+      pp.L0 = opts.L0 > 0.0 ? fmin(opts.L0, Lcap) : Lcap / 16.0;
+      pp.ls_c = opts.acfgm_c;
+    }
     PR_TRY(hipMemcpyAsync(c->bstatus + (int64_t)q * p, sts[(size_t)i].data(), (size_t)p, hipMemcpyHostToDevice, s));
     if (B0) PR_TRY(hipMemcpyAsync(c->bxbest + (int64_t)q * p, B0 + (int64_t)i * p, sizeof(double) * p,
                                   hipMemcpyDeviceToDevice, s));
@@ -1930,7 +1948,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (rc != PR_OK) return rc;
     infeas[(size_t)i] = inf;
   }
-  if (!c->batch_ok || opts.method >= kAcfgmGap) {  // AC-FGM and backtracking FISTA: node by node
+  if (!c->batch_ok || opts.method == kAcfgmGap || opts.method == kAcfgm) {  // AC-FGM: node by node
     for (int32_t i = 0; i < m; i++) {
       int rc = pr_solve(c, &nodes[i], &opts, B0 ? B0 + (int64_t)i * p : nullptr,
                         B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);
@@ -1958,13 +1976,16 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     return PR_OK;
   }
   const double L = opts.L > 0.0 ? opts.L : 1.01 * curvature(c->P.loss) * c->norm2;
-  int rcs = stage_batch_nodes(c, nodes, slot_of, sts, kbars, pbars, opts, B0);
+  int rcs = stage_batch_nodes(c, nodes, slot_of, sts, kbars, pbars, opts, B0, L);
   if (rcs != PR_OK) return rcs;
-  if (c->Uprev) PR_TRY(hipMemsetAsync(c->Uprev, 0, sizeof(double) * mb * n, s));
+  for (double *u : {c->Uprev, c->Ucur, c->Uy})
+    if (u) PR_TRY(hipMemsetAsync(u, 0, sizeof(double) * mb * n, s));
   int32_t act = mb;
   PR_TRY(hipMemcpyAsync(c->d_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
   BatchBufs bb = batch_bufs(c, mb);
-  PR_TRY(launch_batch_init(c->d_bprm, c->d_bstate, bb, B0 ? c->bxbest : nullptr, L, p, s));
+  const bool bt = is_bt(opts.method);
+  const double L_init = bt ? (opts.L0 > 0.0 ? fmin(opts.L0, L) : L / 16.0) : L;
+  PR_TRY(launch_batch_init(c->d_bprm, c->d_bstate, bb, B0 ? c->bxbest : nullptr, L_init, p, s));
   c->union_on = false;
   int rc = ensure_batch_graph(c, mb, opts.check_every);
   if (rc != PR_OK) return rc;
@@ -1975,7 +1996,8 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (e != hipSuccess) return e;
     return hipEventRecord(c->ev[slot], s);
   };
-  const int64_t max_launches = (int64_t)opts.max_iter / opts.check_every + 3;
+  // backtracking: rejected trials take evaluations beyond the iteration budget
+  const int64_t max_launches = ((int64_t)opts.max_iter / opts.check_every + 3) * (bt ? 2 : 1);
   int64_t launched = 0;
   PR_TRY(issue(0));
   launched++;
@@ -2067,9 +2089,10 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
       r.lower_bound = lb;
       r.primal = ub;
       r.rel_gap = rel;
-      r.L = L;
+      r.L = hs.L;
       r.iters = hs.iter;
       r.restarts = hs.restarts;
+      r.trials = hs.trials;
       r.status = st;
       if (B_out) PR_TRY(hipMemcpyAsync(B_out + (int64_t)i * p, xq, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     } else {
@@ -2080,6 +2103,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
       r.rel_gap = (r.primal - r.lower_bound) / fmax(fabs(r.primal), 1e-300);
       r.iters += hs.iter;
       r.restarts += hs.restarts;
+      r.trials += hs.trials;
     }
   }
   PR_TRY(hipStreamSynchronize(s));

@@ -405,17 +405,24 @@ __global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ in, T *
 //                  2 node + 1, and u into Uprev for the next iteration; sums
 //                  of sum_i log(1 + exp(-y_i u_i)) and the binary entropies
 //                  of a_i = 1 / (1 + exp(y_i u_i)).
+//                  Backtracking nodes keep X x of the last evaluation (Ucur),
+//                  of the last accepted iterate (Uprev) and of the pending
+//                  trial's momentum point (Uy, formed when the last evaluation
+//                  was accepted), and sum the row-wise Bregman remainder of F
+//                  between u and X y per block into dsum.
 __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ U, const int32_t *__restrict__ ksp,
                                                      int64_t n, int Nr, const double *__restrict__ y,
                                                      double *__restrict__ R, double *__restrict__ fsum,
-                                                     const NodeState *S, int32_t loss, double *__restrict__ Uprev) {
+                                                     const NodeState *S, int32_t loss, double *__restrict__ Uprev,
+                                                     double *__restrict__ Ucur, double *__restrict__ Uy,
+                                                     double *__restrict__ dsum) {
   __shared__ double red[4 * 4];
   const int node = blockIdx.y;
   if (S && S[node].done) return;  // S == NULL: every row (certification)
   const int KSF = *ksp;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
   const int64_t plane = (int64_t)Nr * n;
-  double s[2] = {0.0, 0.0};
+  double s[3] = {0.0, 0.0, 0.0};
   if (i0 < n) {
     double u[2];
 #pragma unroll
@@ -434,10 +441,14 @@ __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ 
         s[1] += 2.0 * ri * y[i] - ri * ri;
       }
     } else {
-      double mt = 0.0;
+      double mt = 0.0, mp = 0.0;
+      int bt = 0, acc = 0;
       if (S) {
         const double t = S[node].t;
         mt = (t - 1.0) / fista_next_t(t);
+        bt = S[node].bt;
+        acc = S[node].bt_acc;
+        mp = S[node].mom;
       }
       double *zr = R + (int64_t)(2 * node) * n, *gr = zr + n;
       double *up = Uprev + (int64_t)node * n;
@@ -450,7 +461,25 @@ __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ 
         zr[i] = yi * a;
         s[0] += softplus(-z);
         s[1] += a * softplus(z) + (1.0 - a) * softplus(-z);
-        if (S) {
+        if (S && bt) {
+          const int64_t ni = (int64_t)node * n + i;
+          const double uc = Ucur[ni];
+          double ua = up[i], uyv;
+          if (acc) {
+            uyv = (1.0 + mp) * uc - mp * ua;
+            Uy[ni] = uyv;
+            ua = uc;
+            up[i] = ua;
+          } else {
+            uyv = Uy[ni];
+          }
+          Ucur[ni] = u[e];
+          const double aa = -yi * uyv, dd = -yi * (u[e] - uyv);
+          const double sg = 1.0 / (1.0 + exp(-aa));
+          s[2] += log1p(sg * expm1(dd)) - sg * dd;
+          const double sm = (1.0 + mt) * u[e] - mt * ua;
+          gr[i] = -yi / (1.0 + exp(yi * sm));
+        } else if (S) {
           const double uo = up[i];
           up[i] = u[e];
           const double sm = (1.0 + mt) * u[e] - mt * uo;
@@ -459,10 +488,11 @@ __global__ __launch_bounds__(256) void k_batch_resid(const double *__restrict__ 
       }
     }
   }
-  block_sum<256, 2>(s, red);
+  block_sum<256, 3>(s, red);
   if (threadIdx.x == 0) {
     fsum[2 * ((int64_t)node * gridDim.x + blockIdx.x)] = s[0];
     fsum[2 * ((int64_t)node * gridDim.x + blockIdx.x) + 1] = s[1];
+    if (dsum) dsum[(int64_t)node * gridDim.x + blockIdx.x] = s[2];
   }
 }
 
@@ -734,10 +764,10 @@ int batch_resid_blocks(int64_t n) { return (int)((n + 511) / 512); }
 
 hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, int m, int Nr, const double *y,
                               double *R, double *fsum, const NodeState *S, int32_t loss, double *Uprev,
-                              hipStream_t s) {
+                              hipStream_t s, double *Ucur, double *Uy, double *dsum) {
   if (loss != kLsq && (loss != kLogistic || (S && !Uprev))) return hipErrorInvalidValue;
   dim3 grid((unsigned)batch_resid_blocks(n), (unsigned)m);
-  k_batch_resid<<<grid, 256, 0, s>>>(U, ksp, n, Nr, y, R, fsum, S, loss, Uprev);
+  k_batch_resid<<<grid, 256, 0, s>>>(U, ksp, n, Nr, y, R, fsum, S, loss, Uprev, Ucur, Uy, dsum);
   return hipGetLastError();
 }
 

@@ -123,6 +123,8 @@ struct BatchBufs {
   int64_t stpw;
   const double *gb;     // Gram mode: b = X^T y (NULL: products over X); gyy = y^T y
   double gyy;
+  double *ybt, *gbt;    // backtracking: per node the momentum point of the pending trial and grad f there [m][p]
+  const double *dsum;   // logistic backtracking: per (node, residual block) Bregman remainder [m][nfb]
 };
 
 // AC-FGM state of a single-node solve (pr_variants.hip), device resident.
@@ -203,7 +205,7 @@ int batch_resid_blocks(int64_t n);
 // 2q+1 = gradient at the momentum point while iterating, u kept in Uprev)
 hipError_t launch_batch_resid(const double *U, const int32_t *ksp, int64_t n, int m, int Nr, const double *y,
                               double *R, double *fsum, const NodeState *S, int32_t loss, double *Uprev,
-                              hipStream_t s);
+                              hipStream_t s, double *Ucur = nullptr, double *Uy = nullptr, double *dsum = nullptr);
 hipError_t launch_gemm_f64(const uint16_t *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t Mc,
                            int64_t Nr, int64_t K, int KS, const int32_t *active, const int32_t *rowmap,
                            const int32_t *nrow, const int32_t *ksp, int ks_max, int32_t *counter, hipStream_t s);

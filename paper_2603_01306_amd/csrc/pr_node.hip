@@ -1499,6 +1499,7 @@ __global__ __launch_bounds__(NT) void k_batch_init(const NodeParams *__restrict_
     s.status = kMaxIter;
     s.nsupp = is.nsupp;
     s.indom = is.indom;
+    s.bt = is_bt(prm->method) ? 1 : 0;
     *S = s;
   }
 }
@@ -1514,11 +1515,15 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   const int64_t off = (int64_t)node * p;
   const double *__restrict__ gb = bb.gb;
   // scalar state: independent loads, issued with the vector loads below
-  const int done0 = S->done, parity = S->parity, indom0 = S->indom;
-  const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw;
+  const int done0 = S->done, parity = S->parity, indom0 = S->indom, it0 = S->iter;
+  const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw, dxy0 = S->dxy;
   const int kbar = prm->kbar;
   const double lam2 = prm->lambda2, M = prm->M;
-  const double *__restrict__ xc = (parity ? bb.x1 : bb.x0) + off;
+  const bool bt = is_bt(prm->method);
+  // x^k; backtracking writes a redone trial over a rejected one (xcw, same
+  // buffer, so xc carries no restrict qualifier) and keeps the parity
+  const double *xc = (parity ? bb.x1 : bb.x0) + off;
+  double *xcw = (parity ? bb.x1 : bb.x0) + off;
   double *__restrict__ xn = (parity ? bb.x0 : bb.x1) + off;
   PackedStatus<EPT> sv;
   load_packed_status<EPT>(sv, bb.stp + (int64_t)node * bb.stpw);
@@ -1559,6 +1564,98 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   if (!gb) {
     Fk = wave_sum(Fk);
     negconj = wave_sum(negconj);
+  }
+  // The proximal step from v (in h[]) with step constant Ls, shared by the
+  // accepted and the rejected branch (the single-node step's form): the new
+  // point goes to the next buffer (accepted) or over the rejected trial, and to
+  // the node's row of the forward GEMM's operand; backtracking keeps
+  // ||x - y||^2 for the test of the new trial.
+  double *__restrict__ ybt = bb.ybt + off;
+  auto prox_finish = [&](double Ls, bool rejected) {
+    const double rho = 2.0 * lam2 / Ls;
+    int evals = 0;
+    auto vabs = [&](int e) { return sv(e) == kFree ? fabs(h[e]) : -1.0; };
+    const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
+    const double inv1p = 1.0 / (1.0 + rho);
+    double *dst = rejected ? xcw : xn;
+    double dxy[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+      const int s = sv(e);
+      double xv = 0.0;
+      if (s != 3) {
+        if (s != kZero) {
+          const double av = fabs(h[e]);
+          double r = fmin(av * inv1p, M);
+          if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
+          xv = (r == 0.0) ? 0.0 : copysign(r, h[e]);
+        }
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        dst[j] = xv;
+        bb.Bx[off + j] = xv;
+        if (bt) {
+          const double dy = xv - ybt[j];
+          dxy[0] += dy * dy;
+        }
+      }
+      h[e] = xv;
+    }
+    if (bt) R.sum(dxy);
+    IterStats is = finish_2<EPT>(h, sv, kbar, M, bb.sidx + off, bb.sval + off, lds, R);
+    if (tid == 0) {
+      S->gval = is.gval;
+      S->indom = is.indom;
+      S->nsupp = is.nsupp;
+      S->tau = tau;
+      S->tau_iters = evals;
+      if (!rejected) {
+        S->parity = parity ^ 1;
+        S->iter = S->iter + 1;
+      }
+      if (bt) {
+        S->L = Ls;
+        S->dxy = dxy[0];
+        S->bt_acc = rejected ? 0 : 1;
+        if (rejected) S->trials = S->trials + 1;
+      }
+    }
+  };
+  // Backtracking: every point after the start is a trial of the step from the
+  // momentum point y, accepted when f(x) - f(y) - <grad f(y), x - y> <=
+  // (L / 2) ||x - y||^2 (or L has reached Lmax); else the step is redone from
+  // the saved y and grad f(y) with c L and the trial is not evaluated.
+  if (bt && it0 > 0) {
+    const double *__restrict__ gbt = bb.gbt + off;
+    double dv = 0.0;
+    if (lsq) {
+      // ||X (x - y)||^2 = (x - y)^T (h(y) - h(x)), h(y) = -grad f(y) / 2
+      // (Gram mode: h = b - G x from the planes of G x)
+      double d1[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        if (sv(e) == 3) continue;
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        const double hx = gb ? gb[j] - h[e] : h[e];
+        d1[0] += (xk[e] - ybt[j]) * (-0.5 * gbt[j] - hx);
+      }
+      R.sum(d1);
+      dv = d1[0];
+    } else {
+      // logistic: the residual kernel summed the remainder row by row per block
+      for (int i = lane_id(); i < bb.nfb; i += 64) dv += bb.dsum[(int64_t)node * bb.nfb + i];
+      dv = wave_sum(dv);
+    }
+    if (!(L >= prm->Lmax || dv <= 0.5 * L * dxy0)) {
+      const double Ls = fmin(prm->ls_c * L, prm->Lmax);
+      const double invLs = 1.0 / Ls;
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        h[e] = sv(e) != 3 ? ybt[j] - gbt[j] * invLs : 0.0;
+      }
+      prox_finish(Ls, true);
+      return;
+    }
   }
   // dual at x^k: w = X^T zeta / (2 lambda2) (least squares h / lambda2, logistic
   // h / (2 lambda2)); the top-kbar window of free |w| around the previous
@@ -1726,51 +1823,27 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   }
   const double m = lds.bcd[0];
   const bool restart = lds.bci[1] != 0;
-  const double invL = 1.0 / L;
+  // backtracking: a restart runs the method afresh, the line search from L0
+  const double Lnew = (bt && restart) ? prm->L0 : L;
+  const double invL = 1.0 / Lnew;
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
     const double yj = xk[e] + m * (xk[e] - xq[e]);
     const double gj = lsq ? -2.0 * ((1.0 + m) * h[e] - m * hq[e]) : (restart ? -h[e] : hq[e]);
     hq[e] = h[e];
     h[e] = sv(e) != 3 ? yj - gj * invL : 0.0;  // h[] now holds v
+    if (bt && sv(e) != 3) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      ybt[j] = yj;
+      bb.gbt[off + j] = gj;
+    }
   }
   if (lsq) {
 #pragma unroll
     for (int e = 0; e < EPT; e++)
       if (sv(e) != 3) hp[(uint32_t)(tid + e * NT)] = hq[e];
   }
-  const double rho = 2.0 * lam2 * invL;
-  int evals = 0;
-  auto vabs = [&](int e) { return sv(e) == kFree ? fabs(h[e]) : -1.0; };
-  const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
-  const double inv1p = 1.0 / (1.0 + rho);
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const int s = sv(e);
-    double xv = 0.0;
-    if (s != 3) {
-      if (s != kZero) {
-        const double av = fabs(h[e]);
-        double r = fmin(av * inv1p, M);
-        if (s == kFree) r = fmin(r, fmax(av - tau, 0.0));
-        xv = (r == 0.0) ? 0.0 : copysign(r, h[e]);
-      }
-      const uint32_t j = (uint32_t)(tid + e * NT);
-      xn[j] = xv;
-      bb.Bx[off + j] = xv;
-    }
-    h[e] = xv;
-  }
-  IterStats is = finish_2<EPT>(h, sv, kbar, M, bb.sidx + off, bb.sval + off, lds, R);
-  if (tid == 0) {
-    S->gval = is.gval;
-    S->indom = is.indom;
-    S->nsupp = is.nsupp;
-    S->tau = tau;
-    S->tau_iters = evals;
-    S->parity = parity ^ 1;
-    S->iter = S->iter + 1;
-  }
+  prox_finish(Lnew, false);
 }
 
 }  // namespace

@@ -247,6 +247,69 @@ def test_gemm_rejects_bad_shapes(dev):
         pr.gemm(A, B, KS=3)     # K not a multiple of 32 * KS
 
 
+@pytest.mark.parametrize("loss,storage", [(0, "bf16"), (1, "f32"), (0, "f32")])
+@pytest.mark.parametrize("K", [1, 6, 40])
+def test_batch_backtracking_iterates_match_oracle(dev, loss, storage, K):
+    """FISTA with backtracking and the gap restart on the batched path: after
+    exactly K accepted iterations each node's iterate equals the oracle's
+    x^K (same L0, growth and cap), with the same number of rejected trials."""
+    pr = _pr()
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=loss, seed=60 + loss, storage=storage)
+    ctx = _ctx(dev, inst, 16)
+    raw = make_nodes(inst.p, 7, seed=7, max_j0=40, max_j1=6)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    Lmax = (2.0 if loss == 0 else 0.25) * 1.01 * ctx.norm2()
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-15, max_iter=K, check_every=2, method=pr.FISTA_BT_GAP,
+                             L=Lmax, L0=Lmax / 16.0, acfgm_c=2.0)
+    B = B.cpu().numpy()
+    for i, (nd, r) in enumerate(zip(nodes, res)):
+        st = nd.status(inst.p)
+        # a node may close its gap to rounding level (1e-15) before K; it is
+        # then compared at the iterate where it stopped
+        assert r["iters"] == K or (r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-14), r
+        kk = r["iters"]
+        ref = oracle.solve_bt(inst.Xcm, inst.y, loss, 0.2, 2.0, 8, status=st, L0=Lmax / 16.0, c=2.0, Lmax=Lmax,
+                              tol=-1.0, max_iter=kk)
+        scale = max(1.0, float(np.max(np.abs(ref["beta"]))))
+        err = float(np.max(np.abs(B[i] - ref["beta"])))
+        print(K, i, r["iters"], r["trials"], ref["rejected"], r["restarts"], ref["restarts"], err, flush=True)
+        assert ref["iters"] == kk and (kk < K or r["status"] == pr.MAXITER)
+        assert err <= 1e-12 * scale
+        if kk < K:
+            continue       # at a gap of 1e-15 the model test compares rounding noise: counts may differ
+        assert r["trials"] == ref["rejected"]
+        assert ref["restarts"] - 1 <= r["restarts"] <= ref["restarts"]
+    ctx.close()
+
+
+@pytest.mark.parametrize("loss,storage", [(0, "bf16"), (1, "f32")])
+def test_batch_backtracking_converges_per_node(dev, loss, storage):
+    """Batched FISTA with backtracking to 1e-7: every node's bound against the
+    oracle's and its returned pair recertified by the oracle; fewer
+    evaluations than the batched fixed step."""
+    pr = _pr()
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=loss, seed=40 + loss, storage=storage)
+    ctx = _ctx(dev, inst, 16)
+    raw = make_nodes(inst.p, 11, seed=4, max_j0=40, max_j1=6)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    res, B = ctx.solve_batch(nodes, rel_gap_tol=1e-7, max_iter=20000, method=pr.FISTA_BT_GAP)
+    fixed, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-7, max_iter=20000, want_beta=False)
+    B = B.cpu().numpy()
+    for i, (nd, r) in enumerate(zip(nodes, res)):
+        st = nd.status(inst.p)
+        ref = oracle.solve(inst.Xcm, inst.y, loss, 0.2, 2.0, 8, status=st, tol=1e-10)
+        assert r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-7
+        assert abs(r["lower_bound"] - ref["lb"]) <= 1.5e-7 * abs(r["primal"])
+        phi = oracle.primal(inst.Xcm, inst.y, B[i], loss, 0.2, 2.0, 8, status=st)
+        psi = oracle.dual(inst.Xcm, inst.y, _zeta(inst, B[i]), loss, 0.2, 2.0, 8, status=st)
+        assert abs(phi - r["primal"]) <= 1e-11 * abs(phi) and abs(psi - r["lower_bound"]) <= 1e-10 * abs(phi)
+    ev_bt = sum(r["iters"] + r["trials"] for r in res)
+    ev_fx = sum(r["iters"] for r in fixed)
+    print("evaluations: backtracking", ev_bt, "fixed step", ev_fx, flush=True)
+    assert ev_bt < ev_fx
+    ctx.close()
+
+
 def test_batch_full_size_logistic_fp32(dev):
     """64 logistic nodes on the FP32 n=32768, p=16384 design: every node
     converges on the batched path, and the oracle recomputes Phi and Psi at
