@@ -658,8 +658,10 @@ def e1_bench(reps=20, seeds=5):
 
 def e3_bench(max_iter=20000):
     """Convergence of the iteration variants on the bench workload (and the
-    logistic workload): FISTA with the duality-gap restart at eta = e^3 and
-    eta = e (the paper's convergence-study setting), FISTA without restart,
+    logistic workload): FISTA with line search (backtracking) with and
+    without the duality-gap restart, FISTA with the fixed step and the
+    duality-gap restart at eta = e^3 and eta = e (the paper's
+    convergence-study setting), FISTA without restart,
     FISTA with function-value restart, proximal gradient.  Per-iterate
     (Phi, Psi) traces from the GPU; reported: iterations to reach relative
     gaps 1e-2 .. 1e-6 (best-so-far bounds) and the fitted log-gap slope."""
@@ -677,7 +679,10 @@ def e3_bench(max_iter=20000):
         node = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
         cap = max_iter if loss == pr.LSQ else max_iter // 4
         res = {}
-        for name, meth, eta in (("fista_gap_restart_e3", pr.FISTA_GAP, math.exp(3.0)),
+        for name, meth, eta in (("fista_linesearch_gap_restart_e3", pr.FISTA_BT_GAP, math.exp(3.0)),
+                                ("fista_linesearch_gap_restart_e", pr.FISTA_BT_GAP, math.e),
+                                ("fista_linesearch_no_restart", pr.FISTA_BT, math.exp(3.0)),
+                                ("fista_gap_restart_e3", pr.FISTA_GAP, math.exp(3.0)),
                                 ("fista_gap_restart_e", pr.FISTA_GAP, math.e),
                                 ("fista_no_restart", pr.FISTA, math.exp(3.0)),
                                 ("fista_function_value_restart", pr.FISTA_FV, math.exp(3.0)),
@@ -794,13 +799,15 @@ def bnb_bench(n=16000, p=16000, corr=0.5, k=10, lambda2=1.0, M=2.0, seed=0, batc
     setup_s = time.perf_counter() - t0
     print(json.dumps({"progress": "bnb setup", "generate_s": round(gen_s, 1), "context_s": round(setup_s, 2)}),
           flush=True)
-    res, beta = ctx.bnb(pr.Node(k, lambda2, M), rel_gap_tol=1e-4, time_limit_s=time_limit, max_nodes=200000)
+    res, beta = ctx.bnb(pr.Node(k, lambda2, M), node_opts=dict(SOLVE_KW), rel_gap_tol=1e-4, time_limit_s=time_limit,
+                        max_nodes=200000)
     b = beta.cpu().numpy()
     support = np.flatnonzero(b).tolist()
     truth = (np.arange(k) * (p // k)).tolist()
     out = {"metric": "branch and bound to 1e-4 relative optimality gap",
            "loss": "least_squares" if loss == pr.LSQ else "logistic", "n": n, "p": p, "corr": corr, "k": k,
            "lambda2": lambda2, "M": M, "x_storage": storage, "batch": batch, "context_setup_s": round(setup_s, 3),
+           "node_method": METHOD_NAME[SOLVE_KW["method"]],
            **{kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in res.items()},
            "node_relaxations_per_s": round(res["nodes_solved"] / max(res["relaxation_seconds"], 1e-9), 2),
            "incumbent_support": support, "true_support_recovered": sorted(support) == sorted(truth),

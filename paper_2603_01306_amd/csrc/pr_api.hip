@@ -61,6 +61,8 @@ struct pr_ctx {
   hipGraphExec_t gexec = nullptr;
   int32_t graph_units = 0;
   bool graph_gram = false;  // the iteration graph was captured in Gram mode
+  bool step_bt = false;     // the next solve's step is the backtracking variant
+  bool graph_bt = false;    // ... and the captured graph's is
   int32_t debug = 0;        // pr_ctx_set_debug flags
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
@@ -265,7 +267,7 @@ double curvature(int loss) { return loss == kLsq ? 2.0 : 0.25; }
 // `unit` is the unit's position in the captured graph (its parity selects the
 // x buffers; see StepArgs).
 hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
-  const StepArgs a{c->P.p, c->d_stp, c->gram ? c->gb : nullptr, unit & 1};
+  const StepArgs a{c->P.p, c->d_stp, c->gram ? c->gb : nullptr, unit & 1, c->step_bt ? 1 : 0};
   if (c->gram) {
     // h = b - G x over the support of x, then the node step
     hipError_t e = launch_spfwd(c->PG, c->BG, c->nb.sidx, c->nb.sval, &c->d_state->nsupp, kSpGram, c->d_state,
@@ -292,7 +294,7 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
 // is done exit at once).
 int ensure_graph(pr_ctx *c, int32_t units) {
   units += units & 1;
-  if (c->gexec && c->graph_units == units && c->graph_gram == c->gram) return PR_OK;
+  if (c->gexec && c->graph_units == units && c->graph_gram == c->gram && c->graph_bt == c->step_bt) return PR_OK;
   if (c->gexec) {
     (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -314,6 +316,7 @@ int ensure_graph(pr_ctx *c, int32_t units) {
   }
   c->graph_units = units;
   c->graph_gram = c->gram;
+  c->graph_bt = c->step_bt;
   return PR_OK;
 }
 
@@ -1302,6 +1305,7 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   if (opts.method == kAcfgmGap || opts.method == kAcfgm)
     return solve_acfgm(c, &opts, L, beta0, beta_out, zeta_out, out);
   PR_TRY(launch_node_init(c->d_prm, c->d_state, c->nb, beta0, L_init, p, c->stream));
+  c->step_bt = is_bt(opts.method);
   rc = ensure_graph(c, opts.check_every);
   if (rc != PR_OK) return rc;
   // backtracking: rejected trials take evaluations beyond the iteration budget

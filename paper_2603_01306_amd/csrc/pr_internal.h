@@ -74,6 +74,7 @@ struct NodeState {
   double tk;       // kbar-th largest free |w| of the dual at the last iterate (<= 0: none)
   double tkw;      // relative half-width of the selection window around tk
   double dxy;      // backtracking: ||x_trial - y||^2 of the pending trial
+  double bt_A;     // backtracking, least squares: (x_trial - y)^T h(y), h(y) = -grad f(y) / 2
 };
 
 // Node-local vectors.
@@ -192,6 +193,7 @@ struct StepArgs {
   const uint32_t *stp;
   const double *gb;
   int32_t parity;
+  int32_t bt;  // the backtracking variant of the step (pr_opts.method PR_FISTA_BT*)
 };
 hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, const ProbBufs &B,
                             int64_t p, hipStream_t s, const StepArgs *a = nullptr);

@@ -1024,7 +1024,7 @@ __device__ __forceinline__ IterStats finish_2(const double (&x)[EPT], const Pack
   return IterStats{gv, ok, tot};
 }
 
-template <int EPT>
+template <int EPT, bool BT>
 __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict__ prm, NodeState *S,
                                                     NodeBufs nb, ProbBufs B, StepArgs A) {
   __shared__ StepLds<EPT> lds;
@@ -1040,9 +1040,12 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // vector loads below; the done test waits for them only after those
   const int done0 = S->done, indom0 = S->indom, it0 = S->iter;
   const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw, dxy0 = S->dxy;
+  const double btA = S->bt_A;
   const int kbar = prm->kbar, loss = prm->loss;
   const double lam2 = prm->lambda2, M = prm->M;
-  const bool bt = is_bt(prm->method);
+  // backtracking (a compile-time variant, so the fixed-step kernel carries none
+  // of its registers)
+  constexpr bool bt = BT;
   // x^k (backtracking: a rejected trial is overwritten by the last accepted
   // iterate through xcw, so xc carries no restrict qualifier)
   const double *xc = parity ? nb.x1 : nb.x0;
@@ -1126,14 +1129,16 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // by the pooled threshold, written to xn (after a rejected trial the last
   // accepted iterate moves from xn to the current buffer first, so that the
   // parity of the next evaluation finds the new trial current and x^k
-  // previous); backtracking keeps ||x - y||^2 for the test of the new trial.
+  // previous); backtracking keeps ||x - y||^2 and (least squares) the part
+  // (x - y)^T h(y) of the model test of the new trial (h(y) = -grad f(y) / 2),
+  // with y and grad f(y) in xq[] and g2[] where x^k is held in registers.
   auto prox_finish = [&](double Ls, bool rejected) {
     const double rho = 2.0 * lam2 / Ls;
     int evals = 0;
     auto vabs = [&](int e) { return sv(e) == kFree ? fabs(x[e]) : -1.0; };
     const double tau = solve_tau_2<EPT>(vabs, kbar, rho, M, tau0, R, &evals);
     const double inv1p = 1.0 / (1.0 + rho);
-    double dxy[1] = {0.0};
+    double dxy[2] = {0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < EPT; e++) {
       const int s = sv(e);
@@ -1149,8 +1154,17 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
         if (rejected) xcw[j] = xn[j];
         xn[j] = xv;
         if (bt) {
-          const double dy = xv - nb.ybt[j];
+          double yv, gv;
+          if constexpr (kHoldXk) {
+            yv = xq[e];
+            gv = g2[e];
+          } else {
+            yv = nb.ybt[j];
+            gv = nb.gbt[j];
+          }
+          const double dy = xv - yv;
           dxy[0] += dy * dy;
+          dxy[1] -= 0.5 * dy * gv;
         }
       }
       x[e] = xv;
@@ -1179,6 +1193,7 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
       if (bt) {
         S->L = Ls;
         S->dxy = dxy[0];
+        S->bt_A = dxy[1];
         S->bt_acc = rejected ? 0 : 1;
         if (rejected) {
           S->trials = S->trials + 1;
@@ -1191,46 +1206,26 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // momentum point y; it is accepted when f(x) - f(y) - <grad f(y), x - y> <=
   // (L / 2) ||x - y||^2 (or L has reached Lmax), else the step is redone
   // from the saved y and grad f(y) with c L, and the trial is not evaluated.
-  if (bt && it0 > 0) {
-    double dv = 0.0;
-    if (loss == kLsq) {
-      // f(x) - f(y) - <grad f(y), x - y> = ||X (x - y)||^2 = (x - y)^T (h(y) - h(x)),
-      // h = X^T (y_obs - X .) (Gram mode b - G .) and h(y) = -grad f(y) / 2
-      double d1[1] = {0.0};
-#pragma unroll
-      for (int e = 0; e < EPT; e++) {
-        if (sv(e) == 3) continue;
-        const uint32_t j = (uint32_t)(tid + e * NT);
-        double xe;
-        if constexpr (kHoldXk) xe = xk[e];
-        else xe = xc[j];
-        d1[0] += (xe - nb.ybt[j]) * (-0.5 * nb.gbt[j] - x[e]);
-      }
-      R.sum(d1);
-      dv = d1[0];
-    } else {
-      // logistic: the loss epilogue summed the remainder row by row
-      for (int i = lane_id(); i < B.nfin; i += 64) dv += B.dsum[i];
-      dv = wave_sum(dv);
-    }
-    if (!(L >= prm->Lmax || dv <= 0.5 * L * dxy0)) {
-      const double Ls = fmin(prm->ls_c * L, prm->Lmax);
-      const double invLs = 1.0 / Ls;
-#pragma unroll
-      for (int e = 0; e < EPT; e++) {
-        const uint32_t j = (uint32_t)(tid + e * NT);
-        x[e] = sv(e) != 3 ? nb.ybt[j] - nb.gbt[j] * invLs : 0.0;
-      }
-      prox_finish(Ls, true);
-      return;
-    }
+  // The test needs f(x) - f(y) - <grad f(y), x - y>: least squares
+  // ||X (x - y)||^2 = (x - y)^T (h(y) - h(x)) = A - (x - y)^T h(x), A kept by the
+  // step that made x and the second term summed with the dual's first
+  // reduction below (h = X^T (y_obs - X .), Gram mode b - G .); logistic from
+  // the loss epilogue's row-wise remainder.
+  const bool trial = bt && it0 > 0;
+  const bool trial_ls = trial && loss == kLsq;
+  double dlog = 0.0;
+  if (trial && loss != kLsq) {
+    for (int i = lane_id(); i < B.nfin; i += 64) dlog += B.dsum[i];
+    dlog = wave_sum(dlog);
   }
   // dual value at x^k: w = X^T zeta / (2 lambda2); the top-kbar window of
   // free |w| around the previous kbar-th value
   const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
   const bool wv = tkp > 0.0 && kbar > 0;
   const double wa = wv ? tkp * (1.0 - dlt) : INFINITY, wb = wv ? tkp * (1.0 + dlt) : INFINITY;
-  // r1: sum_{J1} H_M(w_j); Gram: x^T (b + h), b^T x; #{w > wb}, #{w >= wa}, sum_{w > wb} H_M(w)
+  // r1: sum_{J1} H_M(w_j); Gram: x^T (b + h), b^T x; #{w > wb}, #{w >= wa}, sum_{w > wb} H_M(w);
+  // backtracking least squares: (x - y)^T h(x)
+  double r1x[1] = {0.0};
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
     const int s = sv(e);
@@ -1245,8 +1240,47 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
       }
       if (aw >= wa) r1[4] += 1.0;
     }
+    if (trial_ls) {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      double xe;
+      if constexpr (kHoldXk) xe = xk[e];
+      else xe = xc[j];
+      r1x[0] += (xe - nb.ybt[j]) * x[e];
+    }
   }
-  R.sum(r1);
+  if (trial_ls) {
+    double r7[7] = {r1[0], r1[1], r1[2], r1[3], r1[4], r1[5], r1x[0]};
+    R.sum(r7);
+#pragma unroll
+    for (int q = 0; q < 6; q++) r1[q] = r7[q];
+    r1x[0] = r7[6];
+  } else {
+    R.sum(r1);
+  }
+  // Backtracking: every point after the start is a trial of the step from the
+  // momentum point y; it is accepted when f(x) - f(y) - <grad f(y), x - y> <=
+  // (L / 2) ||x - y||^2 (or L has reached Lmax), else the step is redone
+  // from the saved y and grad f(y) with c L, and the trial is not evaluated.
+  if (trial) {
+    const double dv = trial_ls ? btA - r1x[0] : dlog;
+    if (!(L >= prm->Lmax || dv <= 0.5 * L * dxy0)) {
+      const double Ls = fmin(prm->ls_c * L, prm->Lmax);
+      const double invLs = 1.0 / Ls;
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        const bool in = sv(e) != 3;
+        const double yj = in ? nb.ybt[j] : 0.0, gj = in ? nb.gbt[j] : 0.0;
+        if constexpr (kHoldXk) {
+          xq[e] = yj;
+          g2[e] = gj;
+        }
+        x[e] = in ? yj - gj * invLs : 0.0;
+      }
+      prox_finish(Ls, true);
+      return;
+    }
+  }
   if (gb) {
     // F(X x) = y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F, as
     // h = b - G x: both from the Gram quantities, no pass over X
@@ -1373,7 +1407,9 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   const double Lnew = (bt && restart) ? prm->L0 : L;
   const double invL = 1.0 / Lnew;
   // gradient step at the momentum point on entries [e0, e1); x[] then holds v
-  auto grad = [&](int e, double xke, double xqe, double g2e) {
+  // (backtracking: y and grad f(y) are stored for a redo and, where x^k is
+  // held in registers, left in xq[] / g2[] for the model-test terms)
+  auto grad = [&](int e, double xke, double &xqe, double &g2e) {
     const double h = x[e];
     const double yj = xke + m * (xke - xqe);
     double gj;
@@ -1385,6 +1421,10 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
       const uint32_t j = (uint32_t)(tid + e * NT);
       nb.ybt[j] = yj;
       nb.gbt[j] = gj;
+    }
+    if (bt) {
+      xqe = yj;
+      g2e = gj;
     }
   };
   if constexpr (kHoldXk) {
@@ -1873,12 +1913,18 @@ hipError_t launch_node_step(const NodeParams *prm, NodeState *S, NodeBufs nb, co
   const int ept = node_ept(p);
   if (ept != 0 && !a) return hipErrorInvalidValue;
   switch (ept) {
-    case 1: k_node_step_r<1><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
-    case 2: k_node_step_r<2><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
-    case 4: k_node_step_r<4><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
-    case 8: k_node_step_r<8><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
-    case 16: k_node_step_r<16><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
-    case 32: k_node_step_r<32><<<1, NT, 0, s>>>(prm, S, nb, B, *a); break;
+#define PR_STEP_CASE(E)                                                          \
+  case E:                                                                        \
+    if (a->bt) k_node_step_r<E, true><<<1, NT, 0, s>>>(prm, S, nb, B, *a);       \
+    else k_node_step_r<E, false><<<1, NT, 0, s>>>(prm, S, nb, B, *a);            \
+    break;
+    PR_STEP_CASE(1)
+    PR_STEP_CASE(2)
+    PR_STEP_CASE(4)
+    PR_STEP_CASE(8)
+    PR_STEP_CASE(16)
+    PR_STEP_CASE(32)
+#undef PR_STEP_CASE
     default: k_node_step<<<1, NT, 0, s>>>(prm, S, nb, B); break;
   }
   return hipGetLastError();
