@@ -170,6 +170,10 @@ int pr_ctx_destroy(pr_ctx *ctx);
  * confirmed by the recomputation over X, so the matrix-vector re-solve runs
  * (lets tests reach that path).  PR_EINVAL for unknown bits. */
 #define PR_DEBUG_GRAM_RECHECK 1
+/* PR_DEBUG_FORCE_BATCH: pr_solve_batch on a context with the batched path
+ * always iterates the nodes together, also where its cost estimate would run
+ * a small round one node at a time. */
+#define PR_DEBUG_FORCE_BATCH 2
 int pr_ctx_set_debug(pr_ctx *ctx, int32_t flags);
 /* Cached estimate of ||X||_2^2 (largest eigenvalue of X^T X). */
 int pr_ctx_norm2(pr_ctx *ctx, double *norm2_out);
@@ -290,7 +294,11 @@ int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
  * iterate and the loss gradient at the momentum point).  Every stopped
  * node's Phi and Psi are then recomputed over the stored X, and a node whose
  * decision (converged / prune / branch) is not confirmed continues alone on
- * the pr_solve path.  Other contexts run pr_solve node by node.  Every
+ * the pr_solve path.  Other contexts run pr_solve node by node, and so does a
+ * round whose measured per-iteration cost is lower one node at a time (the
+ * batch's GEMMs at m active rows, timed at context creation, against m
+ * single-node iterations: a 64-row MFMA tile costs as much for one node as
+ * for 64).  Every
  * iteration variant but AC-FGM (which runs node by node) runs batched, the
  * backtracking line search per node.  Traces (opts->trace) are not recorded.
  *   B0 device m x p (row i = warm start of node i) or NULL; B_out device

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libpr.so")
 
 PR_OK, PR_EINVAL, PR_EOVERLAP, PR_EDEVICE, PR_ENOMEM = 0, -1, -2, -3, -4
 PROX_NOALLOC_MAX_P = 1048576
-DEBUG_GRAM_RECHECK = 1
+DEBUG_GRAM_RECHECK, DEBUG_FORCE_BATCH = 1, 2
 CONVERGED, MAXITER, INFEASIBLE, CUTOFF_PRUNE, CUTOFF_BRANCH = 1, 2, 3, 4, 5
 FREE, ZERO, ONE = 0, 1, 2
 FISTA_GAP, FISTA, FISTA_FV, PGD, ACFGM_GAP, ACFGM, FISTA_BT_GAP, FISTA_BT = 0, 1, 2, 3, 4, 5, 6, 7

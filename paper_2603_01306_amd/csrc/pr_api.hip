@@ -93,6 +93,8 @@ struct pr_ctx {
   int32_t *d_split = nullptr;     // {rows still iterating, forward split, transpose split, compacted Gram split, tile counters x2}
   int32_t *d_ftab = nullptr;      // [kTuneTables][kTuneMax] tuned split factors per active row-tile count
   int32_t h_ftab[kTuneTables * kTuneMax] = {};
+  double h_tbest[kTuneTables * kTuneMax] = {};  // measured ms of the chosen split per active row-tile count
+  double t_gemv_ms = 0.0;                       // one X^T pass of the single-node iteration (measured)
   // batched Gram mode: U = G X_it planes [KSG * f][cap padded][p] (CT's storage when it is large enough)
   int32_t KSG = 1, fmaxG = 1;
   double *CG = nullptr;
@@ -559,13 +561,56 @@ int tune_batch(pr_ctx *c) {
         }
       }
       c->h_ftab[g * kTuneMax + nta] = bestf;
+      c->h_tbest[g * kTuneMax + nta] = best;
     }
-    for (int nta = ntmax + 1; nta < kTuneMax; nta++) c->h_ftab[g * kTuneMax + nta] = c->h_ftab[g * kTuneMax + ntmax];
+    for (int nta = ntmax + 1; nta < kTuneMax; nta++) {
+      c->h_ftab[g * kTuneMax + nta] = c->h_ftab[g * kTuneMax + ntmax];
+      c->h_tbest[g * kTuneMax + nta] = c->h_tbest[g * kTuneMax + ntmax];
+    }
     c->h_ftab[g * kTuneMax] = 1;
   }
   PR_TRY(hipMemcpyAsync(c->d_ftab, c->h_ftab, sizeof(c->h_ftab), hipMemcpyHostToDevice, s));
+  // one X^T pass of the single-node path (its form for this loss), for the
+  // choice between the batched and the one-at-a-time path (batch_pays)
+  {
+    const bool two = c->P.loss == kLogistic;
+    auto pass = [&]() {
+      return launch_gemv_t(c->P, c->B.r, two ? c->B.gm : nullptr, c->B.h1, two ? c->B.h2 : nullptr, nullptr, s);
+    };
+    PR_TRY(pass());
+    PR_TRY(hipEventRecord(c->tev[0], s));
+    for (int r = 0; r < kTuneReps; r++) PR_TRY(pass());
+    PR_TRY(hipEventRecord(c->tev[1], s));
+    PR_TRY(hipEventSynchronize(c->tev[1]));
+    float ms = 0.0f;
+    PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+    c->t_gemv_ms = (double)ms / kTuneReps;
+  }
   PR_TRY(hipStreamSynchronize(s));
   return PR_OK;
+}
+
+// Whether m nodes go faster through the batched iteration than one at a time:
+// per iteration, the batch costs its two GEMMs at m active rows (the tuned
+// times; Gram mode its one product) plus the node steps, the single-node path
+// m times one X^T pass plus the product over the support and the step
+// (Gram mode: the product over the support's Gram columns and the step).  A
+// 64-row MFMA tile costs the same for 1 node as for 64, so small rounds
+// (typically the first levels of a branch-and-bound tree) run one at a time.
+bool batch_pays(const pr_ctx *c, int32_t m) {
+  int nta = nr_of(m) / 64, nta2 = nr_of(c->rs * m) / 64;
+  if (nta >= kTuneMax) nta = kTuneMax - 1;
+  if (nta2 >= kTuneMax) nta2 = kTuneMax - 1;
+  const double step = 0.03;  // ms: the batched node steps / one single-node step
+  double t_batch, t_single;
+  if (c->gram && c->gram_batch_ok) {
+    t_batch = c->h_tbest[2 * kTuneMax + nta] + step;
+    t_single = 0.4 * c->t_gemv_ms + step;
+  } else {
+    t_batch = c->h_tbest[nta] + c->h_tbest[kTuneMax + nta2] + step;
+    t_single = 1.3 * c->t_gemv_ms + step;
+  }
+  return (double)m * t_single >= t_batch;
 }
 
 // Split factor of the second product (X^T R) for a batch of m nodes: the
@@ -691,8 +736,12 @@ int tune_gram_batch(pr_ctx *c) {
       }
     }
     c->h_ftab[2 * kTuneMax + nta] = bestf;
+    c->h_tbest[2 * kTuneMax + nta] = best;
   }
-  for (int nta = ntmax + 1; nta < kTuneMax; nta++) c->h_ftab[2 * kTuneMax + nta] = c->h_ftab[2 * kTuneMax + ntmax];
+  for (int nta = ntmax + 1; nta < kTuneMax; nta++) {
+    c->h_ftab[2 * kTuneMax + nta] = c->h_ftab[2 * kTuneMax + ntmax];
+    c->h_tbest[2 * kTuneMax + nta] = c->h_tbest[2 * kTuneMax + ntmax];
+  }
   c->h_ftab[2 * kTuneMax] = 1;
   PR_TRY(hipMemcpyAsync(c->d_ftab, c->h_ftab, sizeof(c->h_ftab), hipMemcpyHostToDevice, s));
   PR_TRY(hipStreamSynchronize(s));
@@ -1043,7 +1092,7 @@ int pr_ctx_destroy(pr_ctx *c) {
 }
 
 int pr_ctx_set_debug(pr_ctx *c, int32_t flags) {
-  if (!c || (flags & ~PR_DEBUG_GRAM_RECHECK)) return PR_EINVAL;
+  if (!c || (flags & ~(PR_DEBUG_GRAM_RECHECK | PR_DEBUG_FORCE_BATCH))) return PR_EINVAL;
   c->debug = flags;
   return PR_OK;
 }
@@ -1952,7 +2001,9 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (rc != PR_OK) return rc;
     infeas[(size_t)i] = inf;
   }
-  if (!c->batch_ok || opts.method == kAcfgmGap || opts.method == kAcfgm) {  // AC-FGM: node by node
+  // AC-FGM, and rounds too small for the batch to pay (batch_pays), run node by node
+  if (!c->batch_ok || opts.method == kAcfgmGap || opts.method == kAcfgm ||
+      (!(c->debug & PR_DEBUG_FORCE_BATCH) && !batch_pays(c, m))) {
     for (int32_t i = 0; i < m; i++) {
       int rc = pr_solve(c, &nodes[i], &opts, B0 ? B0 + (int64_t)i * p : nullptr,
                         B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &out[i]);

@@ -28,7 +28,10 @@ def _ctx(dev, inst, max_batch):
         X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
     else:
         X = torch.from_numpy(inst.Xcm).to(dev)
-    return pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
+    c = pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
+    if max_batch > 1:
+        c.set_debug(pr.DEBUG_FORCE_BATCH)   # the batched path even where one at a time would be cheaper
+    return c
 
 
 def _zeta(inst, beta):

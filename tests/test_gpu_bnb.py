@@ -22,7 +22,10 @@ def _ctx(inst, dev, max_batch):
         X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
     else:
         X = torch.from_numpy(inst.Xcm).to(dev)
-    return pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
+    c = pr.Context(X, torch.from_numpy(inst.y).to(dev), inst.loss, max_batch=max_batch)
+    if max_batch > 1:
+        c.set_debug(pr.DEBUG_FORCE_BATCH)   # the batched path even for rounds one at a time would win
+    return c
 
 
 def _objective(X, y, b, lam2):

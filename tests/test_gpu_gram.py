@@ -84,6 +84,7 @@ def _bctx(inst, dev, gram, m):
     import paper_2603_01306_amd as pr
     X = torch.from_numpy(inst.Xcm.view(np.int16)).to(dev).view(torch.bfloat16)
     c = pr.Context(X, torch.from_numpy(inst.y).to(dev), 0, max_batch=m)
+    c.set_debug(pr.DEBUG_FORCE_BATCH)
     if gram:
         c.enable_gram()
     return c
