@@ -286,7 +286,7 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
   const bool reg = node_ept(c->P.p) != 0;
   e = launch_gemv_t(c->P, c->B.r, c->P.loss == kLsq ? nullptr : c->B.gm, c->B.h1, c->B.h2,
                     &c->d_state->done, s, reg ? c->d_prm : nullptr, c->d_state, c->nb.sidx, c->nb.sval,
-                    &c->d_state->nsupp);
+                    &c->d_state->nsupp, (reg && c->step_bt) ? c->B.dsum : nullptr, c->B.nfin);
   if (e != hipSuccess) return e;
   return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s, &a);
 }

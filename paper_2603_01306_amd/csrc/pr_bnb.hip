@@ -104,6 +104,7 @@ static int try_incumbent(BnbState &st, const pr_node &node, const std::vector<in
   pr_opts lo;
   pr_opts_default(&lo);
   lo.rel_gap_tol = 1e-9;
+  if (node_ept(p) != 0) lo.method = PR_FISTA_BT_GAP;  // the line search where the register-resident step runs
   pr_result r;
   int rc = pr_solve(st.c, &leaf, &lo, d_beta, st.d_cand, nullptr, &r);
   if (rc != PR_OK) return rc;

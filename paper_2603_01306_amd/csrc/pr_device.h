@@ -149,6 +149,20 @@ __device__ __forceinline__ double softplus(double z) { return fmax(z, 0.0) + log
 
 __device__ __forceinline__ double fista_next_t(double t) { return 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t)); }
 
+// Backtracking model test of a trial, shared by the X^T pass (which skips a
+// rejected trial) and the node step, so that both take the same decision: the
+// remainder f(x) - f(y) - <grad f(y), x - y> summed over the loss epilogue's
+// blocks by one wave in a fixed order, against (L / 2) ||x - y||^2; a trial
+// at the cap Lmax is accepted.
+__device__ __forceinline__ double bt_remainder(const double *dsum, int nfin) {
+  double v = 0.0;
+  for (int i = lane_id(); i < nfin; i += 64) v += dsum[i];
+  return wave_sum(v);
+}
+__device__ __forceinline__ bool bt_accept(double D, double L, double dxy, double Lmax) {
+  return L >= Lmax || D <= 0.5 * L * dxy;
+}
+
 // Restart decision after the evaluation of iterate `it` (gap = Phi - Psi at
 // it, phi_prev = Phi at it - 1): the first iterate always starts an epoch;
 // then the duality-gap restart of Section 3.3 (gap fell by the factor eta

@@ -169,8 +169,12 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
                                                          const NodeParams *__restrict__ node, NodeState *S,
                                                          const int32_t *__restrict__ sidx,
                                                          const double *__restrict__ sval,
-                                                         const int32_t *__restrict__ nlist) {
+                                                         const int32_t *__restrict__ nlist,
+                                                         const double *__restrict__ dsum, int nfin) {
   if (done && *done) return;
+  // backtracking: a rejected trial needs no product (every wave takes the
+  // node step's decision from the same sums)
+  if (dsum && S->bt && S->iter > 0 && !bt_accept(bt_remainder(dsum, nfin), S->L, S->dxy, node->Lmax)) return;
   // with `node` the first workgroup (dispatched first) evaluates g_N of the
   // listed iterate; the product's workgroups follow it
   int bx = (int)blockIdx.x;
@@ -253,15 +257,17 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 
 hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
                          const int32_t *done, hipStream_t s, const NodeParams *node, NodeState *S,
-                         const int32_t *sidx, const double *sval, const int32_t *nlist) {
+                         const int32_t *sidx, const double *sval, const int32_t *nlist, const double *dsum,
+                         int32_t nfin) {
   if (node && (!S || !sidx || !sval || !nlist)) return hipErrorInvalidValue;
+  if (dsum && !node) return hipErrorInvalidValue;
   const bool two = (r2 != nullptr);
   const int cols_per_block = (kGemvThreads / 64) * gemv_cols(two ? 2 : 1);
   dim3 grid((unsigned)((P.p + cols_per_block - 1) / cols_per_block) + (node ? 1u : 0u));
   dim3 block(kGemvThreads);
 #define PR_GEMVT(T, R)                                                                                   \
   k_gemv_t<T, R><<<grid, block, 0, s>>>((const T *)P.X, P.n, P.p, r1, r2, h1, h2, done, node, S, sidx, sval, \
-                                        nlist)
+                                        nlist, dsum, nfin)
   switch (P.xdt) {
     case kF32:
       if (two) PR_GEMVT(float, 2);

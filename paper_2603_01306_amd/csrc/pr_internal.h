@@ -169,11 +169,14 @@ int32_t ctx_max_batch(const pr_ctx *c);
 // ---- kernel launchers ----
 // With `node` (and S, the node's support list sidx / sval of length *nlist),
 // one extra workgroup evaluates g_N and the dom test of the listed iterate
-// into S->gval / S->indom beside the product.
+// into S->gval / S->indom beside the product.  With `node` and dsum
+// (backtracking), a trial the model test rejects (bt_accept over the loss
+// epilogue's remainder sums) skips the product: its step is redone from the
+// saved momentum point without it.
 hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, double *h1, double *h2,
                          const int32_t *done, hipStream_t s, const NodeParams *node = nullptr,
                          NodeState *S = nullptr, const int32_t *sidx = nullptr, const double *sval = nullptr,
-                         const int32_t *nlist = nullptr);
+                         const int32_t *nlist = nullptr, const double *dsum = nullptr, int32_t nfin = 0);
 // u_partials / finalize: generic column-list GEMV u = sum_t X[:, idx[t]] * val[t]
 // followed by the per-row-block epilogue selected by `mode`.
 enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2, kSpGram = 3 };

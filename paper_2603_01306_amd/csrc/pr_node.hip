@@ -1206,18 +1206,16 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // momentum point y; it is accepted when f(x) - f(y) - <grad f(y), x - y> <=
   // (L / 2) ||x - y||^2 (or L has reached Lmax), else the step is redone
   // from the saved y and grad f(y) with c L, and the trial is not evaluated.
-  // The test needs f(x) - f(y) - <grad f(y), x - y>: least squares
-  // ||X (x - y)||^2 = (x - y)^T (h(y) - h(x)) = A - (x - y)^T h(x), A kept by the
-  // step that made x and the second term summed with the dual's first
-  // reduction below (h = X^T (y_obs - X .), Gram mode b - G .); logistic from
-  // the loss epilogue's row-wise remainder.
+  // The test needs f(x) - f(y) - <grad f(y), x - y>: from the loss
+  // epilogue's row-wise remainder (least squares ||X x - X y||^2; the X^T pass
+  // before this step took the same decision and skipped a rejected trial), in
+  // Gram mode ||X (x - y)||^2 = (x - y)^T (h(y) - h(x)) = A - (x - y)^T h(x),
+  // A kept by the step that made x and the second term summed with the dual's
+  // first reduction below (h = b - G .).
   const bool trial = bt && it0 > 0;
-  const bool trial_ls = trial && loss == kLsq;
+  const bool trial_ls = trial && gb != nullptr;
   double dlog = 0.0;
-  if (trial && loss != kLsq) {
-    for (int i = lane_id(); i < B.nfin; i += 64) dlog += B.dsum[i];
-    dlog = wave_sum(dlog);
-  }
+  if (trial && !gb) dlog = bt_remainder(B.dsum, B.nfin);
   // dual value at x^k: w = X^T zeta / (2 lambda2); the top-kbar window of
   // free |w| around the previous kbar-th value
   const double wscale = (loss == kLsq) ? 1.0 / lam2 : 0.5 / lam2;
@@ -1263,7 +1261,7 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // from the saved y and grad f(y) with c L, and the trial is not evaluated.
   if (trial) {
     const double dv = trial_ls ? btA - r1x[0] : dlog;
-    if (!(L >= prm->Lmax || dv <= 0.5 * L * dxy0)) {
+    if (!bt_accept(dv, L, dxy0, prm->Lmax)) {
       const double Ls = fmin(prm->ls_c * L, prm->Lmax);
       const double invLs = 1.0 / Ls;
 #pragma unroll

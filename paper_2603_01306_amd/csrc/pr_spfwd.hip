@@ -160,6 +160,10 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
   }
   const int improved = S->improved;
   if (mode == kSpLsq) {
+    // backtracking: X y of the pending trial as in the logistic branch below,
+    // and its model-test remainder ||X x - X y||^2 row by row
+    const int bt = S->bt, acc = S->bt_acc;
+    const double mp = S->mom;
     if (active) {
 #pragma unroll
       for (int e = 0; e < VEC; e++) {
@@ -170,6 +174,20 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
         B.r[i] = ri;
         sums[0] += ri * ri;
         sums[1] += 2.0 * ri * yi - ri * ri;
+        if (bt) {
+          const double uo = B.ucur[i];
+          double uyv;
+          if (acc) {
+            uyv = (1.0 + mp) * uo - mp * B.uprev[i];
+            B.uy[i] = uyv;
+            B.uprev[i] = uo;
+          } else {
+            uyv = B.uy[i];
+          }
+          B.ucur[i] = u[e];
+          const double du = u[e] - uyv;
+          sums[2] += du * du;
+        }
       }
     }
   } else {
