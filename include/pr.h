@@ -171,8 +171,8 @@ int pr_ctx_destroy(pr_ctx *ctx);
  * (lets tests reach that path).  PR_EINVAL for unknown bits. */
 #define PR_DEBUG_GRAM_RECHECK 1
 /* PR_DEBUG_FORCE_BATCH: pr_solve_batch on a context with the batched path
- * always iterates the nodes together, also where its cost estimate would run
- * a small round one node at a time. */
+ * always iterates the nodes together to the end, also where its cost estimate
+ * would run a small round, or the last nodes of a round, one at a time. */
 #define PR_DEBUG_FORCE_BATCH 2
 int pr_ctx_set_debug(pr_ctx *ctx, int32_t flags);
 /* Cached estimate of ||X||_2^2 (largest eigenvalue of X^T X). */
@@ -298,7 +298,9 @@ int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
  * round whose measured per-iteration cost is lower one node at a time (the
  * batch's GEMMs at m active rows, timed at context creation, against m
  * single-node iterations: a 64-row MFMA tile costs as much for one node as
- * for 64).  Every
+ * for 64); by the same measure, once the nodes still iterating are that few,
+ * they leave the batch and finish on the single-node path from their current
+ * iterates (their iters / restarts / trials count both parts).  Every
  * iteration variant but AC-FGM (which runs node by node) runs batched, the
  * backtracking line search per node.  Traces (opts->trace) are not recorded.
  *   B0 device m x p (row i = warm start of node i) or NULL; B_out device

@@ -2073,11 +2073,20 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
   PR_TRY(issue(1));
   launched++;
   int rebuilds = 0;
+  // tail handoff: once the nodes still iterating are so few that one node at a
+  // time is cheaper per iteration (batch_pays), the batch stops and they
+  // continue on the single-node path from their current iterates
+  bool handoff = false;
+  const bool may_hand_off = !(c->debug & PR_DEBUG_FORCE_BATCH);
   for (int64_t k = 0;; k++) {
     const int slot = (int)(k & 1);
     PR_TRY(hipEventSynchronize(c->ev[slot]));
     if (c->h_active[slot] <= 0) break;
     if (launched >= max_launches) break;
+    if (may_hand_off && !batch_pays(c, c->h_active[slot])) {
+      handoff = true;
+      break;
+    }
     if (c->union_on && rebuilds < kUnionRebuilds) {
       // supports still move in the first launches: once the other launch is
       // done, join the coordinates that left the union when there are more
@@ -2138,7 +2147,7 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
     if (st == kConverged) confirmed = rel <= opts.rel_gap_tol;
     else if (st == kCutoffPrune) confirmed = lb >= opts.cutoff;
     else if (st == kCutoffBranch) confirmed = ub <= opts.cutoff;
-    else confirmed = true;  // iteration limit
+    else confirmed = !(handoff && !hs.done);  // iteration limit; a handed-off node continues
     pr_result &r = out[i];
     if (confirmed) {
       r.lower_bound = lb;
@@ -2151,7 +2160,10 @@ int pr_solve_batch(pr_ctx *c, const pr_node *nodes, int32_t m, const pr_opts *op
       r.status = st;
       if (B_out) PR_TRY(hipMemcpyAsync(B_out + (int64_t)i * p, xq, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     } else {
-      pr_opts o2 = opts;  // a fresh iteration budget on the single-node FP64 path
+      // the single-node FP64 path from the node's iterate: a fresh budget after
+      // an unconfirmed decision, the rest of the budget after a handoff
+      pr_opts o2 = opts;
+      if (!hs.done) o2.max_iter = opts.max_iter > hs.iter ? opts.max_iter - hs.iter : 1;
       rc = pr_solve(c, &nodes[i], &o2, xq, B_out ? B_out + (int64_t)i * p : nullptr, nullptr, &r);
       if (rc != PR_OK) return rc;
       if (r.lower_bound < lb) r.lower_bound = lb;  // both are valid bounds

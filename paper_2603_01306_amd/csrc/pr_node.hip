@@ -813,6 +813,7 @@ struct StepLds {
   SelLds sel;
   int cnt[EPT * NW];       // support entries per (e, wave) group
   int ofs[NW][EPT * NW];   // each wave's copy of their exclusive prefix
+  double xsum[NW * 2];     // per-wave partials summed beside the support list's count exchange
   double bcd[4];
   int bci[4];
 };
@@ -941,7 +942,7 @@ __device__ __forceinline__ double alg1_2(F aval, int kbar, double theta, Red2 &R
 template <int EPT>
 __device__ __forceinline__ int support_list_2(const double (&x)[EPT], const PackedStatus<EPT> &sv,
                                               int32_t *__restrict__ sidx, double *__restrict__ sval,
-                                              StepLds<EPT> &L) {
+                                              StepLds<EPT> &L, double *xs = nullptr) {
   constexpr int NO = EPT * NW;
   constexpr int C = (NO + 63) / 64;
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -950,7 +951,24 @@ __device__ __forceinline__ int support_list_2(const double (&x)[EPT], const Pack
     const unsigned long long mk = __ballot(sv(e) != 3 && x[e] != 0.0);
     if (lane == 0) L.cnt[e * NW + w] = __popcll(mk);
   }
+  // optional: two per-thread partials summed over the block through the same
+  // barrier (per-wave sums in wave order, the same value in every thread)
+  if (xs) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const double v = wave_sum(xs[k]);
+      if (lane == 0) L.xsum[w * 2 + k] = v;
+    }
+  }
   lds_barrier();
+  if (xs) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      double acc = 0.0;
+      for (int q = 0; q < NW; q++) acc += L.xsum[q * 2 + k];
+      xs[k] = acc;
+    }
+  }
   int c[C];
   int loc = 0;
 #pragma unroll
@@ -1154,25 +1172,27 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
         if (rejected) xcw[j] = xn[j];
         xn[j] = xv;
         if (bt) {
-          double yv, gv;
-          if constexpr (kHoldXk) {
-            yv = xq[e];
-            gv = g2[e];
-          } else {
-            yv = nb.ybt[j];
-            gv = nb.gbt[j];
-          }
+          // y from registers (x^k held) or from the LDS copy the gradient
+          // step left (32 entries per thread); grad f(y) only for Gram's A
+          double yv;
+          if constexpr (kHoldXk) yv = xq[e];
+          else yv = wl[j];
           const double dy = xv - yv;
           dxy[0] += dy * dy;
-          dxy[1] -= 0.5 * dy * gv;
+          if (A.gb) {
+            double gv;
+            if constexpr (kHoldXk) gv = g2[e];
+            else gv = nb.gbt[j];
+            dxy[1] -= 0.5 * dy * gv;
+          }
         }
       }
       x[e] = xv;
     }
-    if (bt) R.sum(dxy);
     if (A.gb) {
       // Gram mode: no X^T r product follows, so the step evaluates g_N of the
       // new iterate and its dom test itself
+      if (bt) R.sum(dxy);
       IterStats is = finish_2<EPT>(x, sv, kbar, M, nb.sidx, nb.sval, lds, R);
       if (tid == 0) {
         S->gval = is.gval;
@@ -1181,8 +1201,9 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
       }
     } else {
       // the extra workgroup of the next X^T r product evaluates them from this
-      // support list (S->gval / S->indom before the next step reads them)
-      const int nsupp = support_list_2<EPT>(x, sv, nb.sidx, nb.sval, lds);
+      // support list (S->gval / S->indom before the next step reads them);
+      // backtracking's sums ride on the list's count exchange
+      const int nsupp = support_list_2<EPT>(x, sv, nb.sidx, nb.sval, lds, bt ? dxy : nullptr);
       if (tid == 0) S->nsupp = nsupp;
     }
     if (tid == 0) {
@@ -1272,6 +1293,8 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
         if constexpr (kHoldXk) {
           xq[e] = yj;
           g2[e] = gj;
+        } else {
+          wl[j] = yj;
         }
         x[e] = in ? yj - gj * invLs : 0.0;
       }
@@ -1423,6 +1446,7 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
     if (bt) {
       xqe = yj;
       g2e = gj;
+      if constexpr (!kHoldXk) wl[(uint32_t)(tid + e * NT)] = yj;  // the selection's LDS array is free by now
     }
   };
   if constexpr (kHoldXk) {

@@ -313,6 +313,32 @@ def test_batch_backtracking_converges_per_node(dev, loss, storage):
     ctx.close()
 
 
+@pytest.mark.parametrize("loss,storage", [(0, "bf16"), (1, "f32")])
+def test_batch_cost_rule_and_tail_handoff(dev, loss, storage):
+    """Without the test switch the batch may run a round one node at a time and
+    hand its last nodes to the single-node path: every node still converges
+    with the bound of the forced batched run, and its returned pair
+    recertifies over the stored X."""
+    pr = _pr()
+    inst = make_instance(n=1024, p=512, corr=0.8, k_true=8, snr=5.0, loss=loss, seed=90 + loss, storage=storage)
+    ctx = _ctx(dev, inst, 16)
+    raw = make_nodes(inst.p, 12, seed=11, max_j0=40, max_j1=6)
+    nodes = [pr.Node(8, 0.2, 2.0, J0=a, J1=b) for a, b in raw]
+    forced, _ = ctx.solve_batch(nodes, rel_gap_tol=1e-7, method=pr.FISTA_BT_GAP)
+    ctx.set_debug(0)
+    for sub in (nodes, nodes[:1], nodes[:3]):
+        res, B = ctx.solve_batch(sub, rel_gap_tol=1e-7, method=pr.FISTA_BT_GAP)
+        B = B.cpu().numpy()
+        for i, (nd, r, f) in enumerate(zip(sub, res, forced)):
+            st = nd.status(inst.p)
+            assert r["status"] == pr.CONVERGED and r["rel_gap"] <= 1e-7, r
+            assert abs(r["lower_bound"] - f["lower_bound"]) <= 2e-7 * abs(f["primal"])
+            phi = oracle.primal(inst.Xcm, inst.y, B[i], loss, 0.2, 2.0, 8, status=st)
+            psi = oracle.dual(inst.Xcm, inst.y, _zeta(inst, B[i]), loss, 0.2, 2.0, 8, status=st)
+            assert abs(phi - r["primal"]) <= 1e-11 * abs(phi) and psi <= r["lower_bound"] + 1e-10 * abs(phi)
+    ctx.close()
+
+
 def test_batch_full_size_logistic_fp32(dev):
     """64 logistic nodes on the FP32 n=32768, p=16384 design: every node
     converges on the batched path, and the oracle recomputes Phi and Psi at
