@@ -59,6 +59,7 @@ struct pr_ctx {
   double *d_vprev = nullptr;     // p: previous Lanczos vector
   double *d_regscratch = nullptr;  // 3p
   hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gtail = nullptr;  // the same iterations, kTailUnits of them (the last ones of a solve)
   int32_t graph_units = 0;
   bool graph_gram = false;  // the iteration graph was captured in Gram mode
   bool step_bt = false;     // the next solve's step is the backtracking variant
@@ -169,6 +170,7 @@ void pack_status(const std::vector<int8_t> &st, std::vector<uint32_t> &w) {
 void free_ctx(pr_ctx *c) {
   if (!c) return;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gtail) (void)hipGraphExecDestroy(c->gtail);
   if (c->bgexec) (void)hipGraphExecDestroy(c->bgexec);
   if (c->vgexec) (void)hipGraphExecDestroy(c->vgexec);
   {
@@ -291,16 +293,13 @@ hipError_t enqueue_unit(pr_ctx *c, hipStream_t s, int unit) {
   return launch_node_step(c->d_prm, c->d_state, c->nb, c->B, c->P.p, s, &a);
 }
 
-// The iteration graph: `units` iterations rounded up to an even count, so that
-// every launch starts with x^k in the first buffer (iterations after the node
-// is done exit at once).
-int ensure_graph(pr_ctx *c, int32_t units) {
-  units += units & 1;
-  if (c->gexec && c->graph_units == units && c->graph_gram == c->gram && c->graph_bt == c->step_bt) return PR_OK;
-  if (c->gexec) {
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-  }
+// Captured iterations of a solve after the node is done still cost their
+// launches (each kernel exits at once, ~20 us per iteration): the last ones run
+// as launches of a short graph.
+constexpr int32_t kTailUnits = 8;
+
+// Capture `units` iteration units into an executable graph.
+int capture_units(pr_ctx *c, int32_t units, hipGraphExec_t *out) {
   hipGraph_t g = nullptr;
   PR_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
@@ -310,45 +309,100 @@ int ensure_graph(pr_ctx *c, int32_t units) {
     if (g) (void)hipGraphDestroy(g);
     return PR_EDEVICE;
   }
-  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    c->gexec = nullptr;
+    *out = nullptr;
     return PR_EDEVICE;
   }
+  return PR_OK;
+}
+
+// The iteration graph: `units` iterations rounded up to an even count, so that
+// every launch starts with x^k in the first buffer (iterations after the node
+// is done exit at once), and the short tail graph when it is shorter.
+int ensure_graph(pr_ctx *c, int32_t units) {
+  units += units & 1;
+  if (c->gexec && c->graph_units == units && c->graph_gram == c->gram && c->graph_bt == c->step_bt) return PR_OK;
+  for (hipGraphExec_t *ge : {&c->gexec, &c->gtail})
+    if (*ge) {
+      (void)hipGraphExecDestroy(*ge);
+      *ge = nullptr;
+    }
+  c->graph_units = 0;
+  int rc = capture_units(c, units, &c->gexec);
+  if (rc == PR_OK && units > kTailUnits) rc = capture_units(c, kTailUnits, &c->gtail);
+  if (rc != PR_OK) return rc;
   c->graph_units = units;
   c->graph_gram = c->gram;
   c->graph_bt = c->step_bt;
   return PR_OK;
 }
 
-// Launch a captured iteration graph until the node state reports done (or
-// max_launches): two launches in flight, each followed by a copy of the node
-// state into its own pinned slot and an event.
-hipError_t run_graph(pr_ctx *c, hipGraphExec_t g, int64_t max_launches) {
-  auto issue = [&](int slot) -> hipError_t {
-    hipError_t e = hipGraphLaunch(g, c->stream);
+// Launch a captured iteration graph of `units` iterations until the node state
+// reports done or `max_units` iterations have been launched.  Each launch is
+// followed by a copy of the node state into its own pinned slot and an event;
+// at most two launches are in flight.  Iterations launched after the stop
+// still cost their launches, so the host predicts the stop from the rate at
+// which the relative gap fell over the last `units` or more evaluations: no
+// further launch is queued behind launches that are predicted to reach it, and
+// the last iterations run as launches of the short graph `gs` (`sunits`
+// iterations) when there is one.  The prediction only decides how much is
+// queued; the iterates do not depend on it.
+hipError_t run_graph(pr_ctx *c, hipGraphExec_t g, int32_t units, int64_t max_units, double tol,
+                     hipGraphExec_t gs = nullptr, int32_t sunits = 0) {
+  int slot = 0, head = 0, inflight = 0;
+  int32_t qunits[2] = {0, 0};
+  int64_t issued = 0;
+  auto issue = [&](bool small) -> hipError_t {
+    hipError_t e = hipGraphLaunch(small ? gs : g, c->stream);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(&c->h_state[slot], c->d_state, sizeof(NodeState), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return e;
-    return hipEventRecord(c->ev[slot], c->stream);
+    e = hipEventRecord(c->ev[slot], c->stream);
+    if (e != hipSuccess) return e;
+    qunits[slot] = small ? sunits : units;
+    issued += qunits[slot];
+    slot ^= 1;
+    inflight++;
+    return hipSuccess;
   };
-  int64_t launched = 0;
-  hipError_t e = issue(0);
+  hipError_t e = issue(false);
   if (e != hipSuccess) return e;
-  launched++;
-  e = issue(1);
-  if (e != hipSuccess) return e;
-  launched++;
-  for (int64_t i = 0;; i++) {
-    const int slot = (int)(i & 1);
-    e = hipEventSynchronize(c->ev[slot]);
+  if (issued < max_units) {
+    e = issue(false);
     if (e != hipSuccess) return e;
-    if (c->h_state[slot].done) break;
-    if (launched >= max_launches) break;
-    e = issue(slot);
+  }
+  // (evaluations, relative gap) at each observation with a finite gap
+  std::vector<std::pair<int64_t, double>> hist;
+  while (inflight > 0) {
+    e = hipEventSynchronize(c->ev[head]);
     if (e != hipSuccess) return e;
-    launched++;
+    const NodeState h = c->h_state[head];
+    head ^= 1;
+    inflight--;
+    if (h.done) break;
+    // evaluations predicted before the stop (infinite while the gap has not
+    // fallen over the window)
+    const int64_t ev = (int64_t)h.iter + h.trials;
+    double rem = INFINITY;
+    if (isfinite(h.rel_gap) && h.rel_gap > 0.0) {
+      const std::pair<int64_t, double> *base = nullptr;
+      for (const auto &o : hist)
+        if (ev - o.first >= units || !base) base = &o;
+      if (base && ev > base->first && h.rel_gap < base->second && tol > 0.0)
+        rem = log(h.rel_gap / tol) * (double)(ev - base->first) / log(base->second / h.rel_gap);
+      hist.emplace_back(ev, h.rel_gap);
+    }
+    double queued = inflight ? (double)qunits[head] : 0.0;
+    while (inflight < 2 && issued < max_units) {
+      const double need = rem - queued;
+      if (inflight > 0 && need <= 0.0) break;
+      const bool small = gs && need < (double)units;
+      e = issue(small);
+      if (e != hipSuccess) return e;
+      queued += small ? sunits : units;
+    }
   }
   return hipStreamSynchronize(c->stream);
 }
@@ -1170,7 +1224,8 @@ static int solve_acfgm(pr_ctx *c, const pr_opts *opts, double L, const double *b
   const double key[3] = {opts->acfgm_b, opts->acfgm_c, opts->method == kAcfgmGap ? 1.0 : 0.0};
   rc = ensure_variant_graph(c, 0, key, opts->check_every);
   if (rc != PR_OK) return rc;
-  PR_TRY(run_graph(c, c->vgexec, (int64_t)opts->max_iter / opts->check_every + 3));
+  PR_TRY(run_graph(c, c->vgexec, c->vgraph_units,
+                   ((int64_t)opts->max_iter / opts->check_every + 3) * c->vgraph_units, opts->rel_gap_tol));
   PR_TRY(launch_zbest_final(c->d_state, c->B, c->P.loss, n, c->stream));
   NodeState hs;
   AcState ha;
@@ -1222,7 +1277,8 @@ int pr_lasso_solve(pr_ctx *c, const pr_lasso *lp, const pr_opts *opts_in, const 
   const double key[3] = {lp->lam, 0.0, 0.0};
   rc = ensure_variant_graph(c, 1 + lp->kind, key, opts.check_every);
   if (rc != PR_OK) return rc;
-  PR_TRY(run_graph(c, c->vgexec, (int64_t)opts.max_iter / opts.check_every + 3));
+  PR_TRY(run_graph(c, c->vgexec, c->vgraph_units,
+                   ((int64_t)opts.max_iter / opts.check_every + 3) * c->vgraph_units, opts.rel_gap_tol));
   PR_TRY(launch_zbest_final(c->d_state, c->B, kLsq, n, c->stream));
   NodeState hs;
   LassoState hl;
@@ -1282,11 +1338,12 @@ int pr_ctx_enable_gram(pr_ctx *c) {
     if (rc != PR_OK) return rc;
   }
   c->gram = true;
-  if (c->gexec) {  // the captured iterations change
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-    c->graph_units = 0;
-  }
+  for (hipGraphExec_t *ge : {&c->gexec, &c->gtail})  // the captured iterations change
+    if (*ge) {
+      (void)hipGraphExecDestroy(*ge);
+      *ge = nullptr;
+    }
+  c->graph_units = 0;
   if (c->bgexec) {
     (void)hipGraphExecDestroy(c->bgexec);
     c->bgexec = nullptr;
@@ -1359,7 +1416,8 @@ int pr_solve(pr_ctx *c, const pr_node *node, const pr_opts *opts_in, const doubl
   if (rc != PR_OK) return rc;
   // backtracking: rejected trials take evaluations beyond the iteration budget
   const int64_t launches = (int64_t)opts.max_iter / opts.check_every + 3;
-  PR_TRY(run_graph(c, c->gexec, is_bt(opts.method) ? 2 * launches : launches));
+  PR_TRY(run_graph(c, c->gexec, c->graph_units, (is_bt(opts.method) ? 2 * launches : launches) * c->graph_units,
+                   opts.rel_gap_tol, c->gtail, kTailUnits));
   NodeState hs;
   if (c->gram) {
     PR_TRY(hipMemcpyAsync(&hs, c->d_state, sizeof(hs), hipMemcpyDeviceToHost, c->stream));

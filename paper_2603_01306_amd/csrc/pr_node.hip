@@ -1280,6 +1280,9 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
   // momentum point y; it is accepted when f(x) - f(y) - <grad f(y), x - y> <=
   // (L / 2) ||x - y||^2 (or L has reached Lmax), else the step is redone
   // from the saved y and grad f(y) with c L, and the trial is not evaluated.
+  // a rejected trial skips the evaluation; both branches end in one prox step
+  bool rejected = false;
+  double Lstep = L;
   if (trial) {
     const double dv = trial_ls ? btA - r1x[0] : dlog;
     if (!bt_accept(dv, L, dxy0, prm->Lmax)) {
@@ -1298,211 +1301,214 @@ __global__ __launch_bounds__(NT) void k_node_step_r(const NodeParams *__restrict
         }
         x[e] = in ? yj - gj * invLs : 0.0;
       }
-      prox_finish(Ls, true);
-      return;
+      Lstep = Ls;
+      rejected = true;
     }
   }
-  if (gb) {
-    // F(X x) = y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F, as
-    // h = b - G x: both from the Gram quantities, no pass over X
-    const double yy = prm->gram_yy;
-    Fk = yy - r1[1];
-    negconj = 2.0 * (yy - r1[2]) - Fk;
-  }
-  auto wabs = [&](int e) { return sv(e) == kFree ? fabs(x[e] * wscale) : -1.0; };
-  const double cgt = r1[3], cge = r1[4];
-  const bool fast = wv && cgt < (double)kbar && (double)kbar <= cge && cge - cgt <= (double)kWinCap;
-  double topsum = 0.0, tkn = -1.0;
-  if (kbar > 0 && fast) {
-#pragma unroll
-    for (int e = 0; e < EPT; e++) {
-      const double aw = wabs(e);
-      if (aw >= wa && aw <= wb) lds.sel.gat[atomicAdd(&lds.sel.ngat, 1)] = aw;
+  if (!rejected) {
+    if (gb) {
+      // F(X x) = y^T y - x^T (b + h) and -F*(-zeta) = 2 (y^T y - b^T x) - F, as
+      // h = b - G x: both from the Gram quantities, no pass over X
+      const double yy = prm->gram_yy;
+      Fk = yy - r1[1];
+      negconj = 2.0 * (yy - r1[2]) - Fk;
     }
-    lds_barrier();
-    if (wave_id() == 0) {
-      const int lane = lane_id();
-      const int cw = (int)(cge - cgt);
-      const int mm = kbar - (int)cgt;  // 1 <= mm <= cw
-      double v = (lane < cw) ? lds.sel.gat[lane] : -1.0;
-      v = wave_sort_desc(v);
-      tkn = __shfl(v, mm - 1, 64);
-      topsum = r1[5] + wave_sum(lane < mm ? huber(v, M) : 0.0);
-    }
-  } else if (kbar > 0) {
-    if constexpr (kSelLds) {
-#pragma unroll
-      for (int e = 0; e < EPT; e++) wl[tid + e * NT] = wabs(e);
-      __syncthreads();
-      tkn = select_kth(wl, (int64_t)EPT * NT, kbar, lds.sel);
-    } else {
-      tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
-    }
-    const double Ht = huber(tkn, M);
-    double v1[1] = {0.0};
-#pragma unroll
-    for (int e = 0; e < EPT; e++) {
-      const double aw = wabs(e);
-      if (aw >= 0.0) v1[0] += fmax(huber(aw, M) - Ht, 0.0);
-    }
-    R.sum(v1);
-    topsum = (double)kbar * Ht + v1[0];
-  }
-  if (tid == 0) {
-    const double psi = negconj - 2.0 * lam2 * (r1[0] + topsum);
-    const double phi = indom0 ? Fk + 2.0 * lam2 * gval0 : INFINITY;
-    const int it = S->iter;
-    if (prm->trace && it <= prm->max_iter) {
-      prm->trace[2 * it] = phi;
-      prm->trace[2 * it + 1] = psi;
-    }
-    const double gap = phi - psi;
-    double lb = S->lb, ub = S->ub;
-    int improved = 0, ub_improved = 0;
-    if (psi > lb) {
-      lb = psi;
-      improved = 1;
-    }
-    if (phi < ub) {
-      ub = phi;
-      ub_improved = 1;
-    }
-    const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
-    int done = 0, status = kMaxIter;
-    if (rel <= prm->tol) {
-      done = 1;
-      status = kConverged;
-    } else if (!isnan(prm->cutoff) && lb >= prm->cutoff) {
-      done = 1;
-      status = kCutoffPrune;
-    } else if (!isnan(prm->cutoff) && ub <= prm->cutoff) {
-      done = 1;
-      status = kCutoffBranch;
-    } else if (it >= prm->max_iter) {
-      done = 1;
-      status = kMaxIter;
-    }
-    double m = 0.0, t = S->t, gap_ref = S->gap_ref;
-    int restart = 0, restarts = S->restarts;
-    if (!done) {
-      restart = decide_restart(prm, it, gap, phi, S->phi, gap_ref, restarts);
-      if (restart) {
-        m = 0.0;
-        t = 1.0;
-      } else {
-        const double tn = fista_next_t(t);
-        m = (t - 1.0) / tn;
-        t = tn;
-      }
-    }
-    // next window: twice the relative move of the kbar-th value, narrowed when
-    // the window held the value but had too many entries
-    double tw = 0.25;
-    if (wv && tkn > 0.0) tw = fmin(0.25, fmax(1e-12, 2.0 * fabs(tkn - tkp) / tkn));
-    if (wv && !fast && cgt < (double)kbar && (double)kbar <= cge) tw = fmin(tw, 0.25 * dlt);
-    S->phi = phi;
-    S->psi = psi;
-    S->lb = lb;
-    S->ub = ub;
-    S->rel_gap = rel;
-    S->improved = improved;
-    S->status = status;
-    S->t = t;
-    S->gap_ref = gap_ref;
-    S->restarts = restarts;
-    S->mom = m;
-    S->tk = tkn;
-    S->tkw = tw;
-    if (done) S->done = 1;
-    lds.bcd[0] = m;
-    lds.bci[0] = done;
-    lds.bci[1] = restart;
-    lds.bci[2] = ub_improved;
-    lds.bci[3] = improved;
-  }
-  lds_barrier();
-  const bool done = lds.bci[0] != 0;
-  const double m = lds.bcd[0];
-  const int restart = lds.bci[1];
-  // backtracking: a restart runs the method afresh, the line search from L0
-  const double Lnew = (bt && restart) ? prm->L0 : L;
-  const double invL = 1.0 / Lnew;
-  // gradient step at the momentum point on entries [e0, e1); x[] then holds v
-  // (backtracking: y and grad f(y) are stored for a redo and, where x^k is
-  // held in registers, left in xq[] / g2[] for the model-test terms)
-  auto grad = [&](int e, double xke, double &xqe, double &g2e) {
-    const double h = x[e];
-    const double yj = xke + m * (xke - xqe);
-    double gj;
-    if (loss == kLsq) gj = -2.0 * ((1.0 + m) * h - m * g2e);
-    else gj = restart ? -h : g2e;
-    x[e] = sv(e) != 3 ? yj - gj * invL : 0.0;
-    if (loss == kLsq && sv(e) != 3) nb.hprev[(uint32_t)(tid + e * NT)] = h;
-    if (bt && sv(e) != 3) {
-      const uint32_t j = (uint32_t)(tid + e * NT);
-      nb.ybt[j] = yj;
-      nb.gbt[j] = gj;
-    }
-    if (bt) {
-      xqe = yj;
-      g2e = gj;
-      if constexpr (!kHoldXk) wl[(uint32_t)(tid + e * NT)] = yj;  // the selection's LDS array is free by now
-    }
-  };
-  if constexpr (kHoldXk) {
-    if (lds.bci[2]) {
-#pragma unroll
-      for (int e = 0; e < EPT; e++)
-        if (sv(e) != 3) nb.xbest[(uint32_t)(tid + e * NT)] = xk[e];
-    }
-    if (gb && lds.bci[3]) {
-#pragma unroll
-      for (int e = 0; e < EPT; e++)
-        if (sv(e) != 3) nb.xlb[(uint32_t)(tid + e * NT)] = xk[e];
-    }
-    if (done) return;
-    if (!kPre) {
+    auto wabs = [&](int e) { return sv(e) == kFree ? fabs(x[e] * wscale) : -1.0; };
+    const double cgt = r1[3], cge = r1[4];
+    const bool fast = wv && cgt < (double)kbar && (double)kbar <= cge && cge - cgt <= (double)kWinCap;
+    double topsum = 0.0, tkn = -1.0;
+    if (kbar > 0 && fast) {
 #pragma unroll
       for (int e = 0; e < EPT; e++) {
-        const uint32_t j = (uint32_t)(tid + e * NT);
-        const bool in = j < (uint32_t)p;
-        xq[e] = in ? xn[j] : 0.0;
-        g2[e] = in ? gp[j] : 0.0;
+        const double aw = wabs(e);
+        if (aw >= wa && aw <= wb) lds.sel.gat[atomicAdd(&lds.sel.ngat, 1)] = aw;
       }
+      lds_barrier();
+      if (wave_id() == 0) {
+        const int lane = lane_id();
+        const int cw = (int)(cge - cgt);
+        const int mm = kbar - (int)cgt;  // 1 <= mm <= cw
+        double v = (lane < cw) ? lds.sel.gat[lane] : -1.0;
+        v = wave_sort_desc(v);
+        tkn = __shfl(v, mm - 1, 64);
+        topsum = r1[5] + wave_sum(lane < mm ? huber(v, M) : 0.0);
+      }
+    } else if (kbar > 0) {
+      if constexpr (kSelLds) {
+#pragma unroll
+        for (int e = 0; e < EPT; e++) wl[tid + e * NT] = wabs(e);
+        __syncthreads();
+        tkn = select_kth(wl, (int64_t)EPT * NT, kbar, lds.sel);
+      } else {
+        tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+      }
+      const double Ht = huber(tkn, M);
+      double v1[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < EPT; e++) {
+        const double aw = wabs(e);
+        if (aw >= 0.0) v1[0] += fmax(huber(aw, M) - Ht, 0.0);
+      }
+      R.sum(v1);
+      topsum = (double)kbar * Ht + v1[0];
     }
-#pragma unroll
-    for (int e = 0; e < EPT; e++) grad(e, xk[e], xq[e], g2[e]);
-  } else {
-    constexpr int HE = EPT / 2;
-#pragma unroll
-    for (int hh = 0; hh < 2; hh++) {
-      double xkh[HE], xqh[HE], g2h[HE];
-#pragma unroll
-      for (int i = 0; i < HE; i++) {
-        const uint32_t j = (uint32_t)(tid + (hh * HE + i) * NT);
-        const bool in = j < (uint32_t)p;
-        xkh[i] = in ? xc[j] : 0.0;
-        xqh[i] = (in && !done) ? xn[j] : 0.0;
-        g2h[i] = (in && !done) ? gp[j] : 0.0;
+    if (tid == 0) {
+      const double psi = negconj - 2.0 * lam2 * (r1[0] + topsum);
+      const double phi = indom0 ? Fk + 2.0 * lam2 * gval0 : INFINITY;
+      const int it = S->iter;
+      if (prm->trace && it <= prm->max_iter) {
+        prm->trace[2 * it] = phi;
+        prm->trace[2 * it + 1] = psi;
       }
+      const double gap = phi - psi;
+      double lb = S->lb, ub = S->ub;
+      int improved = 0, ub_improved = 0;
+      if (psi > lb) {
+        lb = psi;
+        improved = 1;
+      }
+      if (phi < ub) {
+        ub = phi;
+        ub_improved = 1;
+      }
+      const double rel = (ub - lb) / fmax(fabs(ub), 1e-300);
+      int done = 0, status = kMaxIter;
+      if (rel <= prm->tol) {
+        done = 1;
+        status = kConverged;
+      } else if (!isnan(prm->cutoff) && lb >= prm->cutoff) {
+        done = 1;
+        status = kCutoffPrune;
+      } else if (!isnan(prm->cutoff) && ub <= prm->cutoff) {
+        done = 1;
+        status = kCutoffBranch;
+      } else if (it >= prm->max_iter) {
+        done = 1;
+        status = kMaxIter;
+      }
+      double m = 0.0, t = S->t, gap_ref = S->gap_ref;
+      int restart = 0, restarts = S->restarts;
+      if (!done) {
+        restart = decide_restart(prm, it, gap, phi, S->phi, gap_ref, restarts);
+        if (restart) {
+          m = 0.0;
+          t = 1.0;
+        } else {
+          const double tn = fista_next_t(t);
+          m = (t - 1.0) / tn;
+          t = tn;
+        }
+      }
+      // next window: twice the relative move of the kbar-th value, narrowed when
+      // the window held the value but had too many entries
+      double tw = 0.25;
+      if (wv && tkn > 0.0) tw = fmin(0.25, fmax(1e-12, 2.0 * fabs(tkn - tkp) / tkn));
+      if (wv && !fast && cgt < (double)kbar && (double)kbar <= cge) tw = fmin(tw, 0.25 * dlt);
+      S->phi = phi;
+      S->psi = psi;
+      S->lb = lb;
+      S->ub = ub;
+      S->rel_gap = rel;
+      S->improved = improved;
+      S->status = status;
+      S->t = t;
+      S->gap_ref = gap_ref;
+      S->restarts = restarts;
+      S->mom = m;
+      S->tk = tkn;
+      S->tkw = tw;
+      if (done) S->done = 1;
+      lds.bcd[0] = m;
+      lds.bci[0] = done;
+      lds.bci[1] = restart;
+      lds.bci[2] = ub_improved;
+      lds.bci[3] = improved;
+    }
+    lds_barrier();
+    const bool done = lds.bci[0] != 0;
+    const double m = lds.bcd[0];
+    const int restart = lds.bci[1];
+    // backtracking: a restart runs the method afresh, the line search from L0
+    const double Lnew = (bt && restart) ? prm->L0 : L;
+    const double invL = 1.0 / Lnew;
+    // gradient step at the momentum point on entries [e0, e1); x[] then holds v
+    // (backtracking: y and grad f(y) are stored for a redo and, where x^k is
+    // held in registers, left in xq[] / g2[] for the model-test terms)
+    auto grad = [&](int e, double xke, double &xqe, double &g2e) {
+      const double h = x[e];
+      const double yj = xke + m * (xke - xqe);
+      double gj;
+      if (loss == kLsq) gj = -2.0 * ((1.0 + m) * h - m * g2e);
+      else gj = restart ? -h : g2e;
+      x[e] = sv(e) != 3 ? yj - gj * invL : 0.0;
+      if (loss == kLsq && sv(e) != 3) nb.hprev[(uint32_t)(tid + e * NT)] = h;
+      if (bt && sv(e) != 3) {
+        const uint32_t j = (uint32_t)(tid + e * NT);
+        nb.ybt[j] = yj;
+        nb.gbt[j] = gj;
+      }
+      if (bt) {
+        xqe = yj;
+        g2e = gj;
+        if constexpr (!kHoldXk) wl[(uint32_t)(tid + e * NT)] = yj;  // the selection's LDS array is free by now
+      }
+    };
+    if constexpr (kHoldXk) {
       if (lds.bci[2]) {
 #pragma unroll
-        for (int i = 0; i < HE; i++)
-          if (sv(hh * HE + i) != 3) nb.xbest[(uint32_t)(tid + (hh * HE + i) * NT)] = xkh[i];
+        for (int e = 0; e < EPT; e++)
+          if (sv(e) != 3) nb.xbest[(uint32_t)(tid + e * NT)] = xk[e];
       }
       if (gb && lds.bci[3]) {
 #pragma unroll
-        for (int i = 0; i < HE; i++)
-          if (sv(hh * HE + i) != 3) nb.xlb[(uint32_t)(tid + (hh * HE + i) * NT)] = xkh[i];
+        for (int e = 0; e < EPT; e++)
+          if (sv(e) != 3) nb.xlb[(uint32_t)(tid + e * NT)] = xk[e];
       }
-      if (!done) {
+      if (done) return;
+      if (!kPre) {
 #pragma unroll
-        for (int i = 0; i < HE; i++) grad(hh * HE + i, xkh[i], xqh[i], g2h[i]);
+        for (int e = 0; e < EPT; e++) {
+          const uint32_t j = (uint32_t)(tid + e * NT);
+          const bool in = j < (uint32_t)p;
+          xq[e] = in ? xn[j] : 0.0;
+          g2[e] = in ? gp[j] : 0.0;
+        }
       }
+#pragma unroll
+      for (int e = 0; e < EPT; e++) grad(e, xk[e], xq[e], g2[e]);
+    } else {
+      constexpr int HE = EPT / 2;
+#pragma unroll
+      for (int hh = 0; hh < 2; hh++) {
+        double xkh[HE], xqh[HE], g2h[HE];
+#pragma unroll
+        for (int i = 0; i < HE; i++) {
+          const uint32_t j = (uint32_t)(tid + (hh * HE + i) * NT);
+          const bool in = j < (uint32_t)p;
+          xkh[i] = in ? xc[j] : 0.0;
+          xqh[i] = (in && !done) ? xn[j] : 0.0;
+          g2h[i] = (in && !done) ? gp[j] : 0.0;
+        }
+        if (lds.bci[2]) {
+#pragma unroll
+          for (int i = 0; i < HE; i++)
+            if (sv(hh * HE + i) != 3) nb.xbest[(uint32_t)(tid + (hh * HE + i) * NT)] = xkh[i];
+        }
+        if (gb && lds.bci[3]) {
+#pragma unroll
+          for (int i = 0; i < HE; i++)
+            if (sv(hh * HE + i) != 3) nb.xlb[(uint32_t)(tid + (hh * HE + i) * NT)] = xkh[i];
+        }
+        if (!done) {
+#pragma unroll
+          for (int i = 0; i < HE; i++) grad(hh * HE + i, xkh[i], xqh[i], g2h[i]);
+        }
+      }
+      if (done) return;
     }
-    if (done) return;
+    Lstep = Lnew;
   }
-  prox_finish(Lnew, false);
+  prox_finish(Lstep, rejected);
 }
 
 
