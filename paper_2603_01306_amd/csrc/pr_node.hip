@@ -1572,16 +1572,26 @@ __global__ __launch_bounds__(NT) void k_batch_init(const NodeParams *__restrict_
   }
 }
 
-template <int EPT>
+// GRAM: the batch runs in Gram mode (bb.gb set); a compile-time variant, so
+// that the other batches carry none of its loads in registers.
+template <int EPT, bool GRAM>
 __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict__ prmA, NodeState *SA, BatchBufs bb) {
   __shared__ StepLds<EPT> lds;
+  // with 32 entries per thread (the single-node step's form): x^k is read
+  // again where it is used and the gradient step runs in two halves, and the
+  // radix selection reads the dual magnitudes from LDS, so that the step stays
+  // out of scratch memory
+  constexpr bool kHoldXk = EPT <= 16;
+  constexpr int EK = kHoldXk ? EPT : 1;
+  constexpr bool kSelLds = EPT > 16;
+  __shared__ double wl[kSelLds ? EPT * NT : 1];
   const int node = blockIdx.x;
   const NodeParams *prm = prmA + node;
   NodeState *S = SA + node;
   const int tid = threadIdx.x;
   const int64_t p = bb.p;
   const int64_t off = (int64_t)node * p;
-  const double *__restrict__ gb = bb.gb;
+  const double *__restrict__ gb = GRAM ? bb.gb : nullptr;
   // scalar state: independent loads, issued with the vector loads below
   const int done0 = S->done, parity = S->parity, indom0 = S->indom, it0 = S->iter;
   const double L = S->L, gval0 = S->gval, tau0 = S->tau, tkp = S->tk, dlt = S->tkw, dxy0 = S->dxy;
@@ -1601,14 +1611,22 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   const int KS = *bb.ksp;
   const bool lsq = bb.loss == kLsq;
   const double *__restrict__ Hn = bb.CT + (int64_t)bb.rs * off;
-  double h[EPT], xk[EPT];
+  double h[EPT], xk[EK];
 #pragma unroll
   for (int e = 0; e < EPT; e++) {
     const uint32_t j = (uint32_t)(tid + e * NT);
     const bool in = j < (uint32_t)p;
     h[e] = in ? Hn[j] : 0.0;
-    xk[e] = in ? xc[j] : 0.0;
+    if constexpr (kHoldXk) xk[e] = in ? xc[j] : 0.0;
   }
+  auto xkv = [&](int e) -> double {
+    if constexpr (kHoldXk) {
+      return xk[e];
+    } else {
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      return j < (uint32_t)p ? xc[j] : 0.0;
+    }
+  };
   for (int z = 1; z < KS; z++) {
 #pragma unroll
     for (int e = 0; e < EPT; e++) {
@@ -1704,7 +1722,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
         if (sv(e) == 3) continue;
         const uint32_t j = (uint32_t)(tid + e * NT);
         const double hx = gb ? gb[j] - h[e] : h[e];
-        d1[0] += (xk[e] - ybt[j]) * (-0.5 * gbt[j] - hx);
+        d1[0] += (xkv(e) - ybt[j]) * (-0.5 * gbt[j] - hx);
       }
       R.sum(d1);
       dv = d1[0];
@@ -1740,8 +1758,9 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     if (gb) {
       const double bj = gb[tid + (int64_t)e * NT];
       h[e] = bj - h[e];
-      r1[1] += xk[e] * (bj + h[e]);
-      r1[2] += bj * xk[e];
+      const double xe = xkv(e);
+      r1[1] += xe * (bj + h[e]);
+      r1[2] += bj * xe;
     }
     const double w = h[e] * wscale;
     if (s == kOne) r1[0] += huber(w, M);
@@ -1781,7 +1800,14 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
       topsum = r1[5] + wave_sum(lane < mm ? huber(v, M) : 0.0);
     }
   } else if (kbar > 0) {
-    tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+    if constexpr (kSelLds) {
+#pragma unroll
+      for (int e = 0; e < EPT; e++) wl[tid + e * NT] = wabs(e);
+      __syncthreads();
+      tkn = select_kth(wl, (int64_t)EPT * NT, kbar, lds.sel);
+    } else {
+      tkn = select_kth_f<EPT>(wabs, kbar, lds.sel);
+    }
     const double Ht = huber(tkn, M);
     double v1[1] = {0.0};
 #pragma unroll
@@ -1864,7 +1890,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
     // the certified point is the iterate whose gap passed the test
 #pragma unroll
     for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xk[e];
+      if (sv(e) != 3) bb.xbest[off + tid + (int64_t)e * NT] = xkv(e);
     return;
   }
   // gradient at the momentum point y = x^k + m (x^k - x^{k-1}):
@@ -1872,45 +1898,50 @@ __global__ __launch_bounds__(NT) void k_batch_step(const NodeParams *__restrict_
   //   logistic the second plane row of the node (hq), or -h at a restart (y = x^k)
   double *__restrict__ hp = bb.hprev + off;
   const double *__restrict__ H2 = Hn + p;
-  double xq[EPT], hq[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const uint32_t j = (uint32_t)(tid + e * NT);
-    const bool in = j < (uint32_t)p;
-    xq[e] = in ? xn[j] : 0.0;
-    hq[e] = in ? (lsq ? hp[j] : H2[j]) : 0.0;
-  }
-  if (!lsq) {
-    for (int z = 1; z < KS; z++) {
-#pragma unroll
-      for (int e = 0; e < EPT; e++) {
-        const uint32_t j = (uint32_t)(tid + e * NT);
-        if (j < (uint32_t)p) hq[e] += H2[z * stride + j];
-      }
-    }
-  }
   const double m = lds.bcd[0];
   const bool restart = lds.bci[1] != 0;
   // backtracking: a restart runs the method afresh, the line search from L0
   const double Lnew = (bt && restart) ? prm->L0 : L;
   const double invL = 1.0 / Lnew;
+  // entries [E0, E0 + HE): x^{k-1} and the previous gradient term loaded, then
+  // the step; h[] then holds v (least squares: h_k stored as the next h_{k-1})
+  constexpr int HE = kHoldXk ? EPT : EPT / 2;
+  auto grad_part = [&](auto e0c) {
+    constexpr int E0 = decltype(e0c)::value;
+    double xkh[HE], xq[HE], hq[HE];
 #pragma unroll
-  for (int e = 0; e < EPT; e++) {
-    const double yj = xk[e] + m * (xk[e] - xq[e]);
-    const double gj = lsq ? -2.0 * ((1.0 + m) * h[e] - m * hq[e]) : (restart ? -h[e] : hq[e]);
-    hq[e] = h[e];
-    h[e] = sv(e) != 3 ? yj - gj * invL : 0.0;  // h[] now holds v
-    if (bt && sv(e) != 3) {
-      const uint32_t j = (uint32_t)(tid + e * NT);
-      ybt[j] = yj;
-      bb.gbt[off + j] = gj;
+    for (int i = 0; i < HE; i++) {
+      const uint32_t j = (uint32_t)(tid + (E0 + i) * NT);
+      const bool in = j < (uint32_t)p;
+      xkh[i] = xkv(E0 + i);
+      xq[i] = in ? xn[j] : 0.0;
+      hq[i] = in ? (lsq ? hp[j] : H2[j]) : 0.0;
     }
-  }
-  if (lsq) {
+    if (!lsq) {
+      for (int z = 1; z < KS; z++) {
 #pragma unroll
-    for (int e = 0; e < EPT; e++)
-      if (sv(e) != 3) hp[(uint32_t)(tid + e * NT)] = hq[e];
-  }
+        for (int i = 0; i < HE; i++) {
+          const uint32_t j = (uint32_t)(tid + (E0 + i) * NT);
+          if (j < (uint32_t)p) hq[i] += H2[z * stride + j];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < HE; i++) {
+      const int e = E0 + i;
+      const uint32_t j = (uint32_t)(tid + e * NT);
+      const double yj = xkh[i] + m * (xkh[i] - xq[i]);
+      const double gj = lsq ? -2.0 * ((1.0 + m) * h[e] - m * hq[i]) : (restart ? -h[e] : hq[i]);
+      if (lsq && sv(e) != 3) hp[j] = h[e];
+      h[e] = sv(e) != 3 ? yj - gj * invL : 0.0;
+      if (bt && sv(e) != 3) {
+        ybt[j] = yj;
+        bb.gbt[off + j] = gj;
+      }
+    }
+  };
+  grad_part(std::integral_constant<int, 0>{});
+  if constexpr (!kHoldXk) grad_part(std::integral_constant<int, HE>{});
   prox_finish(Lnew, false);
 }
 
@@ -1975,15 +2006,21 @@ hipError_t launch_batch_init(const NodeParams *prm, NodeState *S, BatchBufs bb, 
 
 hipError_t launch_batch_step(const NodeParams *prm, NodeState *S, BatchBufs bb, int64_t p, hipStream_t s) {
   const unsigned g = (unsigned)bb.m;
+#define PR_BSTEP_CASE(E)                                                   \
+  case E:                                                                  \
+    if (bb.gb) k_batch_step<E, true><<<g, NT, 0, s>>>(prm, S, bb);         \
+    else k_batch_step<E, false><<<g, NT, 0, s>>>(prm, S, bb);              \
+    break;
   switch (node_ept(p)) {
-    case 1: k_batch_step<1><<<g, NT, 0, s>>>(prm, S, bb); break;
-    case 2: k_batch_step<2><<<g, NT, 0, s>>>(prm, S, bb); break;
-    case 4: k_batch_step<4><<<g, NT, 0, s>>>(prm, S, bb); break;
-    case 8: k_batch_step<8><<<g, NT, 0, s>>>(prm, S, bb); break;
-    case 16: k_batch_step<16><<<g, NT, 0, s>>>(prm, S, bb); break;
-    case 32: k_batch_step<32><<<g, NT, 0, s>>>(prm, S, bb); break;
+    PR_BSTEP_CASE(1)
+    PR_BSTEP_CASE(2)
+    PR_BSTEP_CASE(4)
+    PR_BSTEP_CASE(8)
+    PR_BSTEP_CASE(16)
+    PR_BSTEP_CASE(32)
     default: return hipErrorInvalidValue;
   }
+#undef PR_BSTEP_CASE
   return hipGetLastError();
 }
 
