@@ -824,7 +824,9 @@ def paper_shapes_bench(sizes=(1000, 2000, 4000, 8000, 16000), seeds=(0, 1, 2, 3,
     k = 10 unit coefficients, SNR 5, lambda2 = 1, M = 2, relative gap 1e-6,
     cold start, least squares and logistic, five seeds.  X is stored FP32.
     Per seed: context setup (||X||^2 by Lanczos, once per design),
-    the first solve (graph capture included) and a repeated solve."""
+    the first solve (graph capture included) and a repeated solve with the
+    fixed step, then a repeated solve with the line search (its first solve,
+    which captures its graph, untimed)."""
     import numpy as np
     import torch
     import paper_2603_01306_amd as pr
@@ -833,7 +835,8 @@ def paper_shapes_bench(sizes=(1000, 2000, 4000, 8000, 16000), seeds=(0, 1, 2, 3,
     rows = []
     for loss in (pr.LSQ, pr.LOGISTIC):
         for p in sizes:
-            rec = {"setup_s": [], "first_solve_s": [], "solve_s": [], "iters": [], "converged": []}
+            rec = {"setup_s": [], "first_solve_s": [], "solve_s": [], "iters": [], "converged": [],
+                   "bt_solve_s": [], "bt_iters": [], "bt_trials": []}
             for seed in seeds:
                 inst = make_instance(n=p, p=p, corr=0.5, k_true=10, snr=5.0, loss=loss, seed=seed, storage="f32")
                 X = torch.from_numpy(inst.Xcm).to(dev)
@@ -851,6 +854,16 @@ def paper_shapes_bench(sizes=(1000, 2000, 4000, 8000, 16000), seeds=(0, 1, 2, 3,
                 torch.cuda.synchronize()
                 t3 = time.perf_counter()
                 assert r1["lower_bound"] == r2["lower_bound"]
+                ctx.solve(node, want_beta=False, method=6)
+                torch.cuda.synchronize()
+                t4 = time.perf_counter()
+                r3 = ctx.solve(node, want_beta=False, method=6)
+                torch.cuda.synchronize()
+                t5 = time.perf_counter()
+                rec["bt_solve_s"].append(t5 - t4)
+                rec["bt_iters"].append(r3["iters"])
+                rec["bt_trials"].append(r3["trials"])
+                rec["converged"].append(r3["status"] == pr.CONVERGED and r3["rel_gap"] <= 1e-6)
                 rec["setup_s"].append(t1 - t0)
                 rec["first_solve_s"].append(t2 - t1)
                 rec["solve_s"].append(t3 - t2)
@@ -859,8 +872,9 @@ def paper_shapes_bench(sizes=(1000, 2000, 4000, 8000, 16000), seeds=(0, 1, 2, 3,
                 ctx.close()
                 del X, y, inst
             row = {"loss": "least_squares" if loss == pr.LSQ else "logistic", "n": p, "p": p,
-                   "all_converged": all(rec["converged"]), "iters_mean": float(np.mean(rec["iters"]))}
-            for key in ("setup_s", "first_solve_s", "solve_s"):
+                   "all_converged": all(rec["converged"]), "iters_mean": float(np.mean(rec["iters"])),
+                   "bt_iters_mean": float(np.mean(rec["bt_iters"])), "bt_trials_mean": float(np.mean(rec["bt_trials"]))}
+            for key in ("setup_s", "first_solve_s", "solve_s", "bt_solve_s"):
                 row[key + "_mean"] = round(float(np.mean(rec[key])), 4)
                 row[key + "_std"] = round(float(np.std(rec[key])), 4)
             rows.append(row)
