@@ -279,10 +279,16 @@ int pr_dual_bound(pr_ctx *ctx, const pr_node *node, const double *zeta, const do
 
 /* Dense products with the context's X, FP64 accumulation (test and
  * measurement entry points; the solver uses the same kernels).
- *   pr_gemv:   u = X b,   b device p, u device n
- *   pr_gemv_t: h = X^T r, r device n, h device p */
+ *   pr_gemv:    u = X b,   b device p, u device n
+ *   pr_gemv_t:  h = X^T r, r device n, h device p
+ *   pr_gemv_t2: h1 = X^T r1 and h2 = X^T r2 in one pass over X (the
+ *               transposed product of a logistic iteration, Section 3.2:
+ *               X^T zeta at the iterate and X^T grad F at the momentum
+ *               point); r1, r2 device n, h1, h2 device p, all distinct.
+ * Return PR_EINVAL for NULL arguments. */
 int pr_gemv(pr_ctx *ctx, const double *b, double *u);
 int pr_gemv_t(pr_ctx *ctx, const double *r, double *h);
+int pr_gemv_t2(pr_ctx *ctx, const double *r1, const double *r2, double *h1, double *h2);
 
 /* Solve m nodes that share X (m <= max_batch), each as pr_solve would:
  * same bounds, stopping test, iteration variant and dynamic termination

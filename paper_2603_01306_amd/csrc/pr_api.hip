@@ -1581,6 +1581,13 @@ int pr_gemv_t(pr_ctx *c, const double *r, double *h) {
   return PR_OK;
 }
 
+int pr_gemv_t2(pr_ctx *c, const double *r1, const double *r2, double *h1, double *h2) {
+  if (!c || !r1 || !r2 || !h1 || !h2) return PR_EINVAL;
+  PR_TRY(launch_gemv_t(c->P, r1, r2, h1, h2, nullptr, c->stream));
+  PR_TRY(hipStreamSynchronize(c->stream));
+  return PR_OK;
+}
+
 int pr_time_gemv_t(pr_ctx *c, const double *r, double *h, int32_t reps, double *ms_avg) {
   if (!c || !r || !h || reps < 1 || !ms_avg) return PR_EINVAL;
   // logistic solves run the two-right-hand-side form: [X^T r, X^T r2] with r2

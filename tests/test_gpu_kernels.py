@@ -169,6 +169,28 @@ def test_gemv_and_gemv_t_match_oracle(dev, storage, n, p):
     ctx.close()
 
 
+@pytest.mark.parametrize("storage,n,p", [("f32", 1028, 37), ("f32", 4096, 1031), ("f32", 200, 9), ("f64", 770, 65),
+                                         ("f64", 2, 1), ("bf16", 1032, 77), ("bf16", 16384, 64), ("f32", 32768, 100)])
+def test_gemv_t2_matches_oracle(dev, storage, n, p):
+    """The two-right-hand-side transposed product (the logistic iteration's
+    X^T [zeta, grad F]), whose waves split each column's rows in two parts
+    summed in LDS: both outputs element by element against the oracle's
+    products, n ragged against the row step and with one part empty."""
+    import torch
+    inst = make_instance(n=n, p=p, corr=0.6, k_true=min(3, p), snr=5.0, loss=1, seed=9, storage=storage)
+    ctx = _ctx_for(dev, inst.Xcm, inst.y, loss=1)
+    rng = np.random.default_rng(5)
+    r1 = rng.standard_normal(n)
+    r2 = rng.standard_normal(n) * 1e-3
+    h1, h2 = ctx.gemv_t2(torch.from_numpy(r1).to(dev), torch.from_numpy(r2).to(dev))
+    X64 = inst.X64()
+    for h, r in ((h1.cpu().numpy(), r1), (h2.cpu().numpy(), r2)):
+        ref = oracle.rmatvec(inst.Xcm, r)
+        bound = 1e-13 * (np.abs(X64) @ np.abs(r)) + 1e-300
+        assert np.all(np.abs(h - ref) <= bound)
+    ctx.close()
+
+
 @pytest.mark.parametrize("n,p,corr,storage", [(2048, 512, 0.9, "f32"), (64, 1000, 0.5, "f64"), (300, 1, 0.0, "f64"),
                                                (1000, 3, 0.99, "f64"), (4096, 2048, 0.5, "bf16")])
 def test_norm2_matches_exact_eigenvalue(dev, n, p, corr, storage):
