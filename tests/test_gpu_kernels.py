@@ -173,9 +173,9 @@ def test_gemv_and_gemv_t_match_oracle(dev, storage, n, p):
                                          ("f64", 2, 1), ("bf16", 1032, 77), ("bf16", 16384, 64), ("f32", 32768, 100)])
 def test_gemv_t2_matches_oracle(dev, storage, n, p):
     """The two-right-hand-side transposed product (the logistic iteration's
-    X^T [zeta, grad F]), whose waves split each column's rows in two parts
-    summed in LDS: both outputs element by element against the oracle's
-    products, n ragged against the row step and with one part empty."""
+    X^T [zeta, grad F], eight columns per wave): both outputs element by
+    element against the oracle's products, n ragged against the row step and
+    p against the workgroup's 32 columns."""
     import torch
     inst = make_instance(n=n, p=p, corr=0.6, k_true=min(3, p), snr=5.0, loss=1, seed=9, storage=storage)
     ctx = _ctx_for(dev, inst.Xcm, inst.y, loss=1)
