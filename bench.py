@@ -714,7 +714,23 @@ def e3_bench(max_iter=20000):
                          "final_rel_gap": r["rel_gap"], "iterations_to_rel_gap": reach,
                          "log10_gap_per_iteration": None if slope is None else round(slope, 5)}
             print(json.dumps({"progress": "e3", "workload": wl, "variant": name, **res[name]}), flush=True)
-        out["workloads"][wl] = {"cap": cap, "variants": res}
+        # the restart parameter: the paper's polynomial-rate model gives
+        # eta = e^q (e^2 for accelerated methods) and argues that larger
+        # values can do better in practice; evaluations (iterations + rejected
+        # trials) and time to the 1e-6 gap for eta = e .. e^5
+        sweep = []
+        for meth, mname in ((pr.FISTA_BT_GAP, "fista_linesearch_gap_restart"), (pr.FISTA_GAP, "fista_gap_restart")):
+            for q in (1, 2, 3, 4, 5):
+                ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"], max_iter=cap, method=meth, eta=math.exp(q))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = ctx.solve(node, want_beta=False, rel_gap_tol=cfg["tol"], max_iter=cap, method=meth, eta=math.exp(q))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                sweep.append({"method": mname, "eta": f"e^{q}", "status": r["status"], "iters": r["iters"],
+                              "trials": r["trials"], "restarts": r["restarts"], "seconds": round(dt, 4)})
+                print(json.dumps({"progress": "e3 eta", "workload": wl, **sweep[-1]}), flush=True)
+        out["workloads"][wl] = {"cap": cap, "variants": res, "eta_sweep": sweep}
         ctx.close()
     print(json.dumps(out), flush=True)
 
