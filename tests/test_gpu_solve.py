@@ -229,6 +229,28 @@ def test_warm_start_and_determinism(c1):
     assert cc["lower_bound"] >= a["lower_bound"] - 1e-8 * abs(a["primal"])   # child >= parent
 
 
+@pytest.mark.parametrize("method", ["fixed", "bt"])
+def test_graph_length_does_not_change_the_solve(c1, method):
+    """The host queues captured iterations by its prediction of the stop (long
+    graphs, then a short tail graph): the solve is the same, bit for bit, for
+    every graph length, and an iteration limit that falls inside a graph
+    stops it exactly there."""
+    import torch
+    inst, ctx, lam = c1
+    pr = _pr()
+    kw = {} if method == "fixed" else {"method": pr.FISTA_BT_GAP}
+    runs = [ctx.solve(pr.Node(10, 1.0, 2.0), rel_gap_tol=1e-9, check_every=ce, **kw) for ce in (2, 6, 8, 32, 64)]
+    a = runs[0]
+    assert a["status"] == pr.CONVERGED
+    for r in runs[1:]:
+        assert r["lower_bound"] == a["lower_bound"] and r["primal"] == a["primal"]
+        assert (r["iters"], r["trials"], r["restarts"]) == (a["iters"], a["trials"], a["restarts"])
+        assert torch.equal(r["beta"], a["beta"])
+    for ce, cap in ((32, 37), (64, 9), (8, 41)):
+        r = ctx.solve(pr.Node(10, 1.0, 2.0), rel_gap_tol=0.0, max_iter=cap, check_every=ce, **kw)
+        assert r["status"] == pr.MAXITER and r["iters"] == cap
+
+
 # ----------------------------------------------------------------- full size
 
 @pytest.fixture(scope="module")
