@@ -996,6 +996,15 @@ def main():
             "all_converged": ok, "lower_bound": results[-1]["lower_bound"],
             "setup_s_per_matrix": round(setup_s, 3),
             "roofline": roof}
+    # the dense forward product u = X b (column-list kernel over all columns
+    # plus its summing kernel): the other per-kernel HBM figure of the path
+    b = torch.randn(inst.p, dtype=torch.float64, device=dev)
+    ms_f = ctx.time_gemv(b, reps=50)
+    fwd_bytes = inst.n * inst.p * 4 + 8 * inst.p + 8 * inst.n
+    ach_f = fwd_bytes / (ms_f * 1e-3) / 1e9
+    line["forward_gemv"] = {"bound": "hbm", "achieved": round(ach_f, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(ach_f / HBM_PEAK_GBS, 4), "kernel": "k_spfwd_part<float> + k_spfwd_final",
+                            "bytes_per_launch": fwd_bytes, "avg_launch_ms": round(ms_f, 5)}
     if SOLVE_KW["method"] != 0:
         # the fixed-step method (step 1/L) on the same root, for reference
         torch.cuda.synchronize()

@@ -330,6 +330,12 @@ int pr_time_prox(void *stream, const double *v, int64_t p, double rho, int32_t k
  * the context's workspace); h receives X^T r. */
 int pr_time_gemv_t(pr_ctx *ctx, const double *r, double *h, int32_t reps, double *ms_avg);
 
+/* Time `reps` back-to-back dense forward products u = X b (the column-list
+ * product over all p columns and its summing kernel, as pr_gemv runs them)
+ * with HIP events on the context stream; *ms_avg = elapsed / reps.
+ * b device p, u device n.  PR_EINVAL for NULL arguments or reps < 1. */
+int pr_time_gemv(pr_ctx *ctx, const double *b, double *u, int32_t reps, double *ms_avg);
+
 /* Splits chosen by the context's batched-GEMM autotuner (run at context
  * creation): for i = 0 .. len-1, the number of reduction splits of the forward
  * and of the transpose GEMM when i+1 tiles of 64 rows are active (host arrays

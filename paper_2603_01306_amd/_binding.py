@@ -25,7 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_gemv_t2", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
+           "pr_time_gemv_t", "pr_time_gemv", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
            "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_ctx_set_debug", "pr_lasso_solve", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
@@ -121,6 +121,8 @@ def load():
         L.pr_gemv_t2.argtypes = [P, P, P, P, P]
         L.pr_time_gemv_t.restype = ctypes.c_int
         L.pr_time_gemv_t.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.pr_time_gemv.restype = ctypes.c_int
+        L.pr_time_gemv.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         L.pr_lasso_solve.restype = ctypes.c_int
         L.pr_lasso_solve.argtypes = [P, ctypes.POINTER(PrLasso), ctypes.POINTER(PrOpts), P, P, P,
                                      ctypes.POINTER(PrResult)]
@@ -452,6 +454,14 @@ class Context:
         _check(load().pr_gemv_t2(self.h, _dptr(r1.contiguous()), _dptr(r2.contiguous()), _dptr(h1), _dptr(h2)),
                "pr_gemv_t2")
         return h1, h2
+
+    def time_gemv(self, b, reps=20):
+        import torch
+        u = torch.empty(self.n, dtype=torch.float64, device=self.X.device)
+        ms = ctypes.c_double()
+        _check(load().pr_time_gemv(self.h, _dptr(b.contiguous()), _dptr(u), int(reps), ctypes.byref(ms)),
+               "pr_time_gemv")
+        return ms.value
 
     def time_gemv_t(self, r, reps=20):
         import torch

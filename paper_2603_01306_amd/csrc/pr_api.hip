@@ -1607,6 +1607,20 @@ int pr_time_gemv_t(pr_ctx *c, const double *r, double *h, int32_t reps, double *
   return PR_OK;
 }
 
+int pr_time_gemv(pr_ctx *c, const double *b, double *u, int32_t reps, double *ms_avg) {
+  if (!c || !b || !u || reps < 1 || !ms_avg) return PR_EINVAL;
+  auto fwd = [&]() { return launch_spfwd(c->P, c->B, c->iota, b, c->d_np, kSpPlain, nullptr, u, c->stream); };
+  PR_TRY(fwd());
+  PR_TRY(hipEventRecord(c->tev[0], c->stream));
+  for (int i = 0; i < reps; i++) PR_TRY(fwd());
+  PR_TRY(hipEventRecord(c->tev[1], c->stream));
+  PR_TRY(hipEventSynchronize(c->tev[1]));
+  float ms = 0.0f;
+  PR_TRY(hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+  *ms_avg = (double)ms / reps;
+  return PR_OK;
+}
+
 int pr_batch_tuning(pr_ctx *c, int32_t len, int32_t *ksf_out, int32_t *kst_out) {
   if (!c || !c->batch_ok || len < 1 || !ksf_out || !kst_out) return PR_EINVAL;
   for (int32_t i = 0; i < len; i++) {
