@@ -130,7 +130,10 @@ typedef struct {
   double cutoff;      /* incumbent value for dynamic termination; NaN = off */
   double L;           /* step 1/L; 0 = 1.01 * loss curvature * ||X||^2 estimate */
   int32_t max_iter;   /* default 100000 */
-  int32_t check_every; /* iterations per captured graph launch; default 32 */
+  int32_t check_every; /* iterations per captured graph launch (rounded up to even); default 32.
+                        * pr_solve runs the iterations it predicts to be a solve's last ones
+                        * as launches of an 8-iteration graph; the iterates do not depend on
+                        * either length */
   int32_t method;      /* iteration variant, PR_FISTA_GAP (default) .. PR_FISTA_BT */
   int32_t pad0;
   double *trace;       /* pr_solve / pr_lasso_solve only, optional device array of
