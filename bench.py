@@ -33,6 +33,9 @@ columns of the current support), with the number of solves that repay G.
 "logistic": the logistic root (n = 32768, p = 16384, FP32 X) to a 1e-6 gap,
 with its two-right-hand-side X^T pass against the HBM roofline.  Each of
 these carries its own cpu_baseline (the oracle on the same instance).
+"forward_gemv": the dense forward product u = X b against the HBM roofline.
+"learned": the learned warm start's training kernel (forward + backward of
+the network on 1M random feature rows) against the BF16 MFMA roofline.
 
   python bench.py --kernel-probe     # kernels + a plain copy, for rocprofv3 --pmc
   python bench.py --kernel-probe-logistic   # the same for the logistic X^T pass
@@ -182,6 +185,38 @@ def mlp_probe(rows=1 << 20, reps=10):
     flop = 6 * (8 * 64 + 64 * 64 + 64) * rows
     print(json.dumps({"probe": "mlp_grad", "rows": rows, "ms": round(ms, 4), "rows_per_s": round(rows / ms * 1e3),
                       "tflops_mfma_shaped": round(flop / (ms * 1e-3) / 1e12, 2)}), flush=True)
+
+
+def mlp_kernel_bench(rows=1 << 20, reps=10):
+    """The learned warm start's training kernel (forward + backward of the
+    8-64-64-1 network, pr_mlp_grad) on `rows` random BF16 feature rows:
+    HIP-event time per launch on the stream it runs on, rows/s and the
+    matrix flops it performs against the dense BF16 MFMA peak."""
+    import torch
+    import paper_2603_01306_amd as pr
+    from paper_2603_01306_amd import learned
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(0)
+    F = torch.randn((rows, pr.MLP_NFEAT), generator=g, device=dev).to(torch.bfloat16)
+    T = torch.randn(rows, generator=g, device=dev, dtype=torch.float32)
+    params = learned.init_params(1, dev)
+    work = torch.empty(pr.mlp_workspace(rows), dtype=torch.float32, device=dev)
+    grad = torch.empty(pr.MLP_NPARAM + 1, dtype=torch.float32, device=dev)
+    pr.mlp_grad(params, F, T, work, grad)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pr.mlp_grad(params, F, T, work, grad)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flop = 6 * (8 * 64 + 64 * 64 + 64) * rows
+    tfs = flop / (ms * 1e-3) / 1e12
+    return {"kernel": "pr_mlp_grad (k_mlp<true> + partial-gradient reduction)", "rows": rows, "ms_per_launch": round(ms, 4),
+            "rows_per_s": round(rows / ms * 1e3), "epoch_s_409.6M_rows": round(409.6e6 / (rows / ms * 1e3), 3),
+            "roofline": {"bound": "mfma", "achieved": round(tfs, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(tfs / 2500.0, 4), "traffic": None,
+                         "flop_per_launch": flop}}
 
 
 def _oracle_iters(inst, cfg, loss, iters, Lmax):
@@ -918,6 +953,8 @@ def main():
     ap.add_argument("--logistic-batch-nodes", type=int, default=64,
                     help="logistic nodes solved together on the same design (0 skips them)")
     ap.add_argument("--learned", action="store_true", help="run the learned warm start experiment instead")
+    ap.add_argument("--mlp-rows", type=int, default=1 << 20,
+                    help="rows of the learned warm start's training-kernel measurement (0 skips it)")
     ap.add_argument("--e1", action="store_true", help="time prox and g_N at the paper's microbenchmark shapes instead")
     ap.add_argument("--e3", action="store_true", help="convergence of the iteration variants instead")
     ap.add_argument("--bnb", action="store_true", help="branch and bound on the paper's synthetic setting instead")
@@ -1030,6 +1067,8 @@ def main():
     if args.logistic_steps > 0:
         line["logistic"] = logistic_bench(dev, args.logistic_steps, not args.no_cpu_baseline,
                                           batch_nodes=args.logistic_batch_nodes)
+    if args.mlp_rows > 0:
+        line["learned"] = mlp_kernel_bench(rows=args.mlp_rows)
     print(json.dumps(line), flush=True)
 
 
