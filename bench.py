@@ -583,7 +583,8 @@ def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
     """The learned warm start on the 16384 x 8192 design (BF16): training pairs
     from the seeded branching process (256 children per batched solve), Adam
     training of the network, and 512 held-out children solved from the parent
-    solutions and from the judged network starts, all to a 1e-6 FP64 gap."""
+    solutions and from the judged network starts, all to a 1e-6 FP64 gap with
+    the bench's method (--method)."""
     import numpy as np
     import torch
     import paper_2603_01306_amd as pr
@@ -597,7 +598,7 @@ def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
     rng = np.random.default_rng(seed)
     root = pr.Node(cfg["k"], cfg["lambda2"], cfg["M"])
     t0 = time.perf_counter()
-    pool = learned.BranchingPool(ctx, root, capacity=n_pairs + 1, rel_gap_tol=cfg["tol"])
+    pool = learned.BranchingPool(ctx, root, capacity=n_pairs + 1, rel_gap_tol=cfg["tol"], **SOLVE_KW)
 
     def gen_progress(done, total):
         if done % (256 * 8) == 0 or done == total:
@@ -638,12 +639,12 @@ def learned_bench(n_pairs, epochs, n_eval=512, seed=0):
         ch.extend(c)
         bp.append(Bp)
     Bp = torch.cat(bp)
-    ev = learned.evaluate(ctx, params, ch, Bp, rel_gap_tol=cfg["tol"])
+    ev = learned.evaluate(ctx, params, ch, Bp, rel_gap_tol=cfg["tol"], **SOLVE_KW)
     arrays = {k: ev.pop(k) for k in ("iters_parent", "iters_prox_parent", "iters_learned", "choice", "gaps")}
     ip, ia, im = arrays["iters_parent"], arrays["iters_prox_parent"], arrays["iters_learned"]
     out = {"metric": "learned warm start: iterations and time to 1e-6 FP64 gap vs parent warm start",
            "workload": BATCH_WORKLOAD, "n": inst.n, "p": inst.p, "k": cfg["k"], "lambda2": cfg["lambda2"],
-           "pairs": n_pairs, "rows": n_pairs * inst.p, "generation_s": round(gen_s, 1),
+           "method": METHOD_NAME[SOLVE_KW["method"]], "pairs": n_pairs, "rows": n_pairs * inst.p, "generation_s": round(gen_s, 1),
            "generation_child_iters_mean": round(float(gen_iters.mean()), 1),
            "epochs": epochs, "train_s": round(train_s, 2), "epoch_losses": [float(f"{x:.4g}") for x in losses],
            "grad_kernel_rows": batch_rows, "grad_kernel_ms": round(grad_ms, 4),
