@@ -6,21 +6,31 @@
 // once per launch and should not displace the L2-resident right-hand side),
 // one row step per lane in flight (a measured sweep over 1, 2, 4 steps on
 // MI355X favoured 1), then a deterministic in-wave transpose reduction leaves
-// column c's total in lane (64 / C) c.  With one right-hand side, C = 2 (a
-// sweep over 1, 2, 4, 8 columns per wave): twice the waves of C = 4, which the
-// HBM stream needs to stay full.  With two, C = 8: every wave re-reads both
-// right-hand sides from L2 for its columns, and at small C that L2 traffic
-// (at C = 2 twice the bytes of X) becomes the limit (logistic 32768 x 16384:
-// 585 / 537 / 504 / 498 us per iteration at C = 2 / 4 / 8 / 16; 16 needs 254
-// VGPRs).  Algorithmic bytes per launch: n*p*sizeof(X) + 8n per right-hand
-// side + 8p per output.
+// column c's total in lane (64 / C) c.  With one right-hand side the stream
+// runs best with as many waves as are resident at once (about 5 per SIMD):
+// 4096 waves give 6.9 TB/s, 2048 5.9, and 8192 (1.6 rounds) 5.5-5.7, so C
+// is the smallest of 2, 4, 8 that keeps p / C at or below 5120 (2 up to
+// p = 10240; C = 2 beat 1, 4 and 8 on the 16384 x 8192 design).  With two,
+// C = 8: every wave re-reads both right-hand sides from L2 for its columns,
+// and at small C that L2 traffic (at C = 2 twice the bytes of X) becomes the
+// limit (logistic 32768 x 16384: 585 / 537 / 504 / 498 us per iteration at
+// C = 2 / 4 / 8 / 16; 16 needs 254 VGPRs).  Algorithmic bytes per launch:
+// n*p*sizeof(X) + 8n per right-hand side + 8p per output.
 #include "pr_device.h"
 
 namespace pr {
 namespace {
 using namespace dev;
 
-constexpr int gemv_cols(int nrhs) { return nrhs == 1 ? 2 : 8; }
+constexpr int kGemvWavesMax = 5120;  // waves of one resident round of the one-RHS kernel
+// columns per wave: 8 with two right-hand sides; with one, the smallest of
+// 2, 4, 8 that keeps the grid within one resident round
+inline int gemv_cols(int nrhs, int64_t p) {
+  if (nrhs != 1) return 8;
+  int c = 2;
+  while (c < 8 && p > (int64_t)c * kGemvWavesMax) c *= 2;
+  return c;
+}
 
 // Deterministic transpose reduction of C per-lane partial sums (one per
 // column) over the 64 lanes: at each exchange over lane bit s (32, 16, ...)
@@ -159,7 +169,7 @@ __device__ void list_values(const NodeParams *__restrict__ P, const int32_t *__r
 }
 
 
-template <typename T, int NRHS>
+template <typename T, int NRHS, int C>
 __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X, int64_t n, int64_t p,
                                                          const double *__restrict__ r1,
                                                          const double *__restrict__ r2,
@@ -191,7 +201,6 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
 #endif
   constexpr int U = PR_GEMVT_STEPS;  // row steps in flight
   const int lane = lane_id();
-  constexpr int C = gemv_cols(NRHS);
   const int64_t col0 = ((int64_t)bx * (kGemvThreads / 64) + wave_id()) * C;
   if (col0 >= p) return;
   const T *c[C];
@@ -262,26 +271,34 @@ hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, d
   if (node && (!S || !sidx || !sval || !nlist)) return hipErrorInvalidValue;
   if (dsum && !node) return hipErrorInvalidValue;
   const bool two = (r2 != nullptr);
-  const int cols_per_block = (kGemvThreads / 64) * gemv_cols(two ? 2 : 1);
+  const int cols = gemv_cols(two ? 2 : 1, P.p);
+  const int cols_per_block = (kGemvThreads / 64) * cols;
   dim3 grid((unsigned)((P.p + cols_per_block - 1) / cols_per_block) + (node ? 1u : 0u));
   dim3 block(kGemvThreads);
-#define PR_GEMVT(T, R)                                                                                   \
-  k_gemv_t<T, R><<<grid, block, 0, s>>>((const T *)P.X, P.n, P.p, r1, r2, h1, h2, done, node, S, sidx, sval, \
-                                        nlist, dsum, nfin)
+#define PR_GEMVT(T, R, C)                                                                                \
+  k_gemv_t<T, R, C><<<grid, block, 0, s>>>((const T *)P.X, P.n, P.p, r1, r2, h1, h2, done, node, S, sidx, sval, \
+                                           nlist, dsum, nfin)
+#define PR_GEMVT1(T)                  \
+  switch (cols) {                     \
+    case 2: PR_GEMVT(T, 1, 2); break; \
+    case 4: PR_GEMVT(T, 1, 4); break; \
+    default: PR_GEMVT(T, 1, 8); break; \
+  }
   switch (P.xdt) {
     case kF32:
-      if (two) PR_GEMVT(float, 2);
-      else PR_GEMVT(float, 1);
+      if (two) PR_GEMVT(float, 2, 8);
+      else PR_GEMVT1(float);
       break;
     case kF64:
-      if (two) PR_GEMVT(double, 2);
-      else PR_GEMVT(double, 1);
+      if (two) PR_GEMVT(double, 2, 8);
+      else PR_GEMVT1(double);
       break;
     default:
-      if (two) PR_GEMVT(uint16_t, 2);
-      else PR_GEMVT(uint16_t, 1);
+      if (two) PR_GEMVT(uint16_t, 2, 8);
+      else PR_GEMVT1(uint16_t);
       break;
   }
+#undef PR_GEMVT1
 #undef PR_GEMVT
   return hipGetLastError();
 }

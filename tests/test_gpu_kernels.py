@@ -148,8 +148,13 @@ def _ctx_for(dev, Xcm, y, loss=0):
 
 
 @pytest.mark.parametrize("storage,n,p", [("f64", 500, 200), ("f64", 2, 1), ("f32", 1028, 37),
-                                         ("f32", 4096, 1031), ("bf16", 1032, 77), ("bf16", 16384, 64)])
+                                         ("f32", 4096, 1031), ("bf16", 1032, 77), ("bf16", 16384, 64),
+                                         ("f32", 260, 10241), ("f64", 64, 16390), ("bf16", 520, 20483),
+                                         ("f32", 128, 41000)])
 def test_gemv_and_gemv_t_match_oracle(dev, storage, n, p):
+    """Dense forward and transposed products element by element against the
+    oracle's; p past 10240 and 20480 runs the transposed kernel with 4 and 8
+    columns per wave, ragged against the workgroup's columns."""
     import torch
     inst = make_instance(n=n, p=p, corr=0.6, k_true=min(3, p), snr=5.0, loss=0, seed=7, storage=storage)
     ctx = _ctx_for(dev, inst.Xcm, inst.y)
