@@ -11,11 +11,14 @@
 // 4096 waves give 6.9 TB/s, 2048 5.9, and 8192 (1.6 rounds) 5.5-5.7, so C
 // is the smallest of 2, 4, 8 that keeps p / C at or below 5120 (2 up to
 // p = 10240; C = 2 beat 1, 4 and 8 on the 16384 x 8192 design).  With two,
-// C = 8: every wave re-reads both right-hand sides from L2 for its columns,
-// and at small C that L2 traffic (at C = 2 twice the bytes of X) becomes the
-// limit (logistic 32768 x 16384: 585 / 537 / 504 / 498 us per iteration at
-// C = 2 / 4 / 8 / 16; 16 needs 254 VGPRs).  Algorithmic bytes per launch:
-// n*p*sizeof(X) + 8n per right-hand side + 8p per output.
+// every wave re-reads both right-hand sides from L2 for its columns, and at
+// small C that L2 traffic (at C = 2 twice the bytes of X) competes with X
+// (logistic 32768 x 16384: 585 / 537 / 504 / 498 us per iteration at C = 2 /
+// 4 / 8 / 16; 16 needs 254 VGPRs), while at large C small designs leave the
+// grid short of waves (16384 x 8192: 5.6 TB/s at C = 8, 6.0 at C = 4): C is
+// the smallest of 2, 4, 8 that keeps p / C at or below 2048 waves.
+// Algorithmic bytes per launch: n*p*sizeof(X) + 8n per right-hand side + 8p
+// per output.
 #include "pr_device.h"
 
 namespace pr {
@@ -23,12 +26,13 @@ namespace {
 using namespace dev;
 
 constexpr int kGemvWavesMax = 5120;  // waves of one resident round of the one-RHS kernel
-// columns per wave: 8 with two right-hand sides; with one, the smallest of
-// 2, 4, 8 that keeps the grid within one resident round
+constexpr int kGemvWaves2 = 2048;    // waves the two-RHS kernel aims for
+// columns per wave, the smallest of 2, 4, 8 that keeps the grid within
+// kGemvWavesMax waves (one right-hand side) or kGemvWaves2 (two)
 inline int gemv_cols(int nrhs, int64_t p) {
-  if (nrhs != 1) return 8;
+  const int64_t wmax = nrhs == 1 ? kGemvWavesMax : kGemvWaves2;
   int c = 2;
-  while (c < 8 && p > (int64_t)c * kGemvWavesMax) c *= 2;
+  while (c < 8 && p > (int64_t)c * wmax) c *= 2;
   return c;
 }
 
@@ -278,24 +282,24 @@ hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, d
 #define PR_GEMVT(T, R, C)                                                                                \
   k_gemv_t<T, R, C><<<grid, block, 0, s>>>((const T *)P.X, P.n, P.p, r1, r2, h1, h2, done, node, S, sidx, sval, \
                                            nlist, dsum, nfin)
-#define PR_GEMVT1(T)                  \
-  switch (cols) {                     \
-    case 2: PR_GEMVT(T, 1, 2); break; \
-    case 4: PR_GEMVT(T, 1, 4); break; \
-    default: PR_GEMVT(T, 1, 8); break; \
+#define PR_GEMVT1(T, R)                \
+  switch (cols) {                      \
+    case 2: PR_GEMVT(T, R, 2); break;  \
+    case 4: PR_GEMVT(T, R, 4); break;  \
+    default: PR_GEMVT(T, R, 8); break; \
   }
   switch (P.xdt) {
     case kF32:
-      if (two) PR_GEMVT(float, 2, 8);
-      else PR_GEMVT1(float);
+      if (two) PR_GEMVT1(float, 2)
+      else PR_GEMVT1(float, 1)
       break;
     case kF64:
-      if (two) PR_GEMVT(double, 2, 8);
-      else PR_GEMVT1(double);
+      if (two) PR_GEMVT1(double, 2)
+      else PR_GEMVT1(double, 1)
       break;
     default:
-      if (two) PR_GEMVT(uint16_t, 2, 8);
-      else PR_GEMVT1(uint16_t);
+      if (two) PR_GEMVT1(uint16_t, 2)
+      else PR_GEMVT1(uint16_t, 1)
       break;
   }
 #undef PR_GEMVT1

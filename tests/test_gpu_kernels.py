@@ -175,12 +175,13 @@ def test_gemv_and_gemv_t_match_oracle(dev, storage, n, p):
 
 
 @pytest.mark.parametrize("storage,n,p", [("f32", 1028, 37), ("f32", 4096, 1031), ("f32", 200, 9), ("f64", 770, 65),
-                                         ("f64", 2, 1), ("bf16", 1032, 77), ("bf16", 16384, 64), ("f32", 32768, 100)])
+                                         ("f64", 2, 1), ("bf16", 1032, 77), ("bf16", 16384, 64), ("f32", 32768, 100),
+                                         ("f32", 520, 6001), ("f64", 130, 9007), ("bf16", 1032, 16390)])
 def test_gemv_t2_matches_oracle(dev, storage, n, p):
     """The two-right-hand-side transposed product (the logistic iteration's
-    X^T [zeta, grad F], eight columns per wave): both outputs element by
-    element against the oracle's products, n ragged against the row step and
-    p against the workgroup's 32 columns."""
+    X^T [zeta, grad F]; 2, 4 or 8 columns per wave as p grows past 4096 and
+    8192): both outputs element by element against the oracle's products, n
+    ragged against the row step and p against the workgroup's columns."""
     import torch
     inst = make_instance(n=n, p=p, corr=0.6, k_true=min(3, p), snr=5.0, loss=1, seed=9, storage=storage)
     ctx = _ctx_for(dev, inst.Xcm, inst.y, loss=1)
