@@ -409,7 +409,7 @@ def logistic_bench(dev, steps, with_cpu, budget_s=15.0, batch_nodes=64):
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4),
                         "traffic": _traffic_from_summary(PMC_SUMMARY_LOGISTIC),
-                        "kernel": "k_gemv_t<float,2>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}}
+                        "kernel": "k_gemv_t<float,2,8>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}}
     if batch_nodes > 0:
         out["batch"] = logistic_batch_bench(dev, inst, cfg, ctx, X, y, batch_nodes, max(1, min(2, steps)))
     nrm2 = ctx.norm2()
@@ -1018,7 +1018,7 @@ def main():
     achieved = per_launch / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic_from_summary(),
-            "kernel": "k_gemv_t<float,1>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}
+            "kernel": "k_gemv_t<float,1,2>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}
     line = {"metric": "node relaxations/sec to 1e-6 rel. duality gap; GEMV HBM GB/s vs peak",
             "value": round(value, 4), "unit": "node relaxations/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
