@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kFinThreads) void k_spfwd_final(int64_t n, const do
       }
     }
   }
-  block_sum<kSpThreads, 3>(sums, red);
+  block_sum<kFinThreads, 3>(sums, red);
   if (threadIdx.x == 0) {
     B.rbsum[2 * fb] = sums[0];
     B.rbsum[2 * fb + 1] = sums[1];
