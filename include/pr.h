@@ -117,9 +117,10 @@ typedef struct {
  * (opts->L, default as above), at which a trial is accepted.  Momentum, the
  * bounds, the stopping test and the restart act at accepted iterates; a
  * restart runs the method afresh from its iterate, the line search from L0.
- * A rejected trial costs one product over its support and one X^T pass and
- * is not evaluated; pr_result.iters counts accepted iterates, .trials the
- * rejected ones, .L is the last step constant.  p <= 16384 (pr_solve returns
+ * A rejected trial is not evaluated: it costs one product over its support
+ * (the X^T pass takes the same decision from the same sums and exits at
+ * once) and the redone step; pr_result.iters counts accepted iterates,
+ * .trials the rejected ones, .L is the last step constant.  p <= 16384 (pr_solve returns
  * PR_EINVAL beyond); pr_solve_batch runs it per node on the batched path. */
 #define PR_FISTA_BT_GAP 6
 #define PR_FISTA_BT 7
@@ -152,7 +153,8 @@ typedef struct {
   int32_t iters;      /* proximal-gradient steps taken */
   int32_t restarts;   /* duality-gap restarts */
   int32_t status;     /* PR_CONVERGED ... PR_CUTOFF_BRANCH */
-  int32_t trials;     /* AC-FGM: first-step trials rejected by the line search; else 0 */
+  int32_t trials;     /* trials rejected by a line search (AC-FGM's first step, FISTA with
+                         backtracking); else 0 */
 } pr_result;
 
 typedef struct pr_ctx pr_ctx;
