@@ -197,37 +197,51 @@ __device__ __forceinline__ int decide_restart(const NodeParams *prm, int it, dou
   }
 }
 
+// One 16-byte non-temporal load of the stored X (raw), its exact widening to
+// FP64 (cvt), or both (load).  Kernels that must have every load of a step in
+// flight before any arithmetic issue the raw loads first.
 template <typename T>
 struct XLoad;
 
 template <>
 struct XLoad<float> {
   static constexpr int VEC = 4;
-  __device__ __forceinline__ static void load(const float *p, double (&d)[4]) {
-    f4_t v = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(p));
+  typedef f4_t raw_t;
+  __device__ __forceinline__ static raw_t raw(const float *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(p));
+  }
+  __device__ __forceinline__ static void cvt(const raw_t &v, double (&d)[4]) {
     d[0] = (double)v.x;
     d[1] = (double)v.y;
     d[2] = (double)v.z;
     d[3] = (double)v.w;
   }
+  __device__ __forceinline__ static void load(const float *p, double (&d)[4]) { cvt(raw(p), d); }
 };
 
 template <>
 struct XLoad<double> {
   static constexpr int VEC = 2;
-  __device__ __forceinline__ static void load(const double *p, double (&d)[2]) {
-    d2_t v = __builtin_nontemporal_load(reinterpret_cast<const d2_t *>(p));
+  typedef d2_t raw_t;
+  __device__ __forceinline__ static raw_t raw(const double *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const d2_t *>(p));
+  }
+  __device__ __forceinline__ static void cvt(const raw_t &v, double (&d)[2]) {
     d[0] = v.x;
     d[1] = v.y;
   }
+  __device__ __forceinline__ static void load(const double *p, double (&d)[2]) { cvt(raw(p), d); }
 };
 
 // bf16 stored as uint16_t bit patterns
 template <>
 struct XLoad<uint16_t> {
   static constexpr int VEC = 8;
-  __device__ __forceinline__ static void load(const uint16_t *p, double (&d)[8]) {
-    u4_t v = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(p));
+  typedef u4_t raw_t;
+  __device__ __forceinline__ static raw_t raw(const uint16_t *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(p));
+  }
+  __device__ __forceinline__ static void cvt(const raw_t &v, double (&d)[8]) {
     const unsigned int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int q = 0; q < 4; q++) {
@@ -235,6 +249,7 @@ struct XLoad<uint16_t> {
       d[2 * q + 1] = (double)__uint_as_float(w[q] & 0xffff0000u);
     }
   }
+  __device__ __forceinline__ static void load(const uint16_t *p, double (&d)[8]) { cvt(raw(p), d); }
 };
 
 template <int VEC>

@@ -220,38 +220,50 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
     for (int q = 0; q < C; q++) acc[h][q] = 0.0;
   const int64_t step = 64 * VEC;
   int64_t i = (int64_t)lane * VEC;
+  // every load of a step is issued before its first use: the scheduling
+  // barrier keeps the compiler from sinking the right-hand-side loads below
+  // the widening of the first X vector, which made a step two or three
+  // dependent memory round trips instead of one
   for (; i + (U - 1) * step + VEC <= n; i += U * step) {
-    double xv[U][C][VEC];
+    typename XLoad<T>::raw_t xr[U][C];
     double rv[U][NRHS][VEC];
 #pragma unroll
     for (int u = 0; u < U; u++) {
 #pragma unroll
-      for (int q = 0; q < C; q++) XLoad<T>::load(c[q] + i + u * step, xv[u][q]);
+      for (int q = 0; q < C; q++) xr[u][q] = XLoad<T>::raw(c[q] + i + u * step);
       load_rhs<VEC>(r1, i + u * step, rv[u][0]);
       if (NRHS > 1) load_rhs<VEC>(r2, i + u * step, rv[u][NRHS - 1]);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; u++)
 #pragma unroll
-      for (int h = 0; h < NRHS; h++)
+      for (int q = 0; q < C; q++) {
+        double xv[VEC];
+        XLoad<T>::cvt(xr[u][q], xv);
 #pragma unroll
-        for (int q = 0; q < C; q++)
+        for (int h = 0; h < NRHS; h++)
 #pragma unroll
-          for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[u][q][e], rv[u][h][e], acc[h][q]);
+          for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[e], rv[u][h][e], acc[h][q]);
+      }
   }
   for (; i + VEC <= n; i += step) {
-    double xv[C][VEC];
+    typename XLoad<T>::raw_t xr[C];
     double rv[NRHS][VEC];
 #pragma unroll
-    for (int q = 0; q < C; q++) XLoad<T>::load(c[q] + i, xv[q]);
+    for (int q = 0; q < C; q++) xr[q] = XLoad<T>::raw(c[q] + i);
     load_rhs<VEC>(r1, i, rv[0]);
     if (NRHS > 1) load_rhs<VEC>(r2, i, rv[NRHS - 1]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int h = 0; h < NRHS; h++)
+    for (int q = 0; q < C; q++) {
+      double xv[VEC];
+      XLoad<T>::cvt(xr[q], xv);
 #pragma unroll
-      for (int q = 0; q < C; q++)
+      for (int h = 0; h < NRHS; h++)
 #pragma unroll
-        for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[q][e], rv[h][e], acc[h][q]);
+        for (int e = 0; e < VEC; e++) acc[h][q] = fma(xv[e], rv[h][e], acc[h][q]);
+    }
   }
   constexpr int LPC = 64 / C;  // lanes per column after the reduction
   const int64_t col = col0 + lane / LPC;
