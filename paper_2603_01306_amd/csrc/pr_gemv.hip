@@ -16,7 +16,11 @@
 // (logistic 32768 x 16384: 585 / 537 / 504 / 498 us per iteration at C = 2 /
 // 4 / 8 / 16; 16 needs 254 VGPRs), while at large C small designs leave the
 // grid short of waves (16384 x 8192: 5.6 TB/s at C = 8, 6.0 at C = 4): C is
-// the smallest of 2, 4, 8 that keeps p / C at or below 2048 waves.
+// the smallest of 2, 4, 8 that keeps p / C at or below 2048 waves.  With
+// all loads of a step issued together (below), C = 4 / 4096 waves and two
+// row steps in flight stayed slower than C = 8, one step (345 / 325 vs 313
+// us), and staging both right-hand sides in LDS per workgroup (one barrier
+// per 1024-row tile) cost 380-440 us.
 // Algorithmic bytes per launch: n*p*sizeof(X) + 8n per right-hand side + 8p
 // per output.
 #include "pr_device.h"
@@ -220,10 +224,14 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
     for (int q = 0; q < C; q++) acc[h][q] = 0.0;
   const int64_t step = 64 * VEC;
   int64_t i = (int64_t)lane * VEC;
-  // every load of a step is issued before its first use: the scheduling
-  // barrier keeps the compiler from sinking the right-hand-side loads below
-  // the widening of the first X vector, which made a step two or three
-  // dependent memory round trips instead of one
+  // With two right-hand sides every load of a step is issued before its first
+  // use: the scheduling barrier keeps the compiler from sinking the
+  // right-hand-side loads below the widening of the first X vector, which
+  // made a step three dependent memory round trips (logistic 32768 x 16384:
+  // 338 -> 312 us).  With one right-hand side the compiler's own order (X,
+  // then the right-hand side once the first column has arrived) measured
+  // faster: 316 vs 340 us on a 32768 x 16384 FP32 design, 89.8 vs 94.0 on
+  // 16000 x 16000 BF16, equal on 16384 x 8192.
   for (; i + (U - 1) * step + VEC <= n; i += U * step) {
     typename XLoad<T>::raw_t xr[U][C];
     double rv[U][NRHS][VEC];
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
       load_rhs<VEC>(r1, i + u * step, rv[u][0]);
       if (NRHS > 1) load_rhs<VEC>(r2, i + u * step, rv[u][NRHS - 1]);
     }
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (NRHS > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; u++)
 #pragma unroll
@@ -254,7 +262,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_t(const T *__restrict__ X
     for (int q = 0; q < C; q++) xr[q] = XLoad<T>::raw(c[q] + i);
     load_rhs<VEC>(r1, i, rv[0]);
     if (NRHS > 1) load_rhs<VEC>(r2, i, rv[NRHS - 1]);
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (NRHS > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < C; q++) {
       double xv[VEC];
