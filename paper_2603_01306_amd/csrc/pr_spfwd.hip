@@ -52,16 +52,15 @@ struct XRaw<uint16_t> {
   }
 };
 
-// One round of kSpInFlight column loads (16 bytes per lane each) for list
-// entries t .. t + kSpInFlight - 1.  A full round reads its indices as one
-// block; in the chunk's last, partial round the slots at or past t1 re-read
+// The chunk's last, partial round of kSpInFlight column loads (16 bytes per
+// lane each) for list entries t .. t1 - 1: the slots at or past t1 re-read
 // the chunk's last column, which sp_use_r then weights by zero.
-template <typename T, bool FULL>
-__device__ __forceinline__ void sp_issue_r(u4_t (&raw)[kSpInFlight], const T *__restrict__ X, int64_t n,
-                                           int64_t row0, const int32_t *__restrict__ idx, int t, int t1) {
+template <typename T>
+__device__ __forceinline__ void sp_issue_tail(u4_t (&raw)[kSpInFlight], const T *__restrict__ X, int64_t n,
+                                              int64_t row0, const int32_t *__restrict__ idx, int t, int t1) {
 #pragma unroll
   for (int c = 0; c < kSpInFlight; c++) {
-    const int tc = (FULL || t + c < t1) ? t + c : t1 - 1;
+    const int tc = (t + c < t1) ? t + c : t1 - 1;
     const T *col = X + (int64_t)(idx[tc] & kIdxMask) * n;   // wave-uniform column base
     raw[c] = __builtin_nontemporal_load(reinterpret_cast<const u4_t *>(col + row0));
   }
@@ -99,14 +98,34 @@ __global__ __launch_bounds__(kSpThreads) void k_spfwd_part(const T *__restrict__
   // full rounds of kSpInFlight columns, then the chunk's remaining columns as
   // one masked round (all its loads in flight together)
   int t = t0;
-  for (; t + kSpInFlight <= t1; t += kSpInFlight) {
-    u4_t raw[kSpInFlight];
-    sp_issue_r<T, true>(raw, X, n, row0, idx, t, t1);
-    sp_use_r<T, true>(raw, acc, val, t, t1);
+  if (t + kSpInFlight <= t1) {
+    // the next round's column indices are loaded while this round's columns
+    // stream, so a round does not start with a wait on its own indices
+    // (root solves 0.7-0.9% faster; issuing the next round's column loads
+    // ahead of this round's arithmetic from two load buffers gained nothing)
+    int32_t ci[kSpInFlight];
+#pragma unroll
+    for (int c = 0; c < kSpInFlight; c++) ci[c] = idx[t + c];
+    for (;;) {
+      u4_t raw[kSpInFlight];
+#pragma unroll
+      for (int c = 0; c < kSpInFlight; c++)
+        raw[c] = __builtin_nontemporal_load(
+            reinterpret_cast<const u4_t *>(X + (int64_t)(ci[c] & kIdxMask) * n + row0));
+      const int tn = t + kSpInFlight;
+      const bool more = tn + kSpInFlight <= t1;
+      if (more) {
+#pragma unroll
+        for (int c = 0; c < kSpInFlight; c++) ci[c] = idx[tn + c];
+      }
+      sp_use_r<T, true>(raw, acc, val, t, t1);
+      t = tn;
+      if (!more) break;
+    }
   }
   if (t < t1) {
     u4_t raw[kSpInFlight];
-    sp_issue_r<T, false>(raw, X, n, row0, idx, t, t1);
+    sp_issue_tail<T>(raw, X, n, row0, idx, t, t1);
     sp_use_r<T, false>(raw, acc, val, t, t1);
   }
   double *part = B.part + (int64_t)ch * n + row0;
