@@ -285,26 +285,41 @@ __global__ __launch_bounds__(256) void k_mlp(const float *__restrict__ P, const 
   if (threadIdx.x == 0) dst[kNP] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
 }
 
-// grad[i] = sum over blocks of part[b][i] in block order; grad[kNP] = loss.
-// The loads of 16 consecutive blocks are issued together and then added in
-// block order, so the sum is the plain sequential one without a memory round
-// trip per block.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ part, int nblk, float inv_n,
-                                                    float *__restrict__ grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > kNP) return;
+// grad[i] = sum over blocks of part[b][i]; grad[kNP] = loss.  A workgroup
+// owns 64 consecutive entries (one per lane) and its kRedWaves waves split
+// the blocks into contiguous ranges: each wave adds its range in block order
+// with the loads of 16 blocks issued together, then lane i of the first wave
+// adds the wave totals in wave order, so the sum is fixed and reproducible.
+// (One thread per entry walking all blocks left 76 waves on the chip, each
+// waiting on nblk / 16 dependent memory round trips.)
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(64 * kRedWaves) void k_mlp_reduce(const float *__restrict__ part, int nblk, float inv_n,
+                                                               float *__restrict__ grad) {
+  __shared__ float red[kRedWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int b0 = (int)((int64_t)nblk * w / kRedWaves), b1 = (int)((int64_t)nblk * (w + 1) / kRedWaves);
   constexpr int kBatch = 16;
   float s = 0.f;
-  int b = 0;
-  for (; b + kBatch <= nblk; b += kBatch) {
-    float v[kBatch];
+  if (i <= kNP) {
+    int b = b0;
+    for (; b + kBatch <= b1; b += kBatch) {
+      float v[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; u++) v[u] = part[(int64_t)(b + u) * kMlpPartStride + i];
+      for (int u = 0; u < kBatch; u++) v[u] = part[(int64_t)(b + u) * kMlpPartStride + i];
 #pragma unroll
-    for (int u = 0; u < kBatch; u++) s += v[u];
+      for (int u = 0; u < kBatch; u++) s += v[u];
+    }
+    for (; b < b1; b++) s += part[(int64_t)b * kMlpPartStride + i];
   }
-  for (; b < nblk; b++) s += part[(int64_t)b * kMlpPartStride + i];
-  grad[i] = i == kNP ? s * inv_n : s;
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i <= kNP) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRedWaves; k++) t += red[k][lane];
+    grad[i] = i == kNP ? t * inv_n : t;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ P, const float *__restrict__ g,
@@ -422,7 +437,7 @@ hipError_t launch_mlp_grad(const float *P, const uint16_t *F, const float *T, in
   k_mlp<true><<<blocks, 256, 0, s>>>(P, F, T, rows, cpb, inv_n, nullptr, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_mlp_reduce<<<(kNP + 1 + 255) / 256, 256, 0, s>>>(part, blocks, inv_n, grad);
+  k_mlp_reduce<<<(kNP + 1 + 63) / 64, 64 * kRedWaves, 0, s>>>(part, blocks, inv_n, grad);
   return hipGetLastError();
 }
 
