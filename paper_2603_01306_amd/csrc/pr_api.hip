@@ -1073,10 +1073,17 @@ int pr_ctx_create(pr_ctx **out, const pr_problem *prob, int32_t max_batch, void 
   c->B.rb = (int32_t)((n + c->B.rows - 1) / c->B.rows);
   // column chunks of the column-list product: 16 at most (fewer planes for
   // the summing kernel; on the 16384 x 8192 root 16 chunks beat 8, 12 and 32
-  // per iteration, and the 500 x 200 root ran 8% faster than with 64)
+  // per iteration, and the 500 x 200 root ran 8% faster than with 64), but
+  // enough for one workgroup per compute unit where the design has few row
+  // blocks and the columns to fill them, at least 64 per chunk (BF16
+  // 16000 x 16000: 8 row blocks of 2048 rows, 32 chunks instead of 16: the
+  // dense product 93 -> 82 us, its root solves 6% faster)
   int nch = 512 / c->B.rb;
   if (nch < 1) nch = 1;
   if (nch > kSpChunksMax) nch = kSpChunksMax;
+  int fill = (kCUs + c->B.rb - 1) / c->B.rb;
+  if (fill > kSpChunksFill) fill = kSpChunksFill;
+  if (fill > nch && (int64_t)fill * 64 <= p) nch = fill;
   if (nch > p) nch = (int)p;
   c->B.nch = nch;
   c->B.nfin = spfwd_final_blocks(n);

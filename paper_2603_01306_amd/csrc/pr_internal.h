@@ -13,6 +13,8 @@ namespace pr {
 constexpr int kNodeThreads = 512;    // threads of a per-node workgroup
 constexpr int kGemvThreads = 256;    // 4 waves of the X^T r kernel
 constexpr int kSpChunksMax = 16;     // column chunks of the column-list product at most
+constexpr int kSpChunksFill = 64;    // ... and at most this many to give every compute unit a workgroup
+constexpr int kCUs = 256;            // compute units of the target (MI355X)
 constexpr int kSpThreads = 256;      // column-list GEMV workgroup
 
 enum : int32_t { kFree = 0, kZero = 1, kOne = 2 };
