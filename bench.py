@@ -14,8 +14,10 @@ headline); the batched solves and their single-node comparisons run the same
 method.
 
 Also reported: the dominant kernel (X^T r, FP64 accumulation) against the
-HBM roofline, timed with HIP events on the stream it runs on, and the FP64
-CPU oracle on a bounded sample of the same workload.
+HBM roofline, timed with HIP events on the stream it runs on, and against the
+best plain streaming read of the same bytes (pr_time_read over a sweep of grid
+sizes: "read_ceiling_gbs", "frac_of_read_ceiling"), and the FP64 CPU oracle on
+a bounded sample of the same workload.
 
 "batch": 256 branch-and-bound node relaxations (uneven fixed-zero / fixed-one
 sets of sizes 0-64 / 0-19) sharing a BF16 copy of the same design, solved
@@ -45,6 +47,7 @@ the network on 1M random feature rows) against the BF16 MFMA roofline.
   python bench.py --lasso            # the gap restart on l1-regularised and l1-ball LASSO
   python bench.py --bnb              # branch and bound on the paper's synthetic setting
   python bench.py --paper-shapes     # root solve times at the paper's n = p = 1000 ... 16000 shapes
+  python bench.py --read-ceiling     # the plain streaming-read rate the HBM-bound kernels are compared with
 """
 import argparse
 import hashlib
@@ -72,6 +75,40 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_01306_amd", "csrc", f) for f in ("
 def _gemv_t_bytes(n, p, xbytes):
     # algorithmic bytes of one X^T r launch: X once, r (FP64) once, h (FP64) once
     return n * p * xbytes + n * 8 + p * 8
+
+
+READ_BLOCKS = (512, 1024, 2048, 4096, 8192, 16384)
+
+
+def read_ceiling(buf, reps=20):
+    """The best plain streaming-read rate over the device tensor `buf`
+    (pr_time_read over grid sizes of 512 to 16384 workgroups and 1 or 4
+    loads in flight per lane): the practical ceiling of an HBM-bound kernel
+    on these bytes, next to the 8 TB/s data-sheet peak."""
+    import paper_2603_01306_amd as pr
+    nbytes = buf.numel() * buf.element_size()
+    rows = []
+    for blocks in READ_BLOCKS:
+        for unroll in (1, 4):
+            ms = pr.time_read(buf, blocks, unroll, reps)
+            rows.append({"blocks": blocks, "unroll": unroll, "ms": round(ms, 5),
+                         "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)})
+    return max(rows, key=lambda r: r["GB/s"]), rows
+
+
+def read_ceiling_bench():
+    """The streaming-read sweep on 512 MiB and 2 GiB device buffers, one JSON
+    line per configuration and one with the best."""
+    import torch
+    dev = torch.device("cuda:0")
+    for nbytes in (512 << 20, 2 << 30):
+        buf = torch.zeros(nbytes // 4, dtype=torch.float32, device=dev)
+        best, rows = read_ceiling(buf)
+        for r in rows:
+            print(json.dumps({"bytes": nbytes, **r}), flush=True)
+        print(json.dumps({"bytes": nbytes, "best": best}), flush=True)
+        del buf
+        torch.cuda.empty_cache()
 
 
 def kernel_source_hash():
@@ -410,6 +447,9 @@ def logistic_bench(dev, steps, with_cpu, budget_s=15.0, batch_nodes=64):
                         "frac": round(ach / HBM_PEAK_GBS, 4),
                         "traffic": _traffic_from_summary(PMC_SUMMARY_LOGISTIC),
                         "kernel": "k_gemv_t<float,2,8>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}}
+    ceil, _ = read_ceiling(X)
+    out["roofline"]["read_ceiling_gbs"] = ceil["GB/s"]
+    out["roofline"]["frac_of_read_ceiling"] = round(ach / ceil["GB/s"], 4)
     if batch_nodes > 0:
         out["batch"] = logistic_batch_bench(dev, inst, cfg, ctx, X, y, batch_nodes, max(1, min(2, steps)))
     nrm2 = ctx.norm2()
@@ -961,6 +1001,8 @@ def main():
     ap.add_argument("--bnb", action="store_true", help="branch and bound on the paper's synthetic setting instead")
     ap.add_argument("--lasso", action="store_true", help="the gap restart on LASSO instead")
     ap.add_argument("--paper-shapes", action="store_true", help="root solve times at the paper's table shapes instead")
+    ap.add_argument("--read-ceiling", action="store_true",
+                    help="the plain streaming-read rate on 512 MiB and 2 GiB buffers instead")
     ap.add_argument("--pairs", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args()
@@ -997,6 +1039,9 @@ def main():
     if args.paper_shapes:
         paper_shapes_bench()
         return
+    if args.read_ceiling:
+        read_ceiling_bench()
+        return
     import torch
     dev = torch.device("cuda:0")
     inst, cfg, ctx, node, setup_s = _setup(dev)
@@ -1019,6 +1064,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic_from_summary(),
             "kernel": "k_gemv_t<float,1,2>", "bytes_per_launch": per_launch, "avg_launch_ms": round(ms, 5)}
+    ceil, _ = read_ceiling(ctx.X)
+    roof["read_ceiling_gbs"] = ceil["GB/s"]
+    roof["frac_of_read_ceiling"] = round(achieved / ceil["GB/s"], 4)
     line = {"metric": "node relaxations/sec to 1e-6 rel. duality gap; GEMV HBM GB/s vs peak",
             "value": round(value, 4), "unit": "node relaxations/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),

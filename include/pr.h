@@ -341,6 +341,18 @@ int pr_time_gemv_t(pr_ctx *ctx, const double *r, double *h, int32_t reps, double
  * b device p, u device n.  PR_EINVAL for NULL arguments or reps < 1. */
 int pr_time_gemv(pr_ctx *ctx, const double *b, double *u, int32_t reps, double *ms_avg);
 
+/* The streaming-read rate that the HBM-bound kernels are measured against:
+ * time `reps` back-to-back launches of a plain read of `bytes` bytes of the
+ * device buffer `buf` (16-byte non-temporal loads, `blocks` workgroups of 256
+ * threads striding over the buffer, `unroll` = 1 or 4 loads per lane in
+ * flight) with HIP events on `stream`, after one untimed launch; *ms_avg =
+ * elapsed / reps.  The buffer is only read (its contents are not changed) and
+ * stays owned by the caller.  PR_EINVAL for a NULL or unaligned (16 B) buffer,
+ * bytes not a positive multiple of 16, blocks outside [1, 2^20], another
+ * unroll, reps < 1 or NULL ms_avg; PR_EDEVICE for a failed launch or event. */
+int pr_time_read(const void *buf, int64_t bytes, int32_t blocks, int32_t unroll, int32_t reps, void *stream,
+                 double *ms_avg);
+
 /* Splits chosen by the context's batched-GEMM autotuner (run at context
  * creation): for i = 0 .. len-1, the number of reduction splits of the forward
  * and of the transpose GEMM when i+1 tiles of 64 rows are active (host arrays

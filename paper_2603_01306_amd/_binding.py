@@ -25,7 +25,7 @@ F64, F32, BF16 = 0, 1, 2
 
 EXPORTS = ["pr_opts_default", "pr_ctx_create", "pr_ctx_destroy", "pr_ctx_norm2", "pr_ctx_enable_gram", "pr_solve",
            "pr_prox", "pr_regularizer", "pr_dual_bound", "pr_gemv", "pr_gemv_t", "pr_gemv_t2", "pr_solve_batch",
-           "pr_time_gemv_t", "pr_time_gemv", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
+           "pr_time_gemv_t", "pr_time_gemv", "pr_time_read", "pr_time_batch_gemm", "pr_time_gram_gemm", "pr_batch_union_size", "pr_time_prox", "pr_batch_tuning", "pr_gemm", "pr_mlp_features", "pr_mlp_forward",
            "pr_mlp_workspace", "pr_mlp_grad", "pr_mlp_adam", "pr_mlp_warm_start", "pr_bnb_opts_default", "pr_bnb", "pr_prox_noalloc", "pr_ctx_set_debug", "pr_lasso_solve", "pr_strerror"]
 
 MLP_NFEAT, MLP_NPARAM = 8, 4801
@@ -123,6 +123,9 @@ def load():
         L.pr_time_gemv_t.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         L.pr_time_gemv.restype = ctypes.c_int
         L.pr_time_gemv.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.pr_time_read.restype = ctypes.c_int
+        L.pr_time_read.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P,
+                                   ctypes.POINTER(ctypes.c_double)]
         L.pr_lasso_solve.restype = ctypes.c_int
         L.pr_lasso_solve.argtypes = [P, ctypes.POINTER(PrLasso), ctypes.POINTER(PrOpts), P, P, P,
                                      ctypes.POINTER(PrResult)]
@@ -503,6 +506,15 @@ def time_prox(v, rho, k, M, status, reps=20):
                                _dptr(status.contiguous()), _dptr(out), int(reps), ctypes.byref(a), ctypes.byref(b)),
            "pr_time_prox")
     return out, a.value, b.value
+
+
+def time_read(buf, blocks, unroll=1, reps=20):
+    """ms per plain streaming read of the CUDA tensor `buf` (pr_time_read,
+    on the current stream)."""
+    ms = ctypes.c_double()
+    _check(load().pr_time_read(_dptr(buf), buf.numel() * buf.element_size(), int(blocks), int(unroll), int(reps),
+                               _stream_ptr(), ctypes.byref(ms)), "pr_time_read")
+    return ms.value
 
 
 def gemm(A, B, KS=1):

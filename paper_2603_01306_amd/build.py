@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpr.so")
 SOURCES = ["pr_gemv.hip", "pr_spfwd.hip", "pr_node.hip", "pr_api.hip", "pr_batch.hip", "pr_mlp.hip", "pr_bnb.hip",
-           "pr_noalloc.hip", "pr_variants.hip"]
+           "pr_noalloc.hip", "pr_variants.hip", "pr_read.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code.

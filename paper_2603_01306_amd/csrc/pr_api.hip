@@ -1631,6 +1631,30 @@ int pr_time_gemv(pr_ctx *c, const double *b, double *u, int32_t reps, double *ms
   return PR_OK;
 }
 
+int pr_time_read(const void *buf, int64_t bytes, int32_t blocks, int32_t unroll, int32_t reps, void *stream,
+                 double *ms_avg) {
+  if (!buf || ((uintptr_t)buf) % 16 || bytes < 16 || bytes % 16 || blocks < 1 || blocks > (1 << 20) ||
+      (unroll != 1 && unroll != 4) || reps < 1 || !ms_avg)
+    return PR_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int rc = PR_OK;
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) rc = PR_EDEVICE;
+  const int64_t n16 = bytes / 16;
+  if (rc == PR_OK && launch_read_stream(buf, n16, blocks, unroll, s) != hipSuccess) rc = PR_EDEVICE;
+  if (rc == PR_OK && hipEventRecord(ev[0], s) != hipSuccess) rc = PR_EDEVICE;
+  for (int i = 0; rc == PR_OK && i < reps; i++)
+    if (launch_read_stream(buf, n16, blocks, unroll, s) != hipSuccess) rc = PR_EDEVICE;
+  if (rc == PR_OK && hipEventRecord(ev[1], s) != hipSuccess) rc = PR_EDEVICE;
+  if (rc == PR_OK && hipEventSynchronize(ev[1]) != hipSuccess) rc = PR_EDEVICE;
+  float ms = 0.0f;
+  if (rc == PR_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) rc = PR_EDEVICE;
+  if (rc == PR_OK) *ms_avg = (double)ms / reps;
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return rc;
+}
+
 int pr_batch_tuning(pr_ctx *c, int32_t len, int32_t *ksf_out, int32_t *kst_out) {
   if (!c || !c->batch_ok || len < 1 || !ksf_out || !kst_out) return PR_EINVAL;
   for (int32_t i = 0; i < len; i++) {

@@ -183,6 +183,7 @@ hipError_t launch_gemv_t(const Problem &P, const double *r1, const double *r2, d
 // u_partials / finalize: generic column-list GEMV u = sum_t X[:, idx[t]] * val[t]
 // followed by the per-row-block epilogue selected by `mode`.
 enum SpMode : int32_t { kSpPlain = 0, kSpLsq = 1, kSpLogistic = 2, kSpGram = 3 };
+hipError_t launch_read_stream(const void *buf, int64_t n16, int blocks, int unroll, hipStream_t s);
 hipError_t launch_spfwd(const Problem &P, const ProbBufs &B, const int32_t *idx, const double *val,
                         const int32_t *nlist, int32_t mode, const NodeState *S, double *u_out,
                         hipStream_t s);

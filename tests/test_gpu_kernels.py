@@ -197,6 +197,36 @@ def test_gemv_t2_matches_oracle(dev, storage, n, p):
     ctx.close()
 
 
+def test_time_read_reads_only_and_rejects_bad_arguments(dev):
+    """pr_time_read (the streaming-read rate the HBM-bound kernels are
+    compared with): a positive time on both unroll forms and on grids whose
+    stride leaves a ragged tail, the buffer unchanged, a read of 1 GiB no
+    faster than 10 TB/s (a kernel whose loads were dropped), and PR_EINVAL before
+    any launch for a length that is not a multiple of 16 bytes, an unaligned
+    buffer, another unroll, an empty grid and zero repetitions."""
+    import ctypes
+    import torch
+    import paper_2603_01306_amd as pr
+    buf = torch.arange(1 << 20, dtype=torch.float32, device=dev)   # 4 MiB
+    ref = buf.clone()
+    for blocks, unroll in ((1, 1), (7, 4), (4096, 1), (3, 1)):
+        assert pr.time_read(buf, blocks, unroll, reps=2) > 0.0
+    torch.cuda.synchronize()
+    assert torch.equal(buf, ref)
+    # the loads are really issued: 1 GiB (4x the last-level cache) cannot be
+    # read faster than 10 TB/s, above the HBM peak
+    big = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
+    assert pr.time_read(big, 2048, 1, reps=3) >= (1 << 30) / 10e12 * 1e3
+    del big
+    lib = pr.load()
+    ms = ctypes.c_double()
+    base = buf.data_ptr()
+    for args in ((base, 24, 1, 1, 1), (base + 4, 16, 1, 1, 1), (base, 16, 1, 3, 1), (base, 16, 0, 1, 1),
+                 (base, 16, 1, 1, 0), (None, 16, 1, 1, 1)):
+        ptr = ctypes.c_void_p(args[0]) if args[0] is not None else None
+        assert lib.pr_time_read(ptr, args[1], args[2], args[3], args[4], None, ctypes.byref(ms)) == -1, args
+
+
 @pytest.mark.parametrize("n,p,corr,storage", [(2048, 512, 0.9, "f32"), (64, 1000, 0.5, "f64"), (300, 1, 0.0, "f64"),
                                                (1000, 3, 0.99, "f64"), (4096, 2048, 0.5, "bf16")])
 def test_norm2_matches_exact_eigenvalue(dev, n, p, corr, storage):
