@@ -25,7 +25,7 @@ namespace {
 using namespace dev;
 
 constexpr int kSpInFlight = 16;   // columns in flight per lane
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 128;  // 2 waves: twice the workgroups of 256, more CUs on the partial planes
 constexpr int kFinRows = 2;       // rows per thread in the finalize kernel
 
 // 16 raw bytes of X and their FP64 value e (exact upcast)

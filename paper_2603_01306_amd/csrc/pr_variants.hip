@@ -29,7 +29,7 @@ namespace {
 using namespace dev;
 
 constexpr int kRows = 2;          // rows per thread of k_ac_resid (the spfwd finalize layout)
-constexpr int kResidThreads = 256;
+constexpr int kResidThreads = 128;  // the spfwd finalize's block (B.nfin blocks cover n)
 
 __device__ __forceinline__ int compact_list(const double *__restrict__ x, int64_t p, int32_t *__restrict__ sidx,
                                             double *__restrict__ sval, int *scan) {
@@ -550,6 +550,7 @@ hipError_t launch_ac_init(const NodeParams *prm, NodeState *S, AcState *A, const
 hipError_t launch_ac_resid(const Problem &P, const ProbBufs &B, const double *uz, double *ucur, const NodeState *S,
                            const AcState *A, hipStream_t s) {
   const int blocks = (int)((P.n + kResidThreads * kRows - 1) / (kResidThreads * kRows));
+  if (blocks != B.nfin) return hipErrorInvalidValue;  // rbsum holds B.nfin block sums
   k_ac_resid<<<blocks, kResidThreads, 0, s>>>(P.n, P.y, P.loss, B, uz, ucur, S, A);
   return hipGetLastError();
 }
